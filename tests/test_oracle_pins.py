@@ -1,0 +1,364 @@
+"""Pins of the FP64 oracle against closed forms, invariants and brute force.
+
+Karp et al., arXiv 2207.07098, Sec. II-A fixes the operator: GLL basis,
+D[i,j] = l'_j(xi_i), G_st = rho_i rho_j rho_k J sum_l dr_s/dx_l dr_t/dx_l,
+w = D^T G D u per element (Eq. (9)), continuity across elements (Eq. (10)),
+direct stiffness summation QQ^T (Eqs. (11)-(12)).  The paper prints no
+worked numeric example, so every expected value below comes from a closed
+form, an identity of the discrete operator, an independent brute force, or
+a library routine (numpy) used as an independent derivation.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import fixtures as F
+import oracle
+from tests import bruteforce as BF
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_gll_golden():
+    out = {}
+    for line in open(os.path.join(GOLD, "gll_closed_forms.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        n, nodes, w = line.split("|")
+        ev = lambda s: [eval(t, {"sqrt": math.sqrt}) for t in s.split(",")]
+        out[int(n)] = (np.array(ev(nodes)), np.array(ev(w)))
+    return out
+
+
+def _read_dhat_golden():
+    mats, cur = [], []
+    for line in open(os.path.join(GOLD, "dhat_closed_forms.txt")):
+        if line.startswith("#"):
+            continue
+        if not line.strip():
+            if cur:
+                mats.append(np.array(cur))
+                cur = []
+            continue
+        cur.append([eval(t) for t in line.split(",")])
+    if cur:
+        mats.append(np.array(cur))
+    return {m.shape[0] - 1: m for m in mats}
+
+
+# ---------------------------------------------------------------- O1: GLL
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+def test_gll_closed_forms(N):
+    xi, rho = oracle.gll(N)
+    gx, gw = _read_gll_golden()[N]
+    np.testing.assert_allclose(xi, gx, atol=1e-15)
+    np.testing.assert_allclose(rho, gw, rtol=1e-14)
+
+
+@pytest.mark.parametrize("N", range(1, 16))
+def test_gll_against_numpy_and_exactness(N):
+    xi, rho = oracle.gll(N)
+    nx, nw = BF.gll_numpy(N)
+    np.testing.assert_allclose(xi, nx, atol=1e-12)
+    np.testing.assert_allclose(rho, nw, atol=1e-11)
+    assert abs(rho.sum() - 2.0) < 1e-13
+    # exact for polynomials of degree <= 2N-1
+    for k in range(2 * N):
+        exact = (1 - (-1) ** (k + 1)) / (k + 1)
+        assert abs(np.dot(rho, xi ** k) - exact) < 1e-12
+    # and not exact at degree 2N (GLL, not Gauss)
+    exact = 2.0 / (2 * N + 1)
+    assert abs(np.dot(rho, xi ** (2 * N)) - exact) > 1e-10
+
+
+# ---------------------------------------------------------------- O2: D
+@pytest.mark.parametrize("N", [1, 2])
+def test_dhat_closed_forms(N):
+    np.testing.assert_allclose(oracle.dhat(N), _read_dhat_golden()[N], atol=1e-15)
+
+
+@pytest.mark.parametrize("N", range(1, 16))
+def test_dhat_differentiates_polynomials(N):
+    xi, _ = oracle.gll(N)
+    D = oracle.dhat(N, xi)
+    for k in range(N + 1):
+        d = D @ xi ** k
+        ref = k * xi ** (k - 1) if k else np.zeros_like(xi)
+        assert np.max(np.abs(d - ref)) < 2e-12 * max(1, N ** 2)
+    # independent numpy derivation of l'_j(xi_i)
+    np.testing.assert_allclose(D, BF.deriv_matrix_numpy(xi), atol=1e-10 * N ** 2)
+
+
+@pytest.mark.parametrize("N", [2, 5, 7, 9])
+def test_1d_stiffness_against_gauss_quadrature(N):
+    """K = D^T W D equals int l'_a l'_b exactly (degree 2N-2 <= 2N-1)."""
+    xi, rho = oracle.gll(N)
+    D = oracle.dhat(N, xi)
+    K = D.T @ np.diag(rho) @ D
+    gx, gw = np.polynomial.legendre.leggauss(N + 2)
+    basis = BF.lagrange_basis(xi)
+    dB = np.array([b.deriv()(gx) for b in basis])
+    Kex = (dB * gw) @ dB.T
+    np.testing.assert_allclose(K, Kex, atol=1e-11 * N ** 3)
+
+
+# ---------------------------------------------------------------- O4/O5: G, Ax
+def test_affine_geometric_factors_closed_form():
+    N = 4
+    hx, hy, hz = 0.7, 1.3, 2.1
+    m = F.box(1, lo=(0.2, -0.1, 0.5), hi=(0.2 + hx, -0.1 + hy, 0.5 + hz))
+    P = oracle.setup(m, N)
+    w = P.rho
+    W3 = np.kron(w, np.kron(w, w))
+    G = P.G[0]
+    np.testing.assert_allclose(G[0], W3 * hy * hz / (2 * hx), rtol=1e-13)
+    np.testing.assert_allclose(G[1], W3 * hx * hz / (2 * hy), rtol=1e-13)
+    np.testing.assert_allclose(G[2], W3 * hx * hy / (2 * hz), rtol=1e-13)
+    assert np.max(np.abs(G[3:])) < 1e-14
+    np.testing.assert_allclose(P.B[0], W3 * hx * hy * hz / 8, rtol=1e-13)
+
+
+def test_affine_element_matrix_kronecker():
+    """A^e = c_x W(x)W(x)K + c_y W(x)K(x)W + c_z K(x)W(x)W, i fastest."""
+    N = 3
+    hx, hy, hz = 0.5, 1.5, 0.8
+    m = F.box(1, hi=(hx, hy, hz))
+    P = oracle.setup(m, N)
+    W = np.diag(P.rho)
+    K = P.D.T @ W @ P.D
+    cx, cy, cz = hy * hz / (2 * hx), hx * hz / (2 * hy), hx * hy / (2 * hz)
+    Aref = (cx * np.kron(W, np.kron(W, K)) + cy * np.kron(W, np.kron(K, W))
+            + cz * np.kron(K, np.kron(W, W)))
+    n = (N + 1) ** 3
+    cols = []
+    for a in range(n):
+        cols.append(oracle.ax_local(N, P.G, np.eye(n)[a][None], P.D)[0])
+    Ae = np.array(cols).T
+    np.testing.assert_allclose(Ae, Aref, atol=1e-13 * np.abs(Aref).max())
+
+
+def _dense(P):
+    return np.stack([P.apply(e) for e in np.eye(P.n_u)], axis=1)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_curvilinear_against_dense_bruteforce(seed):
+    """Oracle A (matrix-free, lattice numbering) vs numpy quadrature assembly
+    (coordinate numbering) on a deformed, re-oriented 2^3 mesh, N = 3."""
+    N = 3
+    m = F.box(2, hi=(2 * np.pi,) * 3, deform=0.15, reorient_seed=seed,
+              dirichlet=(0,) * 6)
+    P = oracle.setup(m, N)
+    Ao = _dense(P)
+    xi_np, _ = BF.gll_numpy(N)
+    Ab, gid_b = BF.assemble(m.coords(xi_np), N)
+    # the two numberings must be related by a bijection
+    perm = np.full(P.n_u, -1)
+    perm[P.gid.ravel()] = gid_b.ravel()
+    assert (perm >= 0).all() and len(set(perm.tolist())) == P.n_u == Ab.shape[0]
+    for e_, (go, gb) in enumerate(zip(P.gid, gid_b)):
+        assert np.array_equal(perm[go], gb)
+    Ab_perm = Ab[np.ix_(perm, perm)]
+    np.testing.assert_allclose(Ao, Ab_perm, atol=1e-11 * np.abs(Ab).max())
+
+
+def test_rotation_invariance():
+    N = 4
+    m = F.box(2, hi=(2 * np.pi,) * 3, deform=0.1, dirichlet=(0,) * 6)
+    xi, _ = oracle.gll(N)
+    X = m.coords(xi)
+    th = 0.7
+    Q = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1]])
+    Q = Q @ np.array([[1, 0, 0], [0, np.cos(0.3), -np.sin(0.3)], [0, np.sin(0.3), np.cos(0.3)]])
+    Xr = np.einsum("ab,ebkji->eakji", Q, X) + np.array([1.0, -2.0, 3.0])[None, :, None, None, None]
+    P1 = oracle.setup(m, N, xyz=X)
+    P2 = oracle.setup(m, N, xyz=Xr)
+    u = np.random.default_rng(3).standard_normal(P1.n_u)
+    np.testing.assert_allclose(P1.apply(u), P2.apply(u), atol=1e-11 * np.abs(P1.apply(u)).max())
+
+
+@pytest.mark.parametrize("N", [2, 5])
+def test_symmetric_spd_and_constant_nullspace(N):
+    m = F.box(2, hi=(2 * np.pi,) * 3, deform=0.1, reorient_seed=7, dirichlet=(0,) * 6)
+    P = oracle.setup(m, N)
+    A = _dense(P)
+    sc = np.abs(A).max()
+    assert np.abs(A - A.T).max() < 1e-13 * sc
+    assert np.abs(A @ np.ones(P.n_u)).max() < 1e-12 * sc     # A 1 = 0 (Neumann)
+    ev = np.linalg.eigvalsh(A)
+    assert abs(ev[0]) < 1e-11 * sc and ev[1] > 1e-8 * sc
+    # with Dirichlet on all faces: SPD on the unmasked block
+    md = F.box(2, hi=(2 * np.pi,) * 3, deform=0.1, reorient_seed=7)
+    Pd = oracle.setup(md, N)
+    Ad = _dense(Pd)
+    keep = Pd.dirichlet == 0
+    np.linalg.cholesky(Ad[np.ix_(keep, keep)])
+    assert np.abs(Ad[~keep]).max() == 0 and np.abs(Ad[:, ~keep]).max() == 0
+
+
+@pytest.mark.parametrize("deform", [0.0, 0.15])
+def test_linear_fields_energy_identity(deform):
+    """For u = a.x (nodal coordinates), u^T A v = (a.b) sum(B): the
+    discrete gradient of a coordinate is exact, so G contracts to rho^3 J."""
+    N = 5
+    m = F.box(2, hi=(2 * np.pi,) * 3, deform=deform, reorient_seed=2, dirichlet=(0,) * 6)
+    P = oracle.setup(m, N)
+    coords = np.zeros((3, P.n_u))
+    for d in range(3):
+        coords[d, P.gid.ravel()] = P.xyz[:, d].reshape(-1)
+    a = np.array([1.0, 2.0, -0.5])
+    b = np.array([0.3, -1.0, 2.0])
+    ua, ub = a @ coords, b @ coords
+    volq = P.B.sum()
+    assert abs(ua @ P.apply(ua) - (a @ a) * volq) < 1e-10 * volq
+    assert abs(ub @ P.apply(ua) - (a @ b) * volq) < 1e-10 * volq
+    assert abs(coords[0] @ P.apply(coords[1])) < 1e-10 * volq
+    if deform == 0.0:
+        assert abs(volq - (2 * np.pi) ** 3) < 1e-10
+
+
+# ---------------------------------------------------------------- O6: numbering
+@pytest.mark.parametrize("K,N", [(1, 3), (2, 2), (3, 4), (4, 5)])
+def test_box_multiplicity_closed_forms(K, N):
+    m = F.box(K)
+    gid, nu = oracle.number(N, m)
+    assert nu == (K * N + 1) ** 3
+    mult, dm = oracle.mult_mask(N, gid, m.face_bc, nu)
+    a = K * N + 1 - (K - 1)
+    counts = np.bincount(mult, minlength=9)
+    assert counts[8] == (K - 1) ** 3
+    assert counts[4] == 3 * (K - 1) ** 2 * a
+    assert counts[2] == 3 * (K - 1) * a ** 2
+    assert counts[1] == a ** 3
+    assert mult.sum() == K ** 3 * (N + 1) ** 3
+    assert dm.sum() == (K * N + 1) ** 3 - (K * N - 1) ** 3
+    # first-appearance order: ids appear in increasing order
+    first = np.unique(gid.ravel(), return_index=True)[1]
+    assert np.all(np.diff(first) > 0)
+
+
+def test_config_sizes():
+    assert oracle.number(5, F.box(4))[1] == 9261
+    assert oracle.number(7, F.box(16))[1] == 1442897
+
+
+def test_ogrid_numbering_periodic():
+    Ka, Kr, Kz, N = 8, 3, 4, 3
+    m = F.ogrid(Ka, Kr, Kz)
+    gid, nu = oracle.number(N, m)
+    assert nu == (Kr * N + 1) * (Ka * N) * (Kz * N)
+    mult, dm = oracle.mult_mask(N, gid, m.face_bc, nu)
+    assert dm.sum() == (Ka * N) * (Kz * N)
+    # coordinates of all copies of a node coincide, modulo the z period
+    xi, _ = oracle.gll(N)
+    X = m.coords(xi).reshape(m.num_elements, 3, -1)
+    ref = np.full((nu, 3), np.nan)
+    for e in range(m.num_elements):
+        for l in range(X.shape[2]):
+            g = gid[e, l]
+            p = X[e, :, l].copy()
+            p[2] = p[2] % (2 * np.pi)
+            if np.isnan(ref[g, 0]):
+                ref[g] = p
+            else:
+                d = np.abs(ref[g] - p)
+                d[2] = min(d[2], 2 * np.pi - d[2])
+                assert d.max() < 1e-9
+
+
+# ---------------------------------------------------------------- O9: Jacobi
+def test_jacobi_diagonal_equals_dense_diagonal():
+    m = F.box(2, hi=(1.0, 2.0, 1.5), deform=0.0, reorient_seed=5)
+    for N in (2, 4):
+        P = oracle.setup(m, N)
+        A = _dense(P)
+        keep = P.dirichlet == 0
+        np.testing.assert_allclose(P.diag[keep], np.diag(A)[keep], rtol=1e-13)
+        assert (P.dinv[~keep] == 0).all()
+    m2 = F.box(2, hi=(2 * np.pi,) * 3, deform=0.2, reorient_seed=4)
+    P = oracle.setup(m2, 3)
+    A = _dense(P)
+    keep = P.dirichlet == 0
+    np.testing.assert_allclose(P.diag[keep], np.diag(A)[keep], rtol=1e-12)
+
+
+# ---------------------------------------------------------------- O11: PCG
+def test_pcg_matches_dense_solve():
+    m = F.box(2, hi=(2 * np.pi,) * 3, deform=0.1, reorient_seed=1)
+    P = oracle.setup(m, 4)
+    f = F.random_unique(P.n_u, 5)
+    b = P.rhs_unique(f)
+    x, info = P.pcg(b, 1e-12)
+    assert info["status"] == 0 and info["true_rel_residual"] <= 1e-12
+    A = _dense(P)
+    keep = P.dirichlet == 0
+    xs = np.zeros(P.n_u)
+    xs[keep] = np.linalg.solve(A[np.ix_(keep, keep)], b[keep])
+    kappa = np.linalg.cond(A[np.ix_(keep, keep)])
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < kappa * 1e-12 * 10
+
+
+def test_pcg_a_norm_error_monotone():
+    m = F.box(3, hi=(1.0, 1.0, 1.0))
+    P = oracle.setup(m, 3)
+    b = P.rhs_unique(F.random_unique(P.n_u, 1))
+    xs, _ = P.pcg(b, 1e-14)
+    errs = []
+    for it in range(1, 25):
+        x, info = P.pcg(b, 1e-30, max_iter=it, max_restart=0)
+        e = x - xs
+        errs.append(e @ P.apply(e))
+    assert all(errs[i + 1] <= errs[i] * (1 + 1e-9) for i in range(len(errs) - 1))
+
+
+def test_pcg_reports_non_convergence():
+    m = F.box(2)
+    P = oracle.setup(m, 4)
+    b = P.rhs_unique(F.random_unique(P.n_u, 0))
+    x, info = P.pcg(b, 1e-12, max_iter=3, max_restart=0)
+    assert info["status"] == 1 and info["iterations"] == 3
+
+
+def _manufactured_error(K, N):
+    w = F.unit_cube(K, N)
+    P = oracle.setup(w.mesh, N)
+    fL = w.f_local(P.xyz)
+    b = P.rhs_local(fL)
+    x, info = P.pcg(b, 1e-13)
+    ue = np.zeros(P.n_u)
+    ue[P.gid.ravel()] = w.u_exact(P.xyz).ravel()
+    return np.max(np.abs(x - ue))
+
+
+def test_manufactured_spectral_convergence():
+    """Error of the sin(pi x) sin(pi y) sin(pi z) solution decays
+    exponentially in N at fixed K and like h^(N+1) at fixed N."""
+    errs = [_manufactured_error(2, N) for N in (3, 5, 7, 9)]
+    for a, b in zip(errs, errs[1:]):
+        assert b < a / 20
+    assert errs[-1] < 1e-7
+    e2, e4 = _manufactured_error(2, 3), _manufactured_error(4, 3)
+    assert e2 / e4 > 2 ** 3.2          # ~h^4 for N = 3
+
+
+# ---------------------------------------------------------------- low precision
+def test_bf16_rounding_emulation():
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 2 ** -7, 1.0 + 3 * 2 ** -8, -3.14159])
+    r = oracle.round_bf16(vals)
+    assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0 + 2 ** -7
+    assert r[3] == 1.0 + 2 ** -6          # tie rounds to even
+    assert abs(r[4] - (-3.140625)) < 1e-12
+
+
+def test_quantized_G_error_levels():
+    m = F.box(2, hi=(2 * np.pi,) * 3, deform=0.1)
+    P = oracle.setup(m, 5)
+    u = F.random_unique(P.n_u, 0)
+    y = P.apply(u)
+    for fmt, lo, hi in (("fp32", 1e-9, 1e-6), ("fp16", 1e-5, 3e-3), ("bf16", 1e-4, 3e-2)):
+        Gq = oracle.quantize_G(P.G, fmt)
+        Pq = oracle.Problem(**{**P.__dict__, "G": Gq})
+        err = np.max(np.abs(Pq.apply(u) - y)) / np.max(np.abs(y))
+        assert lo < err < hi, (fmt, err)
