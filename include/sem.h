@@ -1,0 +1,239 @@
+/*
+ * sem.h -- C ABI of libsem: the matrix-free spectral element Poisson solve
+ * (element Laplacian, direct stiffness summation, Jacobi-preconditioned CG)
+ * on an AMD Instinct MI355X (gfx950).
+ *
+ * The operator is the one of Karp et al., "Large-Scale Direct Numerical
+ * Simulations of Turbulence Using GPUs and Modern Fortran" (arXiv
+ * 2207.07098), Sec. II-A: on E hexahedral elements with a degree-N GLL
+ * basis, A_L = blockdiag(D^T G^e D) (Eq. (9)), u_L = Q u (Eq. (10)) and the
+ * assembled system Q^T A_L Q (Eqs. (11)-(12)).  Homogeneous Dirichlet
+ * conditions enter through a 0/1 mask M: the solved operator is
+ * A = M Q^T A_L Q M.  The Krylov solver is P-CG (Sec. II-B) with the exact
+ * point-Jacobi diagonal.
+ *
+ * Conventions
+ *   n1 = N+1; n_p = n1^3 points per element; n_local = E*n_p.
+ *   E-vector ("local") layout: [E][k][j][i], i fastest.
+ *   Unique vectors are in the library's SOLVER ORDER: first the nodes that
+ *   lie on an element boundary, in order of first appearance (elements
+ *   ascending, local index l = i + n1*(j + n1*k) ascending), then the
+ *   element-interior nodes element by element in l order.
+ *   sem_export_numbering() gives the canonical first-appearance numbering
+ *   and the permutation between the two orders.
+ *   Geometric factors: [E][6][n_p], components (11,22,33,12,13,23).
+ *   Device pointers must be 256-byte aligned device memory of the current
+ *   HIP device; host pointers are ordinary host memory.
+ *
+ * Errors: every call returns a sem_status; nothing aborts or throws across
+ * the ABI.  sem_last_error(ctx) (or NULL for errors without a context)
+ * returns a message describing the last failure on the calling thread.
+ * Validation happens before any device work.  Asynchronous device faults
+ * are reported by the next synchronising call.  A context is not
+ * thread-safe; distinct contexts may be used from distinct threads.
+ *
+ * Ownership: the context owns only host metadata.  All device memory is
+ * owned by the caller: one workspace buffer bound with sem_bind_workspace
+ * plus the vectors passed to each call.  The library never allocates
+ * device memory.
+ */
+#ifndef SEM_H
+#define SEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sem_ctx_s *sem_ctx;
+typedef void *sem_stream;               /* a hipStream_t; NULL = null stream */
+
+typedef enum {
+    SEM_OK = 0,
+    SEM_ERR_INVALID = 1,        /* bad argument or size                     */
+    SEM_ERR_MESH = 2,           /* inconsistent mesh or non-positive Jacobian */
+    SEM_ERR_DEVICE = 3,         /* a HIP call failed                         */
+    SEM_ERR_OOM = 4,            /* workspace too small                       */
+    SEM_ERR_NOT_CONVERGED = 5,  /* iteration cap reached                     */
+    SEM_ERR_BREAKDOWN = 6,      /* p^T A p <= 0 in CG                        */
+    SEM_ERR_NAN = 7,            /* NaN or Inf met in a solve                 */
+    SEM_ERR_UNSUPPORTED = 8,    /* unsupported order or precision            */
+    SEM_ERR_STATE = 9           /* call out of sequence (e.g. no workspace)  */
+} sem_status;
+
+typedef enum {
+    SEM_FP64 = 0,               /* FP64 factors, FP64 vectors                */
+    SEM_FP32 = 1,               /* FP32 factors, FP32 vectors                */
+    SEM_FP16_SCALED = 2,        /* FP16 factors / 2^ceil(log2 max|G_e|),
+                                   FP32 vectors, FP32 accumulation           */
+    SEM_BF16_SCALED = 3         /* same with bfloat16 factors                */
+} sem_precision;
+
+#define SEM_PREC_BIT(p) (1u << (p))
+
+/* Mesh description (host memory, read during sem_setup only). */
+typedef struct {
+    int64_t        num_elements;  /* E >= 1                                   */
+    const int64_t *corner_ids;    /* [E][8] global vertex ids, corner
+                                     c = a + 2b + 4c3 at reference position
+                                     (2a-1, 2b-1, 2c3-1); periodic twins share
+                                     ids; ids must be in [0, num_vertices)    */
+    const uint8_t *face_bc;       /* [E][6] faces (-r,+r,-s,+s,-t,+t):
+                                     1 = homogeneous Dirichlet, 0 = natural   */
+    int64_t        num_vertices;
+    const double  *vertex_xyz;    /* [num_vertices][3] or NULL; used by
+                                     sem_set_geometry(ctx, NULL, ..) for a
+                                     trilinear map                           */
+} sem_mesh;
+
+typedef struct {
+    unsigned precisions;          /* bitmask of SEM_PREC_BIT(p): operator
+                                     copies to build; FP64 is always built   */
+    int      solver;              /* 1: reserve CG/refinement work vectors    */
+} sem_options;
+
+typedef struct {
+    int     N;
+    int64_t num_elements;
+    int64_t n_local;              /* E * (N+1)^3                              */
+    int64_t n_unique;             /* unique nodes                             */
+    int64_t n_boundary;           /* unique nodes on element boundaries       */
+    int64_t n_dirichlet;          /* masked unique nodes                      */
+    int64_t n_bpoints;            /* boundary points per element              */
+} sem_info;
+
+/* 1D GLL nodes xi[0..N] and weights rho[0..N] as used by the library
+ * (Sec. II-A: the basis interpolates at the GLL points).  Host only.
+ * Returns SEM_ERR_UNSUPPORTED unless 1 <= N <= 15. */
+sem_status sem_gll(int N, double *xi, double *rho);
+
+/* Host-side set-up of a context for order N (1..15): validates the
+ * connectivity (ids in range, no repeated corner within an element, no
+ * face shared by more than two elements) and derives the numbering from
+ * corner ids (Eq. (10): copies of a node share its value).  Periodic
+ * directions need at least 3 elements (ids alone identify an edge).  Copies
+ * what it needs from *mesh.  No device work. */
+sem_status sem_setup(const sem_mesh *mesh, int N, const sem_options *opts,
+                     sem_ctx *out);
+void       sem_free(sem_ctx ctx);
+const char *sem_last_error(sem_ctx ctx);
+sem_status sem_query(sem_ctx ctx, sem_info *info);
+
+/* Host copies of the numbering (any pointer may be NULL):
+ *   gid_canonical [n_local]  canonical first-appearance id of each local point
+ *   solver_pos    [n_unique] solver-order position of canonical node g
+ *   dirichlet     [n_unique] 1 for masked nodes (canonical order)
+ *   mult          [n_unique] number of local copies (canonical order)    */
+sem_status sem_export_numbering(sem_ctx ctx, int32_t *gid_canonical,
+                                int32_t *solver_pos, uint8_t *dirichlet,
+                                int32_t *mult);
+
+/* Device workspace: size for this context, then bind a caller-owned device
+ * buffer of at least that many bytes (256-byte aligned).  Binding uploads
+ * the gather-scatter maps and the derivative matrix on `stream`. */
+sem_status sem_workspace_size(sem_ctx ctx, size_t *bytes);
+sem_status sem_bind_workspace(sem_ctx ctx, void *dev_ptr, size_t bytes,
+                              sem_stream stream);
+
+/* Geometry (Sec. II-A, definition of G after Eq. (9)): from host
+ * coordinates gll_xyz [E][3][n_p] evaluated at the library's GLL nodes
+ * (sem_gll), or from the trilinear vertex map when gll_xyz is NULL,
+ * computes on the device the factors G (every configured precision), the
+ * lumped mass B = rho_i rho_j rho_k J and the Jacobi inverse diagonal.
+ * Returns SEM_ERR_MESH (message names the element) when J <= 0 anywhere.
+ * Synchronises `stream`. */
+sem_status sem_set_geometry(sem_ctx ctx, const double *gll_xyz,
+                            sem_stream stream);
+
+/* Host copies of G [E][6][n_p], B [E][n_p] (FP64) and dinv [n_unique]
+ * (solver order); any pointer may be NULL.  Synchronises `stream`. */
+sem_status sem_export_geometry(sem_ctx ctx, double *G, double *B,
+                               double *dinv, sem_stream stream);
+
+/* Element-local operator w_L = A_L u_L (Eq. (9) per element; the paper's
+ * ax_t%compute).  u_L, w_L: device E-vectors, double for SEM_FP64, float
+ * otherwise.  No masking, no summation.  Stream-ordered, asynchronous. */
+sem_status sem_ax_local(sem_ctx ctx, const void *u_L, void *w_L,
+                        sem_precision prec, sem_stream stream);
+
+/* Direct stiffness summation in place on an E-vector, v_L <- Q M Q^T v_L
+ * (Eq. (12), the paper's gs_t, with the Dirichlet mask).  Deterministic:
+ * copies are summed in ascending local order.  double for SEM_FP64, float
+ * for SEM_FP32.  Stream-ordered, asynchronous. */
+sem_status sem_gs(sem_ctx ctx, void *v_L, sem_precision prec,
+                  sem_stream stream);
+
+/* Q and M Q^T between unique (solver order) and E-vectors, FP64. */
+sem_status sem_gather(sem_ctx ctx, const double *u, double *u_L,
+                      sem_stream stream);
+sem_status sem_scatter(sem_ctx ctx, const double *w_L, double *y,
+                       sem_stream stream);
+
+#define SEM_AX_DETERMINISTIC 1u   /* fixed-order summation instead of atomics */
+#define SEM_AX_Y_ZEROED      2u   /* caller guarantees y[0:n_boundary) == 0 on
+                                     entry (e.g. cleared by a fused preceding
+                                     kernel); skips the clearing pass        */
+
+/* Assembled operator on unique vectors: y = M Q^T A_L Q M u (Eqs. (11)-(12)
+ * with the mask), fused in one pass over the elements.  u and y are device
+ * vectors of n_unique entries (solver order), double for SEM_FP64 and float
+ * otherwise; u and y must not overlap.  With SEM_AX_DETERMINISTIC the
+ * summation of element contributions runs in a fixed order (bit-identical
+ * repeats); by default contributions to shared nodes are added with device
+ * atomics into y, whose element-boundary block is cleared first unless
+ * SEM_AX_Y_ZEROED is given.  Stream-ordered, asynchronous. */
+sem_status sem_ax(sem_ctx ctx, const void *u, void *y, sem_precision prec,
+                  unsigned flags, sem_stream stream);
+
+/* Right-hand side b = M Q^T (B_L f_L) with the GLL-lumped mass.  Exactly
+ * one of f_L (device E-vector) and f (device unique vector, solver order;
+ * f_L = Q f) is non-NULL.  FP64. */
+sem_status sem_rhs(sem_ctx ctx, const double *f_L, const double *f,
+                   double *b, sem_stream stream);
+
+typedef struct {
+    double        tol;            /* target ||b - A x||_2 / ||b||_2          */
+    int64_t       max_iter;       /* cap on CG iterations (all levels)       */
+    sem_precision precision;      /* SEM_FP64: plain PCG; otherwise FP64
+                                     iterative refinement around an inner
+                                     PCG in that precision                  */
+    double        inner_tol;      /* inner relative tolerance (refinement)   */
+    int           max_outer;      /* cap on refinement steps                 */
+    int           check_every;    /* CG iterations between convergence polls */
+    int           use_graph;      /* capture check_every iterations in a
+                                     hipGraph and replay it                  */
+    int           zero_guess;     /* 1: start from x = 0 (x is output only)  */
+    int           deterministic;  /* fixed-order summation everywhere        */
+    int           max_restart;    /* FP64 restarts when the true residual
+                                     misses tol after convergence           */
+} sem_solve_options;
+
+typedef struct {
+    sem_status status;
+    int64_t    iterations;        /* CG iterations, all levels               */
+    int        outer_iterations;  /* refinement steps (0 for plain PCG)      */
+    int        restarts;
+    double     true_rel_residual; /* FP64 ||b - A x|| / ||b|| at exit        */
+    double     rel_residual;      /* last recurrence residual estimate       */
+    double     seconds;           /* wall time of the call                   */
+} sem_solve_info;
+
+void sem_default_solve_options(sem_solve_options *opts);
+
+/* Solve A x = b (b: device, unique, solver order, masked; x: device, in:
+ * initial guess unless zero_guess, out: solution).  FP64 vectors.  Blocks
+ * until convergence or failure; the only device-to-host traffic is one
+ * status poll every check_every iterations.  Returns SEM_OK on convergence,
+ * else SEM_ERR_NOT_CONVERGED / SEM_ERR_BREAKDOWN / SEM_ERR_NAN with *info
+ * filled in either case.  Needs opts.solver = 1 at set-up and, for a
+ * reduced-precision solve, that precision among opts.precisions. */
+sem_status sem_cg_solve(sem_ctx ctx, const double *b, double *x,
+                        const sem_solve_options *opts, sem_solve_info *info,
+                        sem_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEM_H */

@@ -1,0 +1,915 @@
+// Host side of libsem: reference-element data, numbering from corner ids,
+// workspace layout, and the C ABI entry points declared in sem.h.
+//
+// The operator follows Karp et al. (arXiv 2207.07098), Sec. II-A; the
+// solver is the P-CG of Sec. II-B with a point-Jacobi preconditioner.
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+
+#include "sem_internal.h"
+
+using namespace sem;
+
+namespace sem {
+
+static thread_local std::string g_last_error;
+
+sem_status fail(sem_ctx ctx, sem_status st, const std::string &msg) {
+    g_last_error = msg;
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+}  // namespace sem
+
+// ---------------------------------------------------------------------------
+// Reference element.
+//
+// GLL nodes are the N+1 roots of q(x) = P_{N+1}(x) - P_{N-1}(x), which is a
+// multiple of (1 - x^2) P_N'(x); q'(x) = (2N+1) P_N(x), so Newton's method
+// needs only P_N.  Weights 2 / (N(N+1) P_N(xi)^2).  The derivative matrix
+// l'_j(xi_i) uses barycentric weights, with the diagonal set to minus the
+// off-diagonal row sum so that D applied to a constant vanishes.
+// ---------------------------------------------------------------------------
+static void legendre_pair(int n, double x, double *pn, double *pnm1, double *pnp1) {
+    // returns P_{n-1}, P_n, P_{n+1}
+    double a = 1.0, b = x;        // P_0, P_1
+    if (n == 0) { *pnm1 = 0.0; *pn = 1.0; *pnp1 = x; return; }
+    for (int k = 1; k <= n; ++k) {
+        double c = ((2.0 * k + 1.0) * x * b - k * a) / (k + 1.0);
+        a = b;
+        b = c;
+    }
+    // now a = P_n, b = P_{n+1}; recompute P_{n-1} by one backward step
+    *pn = a;
+    *pnp1 = b;
+    // P_{n-1} = ((2n+1) x P_n - (n+1) P_{n+1}) / n
+    *pnm1 = ((2.0 * n + 1.0) * x * a - (n + 1.0) * b) / n;
+}
+
+extern "C" sem_status sem_gll(int N, double *xi, double *rho) {
+    if (N < 1 || N >= kMaxN1) return fail(nullptr, SEM_ERR_UNSUPPORTED, "N must be in 1..15");
+    if (!xi || !rho) return fail(nullptr, SEM_ERR_INVALID, "null output");
+    for (int i = 0; i <= N; ++i) {
+        double x = -std::cos(M_PI * i / N);
+        if (i > 0 && i < N) {
+            for (int it = 0; it < 60; ++it) {
+                double pn, pm, pp;
+                legendre_pair(N, x, &pn, &pm, &pp);
+                double dx = (pp - pm) / ((2.0 * N + 1.0) * pn);
+                x -= dx;
+                if (std::fabs(dx) <= 1e-17) break;
+            }
+        }
+        xi[i] = x;
+    }
+    for (int i = 0; i < (N + 1) / 2; ++i) {     // exact antisymmetry
+        double h = 0.5 * (xi[N - i] - xi[i]);
+        xi[i] = -h;
+        xi[N - i] = h;
+    }
+    if (N % 2 == 0) xi[N / 2] = 0.0;
+    for (int i = 0; i <= N; ++i) {
+        double pn, pm, pp;
+        legendre_pair(N, xi[i], &pn, &pm, &pp);
+        rho[i] = 2.0 / (N * (N + 1.0) * pn * pn);
+    }
+    return SEM_OK;
+}
+
+static void derivative_matrix(int N, const double *xi, double *D) {
+    int n1 = N + 1;
+    double lam[kMaxN1];
+    for (int j = 0; j < n1; ++j) {
+        double p = 1.0;
+        for (int k = 0; k < n1; ++k)
+            if (k != j) p *= (xi[j] - xi[k]);
+        lam[j] = 1.0 / p;
+    }
+    for (int i = 0; i < n1; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < n1; ++j) {
+            if (j == i) continue;
+            double v = (lam[j] / lam[i]) / (xi[i] - xi[j]);
+            D[i * n1 + j] = v;
+            s += v;
+        }
+        D[i * n1 + i] = -s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Numbering (Eq. (10): local copies of a physical node share one value).
+//
+// Each GLL point of an element is classified by how many of its indices sit
+// on the element boundary: 3 -> a vertex (keyed by its corner id), 2 -> an
+// edge (keyed by the sorted pair of end-vertex ids and the position measured
+// from the smaller id), 1 -> a face (keyed by the sorted four corner ids and
+// the position in a frame anchored at the smallest id, first axis towards
+// the smaller of its two neighbours), 0 -> an element-interior node.  These
+// keys depend only on vertex ids, so every element sharing an entity sees
+// the same key for the same point whatever its local orientation.  The
+// canonical id is the order of first appearance; the solver order puts the
+// element-boundary nodes first and the interior nodes after them,
+// element by element.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct PairHash {
+    size_t operator()(const std::pair<int64_t, int64_t> &p) const {
+        uint64_t h = (uint64_t)p.first * 0x9E3779B97F4A7C15ull;
+        h ^= (uint64_t)p.second + 0x7F4A7C159E3779B9ull + (h << 6) + (h >> 2);
+        return (size_t)h;
+    }
+};
+struct Quad {
+    int64_t v[4];
+    bool operator==(const Quad &o) const {
+        return v[0] == o.v[0] && v[1] == o.v[1] && v[2] == o.v[2] && v[3] == o.v[3];
+    }
+};
+struct QuadHash {
+    size_t operator()(const Quad &q) const {
+        uint64_t h = 1469598103934665603ull;
+        for (int a = 0; a < 4; ++a) {
+            h ^= (uint64_t)q.v[a] + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+            h *= 1099511628211ull;
+        }
+        return (size_t)h;
+    }
+};
+
+inline int ring_index(int i, int j, int N) {
+    // position of boundary column (i,j) among the 4N boundary columns, l order
+    if (j == 0) return i;
+    if (j == N) return N + 1 + 2 * (N - 1) + i;
+    return N + 1 + 2 * (j - 1) + (i == 0 ? 0 : 1);
+}
+
+}  // namespace
+
+static sem_status build_numbering(sem_ctx c, const sem_mesh *m) {
+    const int N = c->N, n1 = c->n1, np = c->np;
+    const int64_t E = c->E;
+    const int64_t *C = m->corner_ids;
+    const int ne = N - 1;                    // interior points per edge
+    const int nf = ne * ne;                  // interior points per face
+
+    std::unordered_map<std::pair<int64_t, int64_t>, int64_t, PairHash> edges;
+    std::unordered_map<Quad, int64_t, QuadHash> faces;
+    edges.reserve((size_t)E * 4);
+    faces.reserve((size_t)E * 4);
+    std::vector<int32_t> edge_gid, face_gid;
+    std::vector<int8_t> face_users;
+    std::vector<int32_t> vert_gid((size_t)m->num_vertices, -1);
+    c->gid_canon.assign((size_t)c->n_local, 0);
+    std::vector<uint8_t> is_interior;
+    std::vector<uint8_t> dir;
+    std::vector<int32_t> mult;
+    is_interior.reserve((size_t)c->n_local / 2);
+    dir.reserve((size_t)c->n_local / 2);
+    mult.reserve((size_t)c->n_local / 2);
+    int64_t next = 0;
+    auto fresh = [&](bool interior) -> int32_t {
+        is_interior.push_back(interior);
+        dir.push_back(0);
+        mult.push_back(0);
+        return (int32_t)next++;
+    };
+    if ((double)c->n_local >= 2147483647.0)
+        return fail(c, SEM_ERR_UNSUPPORTED, "more than 2^31-1 local points");
+
+    // register faces first to validate conformity (each face used <= 2 times)
+    static const int fcorner[6][4] = {{0, 2, 4, 6}, {1, 3, 5, 7}, {0, 1, 4, 5},
+                                      {2, 3, 6, 7}, {0, 1, 2, 3}, {4, 5, 6, 7}};
+    for (int64_t e = 0; e < E; ++e) {
+        const int64_t *v = C + e * 8;
+        for (int a = 0; a < 8; ++a) {
+            if (v[a] < 0 || v[a] >= m->num_vertices)
+                return fail(c, SEM_ERR_MESH, "element " + std::to_string(e) +
+                                                  ": corner id out of range");
+            for (int b = 0; b < a; ++b)
+                if (v[a] == v[b])
+                    return fail(c, SEM_ERR_MESH, "element " + std::to_string(e) +
+                                                      ": repeated corner id");
+        }
+        for (int f = 0; f < 6; ++f) {
+            Quad q{{v[fcorner[f][0]], v[fcorner[f][1]], v[fcorner[f][2]], v[fcorner[f][3]]}};
+            std::sort(q.v, q.v + 4);
+            auto it = faces.find(q);
+            if (it == faces.end()) {
+                faces.emplace(q, (int64_t)face_users.size());
+                face_users.push_back(1);
+            } else if (++face_users[it->second] > 2) {
+                return fail(c, SEM_ERR_MESH, "face of element " + std::to_string(e) +
+                                                  " shared by more than two elements");
+            }
+        }
+    }
+    face_gid.assign(face_users.size() * (size_t)nf, -1);
+
+    for (int64_t e = 0; e < E; ++e) {
+        const int64_t *v = C + e * 8;
+        const uint8_t *fb = m->face_bc ? m->face_bc + e * 6 : nullptr;
+        for (int k = 0; k < n1; ++k)
+            for (int j = 0; j < n1; ++j)
+                for (int i = 0; i < n1; ++i) {
+                    const int l = i + n1 * (j + n1 * k);
+                    const int ext[3] = {i == 0 || i == N, j == 0 || j == N, k == 0 || k == N};
+                    const int nx = ext[0] + ext[1] + ext[2];
+                    int32_t g;
+                    if (nx == 3) {
+                        int cidx = (i == N) + 2 * (j == N) + 4 * (k == N);
+                        int32_t &slot = vert_gid[(size_t)v[cidx]];
+                        if (slot < 0) slot = fresh(false);
+                        g = slot;
+                    } else if (nx == 2) {
+                        int d = !ext[0] ? 0 : (!ext[1] ? 1 : 2);
+                        int pos = d == 0 ? i : (d == 1 ? j : k);
+                        int c0 = (d == 0 ? 0 : (i == N)) + (d == 1 ? 0 : 2 * (j == N)) +
+                                 (d == 2 ? 0 : 4 * (k == N));
+                        int c1 = c0 + (1 << d);
+                        int64_t a = v[c0], b = v[c1];
+                        if (a > b) { std::swap(a, b); pos = N - pos; }
+                        auto key = std::make_pair(a, b);
+                        auto it = edges.find(key);
+                        int64_t eidx;
+                        if (it == edges.end()) {
+                            eidx = (int64_t)edges.size();
+                            edges.emplace(key, eidx);
+                            edge_gid.resize((size_t)(eidx + 1) * ne, -1);
+                        } else {
+                            eidx = it->second;
+                        }
+                        int32_t &slot = edge_gid[(size_t)eidx * ne + (pos - 1)];
+                        if (slot < 0) slot = fresh(false);
+                        g = slot;
+                    } else if (nx == 1) {
+                        int d = ext[0] ? 0 : (ext[1] ? 1 : 2);
+                        int side = d == 0 ? (i == N) : (d == 1 ? (j == N) : (k == N));
+                        int p = d == 0 ? j : i;            // first in-face axis
+                        int q = d == 2 ? j : k;            // second in-face axis
+                        auto corner = [&](int pa, int qa) -> int64_t {
+                            int cc;
+                            if (d == 0) cc = side + 2 * pa + 4 * qa;
+                            else if (d == 1) cc = 2 * side + pa + 4 * qa;
+                            else cc = 4 * side + pa + 2 * qa;
+                            return v[cc];
+                        };
+                        int64_t vv[2][2] = {{corner(0, 0), corner(0, 1)}, {corner(1, 0), corner(1, 1)}};
+                        int o1 = 0, o2 = 0;
+                        for (int pa = 0; pa < 2; ++pa)
+                            for (int qa = 0; qa < 2; ++qa)
+                                if (vv[pa][qa] < vv[o1][o2]) { o1 = pa; o2 = qa; }
+                        int a1 = o1 ? N - p : p, a2 = o2 ? N - q : q;
+                        int s, t;
+                        if (vv[1 - o1][o2] < vv[o1][1 - o2]) { s = a1; t = a2; } else { s = a2; t = a1; }
+                        Quad key{{vv[0][0], vv[0][1], vv[1][0], vv[1][1]}};
+                        std::sort(key.v, key.v + 4);
+                        int64_t fidx = faces.find(key)->second;
+                        int32_t &slot = face_gid[(size_t)fidx * nf + (s - 1) * ne + (t - 1)];
+                        if (slot < 0) slot = fresh(false);
+                        g = slot;
+                    } else {
+                        g = fresh(true);
+                    }
+                    c->gid_canon[(size_t)e * np + l] = g;
+                    mult[g] += 1;
+                    if (fb && ((i == 0 && fb[0]) || (i == N && fb[1]) || (j == 0 && fb[2]) ||
+                               (j == N && fb[3]) || (k == 0 && fb[4]) || (k == N && fb[5])))
+                        dir[g] = 1;
+                }
+    }
+    c->n_unique = next;
+    c->dir_canon = std::move(dir);
+    c->mult_canon = std::move(mult);
+    c->solver_pos.assign((size_t)next, 0);
+    int64_t pos = 0, ndir = 0;
+    for (int64_t g = 0; g < next; ++g)
+        if (!is_interior[g]) c->solver_pos[g] = (int32_t)pos++;
+    c->n_bnd = pos;
+    for (int64_t g = 0; g < next; ++g) {
+        if (is_interior[g]) c->solver_pos[g] = (int32_t)pos++;
+        ndir += c->dir_canon[g];
+    }
+    c->n_dir = ndir;
+
+    // compact boundary map and the node -> copies CSR
+    const int nb = c->nb;
+    c->bmap.assign((size_t)E * nb, 0);
+    c->bdir.assign((size_t)c->n_bnd, 0);
+    std::vector<int32_t> count((size_t)c->n_bnd + 1, 0);
+    for (int64_t e = 0; e < E; ++e) {
+        int b = 0;
+        for (int k = 0; k < n1; ++k)
+            for (int j = 0; j < n1; ++j)
+                for (int i = 0; i < n1; ++i) {
+                    bool bnd = k == 0 || k == N || i == 0 || i == N || j == 0 || j == N;
+                    if (!bnd) continue;
+                    int32_t g = c->gid_canon[(size_t)e * np + i + n1 * (j + n1 * k)];
+                    int32_t sp = c->solver_pos[g];
+                    uint8_t d = c->dir_canon[g];
+                    c->bmap[(size_t)e * nb + b] = d ? (int32_t)(sp | 0x80000000u) : sp;
+                    c->bdir[sp] = d;
+                    count[sp + 1] += 1;
+                    ++b;
+                }
+    }
+    c->csr_off.assign((size_t)c->n_bnd + 1, 0);
+    for (int64_t g = 0; g < c->n_bnd; ++g) c->csr_off[g + 1] = c->csr_off[g] + count[g + 1];
+    c->csr_idx.assign((size_t)E * nb, 0);
+    std::vector<int32_t> fill(c->csr_off.begin(), c->csr_off.end() - 1);
+    for (int64_t q = 0; q < E * nb; ++q) {
+        int32_t sp = c->bmap[q] & 0x7fffffff;
+        c->csr_idx[fill[sp]++] = (int32_t)q;
+    }
+    return SEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" const char *sem_last_error(sem_ctx ctx) {
+    return ctx ? ctx->err.c_str() : g_last_error.c_str();
+}
+
+extern "C" sem_status sem_setup(const sem_mesh *mesh, int N, const sem_options *opts,
+                                sem_ctx *out) {
+    if (!mesh || !out) return fail(nullptr, SEM_ERR_INVALID, "null argument");
+    *out = nullptr;
+    if (N < 1 || N >= kMaxN1) return fail(nullptr, SEM_ERR_UNSUPPORTED, "N must be in 1..15");
+    if (mesh->num_elements < 1 || !mesh->corner_ids || mesh->num_vertices < 8)
+        return fail(nullptr, SEM_ERR_INVALID, "empty mesh");
+    sem_ctx c = new sem_ctx_s();
+    c->N = N;
+    c->n1 = N + 1;
+    c->np = c->n1 * c->n1 * c->n1;
+    c->ni = (N - 1) * (N - 1) * (N - 1);
+    c->nb = c->np - c->ni;
+    c->E = mesh->num_elements;
+    c->n_local = c->E * c->np;
+    c->precisions = SEM_PREC_BIT(SEM_FP64) | (opts ? opts->precisions : 0u);
+    c->solver = opts ? opts->solver : 0;
+    sem_gll(N, c->xi, c->rho);
+    derivative_matrix(N, c->xi, c->D);
+    sem_status st = build_numbering(c, mesh);
+    if (st != SEM_OK) {
+        g_last_error = c->err;
+        delete c;
+        return st;
+    }
+    if (mesh->vertex_xyz) {
+        c->vertex_xyz.assign(mesh->vertex_xyz, mesh->vertex_xyz + 3 * mesh->num_vertices);
+        c->corners.assign(mesh->corner_ids, mesh->corner_ids + 8 * c->E);
+    }
+    for (int p = 0; p < kNumPrec; ++p) {
+        c->tile[p].epb = std::max(1, 64 / (c->n1 * c->n1));
+        if (c->n1 * c->n1 * c->tile[p].epb < 64 && c->n1 <= 6) c->tile[p].epb = 256 / (c->n1 * c->n1);
+    }
+    *out = c;
+    return SEM_OK;
+}
+
+extern "C" void sem_free(sem_ctx ctx) {
+    if (!ctx) return;
+    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (ctx->solve_event) (void)hipEventDestroy(ctx->solve_event);
+    if (ctx->solve_stream) (void)hipStreamDestroy(ctx->solve_stream);
+    delete ctx;
+}
+
+extern "C" sem_status sem_query(sem_ctx c, sem_info *info) {
+    if (!c || !info) return fail(c, SEM_ERR_INVALID, "null argument");
+    info->N = c->N;
+    info->num_elements = c->E;
+    info->n_local = c->n_local;
+    info->n_unique = c->n_unique;
+    info->n_boundary = c->n_bnd;
+    info->n_dirichlet = c->n_dir;
+    info->n_bpoints = c->nb;
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_export_numbering(sem_ctx c, int32_t *gid, int32_t *pos,
+                                           uint8_t *dir, int32_t *mult) {
+    if (!c) return fail(c, SEM_ERR_INVALID, "null context");
+    if (gid) std::memcpy(gid, c->gid_canon.data(), sizeof(int32_t) * c->n_local);
+    if (pos) std::memcpy(pos, c->solver_pos.data(), sizeof(int32_t) * c->n_unique);
+    if (dir) std::memcpy(dir, c->dir_canon.data(), c->n_unique);
+    if (mult) std::memcpy(mult, c->mult_canon.data(), sizeof(int32_t) * c->n_unique);
+    return SEM_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static void compute_layout(sem_ctx c) {
+    Layout &L = c->L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const size_t nl = (size_t)c->n_local, nu = (size_t)c->n_unique;
+    const size_t nbt = (size_t)c->E * c->nb;
+    const bool low = (c->precisions & ~SEM_PREC_BIT(SEM_FP64)) != 0;
+    L.bmap = take(4 * nbt);
+    L.csr_off = take(4 * ((size_t)c->n_bnd + 1));
+    L.csr_idx = take(4 * nbt);
+    L.bdir = take((size_t)c->n_bnd + 1);
+    L.bpos2l = take(4 * (size_t)c->nb);
+    L.dhat64 = take(8 * (kMaxN1 * kMaxN1 + kMaxN1));
+    L.dhat32 = take(4 * kMaxN1 * kMaxN1);
+    const size_t gsz[kNumPrec] = {8, 4, 2, 2};
+    for (int p = 0; p < kNumPrec; ++p) {
+        bool on = (c->precisions >> p) & 1u;
+        L.G[p] = on ? take(gsz[p] * 6 * nl) : 0;
+        L.gscale[p] = on ? take(4 * (size_t)c->E) : 0;
+    }
+    L.B = take(8 * nl);
+    L.dinv64 = take(8 * nu);
+    L.dinv32 = low ? take(4 * nu) : 0;
+    L.diag = take(8 * nu);
+    L.wb = take(8 * std::max(nbt, (size_t)3 * c->np * 64));
+    if (c->solver) {
+        L.r64 = take(8 * nu);
+        L.p64 = take(8 * nu);
+        L.w64 = take(8 * nu);
+        L.z64 = take(8 * nu);
+        if (low) {
+            L.d32 = take(4 * nu);
+            L.r32 = take(4 * nu);
+            L.p32 = take(4 * nu);
+            L.w32 = take(4 * nu);
+        }
+    }
+    L.partials = take(8 * (size_t)kMaxPartials * 16);
+    L.state = take(sizeof(CgState) * 4);
+    L.errflag = take(256);
+    L.total = off;
+}
+
+extern "C" sem_status sem_workspace_size(sem_ctx c, size_t *bytes) {
+    if (!c || !bytes) return fail(c, SEM_ERR_INVALID, "null argument");
+    compute_layout(c);
+    *bytes = c->L.total;
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_bind_workspace(sem_ctx c, void *dev, size_t bytes, sem_stream stream) {
+    if (!c || !dev) return fail(c, SEM_ERR_INVALID, "null argument");
+    compute_layout(c);
+    if (bytes < c->L.total)
+        return fail(c, SEM_ERR_OOM, "workspace of " + std::to_string(bytes) +
+                                        " bytes, need " + std::to_string(c->L.total));
+    if (((uintptr_t)dev) & 255) return fail(c, SEM_ERR_INVALID, "workspace not 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    int dev_id = 0;
+    SEM_HIP(c, hipGetDevice(&dev_id));
+    hipDeviceProp_t prop;
+    SEM_HIP(c, hipGetDeviceProperties(&prop, dev_id));
+    c->num_cus = prop.multiProcessorCount;
+    c->max_lds = prop.sharedMemPerBlock;
+    c->ws = (char *)dev;
+    c->ws_bytes = bytes;
+    c->geometry_ready = false;
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+    const Layout &L = c->L;
+    SEM_HIP(c, hipMemcpyAsync(c->ws + L.bmap, c->bmap.data(), 4 * c->bmap.size(),
+                              hipMemcpyHostToDevice, s));
+    SEM_HIP(c, hipMemcpyAsync(c->ws + L.csr_off, c->csr_off.data(), 4 * c->csr_off.size(),
+                              hipMemcpyHostToDevice, s));
+    SEM_HIP(c, hipMemcpyAsync(c->ws + L.csr_idx, c->csr_idx.data(), 4 * c->csr_idx.size(),
+                              hipMemcpyHostToDevice, s));
+    if (c->n_bnd)
+        SEM_HIP(c, hipMemcpyAsync(c->ws + L.bdir, c->bdir.data(), c->bdir.size(),
+                                  hipMemcpyHostToDevice, s));
+    double d64[kMaxN1 * kMaxN1 + kMaxN1];
+    float d32[kMaxN1 * kMaxN1];
+    for (int q = 0; q < c->n1 * c->n1; ++q) {
+        d64[q] = c->D[q];
+        d32[q] = (float)c->D[q];
+    }
+    for (int q = 0; q < kMaxN1; ++q) d64[kMaxN1 * kMaxN1 + q] = q < c->n1 ? c->rho[q] : 0.0;
+    // order of boundary points: plane k=0, ring columns of planes 1..N-1, plane k=N
+    std::vector<int32_t> bpos2l(c->nb);
+    {
+        int b = 0;
+        for (int j = 0; j < c->n1; ++j)
+            for (int i = 0; i < c->n1; ++i) bpos2l[b++] = i + c->n1 * j;
+        for (int k = 1; k < c->N; ++k)
+            for (int j = 0; j < c->n1; ++j)
+                for (int i = 0; i < c->n1; ++i)
+                    if (i == 0 || i == c->N || j == 0 || j == c->N)
+                        bpos2l[b++] = i + c->n1 * (j + c->n1 * k);
+        for (int j = 0; j < c->n1; ++j)
+            for (int i = 0; i < c->n1; ++i) bpos2l[b++] = i + c->n1 * (j + c->n1 * c->N);
+    }
+    SEM_HIP(c, hipMemcpyAsync(c->ws + L.bpos2l, bpos2l.data(), 4 * bpos2l.size(),
+                              hipMemcpyHostToDevice, s));
+    SEM_HIP(c, hipMemcpyAsync(c->ws + L.dhat64, d64, sizeof(d64), hipMemcpyHostToDevice, s));
+    SEM_HIP(c, hipMemcpyAsync(c->ws + L.dhat32, d32, 4 * c->n1 * c->n1, hipMemcpyHostToDevice, s));
+    CgState zero[4];
+    std::memset(zero, 0, sizeof(zero));
+    SEM_HIP(c, hipMemcpyAsync(c->ws + L.state, zero, sizeof(zero), hipMemcpyHostToDevice, s));
+    SEM_HIP(c, hipStreamSynchronize(s));
+    return SEM_OK;
+}
+
+static void trilinear_chunk(sem_ctx c, int64_t e0, int64_t ne, double *out) {
+    const int n1 = c->n1, np = c->np;
+    for (int64_t e = e0; e < e0 + ne; ++e) {
+        const int64_t *v = c->corners.data() + e * 8;
+        double *X = out + (e - e0) * 3 * np;
+        for (int k = 0; k < n1; ++k)
+            for (int j = 0; j < n1; ++j)
+                for (int i = 0; i < n1; ++i) {
+                    double r = 0.5 * (c->xi[i] + 1), s = 0.5 * (c->xi[j] + 1), t = 0.5 * (c->xi[k] + 1);
+                    double w[8];
+                    for (int cc = 0; cc < 8; ++cc)
+                        w[cc] = ((cc & 1) ? r : 1 - r) * ((cc & 2) ? s : 1 - s) * ((cc & 4) ? t : 1 - t);
+                    for (int d = 0; d < 3; ++d) {
+                        double acc = 0;
+                        for (int cc = 0; cc < 8; ++cc) acc += w[cc] * c->vertex_xyz[3 * v[cc] + d];
+                        X[(size_t)d * np + i + n1 * (j + n1 * k)] = acc;
+                    }
+                }
+    }
+}
+
+extern "C" sem_status sem_set_geometry(sem_ctx c, const double *gll_xyz, sem_stream stream) {
+    if (!c) return fail(c, SEM_ERR_INVALID, "null context");
+    if (!c->ws) return fail(c, SEM_ERR_STATE, "no workspace bound");
+    if (!gll_xyz && c->vertex_xyz.empty())
+        return fail(c, SEM_ERR_INVALID, "no coordinates: pass gll_xyz or give vertex_xyz at setup");
+    hipStream_t s = (hipStream_t)stream;
+    const Layout &L = c->L;
+    const size_t stage_doubles = std::max((size_t)c->E * c->nb, (size_t)3 * c->np * 64);
+    const int64_t chunk = std::max<int64_t>(1, (int64_t)(stage_doubles / (3 * (size_t)c->np)));
+    int *errflag = dptr<int>(c, L.errflag);
+    int init = INT_MAX;
+    SEM_HIP(c, hipMemcpyAsync(errflag, &init, sizeof(int), hipMemcpyHostToDevice, s));
+    std::vector<double> tmp;
+    if (!gll_xyz) tmp.resize((size_t)chunk * 3 * c->np);
+    double *stage = dptr<double>(c, L.wb);
+    for (int64_t e0 = 0; e0 < c->E; e0 += chunk) {
+        int64_t ne = std::min(chunk, c->E - e0);
+        const double *src = gll_xyz ? gll_xyz + (size_t)e0 * 3 * c->np : tmp.data();
+        if (!gll_xyz) {
+            SEM_HIP(c, hipStreamSynchronize(s));
+            trilinear_chunk(c, e0, ne, tmp.data());
+        }
+        SEM_HIP(c, hipMemcpyAsync(stage, src, sizeof(double) * 3 * c->np * ne,
+                                  hipMemcpyHostToDevice, s));
+        SEM_HIP(c, launch_geometry(c, stage, e0, ne, errflag, s));
+    }
+    int bad = INT_MAX;
+    SEM_HIP(c, hipMemcpyAsync(&bad, errflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    SEM_HIP(c, hipStreamSynchronize(s));
+    if (bad != INT_MAX)
+        return fail(c, SEM_ERR_MESH, "non-positive Jacobian in element " + std::to_string(bad));
+    SEM_HIP(c, launch_lowprec_factors(c, s));
+    SEM_HIP(c, launch_diag(c, s));
+    SEM_HIP(c, hipStreamSynchronize(s));
+    c->geometry_ready = true;
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_export_geometry(sem_ctx c, double *G, double *B, double *dinv,
+                                          sem_stream stream) {
+    if (!c) return fail(c, SEM_ERR_INVALID, "null context");
+    if (!c->geometry_ready) return fail(c, SEM_ERR_STATE, "geometry not set");
+    hipStream_t s = (hipStream_t)stream;
+    const Layout &L = c->L;
+    if (G) SEM_HIP(c, hipMemcpyAsync(G, c->ws + L.G[0], 8 * 6 * (size_t)c->n_local,
+                                     hipMemcpyDeviceToHost, s));
+    if (B) SEM_HIP(c, hipMemcpyAsync(B, c->ws + L.B, 8 * (size_t)c->n_local,
+                                     hipMemcpyDeviceToHost, s));
+    if (dinv) SEM_HIP(c, hipMemcpyAsync(dinv, c->ws + L.dinv64, 8 * (size_t)c->n_unique,
+                                        hipMemcpyDeviceToHost, s));
+    SEM_HIP(c, hipStreamSynchronize(s));
+    return SEM_OK;
+}
+
+static sem_status check_ready(sem_ctx c, int prec) {
+    if (!c) return fail(c, SEM_ERR_INVALID, "null context");
+    if (!c->geometry_ready) return fail(c, SEM_ERR_STATE, "geometry not set");
+    if (prec < 0 || prec >= kNumPrec) return fail(c, SEM_ERR_UNSUPPORTED, "unknown precision");
+    if (!((c->precisions >> prec) & 1u))
+        return fail(c, SEM_ERR_UNSUPPORTED, "precision not configured at setup");
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_ax_local(sem_ctx c, const void *uL, void *wL, sem_precision prec,
+                                   sem_stream stream) {
+    sem_status st = check_ready(c, prec);
+    if (st) return st;
+    if (!uL || !wL) return fail(c, SEM_ERR_INVALID, "null vector");
+    SEM_HIP(c, launch_ax(c, prec, uL, wL, 1, OUT_LOCAL, nullptr, nullptr, c->tile[prec],
+                         (hipStream_t)stream));
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_ax(sem_ctx c, const void *u, void *y, sem_precision prec,
+                             unsigned flags, sem_stream stream) {
+    sem_status st = check_ready(c, prec);
+    if (st) return st;
+    if (!u || !y) return fail(c, SEM_ERR_INVALID, "null vector");
+    if (u == y) return fail(c, SEM_ERR_INVALID, "u and y must not alias");
+    hipStream_t s = (hipStream_t)stream;
+    if (flags & SEM_AX_DETERMINISTIC) {
+        SEM_HIP(c, launch_ax(c, prec, u, y, 0, OUT_COMPACT, nullptr, nullptr, c->tile[prec], s));
+        SEM_HIP(c, launch_gather_sum(c, prec, c->ws + c->L.wb, y, s));
+    } else {
+        if (!(flags & SEM_AX_Y_ZEROED)) {
+            if (prec == SEM_FP64) SEM_HIP(c, launch_fill((double *)y, c->n_bnd, 0.0, s));
+            else SEM_HIP(c, launch_fill32((float *)y, c->n_bnd, 0.0f, s));
+        }
+        SEM_HIP(c, launch_ax(c, prec, u, y, 0, OUT_ATOMIC, nullptr, nullptr, c->tile[prec], s));
+    }
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_gs(sem_ctx c, void *vL, sem_precision prec, sem_stream stream) {
+    if (!c) return fail(c, SEM_ERR_INVALID, "null context");
+    if (!c->ws) return fail(c, SEM_ERR_STATE, "no workspace bound");
+    if (prec != SEM_FP64 && prec != SEM_FP32)
+        return fail(c, SEM_ERR_UNSUPPORTED, "sem_gs takes FP64 or FP32 vectors");
+    if (!vL) return fail(c, SEM_ERR_INVALID, "null vector");
+    SEM_HIP(c, launch_gs_evec(c, prec, vL, (hipStream_t)stream));
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_gather(sem_ctx c, const double *u, double *uL, sem_stream stream) {
+    if (!c || !u || !uL) return fail(c, SEM_ERR_INVALID, "null argument");
+    if (!c->ws) return fail(c, SEM_ERR_STATE, "no workspace bound");
+    SEM_HIP(c, launch_q(c, u, uL, (hipStream_t)stream));
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_scatter(sem_ctx c, const double *wL, double *y, sem_stream stream) {
+    if (!c || !wL || !y) return fail(c, SEM_ERR_INVALID, "null argument");
+    if (!c->ws) return fail(c, SEM_ERR_STATE, "no workspace bound");
+    SEM_HIP(c, launch_qt(c, wL, y, (hipStream_t)stream));
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_rhs(sem_ctx c, const double *fL, const double *f, double *b,
+                              sem_stream stream) {
+    sem_status st = check_ready(c, SEM_FP64);
+    if (st) return st;
+    if ((fL == nullptr) == (f == nullptr) || !b)
+        return fail(c, SEM_ERR_INVALID, "pass exactly one of f_L and f, and b");
+    SEM_HIP(c, launch_rhs(c, fL, f, b, (hipStream_t)stream));
+    return SEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Solvers
+// ---------------------------------------------------------------------------
+extern "C" void sem_default_solve_options(sem_solve_options *o) {
+    if (!o) return;
+    o->tol = 1e-10;
+    o->max_iter = 100000;
+    o->precision = SEM_FP64;
+    o->inner_tol = 1e-4;
+    o->max_outer = 50;
+    o->check_every = 50;
+    o->use_graph = 1;
+    o->zero_guess = 1;
+    o->deterministic = 0;
+    o->max_restart = 3;
+}
+
+namespace {
+
+struct Level {
+    int level;        // index of the CgState
+    int prec;         // operator precision
+    void *x, *r, *p, *w;
+};
+
+// Runs CG iterations (graph-captured in chunks of m) until the device-side
+// state says done.  Returns the host copy of the final state.
+sem_status run_cg(sem_ctx c, const Level &lv, const sem_solve_options &o, int64_t cap,
+                  CgState *host_state, hipStream_t s) {
+    host_state->max_iter = cap;
+    CgState *st = dptr<CgState>(c, c->L.state) + lv.level;
+    const int m = std::max(1, o.check_every);
+    hipGraphExec_t exec = nullptr;
+    if (o.use_graph) {
+        for (auto &g : c->graphs)
+            if (g.key[0] == lv.x && g.key[1] == lv.r && g.key[2] == (void *)(intptr_t)lv.prec &&
+                g.key[3] == (void *)(intptr_t)o.deterministic && g.level == lv.level && g.m == m)
+                exec = g.exec;
+        if (!exec) {
+            hipGraph_t graph;
+            SEM_HIP(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            for (int it = 0; it < m; ++it) {
+                hipError_t e = launch_cg_iteration(c, lv.level, lv.prec, lv.x, lv.r, lv.p, lv.w,
+                                                   st, o.deterministic, s);
+                if (e != hipSuccess) {
+                    hipGraph_t dummy;
+                    (void)hipStreamEndCapture(s, &dummy);
+                    return fail(c, SEM_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+                }
+            }
+            SEM_HIP(c, hipStreamEndCapture(s, &graph));
+            SEM_HIP(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+            (void)hipGraphDestroy(graph);
+            sem_ctx_s::GraphEntry ge;
+            ge.key[0] = lv.x;
+            ge.key[1] = lv.r;
+            ge.key[2] = (void *)(intptr_t)lv.prec;
+            ge.key[3] = (void *)(intptr_t)o.deterministic;
+            ge.level = lv.level;
+            ge.m = m;
+            ge.exec = exec;
+            c->graphs.push_back(ge);
+        }
+    }
+    int64_t launched = 0;
+    for (;;) {
+        if (launched > host_state->max_iter + 2 * (int64_t)m + 2)
+            return fail(c, SEM_ERR_DEVICE, "CG state did not terminate");
+        launched += m;
+        if (exec) {
+            SEM_HIP(c, hipGraphLaunch(exec, s));
+        } else {
+            for (int it = 0; it < m; ++it)
+                SEM_HIP(c, launch_cg_iteration(c, lv.level, lv.prec, lv.x, lv.r, lv.p, lv.w, st,
+                                               o.deterministic, s));
+        }
+        SEM_HIP(c, hipMemcpyAsync(host_state, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+        SEM_HIP(c, hipStreamSynchronize(s));
+        if (host_state->done) break;
+    }
+    return SEM_OK;
+}
+
+// y = A x (FP64) then r = b - y, rr and bb into state[level]
+sem_status residual64(sem_ctx c, const double *b, const double *x, double *y, double *r,
+                      float *r32, int level, int deterministic, hipStream_t s, CgState *hs) {
+    CgState *st = dptr<CgState>(c, c->L.state) + level;
+    if (deterministic) {
+        SEM_HIP(c, launch_ax(c, SEM_FP64, x, y, 0, OUT_COMPACT, nullptr, nullptr, c->tile[0], s));
+        SEM_HIP(c, launch_gather_sum(c, SEM_FP64, c->ws + c->L.wb, y, s));
+    } else {
+        SEM_HIP(c, launch_fill(y, c->n_bnd, 0.0, s));
+        SEM_HIP(c, launch_ax(c, SEM_FP64, x, y, 0, OUT_ATOMIC, nullptr, nullptr, c->tile[0], s));
+    }
+    SEM_HIP(c, launch_residual64(c, b, y, r, r32, st, s));
+    SEM_HIP(c, hipMemcpyAsync(hs, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    SEM_HIP(c, hipStreamSynchronize(s));
+    return SEM_OK;
+}
+
+sem_status status_from_state(const CgState &h) {
+    switch (h.status) {
+        case 0: return SEM_OK;
+        case 1: return SEM_ERR_NOT_CONVERGED;
+        case 2: return SEM_ERR_BREAKDOWN;
+        default: return SEM_ERR_NAN;
+    }
+}
+
+}  // namespace
+
+static sem_status solve_fp64(sem_ctx c, const double *b, double *x, const sem_solve_options &o,
+                             sem_solve_info *info, hipStream_t s, int64_t iter_budget,
+                             bool zero_guess) {
+    const Layout &L = c->L;
+    Level lv{0, SEM_FP64, x, c->ws + L.r64, c->ws + L.p64, c->ws + L.w64};
+    CgState *st = dptr<CgState>(c, L.state);
+    CgState h;
+    int restarts = 0;
+    sem_status result = SEM_ERR_NOT_CONVERGED;
+    for (;;) {
+        // state: tol, cap
+        CgState init;
+        std::memset(&init, 0, sizeof(init));
+        init.tol2 = o.tol * o.tol;     // relative; scaled by bb on the device
+        init.max_iter = iter_budget - info->iterations;
+        SEM_HIP(c, hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, s));
+        SEM_HIP(c, launch_cg_begin(c, 0, b, x, lv.r, lv.p, lv.w, zero_guess ? 1 : 0, st, s));
+        sem_status e = run_cg(c, lv, o, init.max_iter, &h, s);
+        if (e) return e;
+        info->iterations += h.iter;
+        info->rel_residual = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+        if (h.status != 0) { result = status_from_state(h); break; }
+        // true residual in FP64
+        CgState hr;
+        e = residual64(c, b, x, dptr<double>(c, L.w64), dptr<double>(c, L.z64), nullptr, 1,
+                       o.deterministic, s, &hr);
+        if (e) return e;
+        info->true_rel_residual = hr.bb > 0 ? std::sqrt(hr.rr / hr.bb) : 0.0;
+        if (!std::isfinite(info->true_rel_residual)) { result = SEM_ERR_NAN; break; }
+        if (info->true_rel_residual <= o.tol) { result = SEM_OK; break; }
+        if (restarts >= o.max_restart || info->iterations >= iter_budget) {
+            result = SEM_ERR_NOT_CONVERGED;
+            break;
+        }
+        ++restarts;
+        zero_guess = false;
+    }
+    info->restarts += restarts;
+    return result;
+}
+
+static sem_status solve_refined(sem_ctx c, const double *b, double *x,
+                                const sem_solve_options &o, sem_solve_info *info,
+                                hipStream_t s) {
+    const Layout &L = c->L;
+    if (!L.d32) return fail(c, SEM_ERR_STATE, "no reduced-precision work vectors");
+    double *y = dptr<double>(c, L.w64);
+    double *r = dptr<double>(c, L.z64);
+    float *r32 = dptr<float>(c, L.r32);
+    CgState *st_in = dptr<CgState>(c, L.state) + 2;
+    Level lv{2, (int)o.precision, c->ws + L.d32, r32, c->ws + L.p32, c->ws + L.w32};
+    if (o.zero_guess) SEM_HIP(c, launch_fill(x, c->n_unique, 0.0, s));
+    double prev = INFINITY, prev2 = INFINITY;
+    for (int outer = 0;; ++outer) {
+        CgState h;
+        sem_status e = residual64(c, b, x, y, r, r32, 1, o.deterministic, s, &h);
+        if (e) return e;
+        double rel = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+        info->true_rel_residual = rel;
+        info->outer_iterations = outer;
+        if (!std::isfinite(rel)) return SEM_ERR_NAN;
+        if (rel <= o.tol) return SEM_OK;
+        // stagnation: less than a factor 2 over two refinement steps -> FP64 CG
+        if (outer >= o.max_outer || info->iterations >= o.max_iter ||
+            (outer >= 2 && rel > 0.5 * prev2)) {
+            sem_solve_options o64 = o;
+            o64.precision = SEM_FP64;
+            return solve_fp64(c, b, x, o64, info, s, o.max_iter, false);
+        }
+        prev2 = prev;
+        prev = rel;
+        // inner solve A d = r / ||r|| in reduced precision, d0 = 0
+        CgState init;
+        std::memset(&init, 0, sizeof(init));
+        init.tol2 = o.inner_tol * o.inner_tol;
+        init.max_iter = std::max<int64_t>(1, o.max_iter - info->iterations);
+        SEM_HIP(c, hipMemcpyAsync(st_in, &init, sizeof(init), hipMemcpyHostToDevice, s));
+        SEM_HIP(c, launch_cg_begin(c, 2, r, lv.x, lv.r, lv.p, lv.w, 1, st_in, s));
+        CgState hi;
+        e = run_cg(c, lv, o, init.max_iter, &hi, s);
+        if (e) return e;
+        info->iterations += hi.iter;
+        info->rel_residual = hi.bb > 0 ? std::sqrt(hi.rr / hi.bb) : 0.0;
+        if (hi.status == 3 || hi.status == 2) {
+            // reduced precision broke down: finish in FP64
+            sem_solve_options o64 = o;
+            o64.precision = SEM_FP64;
+            return solve_fp64(c, b, x, o64, info, s, o.max_iter, false);
+        }
+        SEM_HIP(c, launch_ir_update(c, x, (const float *)lv.x, dptr<CgState>(c, L.state) + 1, s));
+    }
+}
+
+extern "C" sem_status sem_cg_solve(sem_ctx c, const double *b, double *x,
+                                   const sem_solve_options *opts, sem_solve_info *info,
+                                   sem_stream stream) {
+    sem_solve_info dummy;
+    if (!info) info = &dummy;
+    std::memset(info, 0, sizeof(*info));
+    sem_status st = check_ready(c, SEM_FP64);
+    if (st) return info->status = st;
+    if (!b || !x) return info->status = fail(c, SEM_ERR_INVALID, "null vector");
+    if (!c->solver || !c->L.r64)
+        return info->status = fail(c, SEM_ERR_STATE, "context set up without solver vectors");
+    sem_solve_options o;
+    if (opts) o = *opts; else sem_default_solve_options(&o);
+    if (!(o.tol > 0) || o.max_iter < 1) return info->status = fail(c, SEM_ERR_INVALID, "bad tolerance or cap");
+    if (o.precision != SEM_FP64) {
+        st = check_ready(c, o.precision);
+        if (st) return info->status = st;
+    }
+    // Solves run on a private stream ordered after the caller's stream, so
+    // that the iteration can be captured even when the caller uses the null
+    // stream.
+    if (!c->solve_stream) {
+        SEM_HIP(c, hipStreamCreateWithFlags(&c->solve_stream, hipStreamNonBlocking));
+        SEM_HIP(c, hipEventCreateWithFlags(&c->solve_event, hipEventDisableTiming));
+    }
+    SEM_HIP(c, hipEventRecord(c->solve_event, (hipStream_t)stream));
+    SEM_HIP(c, hipStreamWaitEvent(c->solve_stream, c->solve_event, 0));
+    hipStream_t s = c->solve_stream;
+    auto t0 = std::chrono::steady_clock::now();
+    if (o.precision == SEM_FP64)
+        st = solve_fp64(c, b, x, o, info, s, o.max_iter, o.zero_guess != 0);
+    else
+        st = solve_refined(c, b, x, o, info, s);
+    hipError_t he = hipStreamSynchronize(s);
+    if (he != hipSuccess && st == SEM_OK) st = fail(c, SEM_ERR_DEVICE, hipGetErrorString(he));
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    info->status = st;
+    if (st == SEM_ERR_NOT_CONVERGED && c->err.empty()) c->err = "iteration cap reached";
+    return st;
+}

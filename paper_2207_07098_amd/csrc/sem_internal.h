@@ -1,0 +1,141 @@
+// Internal declarations shared by the host side and the HIP kernels of libsem.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sem.h"
+
+namespace sem {
+
+constexpr int kMaxN1 = 16;           // N <= 15
+constexpr int kMaxPartials = 8192;   // per-block partial sums of one reduction
+constexpr int kNumPrec = 4;
+
+// Device-resident CG scalars.  One instance per solver level.
+struct CgState {
+    double rz;        // r.z of the current iterate
+    double pAp;
+    double alpha;
+    double beta;
+    double rr;        // r.r after the last update
+    double bb;        // b.b (squared norm of the right-hand side)
+    double tol2;      // (tol * ||b||)^2
+    double scale;     // right-hand-side scale of an inner solve
+    long long iter;   // iterations done
+    long long max_iter;
+    int done;         // 1: converged, failed or capped -> kernels are no-ops
+    int status;       // 0 running/converged, 1 cap, 2 breakdown, 3 nan
+    unsigned counter[4];  // last-block-done tickets
+    double pad[4];
+};
+
+// Byte offsets of every array inside the caller's workspace.
+struct Layout {
+    size_t bmap, csr_off, csr_idx, bdir, bpos2l, dhat64, dhat32;  // dhat64 also holds rho
+    size_t G[kNumPrec], gscale[kNumPrec];
+    size_t B, dinv64, dinv32, diag, wb;
+    size_t r64, p64, w64, z64;     // FP64 solver vectors (z64: outer residual / scratch)
+    size_t d32, r32, p32, w32;     // inner solver vectors
+    size_t partials, state, errflag;
+    size_t total;
+};
+
+// Launch shape of the element operator.
+struct AxTile {
+    int epb = 1;          // elements per workgroup
+    int grid_cap = 0;     // max workgroups (0: one per element group)
+    int xcd = 1;          // XCD-aware element chunking
+};
+
+}  // namespace sem
+
+struct sem_ctx_s {
+    int N = 0, n1 = 0, np = 0, nb = 0, ni = 0;
+    int64_t E = 0, n_local = 0, n_unique = 0, n_bnd = 0, n_dir = 0;
+    unsigned precisions = 1;
+    int solver = 0;
+    double xi[sem::kMaxN1], rho[sem::kMaxN1];
+    double D[sem::kMaxN1 * sem::kMaxN1];
+
+    // host numbering
+    std::vector<int32_t> gid_canon;   // [n_local]
+    std::vector<int32_t> solver_pos;  // [n_unique]  canonical -> solver order
+    std::vector<uint8_t> dir_canon;   // [n_unique]
+    std::vector<int32_t> mult_canon;  // [n_unique]
+    std::vector<int32_t> bmap;        // [E][nb] solver index | sign bit when Dirichlet
+    std::vector<int32_t> csr_off;     // [n_bnd+1]
+    std::vector<int32_t> csr_idx;     // [E*nb] compact positions e*nb+bpos
+    std::vector<uint8_t> bdir;        // [n_bnd]
+    std::vector<double> vertex_xyz;   // [num_vertices][3] (optional)
+    std::vector<int64_t> corners;     // [E][8] (kept only with vertex_xyz)
+
+    // device
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    sem::Layout L{};
+    bool geometry_ready = false;
+    int num_cus = 256;
+    hipStream_t solve_stream = nullptr;   // private stream for captured solves
+    hipEvent_t solve_event = nullptr;
+    size_t max_lds = 65536;
+    sem::AxTile tile[sem::kNumPrec];
+
+    // captured CG graphs
+    struct GraphEntry {
+        const void *key[4];
+        int level, m;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+
+    std::string err;
+};
+
+namespace sem {
+
+// Error helpers (thread-local message when no context is available).
+sem_status fail(sem_ctx ctx, sem_status st, const std::string &msg);
+#define SEM_HIP(ctx, call)                                                        \
+    do {                                                                           \
+        hipError_t _e = (call);                                                    \
+        if (_e != hipSuccess)                                                      \
+            return ::sem::fail((ctx), SEM_ERR_DEVICE,                              \
+                               std::string(#call) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+template <typename T>
+inline T *dptr(sem_ctx c, size_t off) { return reinterpret_cast<T *>(c->ws + off); }
+
+// ---- kernel launchers (sem_kernels.hip) ----
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
+hipError_t launch_fill32(float *p, int64_t n, float v, hipStream_t s);
+hipError_t launch_geometry(sem_ctx c, const double *xyz_dev, int64_t e0, int64_t ne,
+                           int *errflag, hipStream_t s);
+hipError_t launch_lowprec_factors(sem_ctx c, hipStream_t s);
+hipError_t launch_diag(sem_ctx c, hipStream_t s);
+hipError_t launch_rhs(sem_ctx c, const double *fL, const double *f, double *b, hipStream_t s);
+hipError_t launch_ax(sem_ctx c, int prec, const void *u, void *y, int in_local, int out_mode,
+                     double *dot_partials, CgState *st, const AxTile &t, hipStream_t s);
+hipError_t launch_gather_sum(sem_ctx c, int prec, const void *wb, void *y, hipStream_t s);
+hipError_t launch_gs_evec(sem_ctx c, int prec, void *vL, hipStream_t s);
+hipError_t launch_q(sem_ctx c, const double *u, double *uL, hipStream_t s);
+hipError_t launch_qt(sem_ctx c, const double *wL, double *y, hipStream_t s);
+
+// CG building blocks, T = double or float.
+hipError_t launch_cg_begin(sem_ctx c, int level, const void *b, void *x, void *r, void *p,
+                           void *w, int x_zero, CgState *st, hipStream_t s);
+hipError_t launch_cg_iteration(sem_ctx c, int level, int prec, void *x, void *r, void *p,
+                               void *w, CgState *st, int deterministic, hipStream_t s);
+hipError_t launch_residual64(sem_ctx c, const double *b, const double *Ax, double *r,
+                             float *r32, CgState *st, hipStream_t s);
+hipError_t launch_ir_update(sem_ctx c, double *x, const float *d, CgState *st,
+                            hipStream_t s);
+
+// Output modes of the element operator.
+enum { OUT_LOCAL = 0, OUT_ATOMIC = 1, OUT_COMPACT = 2 };
+
+}  // namespace sem

@@ -1,0 +1,955 @@
+// HIP kernels of libsem for CDNA4 (gfx950).
+//
+// The hot kernel is k_ax: the element Laplacian w = D^T G D u of Karp et
+// al. (arXiv 2207.07098), Sec. II-A, Eq. (9), fused with the gather Q and
+// the summation Q^T of Eqs. (10)-(12).  Layout and mapping:
+//   * one lane per (i, j) column of an element; the lane keeps the whole
+//     k-column of u in registers, so the t-derivative and its transpose are
+//     register-local and use wave-uniform (scalar) coefficients D[k][m];
+//   * the r- and s-derivatives read the element block from LDS, stored
+//     [k][j][i] with a row pitch of N+2 so that row reads (fixed j) and
+//     column reads (fixed i) hit distinct banks;
+//   * the six geometric factors stream from HBM with unit stride across
+//     lanes ([E][6][k][j][i]);
+//   * element-interior nodes have solver indices that follow from the
+//     element index, so only element-boundary points read an index map and
+//     only they are summed (device atomics or a fixed-order second pass);
+//   * element groups are dealt to the 8 XCDs in contiguous ranges so that
+//     neighbouring elements share each XCD's L2.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+
+#include "sem_internal.h"
+
+namespace sem {
+
+namespace {
+
+constexpr int kVecBlock = 256;
+
+struct bf16_t {
+    uint16_t v;
+};
+
+template <typename GS>
+struct GT;
+template <>
+struct GT<double> {
+    using T = double;
+    static __device__ __forceinline__ double ld(const double *p) { return __builtin_nontemporal_load(p); }
+};
+template <>
+struct GT<float> {
+    using T = float;
+    static __device__ __forceinline__ float ld(const float *p) { return __builtin_nontemporal_load(p); }
+};
+template <>
+struct GT<_Float16> {
+    using T = float;
+    static __device__ __forceinline__ float ld(const _Float16 *p) { return (float)*p; }
+};
+template <>
+struct GT<bf16_t> {
+    using T = float;
+    static __device__ __forceinline__ float ld(const bf16_t *p) {
+        return __uint_as_float((uint32_t)p->v << 16);
+    }
+};
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ int ring_index(int i, int j, int N) {
+    if (j == 0) return i;
+    if (j == N) return N + 1 + 2 * (N - 1) + i;
+    return N + 1 + 2 * (j - 1) + (i == 0 ? 0 : 1);
+}
+
+// position of local point (i,j,k) among the element-boundary points
+__device__ __forceinline__ int bpos_of(int i, int j, int k, int n1) {
+    const int N = n1 - 1, C = n1 * n1;
+    if (k == 0) return i + n1 * j;
+    if (k == N) return C + (N - 1) * 4 * N + i + n1 * j;
+    return C + (k - 1) * 4 * N + ring_index(i, j, N);
+}
+
+__device__ __forceinline__ int64_t interior_index(int64_t n_bnd, int64_t e, int i, int j, int k,
+                                                  int N) {
+    const int nm = N - 1;
+    return n_bnd + e * (int64_t)(nm * nm * nm) + ((k - 1) * nm + (j - 1)) * nm + (i - 1);
+}
+
+// Contiguous element ranges per XCD: workgroup b runs on XCD b % 8.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t n) {
+    const int64_t q = n >> 3, r = n & 7, x = b & 7, idx = b >> 3;
+    return x * q + (x < r ? x : r) + idx;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Fixed-order block sum; every thread gets the result.
+__device__ double block_sum(double v, double *red) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int q = 0; q < nw; ++q) s += red[q];
+    return s;
+}
+
+// Last-block-done reduction of up to 4 values per block.  partials:
+// [gridDim][4].  Returns true in the (single) last block, whose threads
+// then all hold the grid-wide sums in out[0..nv).
+template <int NV>
+__device__ bool grid_reduce(const double (&v)[NV], double *partials, unsigned *counter,
+                            double (&out)[NV]) {
+    __shared__ double red[16];
+    __shared__ int last;
+    double s[NV];
+#pragma unroll
+    for (int a = 0; a < NV; ++a) s[a] = block_sum(v[a], red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int a = 0; a < NV; ++a) partials[(size_t)blockIdx.x * 4 + a] = s[a];
+        __threadfence();
+        unsigned t = atomicAdd(counter, 1u);
+        last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    double acc[NV];
+#pragma unroll
+    for (int a = 0; a < NV; ++a) acc[a] = 0.0;
+    for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x)
+#pragma unroll
+        for (int a = 0; a < NV; ++a)
+            acc[a] += __hip_atomic_load(partials + (size_t)q * 4 + a, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int a = 0; a < NV; ++a) out[a] = block_sum(acc[a], red);
+    if (threadIdx.x == 0) *counter = 0u;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Element operator
+// ---------------------------------------------------------------------------
+template <int N1, typename T>
+struct DMat {
+    T v[N1 * N1];                // row-major D[i][m] = l'_m(xi_i)
+};
+
+template <int N1, typename GS>
+struct AxParams {
+    using T = typename GT<GS>::T;
+    const void *u;
+    void *y;
+    void *wb;                    // compact boundary output (OUT_COMPACT)
+    const GS *G;
+    const float *gscale;         // per-element factor scale (16-bit storage)
+    const int32_t *bmap;
+    int64_t E, n_bnd, ngroups;
+    int epb, in_local, out_mode, xcd;
+    double *partials;            // non-null: reduce u^T A u into st->pAp
+    CgState *st;
+    DMat<N1, T> D;               // by value: wave-uniform entries come from
+                                 // the kernel-argument segment as scalars
+};
+
+// Waves per SIMD the compiler must allow for: bounds the register budget so
+// that several elements' loads are in flight per CU.
+template <int N1, typename GS>
+struct AxOcc {
+    static constexpr int value =
+        sizeof(typename GT<GS>::T) == 8 ? (N1 <= 3 ? 4 : (N1 <= 10 ? 2 : 1))
+                                        : (N1 <= 7 ? 4 : (N1 <= 9 ? 3 : (N1 <= 13 ? 2 : 1)));
+};
+
+template <int N1, typename GS>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, 256),
+                               amdgpu_waves_per_eu(AxOcc<N1, GS>::value)))
+k_ax(AxParams<N1, GS> P) {
+    using T = typename GT<GS>::T;
+    constexpr int N = N1 - 1, C = N1 * N1, NP = C * N1;
+    constexpr int NI = (N - 1) * (N - 1) * (N - 1), NB = NP - NI;
+    constexpr int PITCH = N1 + 1, PLANE = N1 * PITCH, BUF = N1 * PLANE;
+    constexpr bool SCALED = sizeof(GS) == 2;
+    CgState *st = P.st;
+    if (st && st->done) return;
+
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int tid = threadIdx.x;
+    const int nslots = (blockDim.x + C - 1) / C;
+    const int slot = tid / C, col = tid - slot * C;
+    const int i = col % N1, j = col / N1;
+    const bool ring = (i == 0) || (i == N) || (j == 0) || (j == N);
+    const int ridx = ring ? ring_index(i, j, N) : 0;
+    T *S0 = reinterpret_cast<T *>(smem_raw) + (size_t)slot * 2 * BUF;
+    T *S1 = S0 + BUF;
+    // lane-dependent rows of D are read from an LDS copy
+    T *Dl = reinterpret_cast<T *>(smem_raw) + (size_t)nslots * 2 * BUF;
+    for (int q = tid; q < C; q += blockDim.x) {
+#pragma unroll
+        for (int r = 0; r < C; ++r)
+            if (q == r) Dl[q] = P.D.v[r];
+    }
+    const T *__restrict__ U = reinterpret_cast<const T *>(P.u);
+    T *__restrict__ Y = reinterpret_cast<T *>(P.y);
+    T *__restrict__ WB = reinterpret_cast<T *>(P.wb);
+    double dot = 0.0;
+
+    for (int64_t git = blockIdx.x; git < P.ngroups; git += gridDim.x) {
+        const int64_t g = P.xcd ? xcd_remap(git, P.ngroups) : git;
+        const int64_t e = g * P.epb + slot;
+        const bool active = (slot < P.epb) && (e < P.E);
+        const int64_t ec = active ? e : 0;   // inactive lanes read element 0
+
+        T u[N1];
+        int32_t bidx[N1];
+        // ---- gather u_e = (Q M u)_e
+#pragma unroll
+        for (int k = 0; k < N1; ++k) {
+            bidx[k] = -1;
+            const bool bpt = (k == 0) || (k == N) || ring;
+            if (P.in_local) {
+                u[k] = U[ec * NP + k * C + col];
+            } else if (bpt) {
+                const int bp = (k == 0) ? col : (k == N ? C + (N - 1) * 4 * N + col
+                                                        : C + (k - 1) * 4 * N + ridx);
+                // ec is a valid element for every lane, so m is a valid entry
+                const int32_t m = P.bmap[ec * NB + bp];
+                const T v = U[m & 0x7fffffff];
+                const bool take = active && m >= 0;
+                bidx[k] = take ? m : -1;
+                u[k] = take ? v : T(0);
+            } else {
+                u[k] = U[interior_index(P.n_bnd, ec, i, j, k, N)];
+            }
+        }
+        __syncthreads();               // previous element's LDS readers are done
+#pragma unroll
+        for (int k = 0; k < N1; ++k) S0[k * PLANE + j * PITCH + i] = u[k];
+        __syncthreads();
+
+        // ---- D u, then G (D u); the factors of plane k+1 are requested while
+        // plane k is computed, and scheduling barriers keep the compiler from
+        // hoisting every plane's loads (which would exhaust the registers).
+        T wr[N1], ws[N1], wt[N1];
+        double edot = 0.0;
+        const GS *Ge = P.G + (size_t)ec * 6 * NP + col;
+        T gc[6], gn[6];
+#pragma unroll
+        for (int c6 = 0; c6 < 6; ++c6) gc[c6] = GT<GS>::ld(Ge + c6 * NP);
+#pragma unroll
+        for (int k = 0; k < N1; ++k) {
+            if (k + 1 < N1) {
+#pragma unroll
+                for (int c6 = 0; c6 < 6; ++c6) gn[c6] = GT<GS>::ld(Ge + c6 * NP + (k + 1) * C);
+            }
+            T ur = 0, us = 0, ut = 0;
+#pragma unroll
+            for (int m = 0; m < N1; ++m) {
+                ur += Dl[i * N1 + m] * S0[k * PLANE + j * PITCH + m];
+                us += Dl[j * N1 + m] * S0[k * PLANE + m * PITCH + i];
+                ut += P.D.v[k * N1 + m] * u[m];
+            }
+            wr[k] = gc[0] * ur + gc[3] * us + gc[4] * ut;
+            ws[k] = gc[3] * ur + gc[1] * us + gc[5] * ut;
+            wt[k] = gc[4] * ur + gc[5] * us + gc[2] * ut;
+            if (P.partials) edot += (double)(ur * wr[k] + us * ws[k] + ut * wt[k]);
+#pragma unroll
+            for (int c6 = 0; c6 < 6; ++c6) gc[c6] = gn[c6];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        __syncthreads();               // all reads of u from LDS are done
+#pragma unroll
+        for (int k = 0; k < N1; ++k) {
+            S0[k * PLANE + j * PITCH + i] = wr[k];
+            S1[k * PLANE + j * PITCH + i] = ws[k];
+        }
+        __syncthreads();
+
+        // ---- D^T (G D u)
+        const T sc = SCALED ? (T)P.gscale[ec] : T(1);
+        if (P.partials && active) dot += SCALED ? edot * (double)sc : edot;
+#pragma unroll
+        for (int k = 0; k < N1; ++k) {
+            T w = 0;
+#pragma unroll
+            for (int m = 0; m < N1; ++m) {
+                w += Dl[m * N1 + i] * S0[k * PLANE + j * PITCH + m];
+                w += Dl[m * N1 + j] * S1[k * PLANE + m * PITCH + i];
+                w += P.D.v[m * N1 + k] * wt[m];
+            }
+            if (SCALED) w *= sc;
+            const bool bpt = (k == 0) || (k == N) || ring;
+            if (active) {
+                if (P.out_mode == OUT_LOCAL) {
+                    Y[ec * NP + k * C + col] = w;
+                } else if (bpt) {
+                    if (P.out_mode == OUT_ATOMIC) {
+                        if (bidx[k] >= 0) unsafeAtomicAdd(Y + bidx[k], w);
+                    } else {
+                        const int bp = (k == 0) ? col : (k == N ? C + (N - 1) * 4 * N + col
+                                                                : C + (k - 1) * 4 * N + ridx);
+                        WB[ec * NB + bp] = w;
+                    }
+                } else {
+                    Y[interior_index(P.n_bnd, ec, i, j, k, N)] = w;
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+
+    if (P.partials) {
+        double v[1] = {dot}, out[1];
+        if (grid_reduce<1>(v, P.partials, &st->counter[0], out) && threadIdx.x == 0) {
+            const double pAp = out[0];
+            st->pAp = pAp;
+            if (!std::isfinite(pAp)) {
+                st->status = 3;
+                st->done = 1;
+            } else if (!(pAp > 0.0)) {
+                st->status = 2;
+                st->done = 1;
+            } else {
+                st->alpha = st->rz / pAp;
+            }
+        }
+    }
+}
+
+template <int N1, typename GS>
+hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const void *u, void *y,
+                         int in_local, int out_mode, double *partials, CgState *st,
+                         const AxTile &t, hipStream_t s) {
+    using T = typename GT<GS>::T;
+    constexpr int C = N1 * N1;
+    constexpr size_t BUF = (size_t)N1 * N1 * (N1 + 1);
+    int epb = std::max(1, std::min(t.epb, 256 / C));
+    const int threads = ((epb * C + 63) / 64) * 64;
+    const int nslots = (threads + C - 1) / C;      // padding lanes get a slot too
+    const size_t lds = ((size_t)nslots * 2 * BUF + C) * sizeof(T);
+    if (lds > c->max_lds) return hipErrorInvalidConfiguration;
+    AxParams<N1, GS> P;
+    P.u = u;
+    P.y = y;
+    P.wb = c->ws + c->L.wb;
+    P.G = reinterpret_cast<const GS *>(Gp);
+    P.gscale = gscale;
+    P.bmap = dptr<int32_t>(c, c->L.bmap);
+    for (int q = 0; q < C; ++q) P.D.v[q] = (T)c->D[q];
+    P.E = c->E;
+    P.n_bnd = c->n_bnd;
+    P.epb = epb;
+    P.ngroups = (c->E + epb - 1) / epb;
+    P.in_local = in_local;
+    P.out_mode = out_mode;
+    P.xcd = t.xcd;
+    P.partials = partials;
+    P.st = st;
+    int64_t grid = P.ngroups;
+    int64_t cap = t.grid_cap > 0 ? t.grid_cap : INT_MAX;
+    if (partials) cap = std::min<int64_t>(cap, kMaxPartials);
+    if (grid > cap) grid = std::max<int64_t>(8, (cap / 8) * 8);
+    if (grid > P.ngroups) grid = P.ngroups;
+    if (P.xcd && grid < P.ngroups && (grid & 7)) P.xcd = 0;
+    hipLaunchKernelGGL((k_ax<N1, GS>), dim3((unsigned)grid), dim3(threads), lds, s, P);
+    return hipGetLastError();
+}
+
+template <typename GS>
+hipError_t ax_dispatch(sem_ctx c, int prec, const void *u, void *y, int in_local, int out_mode,
+                       double *partials, CgState *st, const AxTile &t, hipStream_t s) {
+    const void *G = c->ws + c->L.G[prec];
+    const float *gsc = dptr<float>(c, c->L.gscale[prec]);
+#define SEM_AXN(n)                                                                      \
+    case n:                                                                             \
+        return ax_dispatch_n<n, GS>(c, G, gsc, u, y, in_local, out_mode, partials, st, t, s);
+    switch (c->n1) {
+        SEM_AXN(2) SEM_AXN(3) SEM_AXN(4) SEM_AXN(5) SEM_AXN(6) SEM_AXN(7) SEM_AXN(8)
+        SEM_AXN(9) SEM_AXN(10) SEM_AXN(11) SEM_AXN(12) SEM_AXN(13) SEM_AXN(14)
+        SEM_AXN(15) SEM_AXN(16)
+        default: return hipErrorInvalidValue;
+    }
+#undef SEM_AXN
+}
+
+// ---------------------------------------------------------------------------
+// Set-up kernels (runtime order)
+// ---------------------------------------------------------------------------
+// Geometric factors and mass from isoparametric coordinates (Sec. II-A,
+// definition of G after Eq. (9)); one workgroup per element.
+__global__ void k_geometry(const double *__restrict__ X, int64_t e0, int n1,
+                           const double *__restrict__ D, const double *__restrict__ rho,
+                           double *__restrict__ G, double *__restrict__ B, int *errflag) {
+    const int np = n1 * n1 * n1;
+    const int64_t el = blockIdx.x, e = e0 + el;
+    const double *Xe = X + (size_t)el * 3 * np;
+    for (int p = threadIdx.x; p < np; p += blockDim.x) {
+        const int i = p % n1, j = (p / n1) % n1, k = p / (n1 * n1);
+        double J[3][3];
+        for (int l = 0; l < 3; ++l) {
+            const double *x = Xe + (size_t)l * np;
+            double a = 0, b = 0, cc = 0;
+            for (int m = 0; m < n1; ++m) {
+                a += D[i * n1 + m] * x[m + n1 * (j + n1 * k)];
+                b += D[j * n1 + m] * x[i + n1 * (m + n1 * k)];
+                cc += D[k * n1 + m] * x[i + n1 * (j + n1 * m)];
+            }
+            J[l][0] = a;
+            J[l][1] = b;
+            J[l][2] = cc;
+        }
+        // cofactors: A[s][l] = cof(J)[l][s]; dr_s/dx_l = A[s][l] / det
+        double A[3][3];
+        A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        A[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+        A[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+        A[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        A[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+        A[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+        A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+        A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        const double det = J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
+        if (!(det > 0.0)) atomicMin(errflag, (int)e);
+        // G_st = w J (A_s . A_t) / det^2 = w (A_s . A_t) / det
+        const double wq = rho[i] * rho[j] * rho[k];
+        const double f = wq / det;
+        auto dotA = [&](int s, int t) {
+            return A[s][0] * A[t][0] + A[s][1] * A[t][1] + A[s][2] * A[t][2];
+        };
+        double *Ge = G + (size_t)e * 6 * np + p;
+        Ge[0 * np] = f * dotA(0, 0);
+        Ge[1 * np] = f * dotA(1, 1);
+        Ge[2 * np] = f * dotA(2, 2);
+        Ge[3 * np] = f * dotA(0, 1);
+        Ge[4 * np] = f * dotA(0, 2);
+        Ge[5 * np] = f * dotA(1, 2);
+        B[(size_t)e * np + p] = wq * det;
+    }
+}
+
+// Reduced-precision copies of G; 16-bit copies are divided by a per-element
+// power of two 2^ceil(log2 max|G_e|) kept in gscale.
+__global__ void k_lowprec(const double *__restrict__ G, int np, float *G32, _Float16 *G16,
+                          bf16_t *Gb, float *s16, float *sb) {
+    __shared__ double red[16];
+    const int64_t e = blockIdx.x;
+    const double *Ge = G + (size_t)e * 6 * np;
+    double mx = 0.0;
+    for (int q = threadIdx.x; q < 6 * np; q += blockDim.x) mx = fmax(mx, fabs(Ge[q]));
+    // block max (reuse the sum machinery on a max-reduced wave)
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    mx = 0.0;
+    for (int q = 0; q < (int)((blockDim.x + 63) >> 6); ++q) mx = fmax(mx, red[q]);
+    double gam = 1.0;
+    if (mx > 0.0) {
+        int ex;
+        double fr = frexp(mx, &ex);      // mx = fr * 2^ex, fr in [0.5, 1)
+        gam = ldexp(1.0, fr == 0.5 ? ex - 1 : ex);
+    }
+    const double inv = 1.0 / gam;
+    for (int q = threadIdx.x; q < 6 * np; q += blockDim.x) {
+        const double v = Ge[q];
+        const size_t o = (size_t)e * 6 * np + q;
+        if (G32) G32[o] = (float)v;
+        if (G16) G16[o] = (_Float16)(float)(v * inv);
+        if (Gb) Gb[o].v = f32_to_bf16_rne((float)(v * inv));
+    }
+    if (threadIdx.x == 0) {
+        if (s16) s16[e] = (float)gam;
+        if (sb) sb[e] = (float)gam;
+    }
+}
+
+// Per-point value -> interior entries of y directly, boundary entries into
+// the compact buffer wb (then k_gather_sum).  mode 0: exact Jacobi diagonal
+// of D^T G D; mode 1: B * f_L; mode 2: B * (Q f).
+__global__ void k_local_values(int mode, int64_t E, int n1, int64_t n_bnd,
+                               const double *__restrict__ D, const double *__restrict__ G,
+                               const double *__restrict__ B, const double *__restrict__ f,
+                               const int32_t *__restrict__ bmap, double *__restrict__ y,
+                               double *__restrict__ wb) {
+    const int N = n1 - 1, np = n1 * n1 * n1, nb = np - (N - 1) * (N - 1) * (N - 1);
+    const int64_t total = E * np;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = q / np;
+        const int p = (int)(q - e * np);
+        const int i = p % n1, j = (p / n1) % n1, k = p / (n1 * n1);
+        const bool bpt = i == 0 || i == N || j == 0 || j == N || k == 0 || k == N;
+        const int bp = bpt ? bpos_of(i, j, k, n1) : 0;
+        double v;
+        if (mode == 0) {
+            const double *g = G + (size_t)e * 6 * np;
+            double s = 0.0;
+            for (int m = 0; m < n1; ++m) {
+                const double a = D[m * n1 + i], b = D[m * n1 + j], cc = D[m * n1 + k];
+                s += a * a * g[0 * np + m + n1 * (j + n1 * k)];
+                s += b * b * g[1 * np + i + n1 * (m + n1 * k)];
+                s += cc * cc * g[2 * np + i + n1 * (j + n1 * m)];
+            }
+            const double di = D[i * n1 + i], dj = D[j * n1 + j], dk = D[k * n1 + k];
+            s += 2.0 * (di * dj * g[3 * np + p] + di * dk * g[4 * np + p] + dj * dk * g[5 * np + p]);
+            v = s;
+        } else if (mode == 1) {
+            v = B[q] * f[q];
+        } else {
+            double fv;
+            if (bpt) fv = f[bmap[e * nb + bp] & 0x7fffffff];
+            else fv = f[interior_index(n_bnd, e, i, j, k, N)];
+            v = B[q] * fv;
+        }
+        if (bpt) wb[e * nb + bp] = v;
+        else y[interior_index(n_bnd, e, i, j, k, N)] = v;
+    }
+}
+
+// y[g] = sum of the copies of boundary node g (fixed ascending order), 0 on
+// Dirichlet nodes.
+template <typename T>
+__global__ void k_gather_sum(int64_t n_bnd, const int32_t *__restrict__ off,
+                             const int32_t *__restrict__ idx, const uint8_t *__restrict__ bdir,
+                             const T *__restrict__ wb, T *__restrict__ y) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_bnd;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        T s = 0;
+        if (!bdir[g])
+            for (int32_t q = off[g]; q < off[g + 1]; ++q) s += wb[idx[q]];
+        y[g] = s;
+    }
+}
+
+__device__ __forceinline__ int64_t evec_pos(int32_t cq, int nb, int np, const int32_t *bpos2l) {
+    const int64_t e = cq / nb;
+    return e * np + bpos2l[cq - e * nb];
+}
+
+// In-place Q M Q^T on an E-vector: boundary copies get the (masked) sum.
+template <typename T>
+__global__ void k_gs_evec(int64_t n_bnd, int nb, int np, const int32_t *__restrict__ off,
+                          const int32_t *__restrict__ idx, const uint8_t *__restrict__ bdir,
+                          const int32_t *__restrict__ bpos2l, T *__restrict__ v) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_bnd;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        T s = 0;
+        const int32_t a = off[g], b = off[g + 1];
+        if (!bdir[g])
+            for (int32_t q = a; q < b; ++q) s += v[evec_pos(idx[q], nb, np, bpos2l)];
+        for (int32_t q = a; q < b; ++q) v[evec_pos(idx[q], nb, np, bpos2l)] = s;
+    }
+}
+
+// M Q^T on an E-vector into a unique vector (boundary part).
+__global__ void k_qt_bnd(int64_t n_bnd, int nb, int np, const int32_t *__restrict__ off,
+                         const int32_t *__restrict__ idx, const uint8_t *__restrict__ bdir,
+                         const int32_t *__restrict__ bpos2l, const double *__restrict__ wL,
+                         double *__restrict__ y) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_bnd;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0;
+        if (!bdir[g])
+            for (int32_t q = off[g]; q < off[g + 1]; ++q) s += wL[evec_pos(idx[q], nb, np, bpos2l)];
+        y[g] = s;
+    }
+}
+
+// Q (mode 0: u_L = Q u over all points) or the interior part of M Q^T
+// (mode 1: y_interior = w_L interior).
+__global__ void k_q_or_qt_int(int mode, int64_t E, int n1, int64_t n_bnd,
+                              const int32_t *__restrict__ bmap, const double *__restrict__ in,
+                              double *__restrict__ out) {
+    const int N = n1 - 1, np = n1 * n1 * n1, nb = np - (N - 1) * (N - 1) * (N - 1);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < E * np;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = q / np;
+        const int p = (int)(q - e * np);
+        const int i = p % n1, j = (p / n1) % n1, k = p / (n1 * n1);
+        const bool bpt = i == 0 || i == N || j == 0 || j == N || k == 0 || k == N;
+        if (mode == 0) {
+            out[q] = bpt ? in[bmap[e * nb + bpos_of(i, j, k, n1)] & 0x7fffffff]
+                         : in[interior_index(n_bnd, e, i, j, k, N)];
+        } else if (!bpt) {
+            out[interior_index(n_bnd, e, i, j, k, N)] = in[q];
+        }
+    }
+}
+
+__global__ void k_dinv(int64_t n_u, int64_t n_bnd, const uint8_t *__restrict__ bdir,
+                       const double *__restrict__ diag, double *__restrict__ d64,
+                       float *__restrict__ d32) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_u;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const bool masked = g < n_bnd && bdir[g];
+        const double v = masked ? 0.0 : 1.0 / diag[g];
+        d64[g] = v;
+        if (d32) d32[g] = (float)v;
+    }
+}
+
+template <typename T>
+__global__ void k_fill(T *p, int64_t n, T v) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        p[q] = v;
+}
+
+// ---------------------------------------------------------------------------
+// CG vector kernels (Sec. II-B, P-CG with point Jacobi)
+// ---------------------------------------------------------------------------
+// Begin: x = 0 and r = b (x_zero), or r = b - w with w = A x; p = dinv r;
+// reduces r.z, r.r, b.b; zeroes w on boundary nodes for the next atomic
+// operator.  With b64 != null (inner solve of a refinement step) the
+// right-hand side is the FP64 outer residual scaled by 1/||r|| (outer state).
+template <typename T>
+__global__ void k_cg_begin(int64_t n, int64_t n_bnd, const T *__restrict__ b,
+                           const double *__restrict__ b64, const CgState *__restrict__ outer,
+                           T *__restrict__ x, T *__restrict__ r, T *__restrict__ p,
+                           T *__restrict__ w, const T *__restrict__ dinv, int x_zero,
+                           double *partials, CgState *st) {
+    double rz = 0, rr = 0, bb = 0;
+    const double scale = b64 ? 1.0 / sqrt(outer->rr) : 1.0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const T bq = b64 ? (T)(b64[q] * scale) : b[q];
+        T rq;
+        if (x_zero) {
+            x[q] = 0;
+            rq = bq;
+        } else {
+            rq = bq - w[q];
+        }
+        if (q < n_bnd) w[q] = 0;
+        const T zq = dinv[q] * rq;
+        r[q] = rq;
+        p[q] = zq;
+        rz += (double)rq * (double)zq;
+        rr += (double)rq * (double)rq;
+        bb += (double)bq * (double)bq;
+    }
+    double v[3] = {rz, rr, bb}, out[3];
+    if (grid_reduce<3>(v, partials, &st->counter[1], out) && threadIdx.x == 0) {
+        st->rz = out[0];
+        st->rr = out[1];
+        st->bb = out[2];
+        st->tol2 = st->tol2 * out[2];
+        st->iter = 0;
+        st->status = 0;
+        st->done = 0;
+        if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
+            st->status = 3;
+            st->done = 1;
+        } else if (out[1] <= st->tol2) {
+            st->done = 1;
+        }
+    }
+}
+
+// x += alpha p; r -= alpha w; reduces r.r and r.z (z = dinv r); updates beta
+// and the convergence state.
+template <typename T>
+__global__ void k_cg_update(int64_t n, T *__restrict__ x, T *__restrict__ r,
+                            const T *__restrict__ p, const T *__restrict__ w,
+                            const T *__restrict__ dinv, double *partials, CgState *st) {
+    if (st->done) return;
+    const T alpha = (T)st->alpha;
+    double rr = 0, rz = 0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        x[q] += alpha * p[q];
+        const T rq = r[q] - alpha * w[q];
+        r[q] = rq;
+        rr += (double)rq * (double)rq;
+        rz += (double)rq * (double)(dinv[q] * rq);
+    }
+    double v[2] = {rr, rz}, out[2];
+    if (grid_reduce<2>(v, partials, &st->counter[2], out) && threadIdx.x == 0) {
+        st->rr = out[0];
+        st->beta = out[1] / st->rz;
+        st->rz = out[1];
+        st->iter += 1;
+        if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
+            st->status = 3;
+            st->done = 1;
+        } else if (out[0] <= st->tol2) {
+            st->done = 1;
+        } else if (st->iter >= st->max_iter) {
+            st->status = 1;
+            st->done = 1;
+        }
+    }
+}
+
+// p = dinv r + beta p; zero w on boundary nodes for the next operator.
+template <typename T>
+__global__ void k_cg_p(int64_t n, int64_t n_bnd, const T *__restrict__ r, T *__restrict__ p,
+                       T *__restrict__ w, const T *__restrict__ dinv, const CgState *st) {
+    if (st->done) return;
+    const T beta = (T)st->beta;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        p[q] = dinv[q] * r[q] + beta * p[q];
+        if (q < n_bnd) w[q] = 0;
+    }
+}
+
+// r = b - y (FP64), reduces r.r and b.b into st (rr, bb).
+__global__ void k_residual64(int64_t n, const double *__restrict__ b,
+                             const double *__restrict__ y, double *__restrict__ r,
+                             double *partials, CgState *st) {
+    double rr = 0, bb = 0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const double rq = b[q] - y[q];
+        r[q] = rq;
+        rr += rq * rq;
+        bb += b[q] * b[q];
+    }
+    double v[2] = {rr, bb}, out[2];
+    if (grid_reduce<2>(v, partials, &st->counter[3], out) && threadIdx.x == 0) {
+        st->rr = out[0];
+        st->bb = out[1];
+    }
+}
+
+// x += ||r|| d (refinement update; ||r|| from the outer residual state).
+__global__ void k_ir_update(int64_t n, double *__restrict__ x, const float *__restrict__ d,
+                            const CgState *outer) {
+    const double s = sqrt(outer->rr);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        x[q] += s * (double)d[q];
+}
+
+inline unsigned vec_grid(int64_t n) {
+    int64_t g = (n + kVecBlock - 1) / kVecBlock;
+    if (g > kMaxPartials) g = kMaxPartials;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<double>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill32(float *p, int64_t n, float v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<float>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_geometry(sem_ctx c, const double *xyz, int64_t e0, int64_t ne, int *errflag,
+                           hipStream_t s) {
+    const double *D = dptr<double>(c, c->L.dhat64);
+    const double *rho = D + kMaxN1 * kMaxN1;
+    hipLaunchKernelGGL(k_geometry, dim3((unsigned)ne), dim3(256), 0, s, xyz, e0, c->n1, D, rho,
+                       dptr<double>(c, c->L.G[0]), dptr<double>(c, c->L.B), errflag);
+    return hipGetLastError();
+}
+
+hipError_t launch_lowprec_factors(sem_ctx c, hipStream_t s) {
+    const Layout &L = c->L;
+    auto on = [&](int p) { return (c->precisions >> p) & 1u; };
+    if (!(on(1) || on(2) || on(3))) return hipSuccess;
+    hipLaunchKernelGGL(k_lowprec, dim3((unsigned)c->E), dim3(256), 0, s,
+                       dptr<double>(c, L.G[0]), c->np, on(1) ? dptr<float>(c, L.G[1]) : nullptr,
+                       on(2) ? dptr<_Float16>(c, L.G[2]) : nullptr,
+                       on(3) ? dptr<bf16_t>(c, L.G[3]) : nullptr,
+                       on(2) ? dptr<float>(c, L.gscale[2]) : nullptr,
+                       on(3) ? dptr<float>(c, L.gscale[3]) : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_sum(sem_ctx c, int prec, const void *wb, void *y, hipStream_t s) {
+    const Layout &L = c->L;
+    if (c->n_bnd == 0) return hipSuccess;
+    if (prec == SEM_FP64)
+        hipLaunchKernelGGL(k_gather_sum<double>, dim3(vec_grid(c->n_bnd)), dim3(kVecBlock), 0, s,
+                           c->n_bnd, dptr<int32_t>(c, L.csr_off), dptr<int32_t>(c, L.csr_idx),
+                           dptr<uint8_t>(c, L.bdir), (const double *)wb, (double *)y);
+    else
+        hipLaunchKernelGGL(k_gather_sum<float>, dim3(vec_grid(c->n_bnd)), dim3(kVecBlock), 0, s,
+                           c->n_bnd, dptr<int32_t>(c, L.csr_off), dptr<int32_t>(c, L.csr_idx),
+                           dptr<uint8_t>(c, L.bdir), (const float *)wb, (float *)y);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(sem_ctx c, hipStream_t s) {
+    const Layout &L = c->L;
+    double *diag = dptr<double>(c, L.diag);
+    hipLaunchKernelGGL(k_local_values, dim3(vec_grid(c->n_local)), dim3(kVecBlock), 0, s, 0, c->E,
+                       c->n1, c->n_bnd, dptr<double>(c, L.dhat64), dptr<double>(c, L.G[0]),
+                       (const double *)nullptr, (const double *)nullptr,
+                       dptr<int32_t>(c, L.bmap), diag, dptr<double>(c, L.wb));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_gather_sum(c, SEM_FP64, c->ws + L.wb, diag, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dinv, dim3(vec_grid(c->n_unique)), dim3(kVecBlock), 0, s, c->n_unique,
+                       c->n_bnd, dptr<uint8_t>(c, L.bdir), diag, dptr<double>(c, L.dinv64),
+                       L.dinv32 ? dptr<float>(c, L.dinv32) : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs(sem_ctx c, const double *fL, const double *f, double *b, hipStream_t s) {
+    const Layout &L = c->L;
+    hipLaunchKernelGGL(k_local_values, dim3(vec_grid(c->n_local)), dim3(kVecBlock), 0, s,
+                       fL ? 1 : 2, c->E, c->n1, c->n_bnd, dptr<double>(c, L.dhat64),
+                       dptr<double>(c, L.G[0]), dptr<double>(c, L.B), fL ? fL : f,
+                       dptr<int32_t>(c, L.bmap), b, dptr<double>(c, L.wb));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_gather_sum(c, SEM_FP64, c->ws + L.wb, b, s);
+}
+
+hipError_t launch_ax(sem_ctx c, int prec, const void *u, void *y, int in_local, int out_mode,
+                     double *partials, CgState *st, const AxTile &t, hipStream_t s) {
+    switch (prec) {
+        case SEM_FP64: return ax_dispatch<double>(c, prec, u, y, in_local, out_mode, partials, st, t, s);
+        case SEM_FP32: return ax_dispatch<float>(c, prec, u, y, in_local, out_mode, partials, st, t, s);
+        case SEM_FP16_SCALED:
+            return ax_dispatch<_Float16>(c, prec, u, y, in_local, out_mode, partials, st, t, s);
+        case SEM_BF16_SCALED:
+            return ax_dispatch<bf16_t>(c, prec, u, y, in_local, out_mode, partials, st, t, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_gs_evec(sem_ctx c, int prec, void *vL, hipStream_t s) {
+    const Layout &L = c->L;
+    if (c->n_bnd == 0) return hipSuccess;
+    if (prec == SEM_FP64)
+        hipLaunchKernelGGL(k_gs_evec<double>, dim3(vec_grid(c->n_bnd)), dim3(kVecBlock), 0, s,
+                           c->n_bnd, c->nb, c->np, dptr<int32_t>(c, L.csr_off),
+                           dptr<int32_t>(c, L.csr_idx), dptr<uint8_t>(c, L.bdir),
+                           dptr<int32_t>(c, L.bpos2l), (double *)vL);
+    else
+        hipLaunchKernelGGL(k_gs_evec<float>, dim3(vec_grid(c->n_bnd)), dim3(kVecBlock), 0, s,
+                           c->n_bnd, c->nb, c->np, dptr<int32_t>(c, L.csr_off),
+                           dptr<int32_t>(c, L.csr_idx), dptr<uint8_t>(c, L.bdir),
+                           dptr<int32_t>(c, L.bpos2l), (float *)vL);
+    return hipGetLastError();
+}
+
+hipError_t launch_q(sem_ctx c, const double *u, double *uL, hipStream_t s) {
+    hipLaunchKernelGGL(k_q_or_qt_int, dim3(vec_grid(c->n_local)), dim3(kVecBlock), 0, s, 0, c->E,
+                       c->n1, c->n_bnd, dptr<int32_t>(c, c->L.bmap), u, uL);
+    return hipGetLastError();
+}
+
+hipError_t launch_qt(sem_ctx c, const double *wL, double *y, hipStream_t s) {
+    const Layout &L = c->L;
+    hipLaunchKernelGGL(k_q_or_qt_int, dim3(vec_grid(c->n_local)), dim3(kVecBlock), 0, s, 1, c->E,
+                       c->n1, c->n_bnd, dptr<int32_t>(c, L.bmap), wL, y);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || c->n_bnd == 0) return e;
+    hipLaunchKernelGGL(k_qt_bnd, dim3(vec_grid(c->n_bnd)), dim3(kVecBlock), 0, s, c->n_bnd, c->nb,
+                       c->np, dptr<int32_t>(c, L.csr_off), dptr<int32_t>(c, L.csr_idx),
+                       dptr<uint8_t>(c, L.bdir), dptr<int32_t>(c, L.bpos2l), wL, y);
+    return hipGetLastError();
+}
+
+static double *partials_site(sem_ctx c, int site) {
+    return dptr<double>(c, c->L.partials) + (size_t)site * kMaxPartials * 4;
+}
+
+hipError_t launch_cg_begin(sem_ctx c, int level, const void *b, void *x, void *r, void *p,
+                           void *w, int x_zero, CgState *st, hipStream_t s) {
+    const Layout &L = c->L;
+    const int64_t n = c->n_unique;
+    if (level == 0) {
+        if (!x_zero) {
+            hipError_t e = launch_fill((double *)w, c->n_bnd, 0.0, s);
+            if (e != hipSuccess) return e;
+            e = launch_ax(c, SEM_FP64, x, w, 0, OUT_ATOMIC, nullptr, nullptr, c->tile[0], s);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_cg_begin<double>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n,
+                           c->n_bnd, (const double *)b, (const double *)nullptr,
+                           (const CgState *)nullptr, (double *)x, (double *)r, (double *)p,
+                           (double *)w, dptr<double>(c, L.dinv64), x_zero, partials_site(c, 1),
+                           st);
+    } else {
+        // inner refinement solve: b is the FP64 outer residual
+        const CgState *outer = dptr<CgState>(c, L.state) + 1;
+        hipLaunchKernelGGL(k_cg_begin<float>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n,
+                           c->n_bnd, (const float *)nullptr, (const double *)b, outer,
+                           (float *)x, (float *)r, (float *)p, (float *)w,
+                           dptr<float>(c, L.dinv32), 1, partials_site(c, 1), st);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_iteration(sem_ctx c, int level, int prec, void *x, void *r, void *p, void *w,
+                               CgState *st, int deterministic, hipStream_t s) {
+    const Layout &L = c->L;
+    const int64_t n = c->n_unique;
+    hipError_t e;
+    if (deterministic) {
+        e = launch_ax(c, prec, p, w, 0, OUT_COMPACT, partials_site(c, 0), st, c->tile[prec], s);
+        if (e != hipSuccess) return e;
+        e = launch_gather_sum(c, prec, c->ws + L.wb, w, s);
+    } else {
+        e = launch_ax(c, prec, p, w, 0, OUT_ATOMIC, partials_site(c, 0), st, c->tile[prec], s);
+    }
+    if (e != hipSuccess) return e;
+    if (prec == SEM_FP64) {
+        hipLaunchKernelGGL(k_cg_update<double>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n,
+                           (double *)x, (double *)r, (const double *)p, (const double *)w,
+                           dptr<double>(c, L.dinv64), partials_site(c, 2), st);
+        hipLaunchKernelGGL(k_cg_p<double>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n, c->n_bnd,
+                           (const double *)r, (double *)p, (double *)w, dptr<double>(c, L.dinv64),
+                           (const CgState *)st);
+    } else {
+        hipLaunchKernelGGL(k_cg_update<float>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n,
+                           (float *)x, (float *)r, (const float *)p, (const float *)w,
+                           dptr<float>(c, L.dinv32), partials_site(c, 2), st);
+        hipLaunchKernelGGL(k_cg_p<float>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n, c->n_bnd,
+                           (const float *)r, (float *)p, (float *)w, dptr<float>(c, L.dinv32),
+                           (const CgState *)st);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_residual64(sem_ctx c, const double *b, const double *Ax, double *r, float *,
+                             CgState *st, hipStream_t s) {
+    const int64_t n = c->n_unique;
+    hipLaunchKernelGGL(k_residual64, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n, b, Ax, r,
+                       partials_site(c, 3), st);
+    return hipGetLastError();
+}
+
+hipError_t launch_ir_update(sem_ctx c, double *x, const float *d, CgState *outer, hipStream_t s) {
+    const int64_t n = c->n_unique;
+    hipLaunchKernelGGL(k_ir_update, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n, x, d,
+                       (const CgState *)outer);
+    return hipGetLastError();
+}
+
+}  // namespace sem

@@ -1,0 +1,243 @@
+"""GPU parity of libsem against the FP64 oracle, through the C ABI.
+
+Bar: FP64 fields agree with the oracle to 1e-12 normwise-relative (max
+norm); index maps bit-exact; reduced-precision operators within a small
+multiple of the error that rounding G alone causes (oracle emulation);
+solves reach the requested true residual, checked with the oracle's own
+operator on the GPU solution.
+"""
+import numpy as np
+import pytest
+
+import fixtures as F
+import oracle
+from tests.common import Pair, relerr, sampled_apply
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2207_07098_amd as sem  # noqa: E402
+
+TOL64 = 1e-12
+
+
+def _meshes():
+    return {
+        "cube4_N5": (F.box(4), 5),
+        "deformed3_N7": (F.box(3, hi=(2 * np.pi,) * 3, deform=0.05), 7),
+        "reoriented_N4": (F.box((3, 2, 2), hi=(2.0, 1.0, 1.5), reorient_seed=3), 4),
+        "ogrid_N3": (F.ogrid(8, 3, 4), 3),
+        "stretched_N9": (F.box(2, hi=(3.0, 1.0, 2.0), widths=[[0.5, 2.0], [1.0, 1.7], [0.6, 0.9]]), 9),
+        "single_N1": (F.box(1, dirichlet=(0,) * 6), 1),
+        "box2_N2": (F.box(2), 2),
+    }
+
+
+_cache = {}
+
+
+def pair(name):
+    if name not in _cache:
+        m, N = _meshes()[name]
+        print("case", name, flush=True)
+        _cache[name] = Pair(m, N)
+    return _cache[name]
+
+
+ALL = list(_meshes().keys())
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_geometry_and_jacobi(name):
+    p = pair(name)
+    G, B, dinv = p.op.geometry()
+    assert relerr(G, p.ora.G) < TOL64
+    assert relerr(B, p.ora.B) < TOL64
+    assert relerr(dinv[p.pos], p.ora.dinv) < TOL64
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_ax_local(name):
+    p = pair(name)
+    rng = np.random.default_rng(1)
+    uL = rng.uniform(-1, 1, (p.op.E, (p.N + 1) ** 3))
+    w = p.op.ax_local(p.local_to_dev(uL)).cpu().numpy().reshape(uL.shape)
+    assert relerr(w, oracle.ax_local(p.N, p.ora.G, uL)) < TOL64
+
+
+@pytest.mark.parametrize("deterministic", [False, True])
+@pytest.mark.parametrize("name", ALL)
+def test_assembled_operator(name, deterministic):
+    p = pair(name)
+    u = F.random_unique(p.op.n_unique, 0)
+    y = p.op.ax(p.to_dev(u), deterministic=deterministic)
+    torch.cuda.synchronize()
+    assert relerr(p.from_dev(y), p.ora.apply(u)) < TOL64
+
+
+@pytest.mark.parametrize("name", ["cube4_N5", "reoriented_N4", "ogrid_N3"])
+def test_gs_gather_scatter(name):
+    p = pair(name)
+    rng = np.random.default_rng(2)
+    vL = rng.uniform(-1, 1, p.op.n_local)
+    # Q M Q^T on an E-vector
+    ref = oracle.q(p.gid, np.where(p.dmask == 1, 0.0, oracle.qt(p.gid, vL, p.op.n_unique)))
+    t = p.local_to_dev(vL)
+    p.op.gs(t)
+    assert relerr(t.cpu().numpy(), ref.ravel()) < TOL64
+    t32 = p.local_to_dev(vL, torch.float32)
+    p.op.gs(t32, precision="fp32")
+    assert relerr(t32.cpu().numpy(), ref.ravel()) < 1e-6
+    # Q and M Q^T between unique and local vectors
+    u = F.random_unique(p.op.n_unique, 3)
+    uL = p.op.gather(p.to_dev(u)).cpu().numpy()
+    assert np.array_equal(uL, oracle.q(p.gid, u).ravel())
+    y = p.op.scatter(p.local_to_dev(vL))
+    yref = np.where(p.dmask == 1, 0.0, oracle.qt(p.gid, vL, p.op.n_unique))
+    assert relerr(p.from_dev(y), yref) < TOL64
+
+
+@pytest.mark.parametrize("name", ["cube4_N5", "ogrid_N3", "stretched_N9"])
+def test_rhs(name):
+    p = pair(name)
+    rng = np.random.default_rng(4)
+    fL = rng.uniform(-1, 1, p.op.n_local)
+    b = p.op.rhs(f_local=p.local_to_dev(fL))
+    assert relerr(p.from_dev(b), p.ora.rhs_local(fL)) < TOL64
+    f = F.random_unique(p.op.n_unique, 5)
+    b2 = p.op.rhs(f_unique=p.to_dev(f))
+    assert relerr(p.from_dev(b2), p.ora.rhs_unique(f)) < TOL64
+
+
+@pytest.mark.parametrize("prec,fmt,dtype", [("fp32", "fp32", "float32"),
+                                            ("fp16", "fp16", "float32"),
+                                            ("bf16", "bf16", "float32")])
+@pytest.mark.parametrize("name", ["cube4_N5", "deformed3_N7", "ogrid_N3", "stretched_N9"])
+def test_reduced_precision_operator(name, prec, fmt, dtype):
+    """Error of the reduced-precision operator against the FP64 oracle is
+    within 4x the error of the oracle run with G rounded the same way, plus
+    FP32 arithmetic noise (~1e-6)."""
+    p = pair(name)
+    u = F.random_unique(p.op.n_unique, 0)
+    y = p.op.ax(p.to_dev(u, getattr(torch, dtype)), precision=prec)
+    torch.cuda.synchronize()
+    err = relerr(p.from_dev(y), p.ora.apply(u))
+    Pq = oracle.Problem(**{**p.ora.__dict__, "G": oracle.quantize_G(p.ora.G, fmt)})
+    emul = relerr(Pq.apply(u), p.ora.apply(u))
+    assert err < 4 * emul + 2e-6, (err, emul)
+
+
+def test_deterministic_operator_is_bitwise_repeatable():
+    p = pair("deformed3_N7")
+    u = p.to_dev(F.random_unique(p.op.n_unique, 7))
+    first = p.op.ax(u, deterministic=True).clone()
+    for _ in range(20):
+        assert torch.equal(p.op.ax(u, deterministic=True), first)
+
+
+# ------------------------------------------------------------------ solves
+def _solve_case(p, b, tol, precision="fp64", **kw):
+    x, info = p.op.solve(p.to_dev(b), tol=tol, precision=precision, **kw)
+    xc = p.from_dev(x)
+    true_rel = p.ora.true_residual(xc, b)
+    return xc, info, true_rel
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "bf16"])
+def test_solve_unit_cube_manufactured(precision):
+    """Config: unit cube 4^3, N=5, f = 3 pi^2 sin sin sin, to 1e-10."""
+    p = pair("cube4_N5")
+    w = F.unit_cube(4, 5)
+    b = p.ora.rhs_local(w.f_local(p.ora.xyz))
+    xc, info, true_rel = _solve_case(p, b, 1e-10, precision)
+    assert info["status"] == "SEM_OK", info
+    assert true_rel <= 1e-10 * 1.01, (true_rel, info)
+    xo, oinfo = p.ora.pcg(b, 1e-12)
+    assert relerr(xc, xo) < 1e-8
+    ue = np.zeros(p.op.n_unique)
+    ue[p.gid.ravel()] = w.u_exact(p.ora.xyz).ravel()
+    assert np.max(np.abs(xc - ue)) < 1e-4        # discretisation error at N=5, K=4
+    if precision == "fp64":
+        assert abs(info["iterations"] - oinfo["iterations"]) <= 0.25 * oinfo["iterations"] + 5
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_solve_graph_and_eager_agree(graph):
+    p = pair("deformed3_N7")
+    b = p.ora.rhs_unique(F.random_unique(p.op.n_unique, 11))
+    xc, info, true_rel = _solve_case(p, b, 1e-10, use_graph=graph, check_every=7)
+    assert info["status"] == "SEM_OK" and true_rel <= 1.01e-10
+
+
+def test_solve_deterministic_repeatable():
+    p = pair("ogrid_N3")
+    b = p.to_dev(p.ora.rhs_unique(F.random_unique(p.op.n_unique, 12)))
+    x1, i1 = p.op.solve(b, tol=1e-10, deterministic=True)
+    x2, i2 = p.op.solve(b, tol=1e-10, deterministic=True)
+    assert torch.equal(x1, x2) and i1["iterations"] == i2["iterations"]
+
+
+def test_solve_warm_start_and_restart():
+    p = pair("reoriented_N4")
+    b = p.ora.rhs_unique(F.random_unique(p.op.n_unique, 13))
+    xo, _ = p.ora.pcg(b, 1e-12)
+    x0 = p.to_dev(xo + 1e-6 * F.random_unique(p.op.n_unique, 14) * (p.dmask == 0))
+    x, info = p.op.solve(p.to_dev(b), x=x0, tol=1e-10)
+    assert info["status"] == "SEM_OK"
+    assert p.ora.true_residual(p.from_dev(x), b) <= 1.01e-10
+
+
+def test_solve_failure_modes():
+    p = pair("cube4_N5")
+    b = p.ora.rhs_unique(F.random_unique(p.op.n_unique, 15))
+    x, info = p.op.solve(p.to_dev(b), tol=1e-10, max_iter=3, raise_on_error=False,
+                         max_restart=0)
+    assert info["status"] == "SEM_ERR_NOT_CONVERGED" and info["iterations"] == 3
+    bn = b.copy()
+    bn[np.nonzero(p.dmask == 0)[0][5]] = np.nan
+    x, info = p.op.solve(p.to_dev(bn), tol=1e-10, raise_on_error=False)
+    assert info["status"] == "SEM_ERR_NAN"
+    # zero right-hand side: immediate exit with x = 0
+    x, info = p.op.solve(p.to_dev(np.zeros(p.op.n_unique)), tol=1e-10, raise_on_error=False)
+    assert torch.count_nonzero(x) == 0
+
+
+def test_inverted_element_is_rejected():
+    m = F.box(2)
+    xi, _ = sem.gll(3)
+    X = m.coords(xi)
+    X[1] = X[1][:, :, :, ::-1]              # mirror element 1 along r
+    with pytest.raises(sem.SemError) as e:
+        sem.Operator(m, 3, gll_xyz=X)
+    assert e.value.status == 2 and "element 1" in str(e.value)
+
+
+def test_trilinear_vertex_geometry_matches_gll_coordinates():
+    m = F.box(3, hi=(1.0, 2.0, 3.0), widths=[[1, 2, 1], [1, 1, 3], [2, 1, 1]])
+    a = sem.Operator(m, 4)                       # from vertex_xyz
+    b = sem.Operator(m, 4, gll_xyz=m.coords(sem.gll(4)[0]))
+    Ga, _, _ = a.geometry()
+    Gb, _, _ = b.geometry()
+    assert relerr(Ga, Gb) < TOL64
+
+
+# ------------------------------------------------------ full-size sampling
+@pytest.mark.parametrize("K", [16, 48])
+def test_full_size_sampled_parity(K):
+    """[0,2pi]^3 with K^3 deformed elements, N=7, in the benchmark's launch
+    configuration: the fused operator at 4096 sampled unique nodes against
+    the oracle evaluated on the elements around them."""
+    w = F.periodic_box_deformed(K, 7)
+    op = sem.Operator(w.mesh, 7, precisions=("fp64",), solver=False)
+    gid, pos, dmask, mult = op.numbering()
+    u = F.random_unique(op.n_unique, 0)
+    uv = np.empty_like(u)
+    uv[pos] = u
+    y = op.ax(torch.from_numpy(uv).cuda()).cpu().numpy()[pos]
+    rng = np.random.default_rng(K)
+    nodes = np.unique(rng.integers(0, op.n_unique, 4096))
+    ref = sampled_apply(w.mesh, 7, u, nodes, gid)
+    assert relerr(y[nodes], ref) < TOL64

@@ -1,0 +1,178 @@
+"""Host-side tests of libsem (no GPU): ABI exports, GLL data, numbering
+bit-exact against the oracle's independent lattice numbering, and mesh
+validation errors."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import fixtures as F
+import oracle
+import paper_2207_07098_amd as sem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "sem.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sem_[a-z_0-9]+)\s*\(", src)) - {"sem_ctx"})
+
+
+def test_library_exports_every_declared_symbol():
+    declared = _declared_functions()
+    assert len(declared) >= 15
+    out = subprocess.check_output(["nm", "-D", "--defined-only", sem.LIB_PATH], text=True)
+    exported = set(re.findall(r" T (sem_\w+)", out))
+    missing = [f for f in declared if f not in exported]
+    assert not missing, missing
+    L = sem.lib()
+    for f in declared:
+        assert hasattr(L, f)
+    assert sorted(sem.EXPORTS) == declared
+
+
+def test_library_is_for_gfx950():
+    out = subprocess.run(["/opt/rocm/bin/roc-obj-ls", sem.LIB_PATH], capture_output=True,
+                         text=True)
+    if out.returncode != 0:
+        pytest.skip("roc-obj-ls unavailable")
+    assert "gfx950" in out.stdout
+
+
+@pytest.mark.parametrize("N", list(range(1, 16)))
+def test_gll_matches_oracle(N):
+    xi, rho = sem.gll(N)
+    oxi, orho = oracle.gll(N)
+    np.testing.assert_allclose(xi, oxi, atol=1e-15)
+    np.testing.assert_allclose(rho, orho, rtol=1e-13)
+
+
+def test_gll_rejects_unsupported_order():
+    with pytest.raises(sem.SemError) as e:
+        sem.gll(16)
+    assert e.value.status == 8
+    with pytest.raises(sem.SemError):
+        sem.gll(0)
+
+
+def _numbering_case(mesh, N):
+    op = sem.Operator(mesh, N, setup_device=False)
+    gid, pos, dmask, mult = op.numbering()
+    ogid, nu = oracle.number(N, mesh)
+    omult, odm = oracle.mult_mask(N, ogid, mesh.face_bc, nu)
+    assert op.n_unique == nu
+    assert np.array_equal(gid, ogid)              # bit-exact canonical numbering
+    assert np.array_equal(mult, omult)
+    assert np.array_equal(dmask, odm)
+    assert op.n_dirichlet == int(odm.sum())
+    # solver order: a permutation with boundary nodes first, interiors after
+    assert np.array_equal(np.sort(pos), np.arange(nu))
+    n1 = N + 1
+    interior = np.zeros((mesh.num_elements, n1, n1, n1), dtype=bool)
+    if N > 1:
+        interior[:, 1:-1, 1:-1, 1:-1] = True
+    is_int = np.zeros(nu, dtype=bool)
+    is_int[gid[interior.reshape(mesh.num_elements, -1)]] = True
+    assert op.n_boundary == nu - is_int.sum()
+    assert (pos[~is_int] < op.n_boundary).all() and (pos[is_int] >= op.n_boundary).all()
+    # interior nodes follow element order, l order inside the element
+    if N > 1:
+        ints = pos[gid[interior.reshape(mesh.num_elements, -1)]]
+        assert np.array_equal(ints.ravel(), op.n_boundary + np.arange(ints.size))
+    return op
+
+
+@pytest.mark.parametrize("K,N", [(1, 1), (2, 1), (2, 2), (3, 4), (4, 5), (2, 7)])
+def test_numbering_box(K, N):
+    _numbering_case(F.box(K), N)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+@pytest.mark.parametrize("N", [2, 3, 6])
+def test_numbering_reoriented_elements(seed, N):
+    """Every element in a random proper rotation of its local frame: the
+    face/edge keys must still identify shared nodes exactly."""
+    _numbering_case(F.box((3, 2, 2), reorient_seed=seed), N)
+
+
+def test_numbering_partial_dirichlet():
+    _numbering_case(F.box(3, dirichlet=(1, 0, 0, 1, 0, 0)), 4)
+
+
+@pytest.mark.parametrize("N", [1, 3, 7])
+def test_numbering_periodic_ogrid(N):
+    _numbering_case(F.ogrid(8, 3, 4), N)
+
+
+def test_numbering_config_sizes():
+    op = sem.Operator(F.box(4), 5, setup_device=False)
+    assert op.n_unique == 9261 and op.n_local == 13824
+    op = sem.Operator(F.box(16), 7, setup_device=False)
+    assert op.n_unique == 1442897 and op.n_local == 2097152
+
+
+def _raw_mesh(corner_ids, num_vertices, face_bc=None):
+    class M:
+        pass
+    m = M()
+    m.num_elements = corner_ids.shape[0]
+    m.corner_ids = corner_ids
+    m.face_bc = np.zeros((m.num_elements, 6), np.uint8) if face_bc is None else face_bc
+    m.num_vertices = num_vertices
+    m.vertex_xyz = None
+    return m
+
+
+def test_setup_rejects_repeated_corner():
+    c = np.arange(8, dtype=np.int64)[None].copy()
+    c[0, 3] = c[0, 0]
+    with pytest.raises(sem.SemError) as e:
+        sem.Operator(_raw_mesh(c, 8), 3, setup_device=False)
+    assert e.value.status == 2 and "repeated corner" in str(e.value)
+
+
+def test_setup_rejects_out_of_range_ids():
+    c = np.arange(8, dtype=np.int64)[None].copy()
+    c[0, 7] = 99
+    with pytest.raises(sem.SemError) as e:
+        sem.Operator(_raw_mesh(c, 8), 3, setup_device=False)
+    assert e.value.status == 2
+
+
+def test_setup_rejects_face_shared_by_three_elements():
+    m = F.box((2, 1, 1))
+    c = np.concatenate([m.corner_ids, m.corner_ids[:1]])
+    with pytest.raises(sem.SemError) as e:
+        sem.Operator(_raw_mesh(c, m.num_vertices), 2, setup_device=False)
+    assert e.value.status == 2 and "more than two" in str(e.value)
+
+
+def test_setup_rejects_unsupported_order():
+    with pytest.raises(sem.SemError) as e:
+        sem.Operator(F.box(1), 16, setup_device=False)
+    assert e.value.status == 8
+
+
+def test_device_calls_need_a_workspace():
+    op = sem.Operator(F.box(1), 2, setup_device=False)
+    st = sem.lib().sem_set_geometry(op._ctx, None, None)
+    assert st == 9      # SEM_ERR_STATE
+    assert b"workspace" in sem.lib().sem_last_error(op._ctx)
+
+
+def test_workspace_size_accounts_for_precisions():
+    m = F.box(2)
+    a = sem.Operator(m, 5, precisions=("fp64",), solver=False, setup_device=False)
+    b = sem.Operator(m, 5, precisions=("fp64", "fp32", "fp16", "bf16"), solver=True,
+                     setup_device=False)
+    sa, sb = ctypes.c_size_t(), ctypes.c_size_t()
+    sem.lib().sem_workspace_size(a._ctx, ctypes.byref(sa))
+    sem.lib().sem_workspace_size(b._ctx, ctypes.byref(sb))
+    nl = a.n_local
+    # G: 48 B/pt fp64 + 24 fp32 + 12 fp16 + 12 bf16
+    assert sb.value - sa.value >= 48 * nl
+    assert sa.value >= 48 * nl + 8 * nl
