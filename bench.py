@@ -77,6 +77,10 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--solve-precisions", default="fp64,fp32,fp16,bf16")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="time a plain device copy of 1 GiB (for counter scaling) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the multi-GPU path (element partitions with a "
@@ -88,6 +92,23 @@ def main():
     import paper_2207_07098_amd as sem
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = (1 << 30) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8,
+                          "ms": ms, "GBps_read_plus_write": 2 * n * 8 / ms / 1e6}))
+        return
     N, K = args.N, args.K
     w = F.periodic_box_deformed(K, N, tol=1e-10)
     t0 = time.perf_counter()
@@ -105,6 +126,13 @@ def main():
     nb = op.n_boundary
     stream = torch.cuda.current_stream()
 
+    tune = {}
+    if not args.no_tune:
+        best, table = op.autotune("fp64", reps=10, cache_path=args.tune_cache)
+        tune["fp64"] = {"best": best, "candidates": [[t["elements_per_block"], t["grid_cap"],
+                                                      t["xcd_remap"], round(ms, 4)]
+                                                     for t, ms in table]}
+        log("autotune fp64:", best, "best %.4f ms" % min(ms for _, ms in table))
     for _ in range(args.warmup):
         op.ax(u, y)
     torch.cuda.synchronize()
@@ -150,7 +178,10 @@ def main():
                      "kernel": "k_ax<8,double> (fused Ax+gs, atomic summation)",
                      "kernel_ms": k_ms, "bytes_per_launch": B},
         "local_points_per_s": op.n_local / (ms_step * 1e-3),
+        "tile": op.get_tile("fp64"),
     }
+    if tune:
+        result["autotune"] = tune
 
     # deterministic (fixed-order) variant, for reference
     torch.cuda.synchronize()
@@ -173,6 +204,11 @@ def main():
         # exact solution at unique nodes (solver order)
         ue = np.zeros(op.n_unique)
         ue[pos[gid.ravel()]] = ue_L
+        if not args.no_tune:
+            for prec in ("fp32", "fp16", "bf16"):
+                best, table = op.autotune(prec, reps=10, cache_path=args.tune_cache)
+                log("autotune", prec, best, "%.4f ms" % min(ms for _, ms in table))
+                tune[prec] = {"best": best, "best_ms": min(ms for _, ms in table)}
         solves = {}
         x64 = None
         for prec in args.solve_precisions.split(","):

@@ -193,6 +193,37 @@ sem_status sem_ax(sem_ctx ctx, const void *u, void *y, sem_precision prec,
 sem_status sem_rhs(sem_ctx ctx, const double *f_L, const double *f,
                    double *b, sem_stream stream);
 
+/* Launch shape of the element operator for one precision. */
+typedef struct {
+    int elements_per_block;       /* elements per workgroup (one lane per
+                                     (i,j) column of an element)            */
+    int grid_cap;                 /* 0: one workgroup per element group;
+                                     otherwise persistent workgroups, a
+                                     multiple of 8                          */
+    int xcd_remap;                /* 1: contiguous element ranges per XCD    */
+} sem_tile;
+
+typedef struct {
+    sem_tile tile;
+    double   ms;                  /* mean time of one fused operator launch  */
+} sem_tune_result;
+
+sem_status sem_get_tile(sem_ctx ctx, sem_precision prec, sem_tile *tile);
+sem_status sem_set_tile(sem_ctx ctx, sem_precision prec, const sem_tile *tile);
+
+/* Autotuner: times the fused assembled operator of precision `prec` for
+ * every candidate tile (elements per workgroup, persistent grid size, XCD
+ * remapping) on this context's mesh with hipEvents on `stream`, keeps the
+ * fastest for later calls and returns it.  Uses the solver work vectors as
+ * scratch (needs opts.solver = 1); their contents are overwritten.
+ * cache_path (may be NULL): a text file of earlier results keyed by
+ * architecture, N, precision and element count; a hit skips the timing,
+ * a miss appends the new result.  results/max_results/n_results (may be
+ * NULL/0/NULL) receive every candidate's timing. */
+sem_status sem_autotune(sem_ctx ctx, sem_precision prec, int reps, const char *cache_path,
+                        sem_tile *best, sem_tune_result *results, int max_results,
+                        int *n_results, sem_stream stream);
+
 typedef struct {
     double        tol;            /* target ||b - A x||_2 / ||b||_2          */
     int64_t       max_iter;       /* cap on CG iterations (all levels)       */

@@ -51,6 +51,19 @@ class _Info(ctypes.Structure):
                 ("n_bpoints", ctypes.c_int64)]
 
 
+class Tile(ctypes.Structure):
+    _fields_ = [("elements_per_block", ctypes.c_int), ("grid_cap", ctypes.c_int),
+                ("xcd_remap", ctypes.c_int)]
+
+    def as_dict(self):
+        return {"elements_per_block": self.elements_per_block, "grid_cap": self.grid_cap,
+                "xcd_remap": self.xcd_remap}
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("tile", Tile), ("ms", ctypes.c_double)]
+
+
 class SolveOptions(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int64),
                 ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double),
@@ -79,7 +92,8 @@ EXPORTS = ["sem_gll", "sem_setup", "sem_free", "sem_last_error", "sem_query",
            "sem_export_numbering", "sem_workspace_size", "sem_bind_workspace",
            "sem_set_geometry", "sem_export_geometry", "sem_ax_local", "sem_gs",
            "sem_gather", "sem_scatter", "sem_ax", "sem_rhs",
-           "sem_default_solve_options", "sem_cg_solve"]
+           "sem_default_solve_options", "sem_cg_solve", "sem_get_tile", "sem_set_tile",
+           "sem_autotune"]
 
 _lib = None
 
@@ -113,6 +127,9 @@ def lib():
         "sem_rhs": ([P, P, P, P, P], i32),
         "sem_default_solve_options": ([P], None),
         "sem_cg_solve": ([P, P, P, P, P, P], i32),
+        "sem_get_tile": ([P, i32, P], i32),
+        "sem_set_tile": ([P, i32, P], i32),
+        "sem_autotune": ([P, i32, i32, ctypes.c_char_p, P, P, i32, P, P], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -322,6 +339,28 @@ class Operator:
         if st and raise_on_error:
             self._check(st)
         return x, d
+
+    # -- launch shapes -----------------------------------------------------
+    def get_tile(self, precision: str = "fp64"):
+        t = Tile()
+        self._check(lib().sem_get_tile(self._ctx, PRECISIONS[precision], ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tile(self, precision: str = "fp64", elements_per_block=1, grid_cap=0, xcd_remap=1):
+        t = Tile(elements_per_block, grid_cap, xcd_remap)
+        self._check(lib().sem_set_tile(self._ctx, PRECISIONS[precision], ctypes.byref(t)))
+
+    def autotune(self, precision: str = "fp64", reps: int = 10, cache_path: Optional[str] = None):
+        """Time every candidate tile of the fused operator, keep the fastest.
+        Returns (best tile dict, list of (tile dict, ms))."""
+        best = Tile()
+        res = (TuneResult * 256)()
+        n = ctypes.c_int()
+        self._check(lib().sem_autotune(self._ctx, PRECISIONS[precision], reps,
+                                       cache_path.encode() if cache_path else None,
+                                       ctypes.byref(best), res, 256, ctypes.byref(n),
+                                       _stream_handle()))
+        return best.as_dict(), [(res[q].tile.as_dict(), res[q].ms) for q in range(n.value)]
 
     # -- host-side ordering helpers (marshalling only) ---------------------
     def to_solver_order(self, v_canonical: np.ndarray, pos=None) -> np.ndarray:

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <climits>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <unordered_map>
 
@@ -666,6 +667,159 @@ extern "C" sem_status sem_rhs(sem_ctx c, const double *fL, const double *f, doub
     if ((fL == nullptr) == (f == nullptr) || !b)
         return fail(c, SEM_ERR_INVALID, "pass exactly one of f_L and f, and b");
     SEM_HIP(c, launch_rhs(c, fL, f, b, (hipStream_t)stream));
+    return SEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Launch shapes and the autotuner
+// ---------------------------------------------------------------------------
+extern "C" sem_status sem_get_tile(sem_ctx c, sem_precision prec, sem_tile *t) {
+    if (!c || !t || (int)prec < 0 || (int)prec >= kNumPrec) return fail(c, SEM_ERR_INVALID, "bad argument");
+    t->elements_per_block = c->tile[prec].epb;
+    t->grid_cap = c->tile[prec].grid_cap;
+    t->xcd_remap = c->tile[prec].xcd;
+    return SEM_OK;
+}
+
+static bool tile_valid(sem_ctx c, int prec, const sem_tile &t) {
+    const int C = c->n1 * c->n1;
+    if (t.elements_per_block < 1 || t.elements_per_block * C > 256) return false;
+    if (t.grid_cap < 0 || (t.grid_cap % 8) != 0) return false;
+    const size_t sz = prec == SEM_FP64 ? 8 : 4;
+    const int threads = ((t.elements_per_block * C + 63) / 64) * 64;
+    const int nslots = (threads + C - 1) / C;
+    const size_t lds = ((size_t)nslots * 2 * c->n1 * c->n1 * (c->n1 + 1) + C) * sz;
+    return lds <= c->max_lds;
+}
+
+extern "C" sem_status sem_set_tile(sem_ctx c, sem_precision prec, const sem_tile *t) {
+    if (!c || !t || (int)prec < 0 || (int)prec >= kNumPrec) return fail(c, SEM_ERR_INVALID, "bad argument");
+    if (!tile_valid(c, prec, *t)) return fail(c, SEM_ERR_INVALID, "tile does not fit this order");
+    c->tile[prec].epb = t->elements_per_block;
+    c->tile[prec].grid_cap = t->grid_cap;
+    c->tile[prec].xcd = t->xcd_remap;
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+    return SEM_OK;
+}
+
+static std::string arch_name() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return "unknown";
+    std::string a = prop.gcnArchName;
+    size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+extern "C" sem_status sem_autotune(sem_ctx c, sem_precision prec, int reps, const char *cache,
+                                   sem_tile *best, sem_tune_result *results, int max_results,
+                                   int *n_results, sem_stream stream) {
+    sem_status st = check_ready(c, prec);
+    if (st) return st;
+    if (!c->L.p64) return fail(c, SEM_ERR_STATE, "autotune needs the solver work vectors");
+    if (n_results) *n_results = 0;
+    const std::string arch = arch_name();
+    char key[256];
+    snprintf(key, sizeof(key), "%s N=%d prec=%d E=%lld", arch.c_str(), c->N, (int)prec,
+             (long long)c->E);
+    if (cache) {
+        FILE *f = fopen(cache, "r");
+        if (f) {
+            char line[512];
+            while (fgets(line, sizeof(line), f)) {
+                if (std::strncmp(line, key, std::strlen(key)) != 0) continue;
+                const char *rest = line + std::strlen(key);
+                sem_tile t;
+                double ms;
+                if (sscanf(rest, " : epb=%d grid=%d xcd=%d ms=%lf", &t.elements_per_block,
+                           &t.grid_cap, &t.xcd_remap, &ms) == 4 && tile_valid(c, prec, t)) {
+                    fclose(f);
+                    sem_set_tile(c, prec, &t);
+                    if (best) *best = t;
+                    if (results && max_results > 0) {
+                        results[0].tile = t;
+                        results[0].ms = ms;
+                        if (n_results) *n_results = 1;
+                    }
+                    return SEM_OK;
+                }
+            }
+            fclose(f);
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    void *u = prec == SEM_FP64 ? (void *)(c->ws + c->L.p64) : (void *)(c->ws + c->L.p32);
+    void *y = prec == SEM_FP64 ? (void *)(c->ws + c->L.w64) : (void *)(c->ws + c->L.w32);
+    if (!c->L.p32 && prec != SEM_FP64) return fail(c, SEM_ERR_STATE, "no reduced-precision vectors");
+    if (prec == SEM_FP64) {
+        SEM_HIP(c, launch_fill((double *)u, c->n_unique, 1.0, s));
+        SEM_HIP(c, launch_fill((double *)y, c->n_unique, 0.0, s));
+    } else {
+        SEM_HIP(c, launch_fill32((float *)u, c->n_unique, 1.0f, s));
+        SEM_HIP(c, launch_fill32((float *)y, c->n_unique, 0.0f, s));
+    }
+    const int C = c->n1 * c->n1;
+    const int max_epb = std::max(1, 256 / C);
+    std::vector<int> epbs;
+    for (int e = 1; e <= max_epb; ++e)
+        if (max_epb <= 8 || e == 1 || e == 2 || e == 4 || e == 8 || e == max_epb) epbs.push_back(e);
+    const int caps[4] = {0, 2 * c->num_cus, 4 * c->num_cus, 8 * c->num_cus};
+    hipEvent_t e0, e1;
+    SEM_HIP(c, hipEventCreate(&e0));
+    SEM_HIP(c, hipEventCreate(&e1));
+    const AxTile saved = c->tile[prec];
+    double best_ms = INFINITY;
+    AxTile best_t = saved;
+    int nres = 0;
+    reps = std::max(1, reps);
+    for (int epb : epbs)
+        for (int cap : caps)
+            for (int xcd = 0; xcd < 2; ++xcd) {
+                sem_tile t{epb, (cap / 8) * 8, xcd};
+                if (!tile_valid(c, prec, t)) continue;
+                AxTile at;
+                at.epb = epb;
+                at.grid_cap = t.grid_cap;
+                at.xcd = xcd;
+                hipError_t he = hipSuccess;
+                for (int r = 0; r < 2 && he == hipSuccess; ++r)
+                    he = launch_ax(c, prec, u, y, 0, OUT_ATOMIC, nullptr, nullptr, at, s);
+                if (he != hipSuccess) continue;
+                SEM_HIP(c, hipEventRecord(e0, s));
+                for (int r = 0; r < reps; ++r)
+                    SEM_HIP(c, launch_ax(c, prec, u, y, 0, OUT_ATOMIC, nullptr, nullptr, at, s));
+                SEM_HIP(c, hipEventRecord(e1, s));
+                SEM_HIP(c, hipEventSynchronize(e1));
+                float ms = 0.f;
+                SEM_HIP(c, hipEventElapsedTime(&ms, e0, e1));
+                const double per = ms / reps;
+                if (results && nres < max_results) {
+                    results[nres].tile = t;
+                    results[nres].ms = per;
+                }
+                ++nres;
+                if (per < best_ms) {
+                    best_ms = per;
+                    best_t = at;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (n_results) *n_results = std::min(nres, max_results);
+    c->tile[prec] = best_t;
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+    if (best) *best = sem_tile{best_t.epb, best_t.grid_cap, best_t.xcd};
+    if (cache && std::isfinite(best_ms)) {
+        FILE *f = fopen(cache, "a");
+        if (f) {
+            fprintf(f, "%s : epb=%d grid=%d xcd=%d ms=%.6f\n", key, best_t.epb, best_t.grid_cap,
+                    best_t.xcd, best_ms);
+            fclose(f);
+        }
+    }
     return SEM_OK;
 }
 
