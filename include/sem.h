@@ -239,6 +239,13 @@ typedef struct {
     int           deterministic;  /* fixed-order summation everywhere        */
     int           max_restart;    /* FP64 restarts when the true residual
                                      misses tol after convergence           */
+    double        reliable_delta; /* refinement variant: 0 = restart the
+                                     inner PCG at every FP64 correction;
+                                     delta in (0,1) = reliable updates: the
+                                     inner PCG keeps its search direction and
+                                     its residual is replaced by the FP64
+                                     residual whenever it has dropped by
+                                     delta since the last replacement        */
 } sem_solve_options;
 
 typedef struct {

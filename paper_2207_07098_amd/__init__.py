@@ -69,7 +69,8 @@ class SolveOptions(ctypes.Structure):
                 ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("zero_guess", ctypes.c_int),
-                ("deterministic", ctypes.c_int), ("max_restart", ctypes.c_int)]
+                ("deterministic", ctypes.c_int), ("max_restart", ctypes.c_int),
+                ("reliable_delta", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -314,7 +315,8 @@ class Operator:
     def solve(self, b, x=None, tol: float = 1e-10, precision: str = "fp64",
               max_iter: int = 100000, inner_tol: Optional[float] = None,
               check_every: int = 50, use_graph: bool = True, deterministic: bool = False,
-              max_outer: int = 50, max_restart: int = 3, raise_on_error: bool = True):
+              max_outer: int = 50, max_restart: int = 3, raise_on_error: bool = True,
+              reliable_delta: Optional[float] = None):
         """Jacobi-PCG (fp64) or FP64 iterative refinement around a reduced-
         precision PCG.  Returns (x, info dict)."""
         o = SolveOptions()
@@ -329,6 +331,8 @@ class Operator:
         o.deterministic = 1 if deterministic else 0
         o.max_outer = max_outer
         o.max_restart = max_restart
+        if reliable_delta is not None:
+            o.reliable_delta = reliable_delta
         o.zero_guess = 1 if x is None else 0
         if x is None:
             x = self.vector()

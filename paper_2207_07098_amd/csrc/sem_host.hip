@@ -587,8 +587,18 @@ extern "C" sem_status sem_export_geometry(sem_ctx c, double *G, double *B, doubl
     if (!c->geometry_ready) return fail(c, SEM_ERR_STATE, "geometry not set");
     hipStream_t s = (hipStream_t)stream;
     const Layout &L = c->L;
-    if (G) SEM_HIP(c, hipMemcpyAsync(G, c->ws + L.G[0], 8 * 6 * (size_t)c->n_local,
-                                     hipMemcpyDeviceToHost, s));
+    if (G) {
+        // device layout is point-major [E][n_p][6]; the ABI layout is [E][6][n_p]
+        std::vector<double> tmp(6 * (size_t)c->n_local);
+        SEM_HIP(c, hipMemcpyAsync(tmp.data(), c->ws + L.G[0], 8 * tmp.size(),
+                                  hipMemcpyDeviceToHost, s));
+        SEM_HIP(c, hipStreamSynchronize(s));
+        const size_t np = c->np;
+        for (int64_t e = 0; e < c->E; ++e)
+            for (size_t p = 0; p < np; ++p)
+                for (int cc = 0; cc < 6; ++cc)
+                    G[((size_t)e * 6 + cc) * np + p] = tmp[((size_t)e * np + p) * 6 + cc];
+    }
     if (B) SEM_HIP(c, hipMemcpyAsync(B, c->ws + L.B, 8 * (size_t)c->n_local,
                                      hipMemcpyDeviceToHost, s));
     if (dinv) SEM_HIP(c, hipMemcpyAsync(dinv, c->ws + L.dinv64, 8 * (size_t)c->n_unique,
@@ -838,6 +848,7 @@ extern "C" void sem_default_solve_options(sem_solve_options *o) {
     o->zero_guess = 1;
     o->deterministic = 0;
     o->max_restart = 3;
+    o->reliable_delta = 0.1;
 }
 
 namespace {
@@ -851,7 +862,7 @@ struct Level {
 // Runs CG iterations (graph-captured in chunks of m) until the device-side
 // state says done.  Returns the host copy of the final state.
 sem_status run_cg(sem_ctx c, const Level &lv, const sem_solve_options &o, int64_t cap,
-                  CgState *host_state, hipStream_t s) {
+                  CgState *host_state, hipStream_t s, bool one_chunk = false) {
     host_state->max_iter = cap;
     CgState *st = dptr<CgState>(c, c->L.state) + lv.level;
     const int m = std::max(1, o.check_every);
@@ -901,7 +912,7 @@ sem_status run_cg(sem_ctx c, const Level &lv, const sem_solve_options &o, int64_
         }
         SEM_HIP(c, hipMemcpyAsync(host_state, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
         SEM_HIP(c, hipStreamSynchronize(s));
-        if (host_state->done) break;
+        if (host_state->done || one_chunk) break;
     }
     return SEM_OK;
 }
@@ -1023,7 +1034,76 @@ static sem_status solve_refined(sem_ctx c, const double *b, double *x,
             o64.precision = SEM_FP64;
             return solve_fp64(c, b, x, o64, info, s, o.max_iter, false);
         }
-        SEM_HIP(c, launch_ir_update(c, x, (const float *)lv.x, dptr<CgState>(c, L.state) + 1, s));
+        SEM_HIP(c, launch_ir_update(c, x, (const float *)lv.x, dptr<CgState>(c, L.state) + 1, 1, s));
+    }
+}
+
+// Refinement with reliable updates: the reduced-precision PCG runs without
+// restarts; whenever its recurrence residual has dropped by `delta` since
+// the last replacement (or it reports convergence), its iterate is added to
+// the FP64 solution, the FP64 residual b - A x is recomputed and replaces
+// the inner residual, and the inner iterate restarts from zero while the
+// search direction is kept.  Convergence is decided on the FP64 residual.
+static sem_status solve_reliable(sem_ctx c, const double *b, double *x,
+                                 const sem_solve_options &o, sem_solve_info *info,
+                                 hipStream_t s) {
+    const Layout &L = c->L;
+    if (!L.d32) return fail(c, SEM_ERR_STATE, "no reduced-precision work vectors");
+    double *y = dptr<double>(c, L.w64);
+    double *r = dptr<double>(c, L.z64);
+    CgState *st_in = dptr<CgState>(c, L.state) + 2;
+    Level lv{2, (int)o.precision, c->ws + L.d32, c->ws + L.r32, c->ws + L.p32, c->ws + L.w32};
+    if (o.zero_guess) SEM_HIP(c, launch_fill(x, c->n_unique, 0.0, s));
+    CgState h;
+    sem_status e = residual64(c, b, x, y, r, nullptr, 1, o.deterministic, s, &h);
+    if (e) return e;
+    const double bb = h.bb;
+    double rel = bb > 0 ? std::sqrt(h.rr / bb) : 0.0;
+    info->true_rel_residual = rel;
+    if (!std::isfinite(rel)) return SEM_ERR_NAN;
+    if (rel <= o.tol) return SEM_OK;
+    CgState init;
+    std::memset(&init, 0, sizeof(init));
+    init.tol2 = (o.tol * o.tol) * bb / h.rr;     // absolute target (tol ||b||)^2 after begin
+    init.max_iter = o.max_iter;
+    SEM_HIP(c, hipMemcpyAsync(st_in, &init, sizeof(init), hipMemcpyHostToDevice, s));
+    SEM_HIP(c, launch_cg_begin(c, 2, r, lv.x, lv.r, lv.p, lv.w, 1, st_in, s, 0));
+    double rmax = std::sqrt(h.rr);
+    double last_rel = rel;
+    int stalls = 0;
+    auto fallback = [&]() {
+        sem_solve_options o64 = o;
+        o64.precision = SEM_FP64;
+        return solve_fp64(c, b, x, o64, info, s, o.max_iter, false);
+    };
+    for (;;) {
+        CgState hi;
+        e = run_cg(c, lv, o, o.max_iter, &hi, s, true);
+        if (e) return e;
+        info->iterations = hi.iter;
+        info->rel_residual = bb > 0 ? std::sqrt(hi.rr / bb) : 0.0;
+        const bool bad = hi.status == 2 || hi.status == 3;
+        if (!(hi.done || std::sqrt(hi.rr) < o.reliable_delta * rmax || bad)) continue;
+        // reliable update: x += x_in, FP64 residual
+        if (!bad) SEM_HIP(c, launch_ir_update(c, x, (const float *)lv.x, nullptr, 0, s));
+        e = residual64(c, b, x, y, r, nullptr, 1, o.deterministic, s, &h);
+        if (e) return e;
+        rel = std::sqrt(h.rr / bb);
+        info->true_rel_residual = rel;
+        info->outer_iterations += 1;
+        if (!std::isfinite(rel)) return SEM_ERR_NAN;
+        if (rel <= o.tol) return SEM_OK;
+        if (bad) return fallback();
+        if (hi.status == 1 || info->iterations >= o.max_iter) return SEM_ERR_NOT_CONVERGED;
+        if (hi.done) {
+            // inner recurrence met the target but the true residual did not:
+            // allow a few replacements, then finish in FP64
+            stalls = rel > 0.5 * last_rel ? stalls + 1 : 0;
+            if (stalls >= 2 || info->outer_iterations >= o.max_outer) return fallback();
+        }
+        last_rel = rel;
+        SEM_HIP(c, launch_reliable_reset(c, r, (float *)lv.r, (float *)lv.x, st_in, s));
+        rmax = std::sqrt(h.rr);
     }
 }
 
@@ -1058,6 +1138,8 @@ extern "C" sem_status sem_cg_solve(sem_ctx c, const double *b, double *x,
     auto t0 = std::chrono::steady_clock::now();
     if (o.precision == SEM_FP64)
         st = solve_fp64(c, b, x, o, info, s, o.max_iter, o.zero_guess != 0);
+    else if (o.reliable_delta > 0.0 && o.reliable_delta < 1.0)
+        st = solve_reliable(c, b, x, o, info, s);
     else
         st = solve_refined(c, b, x, o, info, s);
     hipError_t he = hipStreamSynchronize(s);

@@ -127,13 +127,15 @@ hipError_t launch_qt(sem_ctx c, const double *wL, double *y, hipStream_t s);
 
 // CG building blocks, T = double or float.
 hipError_t launch_cg_begin(sem_ctx c, int level, const void *b, void *x, void *r, void *p,
-                           void *w, int x_zero, CgState *st, hipStream_t s);
+                           void *w, int x_zero, CgState *st, hipStream_t s, int scaled = 1);
 hipError_t launch_cg_iteration(sem_ctx c, int level, int prec, void *x, void *r, void *p,
                                void *w, CgState *st, int deterministic, hipStream_t s);
 hipError_t launch_residual64(sem_ctx c, const double *b, const double *Ax, double *r,
                              float *r32, CgState *st, hipStream_t s);
-hipError_t launch_ir_update(sem_ctx c, double *x, const float *d, CgState *st,
+hipError_t launch_ir_update(sem_ctx c, double *x, const float *d, CgState *st, int scaled,
                             hipStream_t s);
+hipError_t launch_reliable_reset(sem_ctx c, const double *r64, float *r, float *x, CgState *st,
+                                 hipStream_t s);
 
 // Output modes of the element operator.
 enum { OUT_LOCAL = 0, OUT_ATOMIC = 1, OUT_COMPACT = 2 };

@@ -9,8 +9,10 @@
 //   * the r- and s-derivatives read the element block from LDS, stored
 //     [k][j][i] with a row pitch of N+2 so that row reads (fixed j) and
 //     column reads (fixed i) hit distinct banks;
-//   * the six geometric factors stream from HBM with unit stride across
-//     lanes ([E][6][k][j][i]);
+//   * the six geometric factors of a point are stored together
+//     ([E][k][j][i][6]) and a wave requests all planes of an element at
+//     once, while the index map of its next element is prefetched, so each
+//     element costs about one memory latency per wave;
 //   * element-interior nodes have solver indices that follow from the
 //     element index, so only element-boundary points read an index map and
 //     only they are summed (device atomics or a fixed-order second pass);
@@ -169,15 +171,58 @@ struct AxParams {
                                  // the kernel-argument segment as scalars
 };
 
-// Waves per SIMD the compiler must allow for: bounds the register budget so
-// that several elements' loads are in flight per CU.
+// The six factors of one point are stored together ([E][n_p][6]); a lane
+// fetches them with wide loads: 3 x 16 B (FP64), 3 x 8 B (FP32), 3 x 4 B
+// (16-bit).  The factors are streamed once per application, so the loads
+// carry a non-temporal hint.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void load_g6(const double *p, double (&g)[6]) {
+    const d2v *q = reinterpret_cast<const d2v *>(p);
+    d2v a = __builtin_nontemporal_load(q), b = __builtin_nontemporal_load(q + 1),
+        c = __builtin_nontemporal_load(q + 2);
+    g[0] = a.x; g[1] = a.y; g[2] = b.x; g[3] = b.y; g[4] = c.x; g[5] = c.y;
+}
+__device__ __forceinline__ void load_g6(const float *p, float (&g)[6]) {
+    const f2v *q = reinterpret_cast<const f2v *>(p);
+    f2v a = __builtin_nontemporal_load(q), b = __builtin_nontemporal_load(q + 1),
+        c = __builtin_nontemporal_load(q + 2);
+    g[0] = a.x; g[1] = a.y; g[2] = b.x; g[3] = b.y; g[4] = c.x; g[5] = c.y;
+}
+__device__ __forceinline__ void load_g6(const _Float16 *p, float (&g)[6]) {
+    const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const uint32_t w = __builtin_nontemporal_load(q + a);
+        g[2 * a] = (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
+        g[2 * a + 1] = (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+    }
+}
+__device__ __forceinline__ void load_g6(const bf16_t *p, float (&g)[6]) {
+    const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const uint32_t w = __builtin_nontemporal_load(q + a);
+        g[2 * a] = __uint_as_float(w << 16);
+        g[2 * a + 1] = __uint_as_float(w & 0xffff0000u);
+    }
+}
+
+// Waves per SIMD the compiler must allow for: bounds the register budget.
 template <int N1, typename GS>
 struct AxOcc {
     static constexpr int value =
-        sizeof(typename GT<GS>::T) == 8 ? (N1 <= 3 ? 4 : (N1 <= 10 ? 2 : 1))
-                                        : (N1 <= 7 ? 4 : (N1 <= 9 ? 3 : (N1 <= 13 ? 2 : 1)));
+        sizeof(typename GT<GS>::T) == 8 ? (N1 <= 3 ? 4 : (N1 <= 5 ? 3 : (N1 <= 9 ? 2 : 1)))
+                                        : (N1 <= 6 ? 4 : (N1 <= 9 ? 3 : (N1 <= 12 ? 2 : 1)));
 };
 
+// One pass over element groups.  Per element: the factors of all planes and
+// the gathered u are requested together (the index map of the element was
+// fetched while the previous element was computed), so a wave waits about
+// one memory latency per element; the t-direction work is register-local,
+// the r/s-directions go through LDS (buffers S0 = u, S1 = G-weighted r
+// gradient, S2 = G-weighted s gradient; two barriers per element).
 template <int N1, typename GS>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, 256),
                                amdgpu_waves_per_eu(AxOcc<N1, GS>::value)))
@@ -197,10 +242,11 @@ k_ax(AxParams<N1, GS> P) {
     const int i = col % N1, j = col / N1;
     const bool ring = (i == 0) || (i == N) || (j == 0) || (j == N);
     const int ridx = ring ? ring_index(i, j, N) : 0;
-    T *S0 = reinterpret_cast<T *>(smem_raw) + (size_t)slot * 2 * BUF;
+    T *S0 = reinterpret_cast<T *>(smem_raw) + (size_t)slot * 3 * BUF;
     T *S1 = S0 + BUF;
+    T *S2 = S1 + BUF;
     // lane-dependent rows of D are read from an LDS copy
-    T *Dl = reinterpret_cast<T *>(smem_raw) + (size_t)nslots * 2 * BUF;
+    T *Dl = reinterpret_cast<T *>(smem_raw) + (size_t)nslots * 3 * BUF;
     for (int q = tid; q < C; q += blockDim.x) {
 #pragma unroll
         for (int r = 0; r < C; ++r)
@@ -211,15 +257,39 @@ k_ax(AxParams<N1, GS> P) {
     T *__restrict__ WB = reinterpret_cast<T *>(P.wb);
     double dot = 0.0;
 
-    for (int64_t git = blockIdx.x; git < P.ngroups; git += gridDim.x) {
+    auto bpos_k = [&](int k) {
+        return (k == 0) ? col : (k == N ? C + (N - 1) * 4 * N + col : C + (k - 1) * 4 * N + ridx);
+    };
+    auto elem_of = [&](int64_t git, bool &act) {
         const int64_t g = P.xcd ? xcd_remap(git, P.ngroups) : git;
         const int64_t e = g * P.epb + slot;
-        const bool active = (slot < P.epb) && (e < P.E);
-        const int64_t ec = active ? e : 0;   // inactive lanes read element 0
+        act = (slot < P.epb) && (e < P.E);
+        return act ? e : (int64_t)0;     // inactive lanes read element 0
+    };
+    // map entries of the first element
+    int32_t bm_next[N1];
+    {
+        bool act;
+        const int64_t e0 = elem_of(blockIdx.x, act);
+#pragma unroll
+        for (int k = 0; k < N1; ++k)
+            bm_next[k] = (!P.in_local && ((k == 0) || (k == N) || ring))
+                             ? P.bmap[e0 * NB + bpos_k(k)] : -1;
+    }
 
+    for (int64_t git = blockIdx.x; git < P.ngroups; git += gridDim.x) {
+        bool active;
+        const int64_t ec = elem_of(git, active);
+
+        // ---- request the factors of every plane
+        T g[N1][6];
+        const GS *Ge = P.G + ((size_t)ec * NP + col) * 6;
+#pragma unroll
+        for (int k = 0; k < N1; ++k) load_g6(Ge + (size_t)k * C * 6, g[k]);
+
+        // ---- gather u_e = (Q M u)_e
         T u[N1];
         int32_t bidx[N1];
-        // ---- gather u_e = (Q M u)_e
 #pragma unroll
         for (int k = 0; k < N1; ++k) {
             bidx[k] = -1;
@@ -227,10 +297,7 @@ k_ax(AxParams<N1, GS> P) {
             if (P.in_local) {
                 u[k] = U[ec * NP + k * C + col];
             } else if (bpt) {
-                const int bp = (k == 0) ? col : (k == N ? C + (N - 1) * 4 * N + col
-                                                        : C + (k - 1) * 4 * N + ridx);
-                // ec is a valid element for every lane, so m is a valid entry
-                const int32_t m = P.bmap[ec * NB + bp];
+                const int32_t m = bm_next[k];   // valid entry for every lane
                 const T v = U[m & 0x7fffffff];
                 const bool take = active && m >= 0;
                 bidx[k] = take ? m : -1;
@@ -239,46 +306,44 @@ k_ax(AxParams<N1, GS> P) {
                 u[k] = U[interior_index(P.n_bnd, ec, i, j, k, N)];
             }
         }
-        __syncthreads();               // previous element's LDS readers are done
+        // ---- map entries of the next element
+        if (!P.in_local && git + gridDim.x < P.ngroups) {
+            bool act;
+            const int64_t en = elem_of(git + gridDim.x, act);
+#pragma unroll
+            for (int k = 0; k < N1; ++k)
+                if ((k == 0) || (k == N) || ring) bm_next[k] = P.bmap[en * NB + bpos_k(k)];
+        }
+
 #pragma unroll
         for (int k = 0; k < N1; ++k) S0[k * PLANE + j * PITCH + i] = u[k];
         __syncthreads();
 
-        // ---- D u, then G (D u); the factors of plane k+1 are requested while
-        // plane k is computed, and scheduling barriers keep the compiler from
-        // hoisting every plane's loads (which would exhaust the registers).
-        T wr[N1], ws[N1], wt[N1];
+        // ---- D u, then G (D u): r/s parts to LDS, t part kept in registers
+        T wt[N1];
         double edot = 0.0;
-        const GS *Ge = P.G + (size_t)ec * 6 * NP + col;
-        T gc[6], gn[6];
+        T Di[N1], Dj[N1];
 #pragma unroll
-        for (int c6 = 0; c6 < 6; ++c6) gc[c6] = GT<GS>::ld(Ge + c6 * NP);
+        for (int m = 0; m < N1; ++m) {
+            Di[m] = Dl[i * N1 + m];
+            Dj[m] = Dl[j * N1 + m];
+        }
 #pragma unroll
         for (int k = 0; k < N1; ++k) {
-            if (k + 1 < N1) {
-#pragma unroll
-                for (int c6 = 0; c6 < 6; ++c6) gn[c6] = GT<GS>::ld(Ge + c6 * NP + (k + 1) * C);
-            }
             T ur = 0, us = 0, ut = 0;
 #pragma unroll
             for (int m = 0; m < N1; ++m) {
-                ur += Dl[i * N1 + m] * S0[k * PLANE + j * PITCH + m];
-                us += Dl[j * N1 + m] * S0[k * PLANE + m * PITCH + i];
+                ur += Di[m] * S0[k * PLANE + j * PITCH + m];
+                us += Dj[m] * S0[k * PLANE + m * PITCH + i];
                 ut += P.D.v[k * N1 + m] * u[m];
             }
-            wr[k] = gc[0] * ur + gc[3] * us + gc[4] * ut;
-            ws[k] = gc[3] * ur + gc[1] * us + gc[5] * ut;
-            wt[k] = gc[4] * ur + gc[5] * us + gc[2] * ut;
-            if (P.partials) edot += (double)(ur * wr[k] + us * ws[k] + ut * wt[k]);
-#pragma unroll
-            for (int c6 = 0; c6 < 6; ++c6) gc[c6] = gn[c6];
+            const T wr = g[k][0] * ur + g[k][3] * us + g[k][4] * ut;
+            const T ws = g[k][3] * ur + g[k][1] * us + g[k][5] * ut;
+            wt[k] = g[k][4] * ur + g[k][5] * us + g[k][2] * ut;
+            S1[k * PLANE + j * PITCH + i] = wr;
+            S2[k * PLANE + j * PITCH + i] = ws;
+            if (P.partials) edot += (double)(ur * wr + us * ws + ut * wt[k]);
             __builtin_amdgcn_sched_barrier(0);
-        }
-        __syncthreads();               // all reads of u from LDS are done
-#pragma unroll
-        for (int k = 0; k < N1; ++k) {
-            S0[k * PLANE + j * PITCH + i] = wr[k];
-            S1[k * PLANE + j * PITCH + i] = ws[k];
         }
         __syncthreads();
 
@@ -286,12 +351,17 @@ k_ax(AxParams<N1, GS> P) {
         const T sc = SCALED ? (T)P.gscale[ec] : T(1);
         if (P.partials && active) dot += SCALED ? edot * (double)sc : edot;
 #pragma unroll
+        for (int m = 0; m < N1; ++m) {
+            Di[m] = Dl[m * N1 + i];
+            Dj[m] = Dl[m * N1 + j];
+        }
+#pragma unroll
         for (int k = 0; k < N1; ++k) {
             T w = 0;
 #pragma unroll
             for (int m = 0; m < N1; ++m) {
-                w += Dl[m * N1 + i] * S0[k * PLANE + j * PITCH + m];
-                w += Dl[m * N1 + j] * S1[k * PLANE + m * PITCH + i];
+                w += Di[m] * S1[k * PLANE + j * PITCH + m];
+                w += Dj[m] * S2[k * PLANE + m * PITCH + i];
                 w += P.D.v[m * N1 + k] * wt[m];
             }
             if (SCALED) w *= sc;
@@ -303,9 +373,7 @@ k_ax(AxParams<N1, GS> P) {
                     if (P.out_mode == OUT_ATOMIC) {
                         if (bidx[k] >= 0) unsafeAtomicAdd(Y + bidx[k], w);
                     } else {
-                        const int bp = (k == 0) ? col : (k == N ? C + (N - 1) * 4 * N + col
-                                                                : C + (k - 1) * 4 * N + ridx);
-                        WB[ec * NB + bp] = w;
+                        WB[ec * NB + bpos_k(k)] = w;
                     }
                 } else {
                     Y[interior_index(P.n_bnd, ec, i, j, k, N)] = w;
@@ -343,7 +411,7 @@ hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const v
     int epb = std::max(1, std::min(t.epb, 256 / C));
     const int threads = ((epb * C + 63) / 64) * 64;
     const int nslots = (threads + C - 1) / C;      // padding lanes get a slot too
-    const size_t lds = ((size_t)nslots * 2 * BUF + C) * sizeof(T);
+    const size_t lds = ((size_t)nslots * 3 * BUF + C) * sizeof(T);
     if (lds > c->max_lds) return hipErrorInvalidConfiguration;
     AxParams<N1, GS> P;
     P.u = u;
@@ -434,13 +502,13 @@ __global__ void k_geometry(const double *__restrict__ X, int64_t e0, int n1,
         auto dotA = [&](int s, int t) {
             return A[s][0] * A[t][0] + A[s][1] * A[t][1] + A[s][2] * A[t][2];
         };
-        double *Ge = G + (size_t)e * 6 * np + p;
-        Ge[0 * np] = f * dotA(0, 0);
-        Ge[1 * np] = f * dotA(1, 1);
-        Ge[2 * np] = f * dotA(2, 2);
-        Ge[3 * np] = f * dotA(0, 1);
-        Ge[4 * np] = f * dotA(0, 2);
-        Ge[5 * np] = f * dotA(1, 2);
+        double *Ge = G + ((size_t)e * np + p) * 6;     // point-major [E][n_p][6]
+        Ge[0] = f * dotA(0, 0);
+        Ge[1] = f * dotA(1, 1);
+        Ge[2] = f * dotA(2, 2);
+        Ge[3] = f * dotA(0, 1);
+        Ge[4] = f * dotA(0, 2);
+        Ge[5] = f * dotA(1, 2);
         B[(size_t)e * np + p] = wq * det;
     }
 }
@@ -500,16 +568,16 @@ __global__ void k_local_values(int mode, int64_t E, int n1, int64_t n_bnd,
         const int bp = bpt ? bpos_of(i, j, k, n1) : 0;
         double v;
         if (mode == 0) {
-            const double *g = G + (size_t)e * 6 * np;
+            const double *g = G + (size_t)e * 6 * np;      // point-major [n_p][6]
             double s = 0.0;
             for (int m = 0; m < n1; ++m) {
                 const double a = D[m * n1 + i], b = D[m * n1 + j], cc = D[m * n1 + k];
-                s += a * a * g[0 * np + m + n1 * (j + n1 * k)];
-                s += b * b * g[1 * np + i + n1 * (m + n1 * k)];
-                s += cc * cc * g[2 * np + i + n1 * (j + n1 * m)];
+                s += a * a * g[6 * (m + n1 * (j + n1 * k)) + 0];
+                s += b * b * g[6 * (i + n1 * (m + n1 * k)) + 1];
+                s += cc * cc * g[6 * (i + n1 * (j + n1 * m)) + 2];
             }
             const double di = D[i * n1 + i], dj = D[j * n1 + j], dk = D[k * n1 + k];
-            s += 2.0 * (di * dj * g[3 * np + p] + di * dk * g[4 * np + p] + dj * dk * g[5 * np + p]);
+            s += 2.0 * (di * dj * g[6 * p + 3] + di * dk * g[6 * p + 4] + dj * dk * g[6 * p + 5]);
             v = s;
         } else if (mode == 1) {
             v = B[q] * f[q];
@@ -627,7 +695,7 @@ __global__ void k_cg_begin(int64_t n, int64_t n_bnd, const T *__restrict__ b,
                            T *__restrict__ w, const T *__restrict__ dinv, int x_zero,
                            double *partials, CgState *st) {
     double rz = 0, rr = 0, bb = 0;
-    const double scale = b64 ? 1.0 / sqrt(outer->rr) : 1.0;
+    const double scale = (b64 && outer) ? 1.0 / sqrt(outer->rr) : 1.0;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * blockDim.x) {
         const T bq = b64 ? (T)(b64[q] * scale) : b[q];
@@ -731,13 +799,42 @@ __global__ void k_residual64(int64_t n, const double *__restrict__ b,
     }
 }
 
-// x += ||r|| d (refinement update; ||r|| from the outer residual state).
+// x += s d with s = ||r|| of the outer residual state (scaled inner
+// right-hand side) or s = 1.
 __global__ void k_ir_update(int64_t n, double *__restrict__ x, const float *__restrict__ d,
-                            const CgState *outer) {
-    const double s = sqrt(outer->rr);
+                            const CgState *outer, int scaled) {
+    const double s = scaled ? sqrt(outer->rr) : 1.0;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * blockDim.x)
         x[q] += s * (double)d[q];
+}
+
+// Reliable update of the inner solve: its residual is replaced by the FP64
+// residual r64 (rounded), its iterate restarts at zero, r.z and r.r are
+// recomputed; the search direction p is kept.
+__global__ void k_reliable_reset(int64_t n, const double *__restrict__ r64,
+                                 float *__restrict__ r, float *__restrict__ x,
+                                 const float *__restrict__ dinv, double *partials, CgState *st) {
+    double rz = 0, rr = 0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const float rq = (float)r64[q];
+        r[q] = rq;
+        x[q] = 0.0f;
+        rz += (double)rq * (double)(dinv[q] * rq);
+        rr += (double)rq * (double)rq;
+    }
+    double v[2] = {rz, rr}, out[2];
+    if (grid_reduce<2>(v, partials, &st->counter[1], out) && threadIdx.x == 0) {
+        st->rz = out[0];
+        st->rr = out[1];
+        st->done = 0;
+        st->status = 0;
+        if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
+            st->status = 3;
+            st->done = 1;
+        }
+    }
 }
 
 inline unsigned vec_grid(int64_t n) {
@@ -880,7 +977,7 @@ static double *partials_site(sem_ctx c, int site) {
 }
 
 hipError_t launch_cg_begin(sem_ctx c, int level, const void *b, void *x, void *r, void *p,
-                           void *w, int x_zero, CgState *st, hipStream_t s) {
+                           void *w, int x_zero, CgState *st, hipStream_t s, int scaled) {
     const Layout &L = c->L;
     const int64_t n = c->n_unique;
     if (level == 0) {
@@ -896,8 +993,9 @@ hipError_t launch_cg_begin(sem_ctx c, int level, const void *b, void *x, void *r
                            (double *)w, dptr<double>(c, L.dinv64), x_zero, partials_site(c, 1),
                            st);
     } else {
-        // inner refinement solve: b is the FP64 outer residual
-        const CgState *outer = dptr<CgState>(c, L.state) + 1;
+        // inner refinement solve: b is the FP64 outer residual, optionally
+        // divided by its norm (from the outer residual state)
+        const CgState *outer = scaled ? dptr<CgState>(c, L.state) + 1 : nullptr;
         hipLaunchKernelGGL(k_cg_begin<float>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n,
                            c->n_bnd, (const float *)nullptr, (const double *)b, outer,
                            (float *)x, (float *)r, (float *)p, (float *)w,
@@ -945,10 +1043,19 @@ hipError_t launch_residual64(sem_ctx c, const double *b, const double *Ax, doubl
     return hipGetLastError();
 }
 
-hipError_t launch_ir_update(sem_ctx c, double *x, const float *d, CgState *outer, hipStream_t s) {
+hipError_t launch_ir_update(sem_ctx c, double *x, const float *d, CgState *outer, int scaled,
+                            hipStream_t s) {
     const int64_t n = c->n_unique;
     hipLaunchKernelGGL(k_ir_update, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n, x, d,
-                       (const CgState *)outer);
+                       (const CgState *)outer, scaled);
+    return hipGetLastError();
+}
+
+hipError_t launch_reliable_reset(sem_ctx c, const double *r64, float *r, float *x, CgState *st,
+                                 hipStream_t s) {
+    const int64_t n = c->n_unique;
+    hipLaunchKernelGGL(k_reliable_reset, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n, r64, r, x,
+                       dptr<float>(c, c->L.dinv32), partials_site(c, 1), st);
     return hipGetLastError();
 }
 

@@ -164,6 +164,21 @@ def test_solve_unit_cube_manufactured(precision):
         assert abs(info["iterations"] - oinfo["iterations"]) <= 0.25 * oinfo["iterations"] + 5
 
 
+@pytest.mark.parametrize("delta", [0.0, 0.1, 0.5])
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "bf16"])
+def test_refinement_variants(precision, delta):
+    """Restarted refinement (delta = 0) and reliable updates (delta > 0)
+    both reach a true FP64 residual of 1e-10 on a curvilinear mesh."""
+    p = pair("deformed3_N7")
+    b = p.ora.rhs_unique(F.random_unique(p.op.n_unique, 21))
+    xc, info, true_rel = _solve_case(p, b, 1e-10, precision, reliable_delta=delta,
+                                     inner_tol=1e-4 if precision == "fp32" else 1e-2)
+    assert info["status"] == "SEM_OK", info
+    assert true_rel <= 1.01e-10, (true_rel, info)
+    xo, _ = p.ora.pcg(b, 1e-12)
+    assert relerr(xc, xo) < 1e-7
+
+
 @pytest.mark.parametrize("graph", [True, False])
 def test_solve_graph_and_eager_agree(graph):
     p = pair("deformed3_N7")
