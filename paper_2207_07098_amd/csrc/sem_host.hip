@@ -607,6 +607,8 @@ extern "C" sem_status sem_export_geometry(sem_ctx c, double *G, double *B, doubl
     return SEM_OK;
 }
 
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
 static sem_status check_ready(sem_ctx c, int prec) {
     if (!c) return fail(c, SEM_ERR_INVALID, "null context");
     if (!c->geometry_ready) return fail(c, SEM_ERR_STATE, "geometry not set");
@@ -632,6 +634,7 @@ extern "C" sem_status sem_ax(sem_ctx c, const void *u, void *y, sem_precision pr
     if (st) return st;
     if (!u || !y) return fail(c, SEM_ERR_INVALID, "null vector");
     if (u == y) return fail(c, SEM_ERR_INVALID, "u and y must not alias");
+    if (!aligned16(u) || !aligned16(y)) return fail(c, SEM_ERR_INVALID, "vectors must be 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     if (flags & SEM_AX_DETERMINISTIC) {
         SEM_HIP(c, launch_ax(c, prec, u, y, 0, OUT_COMPACT, nullptr, nullptr, c->tile[prec], s));
@@ -1116,6 +1119,8 @@ extern "C" sem_status sem_cg_solve(sem_ctx c, const double *b, double *x,
     sem_status st = check_ready(c, SEM_FP64);
     if (st) return info->status = st;
     if (!b || !x) return info->status = fail(c, SEM_ERR_INVALID, "null vector");
+    if (!aligned16(b) || !aligned16(x))
+        return info->status = fail(c, SEM_ERR_INVALID, "vectors must be 16-byte aligned");
     if (!c->solver || !c->L.r64)
         return info->status = fail(c, SEM_ERR_STATE, "context set up without solver vectors");
     sem_solve_options o;

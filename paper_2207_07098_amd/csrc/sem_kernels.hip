@@ -732,25 +732,58 @@ __global__ void k_cg_begin(int64_t n, int64_t n_bnd, const T *__restrict__ b,
     }
 }
 
+template <typename T>
+struct Vec;
+template <>
+struct Vec<double> {
+    typedef d2v type;
+    static constexpr int W = 2;
+};
+typedef float f4v __attribute__((ext_vector_type(4)));
+template <>
+struct Vec<float> {
+    typedef f4v type;
+    static constexpr int W = 4;
+};
+
 // x += alpha p; r -= alpha w; reduces r.r and r.z (z = dinv r); updates beta
-// and the convergence state.
+// and the convergence state.  16-byte accesses; n % W entries in a tail.
 template <typename T>
 __global__ void k_cg_update(int64_t n, T *__restrict__ x, T *__restrict__ r,
                             const T *__restrict__ p, const T *__restrict__ w,
                             const T *__restrict__ dinv, double *partials, CgState *st) {
     if (st->done) return;
+    using V = typename Vec<T>::type;
+    constexpr int W = Vec<T>::W;
     const T alpha = (T)st->alpha;
     double rr = 0, rz = 0;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
-         q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t nv = n / W, stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t v = t0; v < nv; v += stride) {
+        V xv = reinterpret_cast<V *>(x)[v];
+        V rv = reinterpret_cast<V *>(r)[v];
+        const V pv = reinterpret_cast<const V *>(p)[v];
+        const V wv = reinterpret_cast<const V *>(w)[v];
+        const V dv = reinterpret_cast<const V *>(dinv)[v];
+        xv += alpha * pv;
+        rv -= alpha * wv;
+        reinterpret_cast<V *>(x)[v] = xv;
+        reinterpret_cast<V *>(r)[v] = rv;
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+            rr += (double)rv[c] * (double)rv[c];
+            rz += (double)rv[c] * (double)(dv[c] * rv[c]);
+        }
+    }
+    for (int64_t q = nv * W + t0; q < n; q += stride) {
         x[q] += alpha * p[q];
         const T rq = r[q] - alpha * w[q];
         r[q] = rq;
         rr += (double)rq * (double)rq;
         rz += (double)rq * (double)(dinv[q] * rq);
     }
-    double v[2] = {rr, rz}, out[2];
-    if (grid_reduce<2>(v, partials, &st->counter[2], out) && threadIdx.x == 0) {
+    double v2[2] = {rr, rz}, out[2];
+    if (grid_reduce<2>(v2, partials, &st->counter[2], out) && threadIdx.x == 0) {
         st->rr = out[0];
         st->beta = out[1] / st->rz;
         st->rz = out[1];
@@ -772,12 +805,22 @@ template <typename T>
 __global__ void k_cg_p(int64_t n, int64_t n_bnd, const T *__restrict__ r, T *__restrict__ p,
                        T *__restrict__ w, const T *__restrict__ dinv, const CgState *st) {
     if (st->done) return;
+    using V = typename Vec<T>::type;
+    constexpr int W = Vec<T>::W;
     const T beta = (T)st->beta;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        p[q] = dinv[q] * r[q] + beta * p[q];
-        if (q < n_bnd) w[q] = 0;
+    const int64_t nv = n / W, stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nbv = n_bnd / W;            // whole vectors inside the boundary block
+    for (int64_t v = t0; v < nv; v += stride) {
+        const V rv = reinterpret_cast<const V *>(r)[v];
+        const V dv = reinterpret_cast<const V *>(dinv)[v];
+        V pv = reinterpret_cast<V *>(p)[v];
+        pv = dv * rv + beta * pv;
+        reinterpret_cast<V *>(p)[v] = pv;
+        if (v < nbv) reinterpret_cast<V *>(w)[v] = V(0);
     }
+    for (int64_t q = nbv * W + t0; q < n_bnd; q += stride) w[q] = 0;
+    for (int64_t q = nv * W + t0; q < n; q += stride) p[q] = dinv[q] * r[q] + beta * p[q];
 }
 
 // r = b - y (FP64), reduces r.r and b.b into st (rr, bb).
