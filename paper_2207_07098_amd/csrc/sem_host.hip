@@ -588,16 +588,17 @@ extern "C" sem_status sem_export_geometry(sem_ctx c, double *G, double *B, doubl
     hipStream_t s = (hipStream_t)stream;
     const Layout &L = c->L;
     if (G) {
-        // device layout is point-major [E][n_p][6]; the ABI layout is [E][6][n_p]
+        // the device layout is goff(); the ABI layout is [E][6][n_p]
         std::vector<double> tmp(6 * (size_t)c->n_local);
         SEM_HIP(c, hipMemcpyAsync(tmp.data(), c->ws + L.G[0], 8 * tmp.size(),
                                   hipMemcpyDeviceToHost, s));
         SEM_HIP(c, hipStreamSynchronize(s));
-        const size_t np = c->np;
+        const size_t np = c->np, C = (size_t)c->n1 * c->n1;
         for (int64_t e = 0; e < c->E; ++e)
             for (size_t p = 0; p < np; ++p)
                 for (int cc = 0; cc < 6; ++cc)
-                    G[((size_t)e * 6 + cc) * np + p] = tmp[((size_t)e * np + p) * 6 + cc];
+                    G[((size_t)e * 6 + cc) * np + p] =
+                        tmp[goff(8, e, (int)(p / C), (int)(p % C), cc, c->n1)];
     }
     if (B) SEM_HIP(c, hipMemcpyAsync(B, c->ws + L.B, 8 * (size_t)c->n_local,
                                      hipMemcpyDeviceToHost, s));

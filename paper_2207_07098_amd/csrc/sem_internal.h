@@ -51,6 +51,20 @@ struct AxTile {
     int xcd = 1;          // XCD-aware element chunking
 };
 
+// Offset, in values, of factor component q (0..5 = 11,22,33,12,13,23) of
+// point (k, col = i + n1*j) of element e in a factor array of sz-byte
+// values.  Within each (element, k-plane) the six components are split into
+// chunks that one lane fetches with one naturally aligned access -- pairs
+// for FP64 and FP32 (3 x 16 B or 3 x 8 B), all six for 16-bit values
+// (3 x 4 B) -- and each chunk is stored lane-contiguously, so every load
+// instruction of a wave covers one contiguous span.
+__host__ __device__ inline size_t goff(int sz, int64_t e, int k, int col, int q, int n1) {
+    const size_t C = (size_t)n1 * n1;
+    const size_t base = ((size_t)e * n1 + k) * 6 * C;
+    if (sz >= 4) return base + (size_t)(q >> 1) * 2 * C + (size_t)col * 2 + (q & 1);
+    return base + (size_t)col * 6 + q;
+}
+
 }  // namespace sem
 
 struct sem_ctx_s {

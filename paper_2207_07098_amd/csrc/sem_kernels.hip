@@ -111,39 +111,100 @@ __device__ double block_sum(double v, double *red) {
     return s;
 }
 
-// Last-block-done reduction of up to 4 values per block.  partials:
-// [gridDim][4].  Returns true in the (single) last block, whose threads
-// then all hold the grid-wide sums in out[0..nv).
+// Per-block partial sums of up to 4 values, written with plain stores to
+// partials[blockIdx][0..NV); the grid-wide sum is formed by k_finish in a
+// fixed order after the kernel ends (the kernel boundary orders the
+// stores, so no device-scope fence is needed inside the streaming kernels).
 template <int NV>
-__device__ bool grid_reduce(const double (&v)[NV], double *partials, unsigned *counter,
-                            double (&out)[NV]) {
+__device__ void block_partial(const double (&v)[NV], double *partials) {
     __shared__ double red[16];
-    __shared__ int last;
     double s[NV];
 #pragma unroll
     for (int a = 0; a < NV; ++a) s[a] = block_sum(v[a], red);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int a = 0; a < NV; ++a) partials[(size_t)blockIdx.x * 4 + a] = s[a];
-        __threadfence();
-        unsigned t = atomicAdd(counter, 1u);
-        last = (t == gridDim.x - 1);
     }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    double acc[NV];
+}
+
+enum { FIN_AX = 0, FIN_BEGIN = 1, FIN_UPDATE = 2, FIN_RESID = 3, FIN_RESET = 4 };
+
+// Grid-wide sums of the partials of the preceding kernel and the scalar
+// CG logic that depends on them.
+__global__ void __launch_bounds__(1024) k_finish(int site, const double *__restrict__ partials,
+                                                 int nblocks, CgState *st) {
+    if ((site == FIN_AX || site == FIN_UPDATE) && st->done) return;
+    __shared__ double red[16];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int q = threadIdx.x; q < nblocks; q += blockDim.x)
 #pragma unroll
-    for (int a = 0; a < NV; ++a) acc[a] = 0.0;
-    for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x)
+        for (int a = 0; a < 3; ++a) acc[a] += partials[(size_t)q * 4 + a];
+    double out[3];
 #pragma unroll
-        for (int a = 0; a < NV; ++a)
-            acc[a] += __hip_atomic_load(partials + (size_t)q * 4 + a, __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT);
-#pragma unroll
-    for (int a = 0; a < NV; ++a) out[a] = block_sum(acc[a], red);
-    if (threadIdx.x == 0) *counter = 0u;
-    return true;
+    for (int a = 0; a < 3; ++a) out[a] = block_sum(acc[a], red);
+    if (threadIdx.x != 0) return;
+    switch (site) {
+        case FIN_AX: {                                   // p^T A p -> alpha
+            const double pAp = out[0];
+            st->pAp = pAp;
+            if (!std::isfinite(pAp)) {
+                st->status = 3;
+                st->done = 1;
+            } else if (!(pAp > 0.0)) {
+                st->status = 2;
+                st->done = 1;
+            } else {
+                st->alpha = st->rz / pAp;
+            }
+            break;
+        }
+        case FIN_BEGIN: {                                // r.z, r.r, b.b
+            st->rz = out[0];
+            st->rr = out[1];
+            st->bb = out[2];
+            st->tol2 = st->tol2 * out[2];
+            st->iter = 0;
+            st->status = 0;
+            st->done = 0;
+            if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
+                st->status = 3;
+                st->done = 1;
+            } else if (out[1] <= st->tol2) {
+                st->done = 1;
+            }
+            break;
+        }
+        case FIN_UPDATE: {                               // r.r, r.z -> beta
+            st->rr = out[0];
+            st->beta = out[1] / st->rz;
+            st->rz = out[1];
+            st->iter += 1;
+            if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
+                st->status = 3;
+                st->done = 1;
+            } else if (out[0] <= st->tol2) {
+                st->done = 1;
+            } else if (st->iter >= st->max_iter) {
+                st->status = 1;
+                st->done = 1;
+            }
+            break;
+        }
+        case FIN_RESID:                                  // r.r, b.b
+            st->rr = out[0];
+            st->bb = out[1];
+            break;
+        case FIN_RESET:                                  // r.z, r.r
+            st->rz = out[0];
+            st->rr = out[1];
+            st->done = 0;
+            st->status = 0;
+            if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
+                st->status = 3;
+                st->done = 1;
+            }
+            break;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -171,27 +232,30 @@ struct AxParams {
                                  // the kernel-argument segment as scalars
 };
 
-// The six factors of one point are stored together ([E][n_p][6]); a lane
-// fetches them with wide loads: 3 x 16 B (FP64), 3 x 8 B (FP32), 3 x 4 B
-// (16-bit).  The factors are streamed once per application, so the loads
-// carry a non-temporal hint.
+// Factor loads of one lane for one k-plane (layout of goff()): 3 x 16 B
+// (FP64), 3 x 8 B (FP32), 3 x 4 B (16-bit).  The factors are streamed once
+// per application, so the loads carry a non-temporal hint.
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ void load_g6(const double *p, double (&g)[6]) {
-    const d2v *q = reinterpret_cast<const d2v *>(p);
-    d2v a = __builtin_nontemporal_load(q), b = __builtin_nontemporal_load(q + 1),
-        c = __builtin_nontemporal_load(q + 2);
+template <int C>
+__device__ __forceinline__ void load_g6(const double *plane, int col, double (&g)[6]) {
+    const d2v *q = reinterpret_cast<const d2v *>(plane) + col;
+    d2v a = __builtin_nontemporal_load(q), b = __builtin_nontemporal_load(q + C),
+        c = __builtin_nontemporal_load(q + 2 * C);
     g[0] = a.x; g[1] = a.y; g[2] = b.x; g[3] = b.y; g[4] = c.x; g[5] = c.y;
 }
-__device__ __forceinline__ void load_g6(const float *p, float (&g)[6]) {
-    const f2v *q = reinterpret_cast<const f2v *>(p);
-    f2v a = __builtin_nontemporal_load(q), b = __builtin_nontemporal_load(q + 1),
-        c = __builtin_nontemporal_load(q + 2);
+template <int C>
+__device__ __forceinline__ void load_g6(const float *plane, int col, float (&g)[6]) {
+    const f2v *q = reinterpret_cast<const f2v *>(plane) + col;
+    f2v a = __builtin_nontemporal_load(q), b = __builtin_nontemporal_load(q + C),
+        c = __builtin_nontemporal_load(q + 2 * C);
     g[0] = a.x; g[1] = a.y; g[2] = b.x; g[3] = b.y; g[4] = c.x; g[5] = c.y;
 }
-__device__ __forceinline__ void load_g6(const _Float16 *p, float (&g)[6]) {
-    const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
+template <int C>
+__device__ __forceinline__ void load_g6(const _Float16 *plane, int col, float (&g)[6]) {
+    const uint32_t *q = reinterpret_cast<const uint32_t *>(plane + (size_t)col * 6);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const uint32_t w = __builtin_nontemporal_load(q + a);
@@ -199,8 +263,9 @@ __device__ __forceinline__ void load_g6(const _Float16 *p, float (&g)[6]) {
         g[2 * a + 1] = (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
     }
 }
-__device__ __forceinline__ void load_g6(const bf16_t *p, float (&g)[6]) {
-    const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
+template <int C>
+__device__ __forceinline__ void load_g6(const bf16_t *plane, int col, float (&g)[6]) {
+    const uint32_t *q = reinterpret_cast<const uint32_t *>(plane + (size_t)col * 6);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const uint32_t w = __builtin_nontemporal_load(q + a);
@@ -217,187 +282,217 @@ struct AxOcc {
                                         : (N1 <= 6 ? 4 : (N1 <= 9 ? 3 : (N1 <= 12 ? 2 : 1)));
 };
 
-// One pass over element groups.  Per element: the factors of all planes and
-// the gathered u are requested together (the index map of the element was
-// fetched while the previous element was computed), so a wave waits about
-// one memory latency per element; the t-direction work is register-local,
-// the r/s-directions go through LDS (buffers S0 = u, S1 = G-weighted r
-// gradient, S2 = G-weighted s gradient; two barriers per element).
+// Per-workgroup geometry of the element loop: lane -> (slot, column i,j).
+template <int N1>
+struct Lane {
+    static constexpr int N = N1 - 1, C = N1 * N1;
+    int slot, col, i, j, ridx;
+    bool ring;
+    __device__ Lane(int tid) {
+        slot = tid / C;
+        col = tid - slot * C;
+        i = col % N1;
+        j = col / N1;
+        ring = (i == 0) || (i == N) || (j == 0) || (j == N);
+        ridx = ring ? ring_index(i, j, N) : 0;
+    }
+    __device__ int bpos(int k) const {
+        return (k == 0) ? col : (k == N ? C + (N - 1) * 4 * N + col : C + (k - 1) * 4 * N + ridx);
+    }
+    __device__ bool bpt(int k) const { return (k == 0) || (k == N) || ring; }
+};
+
+// Operator data of one mesh as seen by the element loop.
+template <typename GS>
+struct AxMesh {
+    const void *u;
+    void *y;
+    void *wb;
+    const GS *G;
+    const float *gscale;
+    const int32_t *bmap;
+    int64_t E, n_bnd;
+    int in_local, out_mode;
+};
+
+template <int N1>
+__device__ __forceinline__ void load_map(const int32_t *bmap, const Lane<N1> &L, int64_t e,
+                                         int32_t (&bm)[N1]) {
+    constexpr int N = N1 - 1, NP = N1 * N1 * N1, NB = NP - (N - 1) * (N - 1) * (N - 1);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) bm[k] = L.bpt(k) ? bmap[e * NB + L.bpos(k)] : -1;
+}
+
+// One element per lane slot: w_e = D^T G_e D u_e with gather/mask/summation.
+// `bm` holds the map entries of element ec (fetched earlier); when
+// `next_e >= 0` the entries of element next_e are fetched into it after the
+// loads of this element have been issued.  S0/S1/S2: this slot's LDS
+// buffers, Dl: LDS copy of D.  Adds u_e^T A_e u_e to `dot` when want_dot.
 template <int N1, typename GS>
-__global__ void __attribute__((amdgpu_flat_work_group_size(1, 256),
-                               amdgpu_waves_per_eu(AxOcc<N1, GS>::value)))
-k_ax(AxParams<N1, GS> P) {
+__device__ __forceinline__ void ax_element(const AxMesh<GS> &M,
+                                           const DMat<N1, typename GT<GS>::T> &Dk,
+                                           const typename GT<GS>::T *Dl, const Lane<N1> &L,
+                                           typename GT<GS>::T *S0, int64_t ec, bool active,
+                                           int64_t next_e, int32_t (&bm)[N1], bool want_dot,
+                                           double &dot) {
     using T = typename GT<GS>::T;
     constexpr int N = N1 - 1, C = N1 * N1, NP = C * N1;
     constexpr int NI = (N - 1) * (N - 1) * (N - 1), NB = NP - NI;
     constexpr int PITCH = N1 + 1, PLANE = N1 * PITCH, BUF = N1 * PLANE;
     constexpr bool SCALED = sizeof(GS) == 2;
-    CgState *st = P.st;
-    if (st && st->done) return;
-
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int tid = threadIdx.x;
-    const int nslots = (blockDim.x + C - 1) / C;
-    const int slot = tid / C, col = tid - slot * C;
-    const int i = col % N1, j = col / N1;
-    const bool ring = (i == 0) || (i == N) || (j == 0) || (j == N);
-    const int ridx = ring ? ring_index(i, j, N) : 0;
-    T *S0 = reinterpret_cast<T *>(smem_raw) + (size_t)slot * 3 * BUF;
     T *S1 = S0 + BUF;
     T *S2 = S1 + BUF;
-    // lane-dependent rows of D are read from an LDS copy
-    T *Dl = reinterpret_cast<T *>(smem_raw) + (size_t)nslots * 3 * BUF;
-    for (int q = tid; q < C; q += blockDim.x) {
+    const int i = L.i, j = L.j, col = L.col;
+    const T *__restrict__ U = reinterpret_cast<const T *>(M.u);
+    T *__restrict__ Y = reinterpret_cast<T *>(M.y);
+    T *__restrict__ WB = reinterpret_cast<T *>(M.wb);
+
+    // ---- request the factors of every plane
+    T g[N1][6];
+    const GS *Ge = M.G + (size_t)ec * NP * 6;
+#pragma unroll
+    for (int k = 0; k < N1; ++k) load_g6<C>(Ge + (size_t)k * C * 6, col, g[k]);
+
+    // ---- gather u_e = (Q M u)_e
+    T u[N1];
+    int32_t bidx[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        bidx[k] = -1;
+        if (M.in_local) {
+            u[k] = U[ec * NP + k * C + col];
+        } else if (L.bpt(k)) {
+            const int32_t m = bm[k];            // a valid entry for every lane
+            const T v = U[m & 0x7fffffff];
+            const bool take = active && m >= 0;
+            bidx[k] = take ? m : -1;
+            u[k] = take ? v : T(0);
+        } else {
+            u[k] = U[interior_index(M.n_bnd, ec, i, j, k, N)];
+        }
+    }
+    // ---- map entries of the next element
+    if (!M.in_local && next_e >= 0) load_map<N1>(M.bmap, L, next_e, bm);
+
+#pragma unroll
+    for (int k = 0; k < N1; ++k) S0[k * PLANE + j * PITCH + i] = u[k];
+    __syncthreads();
+
+    // ---- D u, then G (D u): r/s parts to LDS, t part kept in registers
+    T wt[N1];
+    double edot = 0.0;
+    T Di[N1], Dj[N1];
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+        Di[m] = Dl[i * N1 + m];
+        Dj[m] = Dl[j * N1 + m];
+    }
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        T ur = 0, us = 0, ut = 0;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+            ur += Di[m] * S0[k * PLANE + j * PITCH + m];
+            us += Dj[m] * S0[k * PLANE + m * PITCH + i];
+            ut += Dk.v[k * N1 + m] * u[m];
+        }
+        const T wr = g[k][0] * ur + g[k][3] * us + g[k][4] * ut;
+        const T ws = g[k][3] * ur + g[k][1] * us + g[k][5] * ut;
+        wt[k] = g[k][4] * ur + g[k][5] * us + g[k][2] * ut;
+        S1[k * PLANE + j * PITCH + i] = wr;
+        S2[k * PLANE + j * PITCH + i] = ws;
+        if (want_dot) edot += (double)(ur * wr + us * ws + ut * wt[k]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+
+    // ---- D^T (G D u)
+    const T sc = SCALED ? (T)M.gscale[ec] : T(1);
+    if (want_dot && active) dot += SCALED ? edot * (double)sc : edot;
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+        Di[m] = Dl[m * N1 + i];
+        Dj[m] = Dl[m * N1 + j];
+    }
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        T w = 0;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+            w += Di[m] * S1[k * PLANE + j * PITCH + m];
+            w += Dj[m] * S2[k * PLANE + m * PITCH + i];
+            w += Dk.v[m * N1 + k] * wt[m];
+        }
+        if (SCALED) w *= sc;
+        if (active) {
+            if (M.out_mode == OUT_LOCAL) {
+                Y[ec * NP + k * C + col] = w;
+            } else if (L.bpt(k)) {
+                if (M.out_mode == OUT_ATOMIC) {
+                    if (bidx[k] >= 0) unsafeAtomicAdd(Y + bidx[k], w);
+                } else {
+                    WB[ec * NB + L.bpos(k)] = w;
+                }
+            } else {
+                Y[interior_index(M.n_bnd, ec, i, j, k, N)] = w;
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <int N1, typename T>
+__device__ __forceinline__ void fill_dl(T *Dl, const DMat<N1, T> &Dk) {
+    constexpr int C = N1 * N1;
+    for (int q = threadIdx.x; q < C; q += blockDim.x) {
 #pragma unroll
         for (int r = 0; r < C; ++r)
-            if (q == r) Dl[q] = P.D.v[r];
+            if (q == r) Dl[q] = Dk.v[r];
     }
-    const T *__restrict__ U = reinterpret_cast<const T *>(P.u);
-    T *__restrict__ Y = reinterpret_cast<T *>(P.y);
-    T *__restrict__ WB = reinterpret_cast<T *>(P.wb);
-    double dot = 0.0;
+}
 
-    auto bpos_k = [&](int k) {
-        return (k == 0) ? col : (k == N ? C + (N - 1) * 4 * N + col : C + (k - 1) * 4 * N + ridx);
-    };
+// Persistent pass over element groups of one mesh.  Per element the factors
+// of all planes and the gathered u are requested together (the element's
+// map entries were fetched while the previous element was computed), so a
+// wave waits about one memory latency per element.
+template <int N1, typename GS>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, 256),
+                               amdgpu_waves_per_eu(AxOcc<N1, GS>::value)))
+k_ax(AxParams<N1, GS> P) {
+    using T = typename GT<GS>::T;
+    constexpr int C = N1 * N1, BUF = N1 * N1 * (N1 + 1);
+    CgState *st = P.st;
+    if (st && st->done) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Lane<N1> L(threadIdx.x);
+    const int nslots = (blockDim.x + C - 1) / C;
+    T *S0 = reinterpret_cast<T *>(smem_raw) + (size_t)L.slot * 3 * BUF;
+    T *Dl = reinterpret_cast<T *>(smem_raw) + (size_t)nslots * 3 * BUF;
+    fill_dl<N1, T>(Dl, P.D);
+    AxMesh<GS> M{P.u, P.y, P.wb, P.G, P.gscale, P.bmap, P.E, P.n_bnd, P.in_local, P.out_mode};
     auto elem_of = [&](int64_t git, bool &act) {
         const int64_t g = P.xcd ? xcd_remap(git, P.ngroups) : git;
-        const int64_t e = g * P.epb + slot;
-        act = (slot < P.epb) && (e < P.E);
+        const int64_t e = g * P.epb + L.slot;
+        act = (L.slot < P.epb) && (e < P.E);
         return act ? e : (int64_t)0;     // inactive lanes read element 0
     };
-    // map entries of the first element
-    int32_t bm_next[N1];
+    int32_t bm[N1];
     {
         bool act;
         const int64_t e0 = elem_of(blockIdx.x, act);
-#pragma unroll
-        for (int k = 0; k < N1; ++k)
-            bm_next[k] = (!P.in_local && ((k == 0) || (k == N) || ring))
-                             ? P.bmap[e0 * NB + bpos_k(k)] : -1;
+        if (!P.in_local) load_map<N1>(P.bmap, L, e0, bm);
     }
-
+    __syncthreads();
+    double dot = 0.0;
     for (int64_t git = blockIdx.x; git < P.ngroups; git += gridDim.x) {
-        bool active;
+        bool active, act_n;
         const int64_t ec = elem_of(git, active);
-
-        // ---- request the factors of every plane
-        T g[N1][6];
-        const GS *Ge = P.G + ((size_t)ec * NP + col) * 6;
-#pragma unroll
-        for (int k = 0; k < N1; ++k) load_g6(Ge + (size_t)k * C * 6, g[k]);
-
-        // ---- gather u_e = (Q M u)_e
-        T u[N1];
-        int32_t bidx[N1];
-#pragma unroll
-        for (int k = 0; k < N1; ++k) {
-            bidx[k] = -1;
-            const bool bpt = (k == 0) || (k == N) || ring;
-            if (P.in_local) {
-                u[k] = U[ec * NP + k * C + col];
-            } else if (bpt) {
-                const int32_t m = bm_next[k];   // valid entry for every lane
-                const T v = U[m & 0x7fffffff];
-                const bool take = active && m >= 0;
-                bidx[k] = take ? m : -1;
-                u[k] = take ? v : T(0);
-            } else {
-                u[k] = U[interior_index(P.n_bnd, ec, i, j, k, N)];
-            }
-        }
-        // ---- map entries of the next element
-        if (!P.in_local && git + gridDim.x < P.ngroups) {
-            bool act;
-            const int64_t en = elem_of(git + gridDim.x, act);
-#pragma unroll
-            for (int k = 0; k < N1; ++k)
-                if ((k == 0) || (k == N) || ring) bm_next[k] = P.bmap[en * NB + bpos_k(k)];
-        }
-
-#pragma unroll
-        for (int k = 0; k < N1; ++k) S0[k * PLANE + j * PITCH + i] = u[k];
-        __syncthreads();
-
-        // ---- D u, then G (D u): r/s parts to LDS, t part kept in registers
-        T wt[N1];
-        double edot = 0.0;
-        T Di[N1], Dj[N1];
-#pragma unroll
-        for (int m = 0; m < N1; ++m) {
-            Di[m] = Dl[i * N1 + m];
-            Dj[m] = Dl[j * N1 + m];
-        }
-#pragma unroll
-        for (int k = 0; k < N1; ++k) {
-            T ur = 0, us = 0, ut = 0;
-#pragma unroll
-            for (int m = 0; m < N1; ++m) {
-                ur += Di[m] * S0[k * PLANE + j * PITCH + m];
-                us += Dj[m] * S0[k * PLANE + m * PITCH + i];
-                ut += P.D.v[k * N1 + m] * u[m];
-            }
-            const T wr = g[k][0] * ur + g[k][3] * us + g[k][4] * ut;
-            const T ws = g[k][3] * ur + g[k][1] * us + g[k][5] * ut;
-            wt[k] = g[k][4] * ur + g[k][5] * us + g[k][2] * ut;
-            S1[k * PLANE + j * PITCH + i] = wr;
-            S2[k * PLANE + j * PITCH + i] = ws;
-            if (P.partials) edot += (double)(ur * wr + us * ws + ut * wt[k]);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        __syncthreads();
-
-        // ---- D^T (G D u)
-        const T sc = SCALED ? (T)P.gscale[ec] : T(1);
-        if (P.partials && active) dot += SCALED ? edot * (double)sc : edot;
-#pragma unroll
-        for (int m = 0; m < N1; ++m) {
-            Di[m] = Dl[m * N1 + i];
-            Dj[m] = Dl[m * N1 + j];
-        }
-#pragma unroll
-        for (int k = 0; k < N1; ++k) {
-            T w = 0;
-#pragma unroll
-            for (int m = 0; m < N1; ++m) {
-                w += Di[m] * S1[k * PLANE + j * PITCH + m];
-                w += Dj[m] * S2[k * PLANE + m * PITCH + i];
-                w += P.D.v[m * N1 + k] * wt[m];
-            }
-            if (SCALED) w *= sc;
-            const bool bpt = (k == 0) || (k == N) || ring;
-            if (active) {
-                if (P.out_mode == OUT_LOCAL) {
-                    Y[ec * NP + k * C + col] = w;
-                } else if (bpt) {
-                    if (P.out_mode == OUT_ATOMIC) {
-                        if (bidx[k] >= 0) unsafeAtomicAdd(Y + bidx[k], w);
-                    } else {
-                        WB[ec * NB + bpos_k(k)] = w;
-                    }
-                } else {
-                    Y[interior_index(P.n_bnd, ec, i, j, k, N)] = w;
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
+        const int64_t en = git + gridDim.x < P.ngroups ? elem_of(git + gridDim.x, act_n) : -1;
+        ax_element<N1, GS>(M, P.D, Dl, L, S0, ec, active, en, bm, P.partials != nullptr, dot);
     }
-
     if (P.partials) {
-        double v[1] = {dot}, out[1];
-        if (grid_reduce<1>(v, P.partials, &st->counter[0], out) && threadIdx.x == 0) {
-            const double pAp = out[0];
-            st->pAp = pAp;
-            if (!std::isfinite(pAp)) {
-                st->status = 3;
-                st->done = 1;
-            } else if (!(pAp > 0.0)) {
-                st->status = 2;
-                st->done = 1;
-            } else {
-                st->alpha = st->rz / pAp;
-            }
-        }
+        double v[1] = {dot};
+        block_partial<1>(v, P.partials);
     }
 }
 
@@ -437,6 +532,9 @@ hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const v
     if (grid > P.ngroups) grid = P.ngroups;
     if (P.xcd && grid < P.ngroups && (grid & 7)) P.xcd = 0;
     hipLaunchKernelGGL((k_ax<N1, GS>), dim3((unsigned)grid), dim3(threads), lds, s, P);
+    if (partials)
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, (int)FIN_AX,
+                           (const double *)partials, (int)grid, st);
     return hipGetLastError();
 }
 
@@ -502,27 +600,27 @@ __global__ void k_geometry(const double *__restrict__ X, int64_t e0, int n1,
         auto dotA = [&](int s, int t) {
             return A[s][0] * A[t][0] + A[s][1] * A[t][1] + A[s][2] * A[t][2];
         };
-        double *Ge = G + ((size_t)e * np + p) * 6;     // point-major [E][n_p][6]
-        Ge[0] = f * dotA(0, 0);
-        Ge[1] = f * dotA(1, 1);
-        Ge[2] = f * dotA(2, 2);
-        Ge[3] = f * dotA(0, 1);
-        Ge[4] = f * dotA(0, 2);
-        Ge[5] = f * dotA(1, 2);
+        const int col = i + n1 * j;
+        G[goff(8, e, k, col, 0, n1)] = f * dotA(0, 0);
+        G[goff(8, e, k, col, 1, n1)] = f * dotA(1, 1);
+        G[goff(8, e, k, col, 2, n1)] = f * dotA(2, 2);
+        G[goff(8, e, k, col, 3, n1)] = f * dotA(0, 1);
+        G[goff(8, e, k, col, 4, n1)] = f * dotA(0, 2);
+        G[goff(8, e, k, col, 5, n1)] = f * dotA(1, 2);
         B[(size_t)e * np + p] = wq * det;
     }
 }
 
 // Reduced-precision copies of G; 16-bit copies are divided by a per-element
 // power of two 2^ceil(log2 max|G_e|) kept in gscale.
-__global__ void k_lowprec(const double *__restrict__ G, int np, float *G32, _Float16 *G16,
+__global__ void k_lowprec(const double *__restrict__ G, int n1, float *G32, _Float16 *G16,
                           bf16_t *Gb, float *s16, float *sb) {
     __shared__ double red[16];
+    const int np = n1 * n1 * n1;
     const int64_t e = blockIdx.x;
-    const double *Ge = G + (size_t)e * 6 * np;
+    const double *Ge = G + (size_t)e * 6 * np;         // an element's values are contiguous
     double mx = 0.0;
     for (int q = threadIdx.x; q < 6 * np; q += blockDim.x) mx = fmax(mx, fabs(Ge[q]));
-    // block max (reuse the sum machinery on a max-reduced wave)
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
@@ -532,16 +630,17 @@ __global__ void k_lowprec(const double *__restrict__ G, int np, float *G32, _Flo
     double gam = 1.0;
     if (mx > 0.0) {
         int ex;
-        double fr = frexp(mx, &ex);      // mx = fr * 2^ex, fr in [0.5, 1)
+        const double fr = frexp(mx, &ex);   // mx = fr * 2^ex, fr in [0.5, 1)
         gam = ldexp(1.0, fr == 0.5 ? ex - 1 : ex);
     }
     const double inv = 1.0 / gam;
-    for (int q = threadIdx.x; q < 6 * np; q += blockDim.x) {
-        const double v = Ge[q];
-        const size_t o = (size_t)e * 6 * np + q;
-        if (G32) G32[o] = (float)v;
-        if (G16) G16[o] = (_Float16)(float)(v * inv);
-        if (Gb) Gb[o].v = f32_to_bf16_rne((float)(v * inv));
+    for (int t = threadIdx.x; t < 6 * np; t += blockDim.x) {
+        const int q = t % 6, p = t / 6;
+        const int k = p / (n1 * n1), col = p - k * n1 * n1;
+        const double v = G[goff(8, e, k, col, q, n1)];
+        if (G32) G32[goff(4, e, k, col, q, n1)] = (float)v;
+        if (G16) G16[goff(2, e, k, col, q, n1)] = (_Float16)(float)(v * inv);
+        if (Gb) Gb[goff(2, e, k, col, q, n1)].v = f32_to_bf16_rne((float)(v * inv));
     }
     if (threadIdx.x == 0) {
         if (s16) s16[e] = (float)gam;
@@ -568,16 +667,17 @@ __global__ void k_local_values(int mode, int64_t E, int n1, int64_t n_bnd,
         const int bp = bpt ? bpos_of(i, j, k, n1) : 0;
         double v;
         if (mode == 0) {
-            const double *g = G + (size_t)e * 6 * np;      // point-major [n_p][6]
             double s = 0.0;
             for (int m = 0; m < n1; ++m) {
                 const double a = D[m * n1 + i], b = D[m * n1 + j], cc = D[m * n1 + k];
-                s += a * a * g[6 * (m + n1 * (j + n1 * k)) + 0];
-                s += b * b * g[6 * (i + n1 * (m + n1 * k)) + 1];
-                s += cc * cc * g[6 * (i + n1 * (j + n1 * m)) + 2];
+                s += a * a * G[goff(8, e, k, m + n1 * j, 0, n1)];
+                s += b * b * G[goff(8, e, k, i + n1 * m, 1, n1)];
+                s += cc * cc * G[goff(8, e, m, i + n1 * j, 2, n1)];
             }
             const double di = D[i * n1 + i], dj = D[j * n1 + j], dk = D[k * n1 + k];
-            s += 2.0 * (di * dj * g[6 * p + 3] + di * dk * g[6 * p + 4] + dj * dk * g[6 * p + 5]);
+            const int col = i + n1 * j;
+            s += 2.0 * (di * dj * G[goff(8, e, k, col, 3, n1)] + di * dk * G[goff(8, e, k, col, 4, n1)] +
+                        dj * dk * G[goff(8, e, k, col, 5, n1)]);
             v = s;
         } else if (mode == 1) {
             v = B[q] * f[q];
@@ -714,22 +814,8 @@ __global__ void k_cg_begin(int64_t n, int64_t n_bnd, const T *__restrict__ b,
         rr += (double)rq * (double)rq;
         bb += (double)bq * (double)bq;
     }
-    double v[3] = {rz, rr, bb}, out[3];
-    if (grid_reduce<3>(v, partials, &st->counter[1], out) && threadIdx.x == 0) {
-        st->rz = out[0];
-        st->rr = out[1];
-        st->bb = out[2];
-        st->tol2 = st->tol2 * out[2];
-        st->iter = 0;
-        st->status = 0;
-        st->done = 0;
-        if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
-            st->status = 3;
-            st->done = 1;
-        } else if (out[1] <= st->tol2) {
-            st->done = 1;
-        }
-    }
+    double v[3] = {rz, rr, bb};
+    block_partial<3>(v, partials);
 }
 
 template <typename T>
@@ -739,7 +825,6 @@ struct Vec<double> {
     typedef d2v type;
     static constexpr int W = 2;
 };
-typedef float f4v __attribute__((ext_vector_type(4)));
 template <>
 struct Vec<float> {
     typedef f4v type;
@@ -782,22 +867,8 @@ __global__ void k_cg_update(int64_t n, T *__restrict__ x, T *__restrict__ r,
         rr += (double)rq * (double)rq;
         rz += (double)rq * (double)(dinv[q] * rq);
     }
-    double v2[2] = {rr, rz}, out[2];
-    if (grid_reduce<2>(v2, partials, &st->counter[2], out) && threadIdx.x == 0) {
-        st->rr = out[0];
-        st->beta = out[1] / st->rz;
-        st->rz = out[1];
-        st->iter += 1;
-        if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
-            st->status = 3;
-            st->done = 1;
-        } else if (out[0] <= st->tol2) {
-            st->done = 1;
-        } else if (st->iter >= st->max_iter) {
-            st->status = 1;
-            st->done = 1;
-        }
-    }
+    double v2[2] = {rr, rz};
+    block_partial<2>(v2, partials);
 }
 
 // p = dinv r + beta p; zero w on boundary nodes for the next operator.
@@ -835,11 +906,8 @@ __global__ void k_residual64(int64_t n, const double *__restrict__ b,
         rr += rq * rq;
         bb += b[q] * b[q];
     }
-    double v[2] = {rr, bb}, out[2];
-    if (grid_reduce<2>(v, partials, &st->counter[3], out) && threadIdx.x == 0) {
-        st->rr = out[0];
-        st->bb = out[1];
-    }
+    double v[2] = {rr, bb};
+    block_partial<2>(v, partials);
 }
 
 // x += s d with s = ||r|| of the outer residual state (scaled inner
@@ -867,17 +935,8 @@ __global__ void k_reliable_reset(int64_t n, const double *__restrict__ r64,
         rz += (double)rq * (double)(dinv[q] * rq);
         rr += (double)rq * (double)rq;
     }
-    double v[2] = {rz, rr}, out[2];
-    if (grid_reduce<2>(v, partials, &st->counter[1], out) && threadIdx.x == 0) {
-        st->rz = out[0];
-        st->rr = out[1];
-        st->done = 0;
-        st->status = 0;
-        if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
-            st->status = 3;
-            st->done = 1;
-        }
-    }
+    double v[2] = {rz, rr};
+    block_partial<2>(v, partials);
 }
 
 inline unsigned vec_grid(int64_t n) {
@@ -918,7 +977,7 @@ hipError_t launch_lowprec_factors(sem_ctx c, hipStream_t s) {
     auto on = [&](int p) { return (c->precisions >> p) & 1u; };
     if (!(on(1) || on(2) || on(3))) return hipSuccess;
     hipLaunchKernelGGL(k_lowprec, dim3((unsigned)c->E), dim3(256), 0, s,
-                       dptr<double>(c, L.G[0]), c->np, on(1) ? dptr<float>(c, L.G[1]) : nullptr,
+                       dptr<double>(c, L.G[0]), c->n1, on(1) ? dptr<float>(c, L.G[1]) : nullptr,
                        on(2) ? dptr<_Float16>(c, L.G[2]) : nullptr,
                        on(3) ? dptr<bf16_t>(c, L.G[3]) : nullptr,
                        on(2) ? dptr<float>(c, L.gscale[2]) : nullptr,
@@ -1035,6 +1094,8 @@ hipError_t launch_cg_begin(sem_ctx c, int level, const void *b, void *x, void *r
                            (const CgState *)nullptr, (double *)x, (double *)r, (double *)p,
                            (double *)w, dptr<double>(c, L.dinv64), x_zero, partials_site(c, 1),
                            st);
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, (int)FIN_BEGIN,
+                           (const double *)partials_site(c, 1), (int)vec_grid(n), st);
     } else {
         // inner refinement solve: b is the FP64 outer residual, optionally
         // divided by its norm (from the outer residual state)
@@ -1043,6 +1104,8 @@ hipError_t launch_cg_begin(sem_ctx c, int level, const void *b, void *x, void *r
                            c->n_bnd, (const float *)nullptr, (const double *)b, outer,
                            (float *)x, (float *)r, (float *)p, (float *)w,
                            dptr<float>(c, L.dinv32), 1, partials_site(c, 1), st);
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, (int)FIN_BEGIN,
+                           (const double *)partials_site(c, 1), (int)vec_grid(n), st);
     }
     return hipGetLastError();
 }
@@ -1064,6 +1127,8 @@ hipError_t launch_cg_iteration(sem_ctx c, int level, int prec, void *x, void *r,
         hipLaunchKernelGGL(k_cg_update<double>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n,
                            (double *)x, (double *)r, (const double *)p, (const double *)w,
                            dptr<double>(c, L.dinv64), partials_site(c, 2), st);
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, (int)FIN_UPDATE,
+                           (const double *)partials_site(c, 2), (int)vec_grid(n), st);
         hipLaunchKernelGGL(k_cg_p<double>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n, c->n_bnd,
                            (const double *)r, (double *)p, (double *)w, dptr<double>(c, L.dinv64),
                            (const CgState *)st);
@@ -1071,6 +1136,8 @@ hipError_t launch_cg_iteration(sem_ctx c, int level, int prec, void *x, void *r,
         hipLaunchKernelGGL(k_cg_update<float>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n,
                            (float *)x, (float *)r, (const float *)p, (const float *)w,
                            dptr<float>(c, L.dinv32), partials_site(c, 2), st);
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, (int)FIN_UPDATE,
+                           (const double *)partials_site(c, 2), (int)vec_grid(n), st);
         hipLaunchKernelGGL(k_cg_p<float>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n, c->n_bnd,
                            (const float *)r, (float *)p, (float *)w, dptr<float>(c, L.dinv32),
                            (const CgState *)st);
@@ -1083,6 +1150,8 @@ hipError_t launch_residual64(sem_ctx c, const double *b, const double *Ax, doubl
     const int64_t n = c->n_unique;
     hipLaunchKernelGGL(k_residual64, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n, b, Ax, r,
                        partials_site(c, 3), st);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, (int)FIN_RESID,
+                       (const double *)partials_site(c, 3), (int)vec_grid(n), st);
     return hipGetLastError();
 }
 
@@ -1099,6 +1168,8 @@ hipError_t launch_reliable_reset(sem_ctx c, const double *r64, float *r, float *
     const int64_t n = c->n_unique;
     hipLaunchKernelGGL(k_reliable_reset, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n, r64, r, x,
                        dptr<float>(c, c->L.dinv32), partials_site(c, 1), st);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, (int)FIN_RESET,
+                       (const double *)partials_site(c, 1), (int)vec_grid(n), st);
     return hipGetLastError();
 }
 
