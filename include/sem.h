@@ -271,6 +271,42 @@ sem_status sem_cg_solve(sem_ctx ctx, const double *b, double *x,
                         const sem_solve_options *opts, sem_solve_info *info,
                         sem_stream stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched solve: many independent Poisson problems (meshes of different
+ * sizes and orders N <= 9, each set up as its own context with geometry and
+ * opts.solver = 1) solved together by Jacobi-PCG in FP64.  Every CG phase
+ * of all problems is one persistent launch over a table of work items
+ * (problem, element group) or (problem, node range); per-problem scalars and
+ * convergence flags stay on the device and converged problems turn their
+ * items into no-ops; the iteration is captured once in a hipGraph.  The
+ * contexts must outlive the batch and their work vectors are used by it.
+ * ------------------------------------------------------------------------- */
+typedef struct sem_batch_s *sem_batch;
+
+sem_status sem_batch_create(const sem_ctx *ctxs, int nprob, sem_batch *out);
+void       sem_batch_free(sem_batch batch);
+const char *sem_batch_last_error(sem_batch batch);
+/* Device workspace of the batch (tables, partial sums, per-problem state). */
+sem_status sem_batch_workspace_size(sem_batch batch, size_t *bytes);
+sem_status sem_batch_bind_workspace(sem_batch batch, void *dev_ptr, size_t bytes,
+                                    sem_stream stream);
+/* Tile of the batched operator: elements_per_block carries the threads per
+ * workgroup (a multiple of 64, at least the largest (N+1)^2; each problem
+ * gets threads/(N+1)^2 elements per workgroup), grid_cap as for sem_tile. */
+sem_status sem_batch_set_tile(sem_batch batch, const sem_tile *tile, sem_stream stream);
+/* Times every admissible batch tile (hipEvents) and keeps the fastest. */
+sem_status sem_batch_autotune(sem_batch batch, int reps, sem_tile *best, double *best_ms,
+                              sem_stream stream);
+/* rhs[p], x[p]: device vectors of problem p (solver order, FP64, 16-byte
+ * aligned); x is output (zero initial guess).  opts.precision must be
+ * SEM_FP64.  infos[p] receives each problem's result; problems whose FP64
+ * true residual misses tol after the batched iteration are finished with
+ * sem_cg_solve.  Returns SEM_OK if every problem converged, else the first
+ * failing status.  Blocks until all problems are done. */
+sem_status sem_batch_solve(sem_batch batch, const double *const *rhs, double *const *x,
+                           const sem_solve_options *opts, sem_solve_info *infos,
+                           sem_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

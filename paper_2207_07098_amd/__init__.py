@@ -94,7 +94,9 @@ EXPORTS = ["sem_gll", "sem_setup", "sem_free", "sem_last_error", "sem_query",
            "sem_set_geometry", "sem_export_geometry", "sem_ax_local", "sem_gs",
            "sem_gather", "sem_scatter", "sem_ax", "sem_rhs",
            "sem_default_solve_options", "sem_cg_solve", "sem_get_tile", "sem_set_tile",
-           "sem_autotune"]
+           "sem_autotune", "sem_batch_create", "sem_batch_free", "sem_batch_last_error",
+           "sem_batch_workspace_size", "sem_batch_bind_workspace", "sem_batch_set_tile",
+           "sem_batch_autotune", "sem_batch_solve"]
 
 _lib = None
 
@@ -131,6 +133,14 @@ def lib():
         "sem_get_tile": ([P, i32, P], i32),
         "sem_set_tile": ([P, i32, P], i32),
         "sem_autotune": ([P, i32, i32, ctypes.c_char_p, P, P, i32, P, P], i32),
+        "sem_batch_create": ([P, i32, P], i32),
+        "sem_batch_free": ([P], None),
+        "sem_batch_last_error": ([P], ctypes.c_char_p),
+        "sem_batch_workspace_size": ([P, P], i32),
+        "sem_batch_bind_workspace": ([P, P, ctypes.c_size_t, P], i32),
+        "sem_batch_set_tile": ([P, P, P], i32),
+        "sem_batch_autotune": ([P, i32, P, P, P], i32),
+        "sem_batch_solve": ([P, P, P, P, P, P], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -378,3 +388,66 @@ class Operator:
         if pos is None:
             pos = self.numbering()[1]
         return v_solver[pos]
+
+
+class Batch:
+    """Independent problems (Operators with geometry and solver vectors, N <= 9)
+    solved together: one persistent launch per CG phase, iteration captured
+    in a hipGraph, per-problem convergence on the device."""
+
+    def __init__(self, operators):
+        torch = _torch()
+        self.ops = list(operators)
+        arr = (ctypes.c_void_p * len(self.ops))(*[o._ctx.value for o in self.ops])
+        self._b = ctypes.c_void_p()
+        st = lib().sem_batch_create(arr, len(self.ops), ctypes.byref(self._b))
+        if st:
+            raise SemError(st, lib().sem_last_error(None).decode())
+        nb = ctypes.c_size_t()
+        self._check(lib().sem_batch_workspace_size(self._b, ctypes.byref(nb)))
+        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.ops[0].device)
+        self._check(lib().sem_batch_bind_workspace(self._b, _dptr(self.workspace), nb.value,
+                                                   _stream_handle()))
+
+    def _check(self, st):
+        if st:
+            raise SemError(st, lib().sem_batch_last_error(self._b).decode())
+
+    def __del__(self):
+        try:
+            if self._b:
+                lib().sem_batch_free(self._b)
+                self._b = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    def set_tile(self, threads=256, grid_cap=0):
+        t = Tile(threads, grid_cap, 0)
+        self._check(lib().sem_batch_set_tile(self._b, ctypes.byref(t), _stream_handle()))
+
+    def autotune(self, reps: int = 5):
+        best = Tile()
+        ms = ctypes.c_double()
+        self._check(lib().sem_batch_autotune(self._b, reps, ctypes.byref(best), ctypes.byref(ms),
+                                             _stream_handle()))
+        return {"threads": best.elements_per_block, "grid_cap": best.grid_cap}, ms.value
+
+    def solve(self, rhs, xs=None, tol: float = 1e-8, max_iter: int = 100000,
+              check_every: int = 50, use_graph: bool = True, raise_on_error: bool = True):
+        """rhs: list of device vectors (solver order).  Returns (xs, infos)."""
+        n = len(self.ops)
+        if xs is None:
+            xs = [o.vector() for o in self.ops]
+        o = SolveOptions()
+        lib().sem_default_solve_options(ctypes.byref(o))
+        o.tol = tol
+        o.max_iter = max_iter
+        o.check_every = check_every
+        o.use_graph = 1 if use_graph else 0
+        bp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in rhs])
+        xp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in xs])
+        infos = (SolveInfo * n)()
+        st = lib().sem_batch_solve(self._b, bp, xp, ctypes.byref(o), infos, _stream_handle())
+        if st and raise_on_error:
+            self._check(st)
+        return xs, [i.as_dict() for i in infos]

@@ -1,0 +1,356 @@
+// Batched Jacobi-PCG over many independent meshes (host side).
+//
+// Each problem keeps its own context (numbering, factors, work vectors);
+// the batch adds a device table of per-problem descriptors and work items
+// so that every CG phase of all problems runs as one persistent launch,
+// and the iteration is captured once in a hipGraph.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "sem_internal.h"
+
+using namespace sem;
+
+struct sem_batch_s {
+    std::vector<sem_ctx> ctxs;
+    int nprob = 0, max_n1 = 0, max_c = 0;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    size_t off_probs = 0, off_ax = 0, off_vec = 0, off_axp = 0, off_vecp = 0, off_st = 0;
+    int cap_ax = 0, cap_vec = 0;           // capacity of the item tables
+    int threads = 256, grid_cap = 0;       // tile
+    std::vector<BatchProb> probs;
+    std::vector<BatchAxItem> ax;
+    std::vector<BatchVecItem> vec;
+    BatchLaunch bl{};
+    hipGraphExec_t graph = nullptr;
+    int graph_m = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t event = nullptr;
+    std::string err;
+};
+
+static sem_status bfail(sem_batch b, sem_status st, const std::string &m) {
+    if (b) b->err = m;
+    return fail(nullptr, st, m);
+}
+
+static constexpr int kVecChunk = 16384;    // nodes per vector work item
+
+// Work items for the current tile; capacities fixed at creation (the
+// largest tables over all admissible tiles).
+static void build_items(sem_batch b) {
+    b->ax.clear();
+    b->vec.clear();
+    std::vector<std::pair<int, int>> order;     // heavier orders first
+    for (int p = 0; p < b->nprob; ++p) order.push_back({-b->ctxs[p]->n1, p});
+    std::stable_sort(order.begin(), order.end());
+    for (auto &o : order) {
+        const int p = o.second;
+        sem_ctx c = b->ctxs[p];
+        BatchProb &pb = b->probs[p];
+        pb.epb = std::max(1, b->threads / (c->n1 * c->n1));
+        const int64_t ngroups = (c->E + pb.epb - 1) / pb.epb;
+        pb.ax_begin = (int)b->ax.size();
+        for (int64_t g = 0; g < ngroups; ++g) b->ax.push_back({p, 0, g});
+        pb.ax_end = (int)b->ax.size();
+    }
+    for (int p = 0; p < b->nprob; ++p) {
+        BatchProb &pb = b->probs[p];
+        pb.vec_begin = (int)b->vec.size();
+        for (int64_t q = 0; q < pb.n_u; q += kVecChunk)
+            b->vec.push_back({p, 0, q, std::min<int64_t>(pb.n_u, q + kVecChunk)});
+        pb.vec_end = (int)b->vec.size();
+    }
+}
+
+static void fill_launch(sem_batch b) {
+    BatchLaunch &bl = b->bl;
+    bl.probs = reinterpret_cast<BatchProb *>(b->ws + b->off_probs);
+    bl.ax_items = reinterpret_cast<const BatchAxItem *>(b->ws + b->off_ax);
+    bl.vec_items = reinterpret_cast<const BatchVecItem *>(b->ws + b->off_vec);
+    bl.n_ax = (int)b->ax.size();
+    bl.n_vec = (int)b->vec.size();
+    bl.nprob = b->nprob;
+    bl.ax_partials = reinterpret_cast<double *>(b->ws + b->off_axp);
+    bl.vec_partials = reinterpret_cast<double *>(b->ws + b->off_vecp);
+    bl.threads = b->threads;
+    const int ncu = b->ctxs[0]->num_cus;
+    bl.ax_grid = b->grid_cap > 0 ? std::min(b->grid_cap, bl.n_ax) : bl.n_ax;
+    bl.vec_grid = std::min(bl.n_vec, 8 * ncu);
+    bl.max_n1 = b->max_n1;
+}
+
+static sem_status upload_tables(sem_batch b, hipStream_t s) {
+    build_items(b);
+    if ((int)b->ax.size() > b->cap_ax || (int)b->vec.size() > b->cap_vec)
+        return bfail(b, SEM_ERR_OOM, "batch item tables exceed their capacity");
+    SEM_HIP(nullptr, hipMemcpyAsync(b->ws + b->off_ax, b->ax.data(), sizeof(BatchAxItem) * b->ax.size(),
+                                    hipMemcpyHostToDevice, s));
+    SEM_HIP(nullptr, hipMemcpyAsync(b->ws + b->off_vec, b->vec.data(),
+                                    sizeof(BatchVecItem) * b->vec.size(), hipMemcpyHostToDevice, s));
+    SEM_HIP(nullptr, hipMemcpyAsync(b->ws + b->off_probs, b->probs.data(),
+                                    sizeof(BatchProb) * b->probs.size(), hipMemcpyHostToDevice, s));
+    fill_launch(b);
+    if (b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_batch_create(const sem_ctx *ctxs, int nprob, sem_batch *out) {
+    if (!ctxs || nprob < 1 || !out) return fail(nullptr, SEM_ERR_INVALID, "bad argument");
+    *out = nullptr;
+    sem_batch b = new sem_batch_s();
+    b->nprob = nprob;
+    b->ctxs.assign(ctxs, ctxs + nprob);
+    b->probs.resize(nprob);
+    for (int p = 0; p < nprob; ++p) {
+        sem_ctx c = ctxs[p];
+        if (!c || !c->geometry_ready || !c->solver || !c->L.r64) {
+            delete b;
+            return fail(nullptr, SEM_ERR_STATE,
+                        "problem " + std::to_string(p) + ": needs geometry and solver vectors");
+        }
+        if (c->n1 > kBatchMaxN1) {
+            delete b;
+            return fail(nullptr, SEM_ERR_UNSUPPORTED, "batched solve supports N <= 9");
+        }
+        b->max_n1 = std::max(b->max_n1, c->n1);
+        b->max_c = std::max(b->max_c, c->n1 * c->n1);
+        BatchProb &pb = b->probs[p];
+        std::memset(&pb, 0, sizeof(pb));
+        pb.G = c->ws + c->L.G[0];
+        pb.D = dptr<double>(c, c->L.dhat64);
+        pb.DT = dptr<double>(c, c->L.dhatT64);
+        pb.bmap = dptr<int32_t>(c, c->L.bmap);
+        pb.dinv = dptr<double>(c, c->L.dinv64);
+        pb.r = dptr<double>(c, c->L.r64);
+        pb.p = dptr<double>(c, c->L.p64);
+        pb.w = dptr<double>(c, c->L.w64);
+        pb.E = c->E;
+        pb.n_bnd = c->n_bnd;
+        pb.n_u = c->n_unique;
+        pb.n1 = c->n1;
+    }
+    b->threads = b->max_c > 128 ? 256 : 256;
+    // capacities: one element per group is the largest possible table
+    int64_t nax = 0, nvec = 0;
+    for (int p = 0; p < nprob; ++p) {
+        nax += b->probs[p].E;
+        nvec += (b->probs[p].n_u + kVecChunk - 1) / kVecChunk;
+    }
+    if (nax > INT32_MAX / 2) {
+        delete b;
+        return fail(nullptr, SEM_ERR_UNSUPPORTED, "too many elements in a batch");
+    }
+    b->cap_ax = (int)nax;
+    b->cap_vec = (int)nvec;
+    *out = b;
+    return SEM_OK;
+}
+
+extern "C" void sem_batch_free(sem_batch b) {
+    if (!b) return;
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->event) (void)hipEventDestroy(b->event);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+extern "C" sem_status sem_batch_workspace_size(sem_batch b, size_t *bytes) {
+    if (!b || !bytes) return fail(nullptr, SEM_ERR_INVALID, "bad argument");
+    size_t off = 0;
+    b->off_probs = off; off += a256(sizeof(BatchProb) * b->nprob);
+    b->off_ax = off;    off += a256(sizeof(BatchAxItem) * (size_t)b->cap_ax);
+    b->off_vec = off;   off += a256(sizeof(BatchVecItem) * (size_t)b->cap_vec);
+    b->off_axp = off;   off += a256(sizeof(double) * 4 * (size_t)b->cap_ax);
+    b->off_vecp = off;  off += a256(sizeof(double) * 4 * (size_t)b->cap_vec);
+    b->off_st = off;    off += a256(sizeof(CgState) * b->nprob);
+    *bytes = off;
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_batch_bind_workspace(sem_batch b, void *dev, size_t bytes,
+                                               sem_stream stream) {
+    if (!b || !dev) return fail(nullptr, SEM_ERR_INVALID, "bad argument");
+    size_t need = 0;
+    sem_batch_workspace_size(b, &need);
+    if (bytes < need) return bfail(b, SEM_ERR_OOM, "batch workspace too small");
+    if ((uintptr_t)dev & 255) return bfail(b, SEM_ERR_INVALID, "workspace not 256-byte aligned");
+    b->ws = (char *)dev;
+    b->ws_bytes = bytes;
+    for (int p = 0; p < b->nprob; ++p)
+        b->probs[p].st = reinterpret_cast<CgState *>(b->ws + b->off_st) + p;
+    const size_t lds = batch_lds_bytes(b->threads, b->max_n1);
+    if (lds > b->ctxs[0]->max_lds) return bfail(b, SEM_ERR_UNSUPPORTED, "batch tile exceeds LDS");
+    return upload_tables(b, (hipStream_t)stream);
+}
+
+extern "C" sem_status sem_batch_set_tile(sem_batch b, const sem_tile *t, sem_stream stream) {
+    if (!b || !t || !b->ws) return fail(nullptr, SEM_ERR_INVALID, "bad argument");
+    const int thr = t->elements_per_block;   // for a batch: threads per workgroup
+    if (thr < b->max_c || thr > 256 || (thr % 64) || t->grid_cap < 0)
+        return bfail(b, SEM_ERR_INVALID, "batch tile: threads must be a multiple of 64 in "
+                                         "[max (N+1)^2, 256]");
+    if (batch_lds_bytes(thr, b->max_n1) > b->ctxs[0]->max_lds)
+        return bfail(b, SEM_ERR_INVALID, "batch tile exceeds LDS");
+    b->threads = thr;
+    b->grid_cap = t->grid_cap;
+    return upload_tables(b, (hipStream_t)stream);
+}
+
+extern "C" sem_status sem_batch_autotune(sem_batch b, int reps, sem_tile *best, double *best_ms,
+                                         sem_stream stream) {
+    if (!b || !b->ws) return fail(nullptr, SEM_ERR_INVALID, "bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    // states: not done, so every item works
+    std::vector<CgState> zero(b->nprob);
+    std::memset(zero.data(), 0, sizeof(CgState) * zero.size());
+    SEM_HIP(nullptr, hipMemcpyAsync(b->ws + b->off_st, zero.data(), sizeof(CgState) * zero.size(),
+                                    hipMemcpyHostToDevice, s));
+    hipEvent_t e0, e1;
+    SEM_HIP(nullptr, hipEventCreate(&e0));
+    SEM_HIP(nullptr, hipEventCreate(&e1));
+    const int ncu = b->ctxs[0]->num_cus;
+    double bms = INFINITY;
+    sem_tile bt{b->threads, b->grid_cap, 0};
+    reps = std::max(1, reps);
+    for (int thr = 64; thr <= 256; thr += 64) {
+        if (thr < b->max_c || batch_lds_bytes(thr, b->max_n1) > b->ctxs[0]->max_lds) continue;
+        for (int cap : {0, 2 * ncu, 4 * ncu, 8 * ncu}) {
+            sem_tile t{thr, cap, 0};
+            sem_status st = sem_batch_set_tile(b, &t, stream);
+            if (st) return st;
+            for (int r = 0; r < 2; ++r) SEM_HIP(nullptr, launch_batch_ax_only(b->bl, s));
+            SEM_HIP(nullptr, hipEventRecord(e0, s));
+            for (int r = 0; r < reps; ++r) SEM_HIP(nullptr, launch_batch_ax_only(b->bl, s));
+            SEM_HIP(nullptr, hipEventRecord(e1, s));
+            SEM_HIP(nullptr, hipEventSynchronize(e1));
+            float ms = 0.f;
+            SEM_HIP(nullptr, hipEventElapsedTime(&ms, e0, e1));
+            if (ms / reps < bms) {
+                bms = ms / reps;
+                bt = t;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    sem_status st = sem_batch_set_tile(b, &bt, stream);
+    if (st) return st;
+    if (best) *best = bt;
+    if (best_ms) *best_ms = bms;
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_batch_solve(sem_batch b, const double *const *rhs, double *const *x,
+                                      const sem_solve_options *opts, sem_solve_info *infos,
+                                      sem_stream stream) {
+    if (!b || !rhs || !x || !infos) return fail(nullptr, SEM_ERR_INVALID, "bad argument");
+    if (!b->ws) return bfail(b, SEM_ERR_STATE, "no batch workspace bound");
+    sem_solve_options o;
+    if (opts) o = *opts; else sem_default_solve_options(&o);
+    if (o.precision != SEM_FP64) return bfail(b, SEM_ERR_UNSUPPORTED, "batched solve is FP64");
+    if (!(o.tol > 0) || o.max_iter < 1) return bfail(b, SEM_ERR_INVALID, "bad tolerance or cap");
+    for (int p = 0; p < b->nprob; ++p)
+        if (!rhs[p] || !x[p] || ((uintptr_t)rhs[p] & 15) || ((uintptr_t)x[p] & 15))
+            return bfail(b, SEM_ERR_INVALID, "problem " + std::to_string(p) + ": bad vector");
+    if (!b->stream) {
+        SEM_HIP(nullptr, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+        SEM_HIP(nullptr, hipEventCreateWithFlags(&b->event, hipEventDisableTiming));
+    }
+    SEM_HIP(nullptr, hipEventRecord(b->event, (hipStream_t)stream));
+    SEM_HIP(nullptr, hipStreamWaitEvent(b->stream, b->event, 0));
+    hipStream_t s = b->stream;
+    auto t0 = std::chrono::steady_clock::now();
+    for (int p = 0; p < b->nprob; ++p) {
+        b->probs[p].b = rhs[p];
+        b->probs[p].x = x[p];
+    }
+    SEM_HIP(nullptr, hipMemcpyAsync(b->ws + b->off_probs, b->probs.data(),
+                                    sizeof(BatchProb) * b->probs.size(), hipMemcpyHostToDevice, s));
+    std::vector<CgState> init(b->nprob);
+    std::memset(init.data(), 0, sizeof(CgState) * init.size());
+    for (auto &st : init) {
+        st.tol2 = o.tol * o.tol;
+        st.max_iter = o.max_iter;
+    }
+    SEM_HIP(nullptr, hipMemcpyAsync(b->ws + b->off_st, init.data(), sizeof(CgState) * init.size(),
+                                    hipMemcpyHostToDevice, s));
+    SEM_HIP(nullptr, launch_batch_begin(b->bl, s));
+    const int m = std::max(1, o.check_every);
+    if (o.use_graph && (!b->graph || b->graph_m != m)) {
+        if (b->graph) (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+        hipGraph_t g;
+        SEM_HIP(nullptr, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        for (int it = 0; it < m; ++it) {
+            hipError_t e = launch_batch_iteration(b->bl, s);
+            if (e != hipSuccess) {
+                hipGraph_t dummy;
+                (void)hipStreamEndCapture(s, &dummy);
+                return bfail(b, SEM_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+            }
+        }
+        SEM_HIP(nullptr, hipStreamEndCapture(s, &g));
+        SEM_HIP(nullptr, hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(g);
+        b->graph_m = m;
+    }
+    std::vector<CgState> h(b->nprob);
+    int64_t launched = 0;
+    for (;;) {
+        if (launched > o.max_iter + 2 * (int64_t)m + 2)
+            return bfail(b, SEM_ERR_DEVICE, "batched CG did not terminate");
+        launched += m;
+        if (o.use_graph) {
+            SEM_HIP(nullptr, hipGraphLaunch(b->graph, s));
+        } else {
+            for (int it = 0; it < m; ++it) SEM_HIP(nullptr, launch_batch_iteration(b->bl, s));
+        }
+        SEM_HIP(nullptr, hipMemcpyAsync(h.data(), b->ws + b->off_st, sizeof(CgState) * h.size(),
+                                        hipMemcpyDeviceToHost, s));
+        SEM_HIP(nullptr, hipStreamSynchronize(s));
+        bool all = true;
+        for (auto &st : h) all = all && st.done;
+        if (all) break;
+    }
+    // FP64 true residual per problem; restart those that miss the tolerance
+    sem_status worst = SEM_OK;
+    for (int p = 0; p < b->nprob; ++p) {
+        sem_solve_info &inf = infos[p];
+        std::memset(&inf, 0, sizeof(inf));
+        inf.iterations = h[p].iter;
+        inf.rel_residual = h[p].bb > 0 ? std::sqrt(h[p].rr / h[p].bb) : 0.0;
+        double rel = 0.0;
+        sem_status st = true_residual(b->ctxs[p], rhs[p], x[p], s, &rel);
+        if (st) return st;
+        inf.true_rel_residual = rel;
+        inf.status = h[p].status == 0 ? SEM_OK
+                     : h[p].status == 1 ? SEM_ERR_NOT_CONVERGED
+                     : h[p].status == 2 ? SEM_ERR_BREAKDOWN : SEM_ERR_NAN;
+        if (inf.status == SEM_OK && !(rel <= o.tol)) {
+            sem_solve_options o2 = o;
+            o2.zero_guess = 0;
+            sem_solve_info i2;
+            sem_status st2 = sem_cg_solve(b->ctxs[p], rhs[p], x[p], &o2, &i2, (sem_stream)s);
+            inf.iterations += i2.iterations;
+            inf.restarts = 1 + i2.restarts;
+            inf.true_rel_residual = i2.true_rel_residual;
+            inf.status = st2;
+        }
+        if (inf.status != SEM_OK && worst == SEM_OK) worst = inf.status;
+    }
+    SEM_HIP(nullptr, hipStreamSynchronize(s));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int p = 0; p < b->nprob; ++p) infos[p].seconds = secs;
+    return worst;
+}
+
+extern "C" const char *sem_batch_last_error(sem_batch b) { return b ? b->err.c_str() : ""; }

@@ -425,6 +425,8 @@ static void compute_layout(sem_ctx c) {
     L.bpos2l = take(4 * (size_t)c->nb);
     L.dhat64 = take(8 * (kMaxN1 * kMaxN1 + kMaxN1));
     L.dhat32 = take(4 * kMaxN1 * kMaxN1);
+    L.dhatT64 = take(8 * kMaxN1 * kMaxN1);
+    L.dhatT32 = take(4 * kMaxN1 * kMaxN1);
     const size_t gsz[kNumPrec] = {8, 4, 2, 2};
     for (int p = 0; p < kNumPrec; ++p) {
         bool on = (c->precisions >> p) & 1u;
@@ -514,6 +516,15 @@ extern "C" sem_status sem_bind_workspace(sem_ctx c, void *dev, size_t bytes, sem
     SEM_HIP(c, hipMemcpyAsync(c->ws + L.bpos2l, bpos2l.data(), 4 * bpos2l.size(),
                               hipMemcpyHostToDevice, s));
     SEM_HIP(c, hipMemcpyAsync(c->ws + L.dhat64, d64, sizeof(d64), hipMemcpyHostToDevice, s));
+    double t64[kMaxN1 * kMaxN1];
+    float t32[kMaxN1 * kMaxN1];
+    for (int i = 0; i < c->n1; ++i)
+        for (int m = 0; m < c->n1; ++m) {
+            t64[i * c->n1 + m] = c->D[m * c->n1 + i];
+            t32[i * c->n1 + m] = (float)c->D[m * c->n1 + i];
+        }
+    SEM_HIP(c, hipMemcpyAsync(c->ws + L.dhatT64, t64, 8 * c->n1 * c->n1, hipMemcpyHostToDevice, s));
+    SEM_HIP(c, hipMemcpyAsync(c->ws + L.dhatT32, t32, 4 * c->n1 * c->n1, hipMemcpyHostToDevice, s));
     SEM_HIP(c, hipMemcpyAsync(c->ws + L.dhat32, d32, 4 * c->n1 * c->n1, hipMemcpyHostToDevice, s));
     CgState zero[4];
     std::memset(zero, 0, sizeof(zero));
@@ -948,6 +959,17 @@ sem_status status_from_state(const CgState &h) {
 }
 
 }  // namespace
+
+namespace sem {
+sem_status true_residual(sem_ctx c, const double *b, const double *x, hipStream_t s, double *rel) {
+    CgState h;
+    sem_status e = residual64(c, b, x, dptr<double>(c, c->L.w64), dptr<double>(c, c->L.z64),
+                              nullptr, 1, 0, s, &h);
+    if (e) return e;
+    *rel = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+    return SEM_OK;
+}
+}  // namespace sem
 
 static sem_status solve_fp64(sem_ctx c, const double *b, double *x, const sem_solve_options &o,
                              sem_solve_info *info, hipStream_t s, int64_t iter_budget,

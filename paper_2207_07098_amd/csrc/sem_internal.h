@@ -35,7 +35,8 @@ struct CgState {
 
 // Byte offsets of every array inside the caller's workspace.
 struct Layout {
-    size_t bmap, csr_off, csr_idx, bdir, bpos2l, dhat64, dhat32;  // dhat64 also holds rho
+    size_t bmap, csr_off, csr_idx, bdir, bpos2l;
+    size_t dhat64, dhat32, dhatT64, dhatT32;  // D and its transpose; dhat64 also holds rho
     size_t G[kNumPrec], gscale[kNumPrec];
     size_t B, dinv64, dinv32, diag, wb;
     size_t r64, p64, w64, z64;     // FP64 solver vectors (z64: outer residual / scratch)
@@ -150,6 +151,44 @@ hipError_t launch_ir_update(sem_ctx c, double *x, const float *d, CgState *st, i
                             hipStream_t s);
 hipError_t launch_reliable_reset(sem_ctx c, const double *r64, float *r, float *x, CgState *st,
                                  hipStream_t s);
+
+// ---- batched solve ----
+struct BatchProb {               // device-resident, one per problem
+    const void *G;               // FP64 factors
+    const double *D, *DT;        // derivative matrix and its transpose
+    const int32_t *bmap;
+    const double *dinv, *b;
+    double *x, *r, *p, *w;
+    CgState *st;
+    int64_t E, n_bnd, n_u;
+    int n1, epb;
+    int ax_begin, ax_end;        // operator work items of this problem
+    int vec_begin, vec_end;      // vector work items of this problem
+};
+struct BatchAxItem {
+    int prob, pad;
+    int64_t group;
+};
+struct BatchVecItem {
+    int prob, pad;
+    int64_t begin, end;
+};
+struct BatchLaunch {             // host-side description of one batch launch
+    BatchProb *probs;
+    const BatchAxItem *ax_items;
+    const BatchVecItem *vec_items;
+    int n_ax, n_vec, nprob;
+    double *ax_partials, *vec_partials;
+    int threads, ax_grid, vec_grid, max_n1;
+};
+constexpr int kBatchMaxN1 = 10;
+size_t batch_lds_bytes(int threads, int max_n1);
+hipError_t launch_batch_iteration(const BatchLaunch &bl, hipStream_t s);
+hipError_t launch_batch_begin(const BatchLaunch &bl, hipStream_t s);
+hipError_t launch_batch_ax_only(const BatchLaunch &bl, hipStream_t s);
+
+// FP64 true relative residual ||b - A x|| / ||b|| of a context (sem_host).
+sem_status true_residual(sem_ctx c, const double *b, const double *x, hipStream_t s, double *rel);
 
 // Output modes of the element operator.
 enum { OUT_LOCAL = 0, OUT_ATOMIC = 1, OUT_COMPACT = 2 };

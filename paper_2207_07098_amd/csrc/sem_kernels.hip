@@ -210,11 +210,6 @@ __global__ void __launch_bounds__(1024) k_finish(int site, const double *__restr
 // ---------------------------------------------------------------------------
 // Element operator
 // ---------------------------------------------------------------------------
-template <int N1, typename T>
-struct DMat {
-    T v[N1 * N1];                // row-major D[i][m] = l'_m(xi_i)
-};
-
 template <int N1, typename GS>
 struct AxParams {
     using T = typename GT<GS>::T;
@@ -228,8 +223,8 @@ struct AxParams {
     int epb, in_local, out_mode, xcd;
     double *partials;            // non-null: reduce u^T A u into st->pAp
     CgState *st;
-    DMat<N1, T> D;               // by value: wave-uniform entries come from
-                                 // the kernel-argument segment as scalars
+    const T *D;                  // D[i][m] row-major, and its transpose, in
+    const T *DT;                 // device memory (read with scalar loads)
 };
 
 // Factor loads of one lane for one k-plane (layout of goff()): 3 x 16 B
@@ -328,14 +323,37 @@ __device__ __forceinline__ void load_map(const int32_t *bmap, const Lane<N1> &L,
 // `next_e >= 0` the entries of element next_e are fetched into it after the
 // loads of this element have been issued.  S0/S1/S2: this slot's LDS
 // buffers, Dl: LDS copy of D.  Adds u_e^T A_e u_e to `dot` when want_dot.
-template <int N1, typename GS>
-__device__ __forceinline__ void ax_element(const AxMesh<GS> &M,
-                                           const DMat<N1, typename GT<GS>::T> &Dk,
+// Wave-uniform entries of D (t-direction) are fetched with scalar loads
+// through a constant-address-space pointer that is made opaque per element,
+// so each plane loads its own row right before use instead of the compiler
+// keeping all of D live in scalar registers (which spills them).
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+template <typename T>
+__device__ __forceinline__ const T *uniform_ptr(const T *p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<const T *>(((uint64_t)hi << 32) | lo);
+}
+
+enum { MODE_ATOMIC = 0, MODE_COMPACT = 1, MODE_LOCAL = 2 };
+
+template <int N1, typename GS, int MODE>
+__device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename GT<GS>::T *Dg,
+                                           const typename GT<GS>::T *DTg,
                                            const typename GT<GS>::T *Dl, const Lane<N1> &L,
                                            typename GT<GS>::T *S0, int64_t ec, bool active,
                                            int64_t next_e, int32_t (&bm)[N1], bool want_dot,
                                            double &dot) {
     using T = typename GT<GS>::T;
+    Dg = uniform_ptr(Dg);
+    DTg = uniform_ptr(DTg);
+    asm volatile("" : "+s"(Dg), "+s"(DTg));
+    cptr<T> Dk = (cptr<T>)Dg;
+    cptr<T> DTk = (cptr<T>)DTg;
+    constexpr bool IN_LOCAL = MODE == MODE_LOCAL;
     constexpr int N = N1 - 1, C = N1 * N1, NP = C * N1;
     constexpr int NI = (N - 1) * (N - 1) * (N - 1), NB = NP - NI;
     constexpr int PITCH = N1 + 1, PLANE = N1 * PITCH, BUF = N1 * PLANE;
@@ -359,7 +377,7 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M,
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
         bidx[k] = -1;
-        if (M.in_local) {
+        if (IN_LOCAL) {
             u[k] = U[ec * NP + k * C + col];
         } else if (L.bpt(k)) {
             const int32_t m = bm[k];            // a valid entry for every lane
@@ -372,7 +390,7 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M,
         }
     }
     // ---- map entries of the next element
-    if (!M.in_local && next_e >= 0) load_map<N1>(M.bmap, L, next_e, bm);
+    if (!IN_LOCAL && next_e >= 0) load_map<N1>(M.bmap, L, next_e, bm);
 
 #pragma unroll
     for (int k = 0; k < N1; ++k) S0[k * PLANE + j * PITCH + i] = u[k];
@@ -394,7 +412,7 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M,
         for (int m = 0; m < N1; ++m) {
             ur += Di[m] * S0[k * PLANE + j * PITCH + m];
             us += Dj[m] * S0[k * PLANE + m * PITCH + i];
-            ut += Dk.v[k * N1 + m] * u[m];
+            ut += Dk[k * N1 + m] * u[m];
         }
         const T wr = g[k][0] * ur + g[k][3] * us + g[k][4] * ut;
         const T ws = g[k][3] * ur + g[k][1] * us + g[k][5] * ut;
@@ -421,14 +439,14 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M,
         for (int m = 0; m < N1; ++m) {
             w += Di[m] * S1[k * PLANE + j * PITCH + m];
             w += Dj[m] * S2[k * PLANE + m * PITCH + i];
-            w += Dk.v[m * N1 + k] * wt[m];
+            w += DTk[k * N1 + m] * wt[m];
         }
         if (SCALED) w *= sc;
         if (active) {
-            if (M.out_mode == OUT_LOCAL) {
+            if (MODE == MODE_LOCAL) {
                 Y[ec * NP + k * C + col] = w;
             } else if (L.bpt(k)) {
-                if (M.out_mode == OUT_ATOMIC) {
+                if (MODE == MODE_ATOMIC) {
                     if (bidx[k] >= 0) unsafeAtomicAdd(Y + bidx[k], w);
                 } else {
                     WB[ec * NB + L.bpos(k)] = w;
@@ -442,20 +460,16 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M,
 }
 
 template <int N1, typename T>
-__device__ __forceinline__ void fill_dl(T *Dl, const DMat<N1, T> &Dk) {
+__device__ __forceinline__ void fill_dl(T *Dl, const T *Dg) {
     constexpr int C = N1 * N1;
-    for (int q = threadIdx.x; q < C; q += blockDim.x) {
-#pragma unroll
-        for (int r = 0; r < C; ++r)
-            if (q == r) Dl[q] = Dk.v[r];
-    }
+    for (int q = threadIdx.x; q < C; q += blockDim.x) Dl[q] = Dg[q];
 }
 
 // Persistent pass over element groups of one mesh.  Per element the factors
 // of all planes and the gathered u are requested together (the element's
 // map entries were fetched while the previous element was computed), so a
 // wave waits about one memory latency per element.
-template <int N1, typename GS>
+template <int N1, typename GS, int MODE>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, 256),
                                amdgpu_waves_per_eu(AxOcc<N1, GS>::value)))
 k_ax(AxParams<N1, GS> P) {
@@ -480,7 +494,7 @@ k_ax(AxParams<N1, GS> P) {
     {
         bool act;
         const int64_t e0 = elem_of(blockIdx.x, act);
-        if (!P.in_local) load_map<N1>(P.bmap, L, e0, bm);
+        if (MODE != MODE_LOCAL) load_map<N1>(P.bmap, L, e0, bm);
     }
     __syncthreads();
     double dot = 0.0;
@@ -488,7 +502,8 @@ k_ax(AxParams<N1, GS> P) {
         bool active, act_n;
         const int64_t ec = elem_of(git, active);
         const int64_t en = git + gridDim.x < P.ngroups ? elem_of(git + gridDim.x, act_n) : -1;
-        ax_element<N1, GS>(M, P.D, Dl, L, S0, ec, active, en, bm, P.partials != nullptr, dot);
+        ax_element<N1, GS, MODE>(M, P.D, P.DT, Dl, L, S0, ec, active, en, bm,
+                                 P.partials != nullptr, dot);
     }
     if (P.partials) {
         double v[1] = {dot};
@@ -497,9 +512,9 @@ k_ax(AxParams<N1, GS> P) {
 }
 
 template <int N1, typename GS>
-hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const void *u, void *y,
-                         int in_local, int out_mode, double *partials, CgState *st,
-                         const AxTile &t, hipStream_t s) {
+hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const void *Dp,
+                         const void *DTp, const void *u, void *y, int in_local, int out_mode,
+                         double *partials, CgState *st, const AxTile &t, hipStream_t s) {
     using T = typename GT<GS>::T;
     constexpr int C = N1 * N1;
     constexpr size_t BUF = (size_t)N1 * N1 * (N1 + 1);
@@ -515,7 +530,8 @@ hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const v
     P.G = reinterpret_cast<const GS *>(Gp);
     P.gscale = gscale;
     P.bmap = dptr<int32_t>(c, c->L.bmap);
-    for (int q = 0; q < C; ++q) P.D.v[q] = (T)c->D[q];
+    P.D = reinterpret_cast<const T *>(Dp);
+    P.DT = reinterpret_cast<const T *>(DTp);
     P.E = c->E;
     P.n_bnd = c->n_bnd;
     P.epb = epb;
@@ -531,7 +547,12 @@ hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const v
     if (grid > cap) grid = std::max<int64_t>(8, (cap / 8) * 8);
     if (grid > P.ngroups) grid = P.ngroups;
     if (P.xcd && grid < P.ngroups && (grid & 7)) P.xcd = 0;
-    hipLaunchKernelGGL((k_ax<N1, GS>), dim3((unsigned)grid), dim3(threads), lds, s, P);
+    if (in_local)
+        hipLaunchKernelGGL((k_ax<N1, GS, MODE_LOCAL>), dim3((unsigned)grid), dim3(threads), lds, s, P);
+    else if (out_mode == OUT_COMPACT)
+        hipLaunchKernelGGL((k_ax<N1, GS, MODE_COMPACT>), dim3((unsigned)grid), dim3(threads), lds, s, P);
+    else
+        hipLaunchKernelGGL((k_ax<N1, GS, MODE_ATOMIC>), dim3((unsigned)grid), dim3(threads), lds, s, P);
     if (partials)
         hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, (int)FIN_AX,
                            (const double *)partials, (int)grid, st);
@@ -543,9 +564,13 @@ hipError_t ax_dispatch(sem_ctx c, int prec, const void *u, void *y, int in_local
                        double *partials, CgState *st, const AxTile &t, hipStream_t s) {
     const void *G = c->ws + c->L.G[prec];
     const float *gsc = dptr<float>(c, c->L.gscale[prec]);
-#define SEM_AXN(n)                                                                      \
-    case n:                                                                             \
-        return ax_dispatch_n<n, GS>(c, G, gsc, u, y, in_local, out_mode, partials, st, t, s);
+    const bool f64 = prec == SEM_FP64;
+    const void *D = c->ws + (f64 ? c->L.dhat64 : c->L.dhat32);
+    const void *DT = c->ws + (f64 ? c->L.dhatT64 : c->L.dhatT32);
+#define SEM_AXN(n)                                                                         \
+    case n:                                                                                \
+        return ax_dispatch_n<n, GS>(c, G, gsc, D, DT, u, y, in_local, out_mode, partials, st, \
+                                    t, s);
     switch (c->n1) {
         SEM_AXN(2) SEM_AXN(3) SEM_AXN(4) SEM_AXN(5) SEM_AXN(6) SEM_AXN(7) SEM_AXN(8)
         SEM_AXN(9) SEM_AXN(10) SEM_AXN(11) SEM_AXN(12) SEM_AXN(13) SEM_AXN(14)
@@ -939,6 +964,174 @@ __global__ void k_reliable_reset(int64_t n, const double *__restrict__ r64,
     block_partial<2>(v, partials);
 }
 
+// ---------------------------------------------------------------------------
+// Batched solve: many independent meshes, one persistent launch per phase.
+// Work items are (problem, element group) for the operator and (problem,
+// node range) for vector kernels; per-problem scalars live in BatchProb.st.
+// Problems that have converged turn their items into no-ops.
+// ---------------------------------------------------------------------------
+struct BatchArgs {
+    BatchProb *probs;
+    const BatchAxItem *ax_items;
+    const BatchVecItem *vec_items;
+    int n_ax, n_vec;
+    double *ax_partials;     // [n_ax][4]
+    double *vec_partials;    // [n_vec][4]
+};
+
+template <int N1>
+__device__ __forceinline__ void batch_group(const BatchArgs &A, const BatchProb &pb,
+                                            int64_t group, double *lds, double &dot) {
+    constexpr int C = N1 * N1, BUF = N1 * N1 * (N1 + 1);
+    const Lane<N1> L(threadIdx.x);
+    const int nslots = (blockDim.x + C - 1) / C;
+    double *S0 = lds + (size_t)L.slot * 3 * BUF;
+    double *Dl = lds + (size_t)nslots * 3 * BUF;
+    fill_dl<N1, double>(Dl, pb.D);
+    const int64_t e = group * pb.epb + L.slot;
+    const bool active = L.slot < pb.epb && e < pb.E;
+    const int64_t ec = active ? e : 0;
+    AxMesh<double> M{pb.p, pb.w, nullptr, reinterpret_cast<const double *>(pb.G), nullptr,
+                     pb.bmap, pb.E, pb.n_bnd, 0, OUT_ATOMIC};
+    int32_t bm[N1];
+    load_map<N1>(pb.bmap, L, ec, bm);
+    __syncthreads();
+    ax_element<N1, double, MODE_ATOMIC>(M, pb.D, pb.DT, Dl, L, S0, ec, active, -1, bm, true,
+                                        dot);
+}
+
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, 256), amdgpu_waves_per_eu(1)))
+k_ax_batch(BatchArgs A) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double *lds = reinterpret_cast<double *>(smem_raw);
+    for (int w = blockIdx.x; w < A.n_ax; w += gridDim.x) {
+        const BatchAxItem it = A.ax_items[w];
+        const BatchProb &pb = A.probs[it.prob];
+        double dot = 0.0;
+        if (!pb.st->done) {
+            switch (pb.n1) {
+                case 2: batch_group<2>(A, pb, it.group, lds, dot); break;
+                case 3: batch_group<3>(A, pb, it.group, lds, dot); break;
+                case 4: batch_group<4>(A, pb, it.group, lds, dot); break;
+                case 5: batch_group<5>(A, pb, it.group, lds, dot); break;
+                case 6: batch_group<6>(A, pb, it.group, lds, dot); break;
+                case 7: batch_group<7>(A, pb, it.group, lds, dot); break;
+                case 8: batch_group<8>(A, pb, it.group, lds, dot); break;
+                case 9: batch_group<9>(A, pb, it.group, lds, dot); break;
+                case 10: batch_group<10>(A, pb, it.group, lds, dot); break;
+                default: break;
+            }
+        }
+        __shared__ double red[16];
+        const double sdot = block_sum(dot, red);
+        if (threadIdx.x == 0) A.ax_partials[(size_t)w * 4] = sdot;
+        __syncthreads();                 // LDS layout changes with the next item's order
+    }
+}
+
+// mode 0: begin (x = 0, r = b, p = dinv r, w_bnd = 0; partials r.z, r.r, b.b)
+// mode 1: update (x += alpha p, r -= alpha w; partials r.r, r.z)
+// mode 2: p = dinv r + beta p, w_bnd = 0 (no partials)
+__global__ void __launch_bounds__(256) k_vec_batch(BatchArgs A, int mode) {
+    for (int w = blockIdx.x; w < A.n_vec; w += gridDim.x) {
+        const BatchVecItem it = A.vec_items[w];
+        const BatchProb &pb = A.probs[it.prob];
+        double s0 = 0, s1 = 0, s2 = 0;
+        const bool skip = mode != 0 && pb.st->done;
+        if (!skip) {
+            double *x = pb.x, *r = pb.r, *p = pb.p, *wv = pb.w;
+            const double *b = pb.b, *dinv = pb.dinv;
+            const double alpha = pb.st->alpha, beta = pb.st->beta;
+            for (int64_t q = it.begin + threadIdx.x; q < it.end; q += blockDim.x) {
+                if (mode == 0) {
+                    const double bq = b[q], zq = dinv[q] * bq;
+                    x[q] = 0.0;
+                    r[q] = bq;
+                    p[q] = zq;
+                    if (q < pb.n_bnd) wv[q] = 0.0;
+                    s0 += bq * zq;
+                    s1 += bq * bq;
+                    s2 += bq * bq;
+                } else if (mode == 1) {
+                    x[q] += alpha * p[q];
+                    const double rq = r[q] - alpha * wv[q];
+                    r[q] = rq;
+                    s0 += rq * rq;
+                    s1 += rq * (dinv[q] * rq);
+                } else {
+                    p[q] = dinv[q] * r[q] + beta * p[q];
+                    if (q < pb.n_bnd) wv[q] = 0.0;
+                }
+            }
+        }
+        if (mode != 2) {
+            __shared__ double red[16];
+            const double a0 = block_sum(s0, red), a1 = block_sum(s1, red), a2 = block_sum(s2, red);
+            if (threadIdx.x == 0) {
+                A.vec_partials[(size_t)w * 4 + 0] = a0;
+                A.vec_partials[(size_t)w * 4 + 1] = a1;
+                A.vec_partials[(size_t)w * 4 + 2] = a2;
+            }
+        }
+    }
+}
+
+// One workgroup per problem: fixed-order sum of its items' partials, then
+// the same scalar logic as k_finish.
+__global__ void __launch_bounds__(256) k_finish_batch(BatchArgs A, int site) {
+    BatchProb &pb = A.probs[blockIdx.x];
+    CgState *st = pb.st;
+    if ((site == FIN_AX || site == FIN_UPDATE) && st->done) return;
+    const bool ax = site == FIN_AX;
+    const double *part = ax ? A.ax_partials : A.vec_partials;
+    const int lo = ax ? pb.ax_begin : pb.vec_begin, hi = ax ? pb.ax_end : pb.vec_end;
+    __shared__ double red[16];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int q = lo + threadIdx.x; q < hi; q += blockDim.x)
+        for (int a = 0; a < 3; ++a) acc[a] += part[(size_t)q * 4 + a];
+    double out[3];
+    for (int a = 0; a < 3; ++a) out[a] = block_sum(acc[a], red);
+    if (threadIdx.x != 0) return;
+    if (site == FIN_AX) {
+        st->pAp = out[0];
+        if (!std::isfinite(out[0])) {
+            st->status = 3;
+            st->done = 1;
+        } else if (!(out[0] > 0.0)) {
+            st->status = 2;
+            st->done = 1;
+        } else {
+            st->alpha = st->rz / out[0];
+        }
+    } else if (site == FIN_BEGIN) {
+        st->rz = out[0];
+        st->rr = out[1];
+        st->bb = out[2];
+        st->tol2 = st->tol2 * out[2];
+        st->iter = 0;
+        st->status = 0;
+        st->done = (out[1] <= st->tol2) ? 1 : 0;
+        if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
+            st->status = 3;
+            st->done = 1;
+        }
+    } else {
+        st->rr = out[0];
+        st->beta = out[1] / st->rz;
+        st->rz = out[1];
+        st->iter += 1;
+        if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
+            st->status = 3;
+            st->done = 1;
+        } else if (out[0] <= st->tol2) {
+            st->done = 1;
+        } else if (st->iter >= st->max_iter) {
+            st->status = 1;
+            st->done = 1;
+        }
+    }
+}
+
 inline unsigned vec_grid(int64_t n) {
     int64_t g = (n + kVecBlock - 1) / kVecBlock;
     if (g > kMaxPartials) g = kMaxPartials;
@@ -1170,6 +1363,56 @@ hipError_t launch_reliable_reset(sem_ctx c, const double *r64, float *r, float *
                        dptr<float>(c, c->L.dinv32), partials_site(c, 1), st);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, (int)FIN_RESET,
                        (const double *)partials_site(c, 1), (int)vec_grid(n), st);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched launchers
+// ---------------------------------------------------------------------------
+static BatchArgs batch_args(const BatchLaunch &bl) {
+    BatchArgs A;
+    A.probs = bl.probs;
+    A.ax_items = bl.ax_items;
+    A.vec_items = bl.vec_items;
+    A.n_ax = bl.n_ax;
+    A.n_vec = bl.n_vec;
+    A.ax_partials = bl.ax_partials;
+    A.vec_partials = bl.vec_partials;
+    return A;
+}
+
+size_t batch_lds_bytes(int threads, int max_n1) {
+    size_t best = 0;
+    for (int n1 = 2; n1 <= max_n1; ++n1) {
+        const int C = n1 * n1;
+        const int nslots = (threads + C - 1) / C;
+        best = std::max(best, ((size_t)nslots * 3 * n1 * n1 * (n1 + 1) + C) * sizeof(double));
+    }
+    return best;
+}
+
+hipError_t launch_batch_iteration(const BatchLaunch &bl, hipStream_t s) {
+    BatchArgs A = batch_args(bl);
+    const size_t lds = batch_lds_bytes(bl.threads, bl.max_n1);
+    hipLaunchKernelGGL(k_ax_batch, dim3(bl.ax_grid), dim3(bl.threads), lds, s, A);
+    hipLaunchKernelGGL(k_finish_batch, dim3(bl.nprob), dim3(256), 0, s, A, (int)FIN_AX);
+    hipLaunchKernelGGL(k_vec_batch, dim3(bl.vec_grid), dim3(256), 0, s, A, 1);
+    hipLaunchKernelGGL(k_finish_batch, dim3(bl.nprob), dim3(256), 0, s, A, (int)FIN_UPDATE);
+    hipLaunchKernelGGL(k_vec_batch, dim3(bl.vec_grid), dim3(256), 0, s, A, 2);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_begin(const BatchLaunch &bl, hipStream_t s) {
+    BatchArgs A = batch_args(bl);
+    hipLaunchKernelGGL(k_vec_batch, dim3(bl.vec_grid), dim3(256), 0, s, A, 0);
+    hipLaunchKernelGGL(k_finish_batch, dim3(bl.nprob), dim3(256), 0, s, A, (int)FIN_BEGIN);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_ax_only(const BatchLaunch &bl, hipStream_t s) {
+    BatchArgs A = batch_args(bl);
+    const size_t lds = batch_lds_bytes(bl.threads, bl.max_n1);
+    hipLaunchKernelGGL(k_ax_batch, dim3(bl.ax_grid), dim3(bl.threads), lds, s, A);
     return hipGetLastError();
 }
 

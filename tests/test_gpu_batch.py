@@ -1,0 +1,86 @@
+"""GPU tests of the batched solve against the FP64 oracle (through the C ABI).
+
+Independent problems of different sizes and orders are solved together;
+each result must reach the requested FP64 true residual, checked with the
+oracle's operator on the GPU solution, and agree with the oracle's own PCG
+solution within the conditioning of the problem.
+"""
+import numpy as np
+import pytest
+
+import fixtures as F
+import oracle
+from tests.common import relerr
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2207_07098_amd as sem  # noqa: E402
+
+
+def _problems(nprob, seed, kmax=4, orders=(3, 5, 7, 9)):
+    out = []
+    for bp in F.batch_problems(nprob, seed=seed, kmin=1, kmax=kmax, orders=orders):
+        m = F.batch_mesh(bp)
+        op = sem.Operator(m, bp.N, precisions=("fp64",), solver=True)
+        ora = oracle.setup(m, bp.N)
+        gid, pos, _, _ = op.numbering()
+        f = F.random_unique(op.n_unique, bp.seed)
+        b = ora.rhs_unique(f)
+        bs = np.empty_like(b)
+        bs[pos] = b
+        out.append((op, ora, pos, b, torch.from_numpy(bs).cuda()))
+    return out
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batched_solve_matches_oracle(graph):
+    probs = _problems(7, seed=3)
+    batch = sem.Batch([p[0] for p in probs])
+    xs, infos = batch.solve([p[4] for p in probs], tol=1e-8, use_graph=graph, check_every=9)
+    for (op, ora, pos, b, _), x, info in zip(probs, xs, infos):
+        assert info["status"] == "SEM_OK", info
+        xc = x.cpu().numpy()[pos]
+        assert ora.true_residual(xc, b) <= 1.01e-8, info
+        xo, _ = ora.pcg(b, 1e-12)
+        assert relerr(xc, xo) < 1e-5
+
+
+def test_batched_iterations_match_single_solves():
+    probs = _problems(5, seed=4, orders=(5, 7))
+    batch = sem.Batch([p[0] for p in probs])
+    _, infos = batch.solve([p[4] for p in probs], tol=1e-8)
+    for (op, ora, pos, b, bt), info in zip(probs, infos):
+        _, single = op.solve(bt, tol=1e-8)
+        assert abs(info["iterations"] - single["iterations"]) <= 2, (info, single)
+
+
+def test_batch_tiles_and_autotune_agree():
+    probs = _problems(4, seed=5)
+    batch = sem.Batch([p[0] for p in probs])
+    rhs = [p[4] for p in probs]
+    ref, _ = batch.solve(rhs, tol=1e-10)
+    ref = [r.clone() for r in ref]
+    best, ms = batch.autotune(reps=3)
+    assert ms > 0 and best["threads"] % 64 == 0
+    for thr, cap in ((128, 0), (256, 64)):
+        batch.set_tile(thr, cap)
+        xs, infos = batch.solve(rhs, tol=1e-10)
+        for a, b_ in zip(xs, ref):
+            assert relerr(a.cpu().numpy(), b_.cpu().numpy()) < 1e-7
+
+
+def test_batch_with_zero_rhs_and_order_limit():
+    probs = _problems(3, seed=6, orders=(5,))
+    zero = torch.zeros_like(probs[1][4])
+    batch = sem.Batch([p[0] for p in probs])
+    xs, infos = batch.solve([probs[0][4], zero, probs[2][4]], tol=1e-8)
+    assert torch.count_nonzero(xs[1]) == 0
+    assert infos[0]["status"] == "SEM_OK" and infos[2]["status"] == "SEM_OK"
+    big = sem.Operator(F.box(1), 11, precisions=("fp64",), solver=True)
+    with pytest.raises(sem.SemError) as e:
+        sem.Batch([probs[0][0], big])
+    assert e.value.status == 8
