@@ -126,7 +126,10 @@ def main():
     ap.add_argument("--N", type=int, default=7)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--solve-precisions", default="fp64,fp32,fp16,bf16")
+    ap.add_argument("--solve-precisions", default="fp64,fp32,fp16,bf16,fp32v,fp16v,bf16v",
+                    help="fp64 = plain PCG; fp32/fp16/bf16 = refinement around a reduced-"
+                         "precision PCG (FP32 vectors, reliable updates); a trailing v = FP64 "
+                         "vectors with the reduced-precision operator")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file")
     ap.add_argument("--workload", default="box", choices=["box", "batch", "ogrid"],
@@ -282,9 +285,11 @@ def main():
         x64 = None
         for prec in args.solve_precisions.split(","):
             log("solve", prec)
-            x, info = op.solve(b, tol=1e-10, precision=prec, max_iter=200000,
-                               inner_tol=1e-4 if prec == "fp32" else 1e-2,
-                               raise_on_error=False)
+            v64 = prec.endswith("v")
+            op_prec = prec[:-1] if v64 else prec
+            x, info = op.solve(b, tol=1e-10, precision=op_prec, max_iter=200000,
+                               inner_tol=1e-4 if op_prec == "fp32" else 1e-2,
+                               fp64_vectors=v64, raise_on_error=False)
             xc = x.cpu().numpy()
             if prec == "fp64":
                 x64 = xc

@@ -246,6 +246,12 @@ typedef struct {
                                      its residual is replaced by the FP64
                                      residual whenever it has dropped by
                                      delta since the last replacement        */
+    int           fp64_vectors;   /* reduced-precision solves: 1 = keep all
+                                     CG vectors in FP64 and use the reduced-
+                                     precision factors only inside operator
+                                     applications, with FP64 residual
+                                     replacement every delta reduction
+                                     (needs reliable_delta in (0,1))         */
 } sem_solve_options;
 
 typedef struct {

@@ -864,6 +864,7 @@ extern "C" void sem_default_solve_options(sem_solve_options *o) {
     o->deterministic = 0;
     o->max_restart = 3;
     o->reliable_delta = 0.1;
+    o->fp64_vectors = 0;
 }
 
 namespace {
@@ -1129,7 +1130,71 @@ static sem_status solve_reliable(sem_ctx c, const double *b, double *x,
         }
         last_rel = rel;
         SEM_HIP(c, launch_reliable_reset(c, r, (float *)lv.r, (float *)lv.x, st_in, s));
+        // the p kernel is skipped in the iteration that reports convergence,
+        // so the boundary block of w may not have been cleared
+        SEM_HIP(c, launch_fill32((float *)lv.w, c->n_bnd, 0.0f, s));
         rmax = std::sqrt(h.rr);
+    }
+}
+
+// FP64 vectors with a reduced-precision operator: PCG in FP64 whose
+// operator applications use the 32- or 16-bit factors; whenever the
+// recurrence residual has dropped by `delta` (or meets the target), it is
+// replaced by the FP64 residual b - A x and r.z is recomputed, keeping the
+// search direction.  Convergence is decided on the FP64 residual.
+static sem_status solve_approx_op(sem_ctx c, const double *b, double *x,
+                                  const sem_solve_options &o, sem_solve_info *info,
+                                  hipStream_t s) {
+    const Layout &L = c->L;
+    double *r = dptr<double>(c, L.r64), *w = dptr<double>(c, L.w64);
+    Level lv{0, (int)o.precision, x, r, c->ws + L.p64, w};
+    CgState *st = dptr<CgState>(c, L.state);
+    CgState init, h;
+    std::memset(&init, 0, sizeof(init));
+    init.tol2 = o.tol * o.tol;
+    init.max_iter = o.max_iter;
+    SEM_HIP(c, hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, s));
+    SEM_HIP(c, launch_cg_begin(c, 0, b, x, r, lv.p, w, o.zero_guess ? 1 : 0, st, s));
+    SEM_HIP(c, hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
+    SEM_HIP(c, hipStreamSynchronize(s));
+    const double bb = h.bb;
+    if (!(bb > 0)) {
+        info->true_rel_residual = 0.0;
+        return SEM_OK;
+    }
+    double rmax = std::sqrt(h.rr), last_rel = rmax / std::sqrt(bb);
+    int stalls = 0;
+    auto fallback = [&]() {
+        sem_solve_options o64 = o;
+        o64.precision = SEM_FP64;
+        return solve_fp64(c, b, x, o64, info, s, o.max_iter, false);
+    };
+    for (;;) {
+        CgState hc;
+        sem_status e = run_cg(c, lv, o, o.max_iter, &hc, s, true);
+        if (e) return e;
+        info->iterations = hc.iter;
+        info->rel_residual = std::sqrt(hc.rr / bb);
+        const bool bad = hc.status == 2 || hc.status == 3;
+        if (!(hc.done || std::sqrt(hc.rr) < o.reliable_delta * rmax || bad)) continue;
+        CgState hr;
+        e = residual64(c, b, x, dptr<double>(c, L.z64), r, nullptr, 1, o.deterministic, s, &hr);
+        if (e) return e;
+        const double rel = std::sqrt(hr.rr / bb);
+        info->true_rel_residual = rel;
+        info->outer_iterations += 1;
+        if (!std::isfinite(rel)) return SEM_ERR_NAN;
+        if (rel <= o.tol) return SEM_OK;
+        if (bad) return fallback();
+        if (hc.status == 1 || info->iterations >= o.max_iter) return SEM_ERR_NOT_CONVERGED;
+        if (hc.done) {
+            stalls = rel > 0.5 * last_rel ? stalls + 1 : 0;
+            if (stalls >= 2 || info->outer_iterations >= o.max_outer) return fallback();
+        }
+        last_rel = rel;
+        SEM_HIP(c, launch_rz_rr(c, r, st, s));
+        SEM_HIP(c, launch_fill(w, c->n_bnd, 0.0, s));
+        rmax = std::sqrt(hr.rr);
     }
 }
 
@@ -1166,6 +1231,8 @@ extern "C" sem_status sem_cg_solve(sem_ctx c, const double *b, double *x,
     auto t0 = std::chrono::steady_clock::now();
     if (o.precision == SEM_FP64)
         st = solve_fp64(c, b, x, o, info, s, o.max_iter, o.zero_guess != 0);
+    else if (o.fp64_vectors)
+        st = solve_approx_op(c, b, x, o, info, s);
     else if (o.reliable_delta > 0.0 && o.reliable_delta < 1.0)
         st = solve_reliable(c, b, x, o, info, s);
     else

@@ -134,7 +134,9 @@ hipError_t launch_lowprec_factors(sem_ctx c, hipStream_t s);
 hipError_t launch_diag(sem_ctx c, hipStream_t s);
 hipError_t launch_rhs(sem_ctx c, const double *fL, const double *f, double *b, hipStream_t s);
 hipError_t launch_ax(sem_ctx c, int prec, const void *u, void *y, int in_local, int out_mode,
-                     double *dot_partials, CgState *st, const AxTile &t, hipStream_t s);
+                     double *dot_partials, CgState *st, const AxTile &t, hipStream_t s,
+                     bool vec64 = false);
+hipError_t launch_rz_rr(sem_ctx c, const double *r, CgState *st, hipStream_t s);
 hipError_t launch_gather_sum(sem_ctx c, int prec, const void *wb, void *y, hipStream_t s);
 hipError_t launch_gs_evec(sem_ctx c, int prec, void *vL, hipStream_t s);
 hipError_t launch_q(sem_ctx c, const double *u, double *uL, hipStream_t s);

@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 #include <cmath>
 
 #include "sem_internal.h"
@@ -340,7 +341,7 @@ __device__ __forceinline__ const T *uniform_ptr(const T *p) {
 
 enum { MODE_ATOMIC = 0, MODE_COMPACT = 1, MODE_LOCAL = 2 };
 
-template <int N1, typename GS, int MODE>
+template <int N1, typename GS, int MODE, typename VT = typename GT<GS>::T>
 __device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename GT<GS>::T *Dg,
                                            const typename GT<GS>::T *DTg,
                                            const typename GT<GS>::T *Dl, const Lane<N1> &L,
@@ -361,9 +362,10 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename G
     T *S1 = S0 + BUF;
     T *S2 = S1 + BUF;
     const int i = L.i, j = L.j, col = L.col;
-    const T *__restrict__ U = reinterpret_cast<const T *>(M.u);
-    T *__restrict__ Y = reinterpret_cast<T *>(M.y);
-    T *__restrict__ WB = reinterpret_cast<T *>(M.wb);
+    // vectors may be wider than the arithmetic (FP64 vectors, 32/16-bit factors)
+    const VT *__restrict__ U = reinterpret_cast<const VT *>(M.u);
+    VT *__restrict__ Y = reinterpret_cast<VT *>(M.y);
+    VT *__restrict__ WB = reinterpret_cast<VT *>(M.wb);
 
     // ---- request the factors of every plane
     T g[N1][6];
@@ -378,15 +380,15 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename G
     for (int k = 0; k < N1; ++k) {
         bidx[k] = -1;
         if (IN_LOCAL) {
-            u[k] = U[ec * NP + k * C + col];
+            u[k] = (T)U[ec * NP + k * C + col];
         } else if (L.bpt(k)) {
             const int32_t m = bm[k];            // a valid entry for every lane
-            const T v = U[m & 0x7fffffff];
+            const T v = (T)U[m & 0x7fffffff];
             const bool take = active && m >= 0;
             bidx[k] = take ? m : -1;
             u[k] = take ? v : T(0);
         } else {
-            u[k] = U[interior_index(M.n_bnd, ec, i, j, k, N)];
+            u[k] = (T)U[interior_index(M.n_bnd, ec, i, j, k, N)];
         }
     }
     // ---- map entries of the next element
@@ -444,15 +446,15 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename G
         if (SCALED) w *= sc;
         if (active) {
             if (MODE == MODE_LOCAL) {
-                Y[ec * NP + k * C + col] = w;
+                Y[ec * NP + k * C + col] = (VT)w;
             } else if (L.bpt(k)) {
                 if (MODE == MODE_ATOMIC) {
-                    if (bidx[k] >= 0) unsafeAtomicAdd(Y + bidx[k], w);
+                    if (bidx[k] >= 0) unsafeAtomicAdd(Y + bidx[k], (VT)w);
                 } else {
-                    WB[ec * NB + L.bpos(k)] = w;
+                    WB[ec * NB + L.bpos(k)] = (VT)w;
                 }
             } else {
-                Y[interior_index(M.n_bnd, ec, i, j, k, N)] = w;
+                Y[interior_index(M.n_bnd, ec, i, j, k, N)] = (VT)w;
             }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -469,7 +471,7 @@ __device__ __forceinline__ void fill_dl(T *Dl, const T *Dg) {
 // of all planes and the gathered u are requested together (the element's
 // map entries were fetched while the previous element was computed), so a
 // wave waits about one memory latency per element.
-template <int N1, typename GS, int MODE>
+template <int N1, typename GS, int MODE, typename VT>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, 256),
                                amdgpu_waves_per_eu(AxOcc<N1, GS>::value)))
 k_ax(AxParams<N1, GS> P) {
@@ -502,8 +504,8 @@ k_ax(AxParams<N1, GS> P) {
         bool active, act_n;
         const int64_t ec = elem_of(git, active);
         const int64_t en = git + gridDim.x < P.ngroups ? elem_of(git + gridDim.x, act_n) : -1;
-        ax_element<N1, GS, MODE>(M, P.D, P.DT, Dl, L, S0, ec, active, en, bm,
-                                 P.partials != nullptr, dot);
+        ax_element<N1, GS, MODE, VT>(M, P.D, P.DT, Dl, L, S0, ec, active, en, bm,
+                                     P.partials != nullptr, dot);
     }
     if (P.partials) {
         double v[1] = {dot};
@@ -514,7 +516,8 @@ k_ax(AxParams<N1, GS> P) {
 template <int N1, typename GS>
 hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const void *Dp,
                          const void *DTp, const void *u, void *y, int in_local, int out_mode,
-                         double *partials, CgState *st, const AxTile &t, hipStream_t s) {
+                         double *partials, CgState *st, const AxTile &t, hipStream_t s,
+                         bool vec64) {
     using T = typename GT<GS>::T;
     constexpr int C = N1 * N1;
     constexpr size_t BUF = (size_t)N1 * N1 * (N1 + 1);
@@ -547,12 +550,20 @@ hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const v
     if (grid > cap) grid = std::max<int64_t>(8, (cap / 8) * 8);
     if (grid > P.ngroups) grid = P.ngroups;
     if (P.xcd && grid < P.ngroups && (grid & 7)) P.xcd = 0;
-    if (in_local)
-        hipLaunchKernelGGL((k_ax<N1, GS, MODE_LOCAL>), dim3((unsigned)grid), dim3(threads), lds, s, P);
-    else if (out_mode == OUT_COMPACT)
-        hipLaunchKernelGGL((k_ax<N1, GS, MODE_COMPACT>), dim3((unsigned)grid), dim3(threads), lds, s, P);
-    else
-        hipLaunchKernelGGL((k_ax<N1, GS, MODE_ATOMIC>), dim3((unsigned)grid), dim3(threads), lds, s, P);
+    if (vec64 && !std::is_same<T, double>::value) {
+        if (in_local || out_mode != OUT_ATOMIC) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_ax<N1, GS, MODE_ATOMIC, double>), dim3((unsigned)grid), dim3(threads),
+                           lds, s, P);
+    } else if (in_local) {
+        hipLaunchKernelGGL((k_ax<N1, GS, MODE_LOCAL, T>), dim3((unsigned)grid), dim3(threads), lds,
+                           s, P);
+    } else if (out_mode == OUT_COMPACT) {
+        hipLaunchKernelGGL((k_ax<N1, GS, MODE_COMPACT, T>), dim3((unsigned)grid), dim3(threads),
+                           lds, s, P);
+    } else {
+        hipLaunchKernelGGL((k_ax<N1, GS, MODE_ATOMIC, T>), dim3((unsigned)grid), dim3(threads),
+                           lds, s, P);
+    }
     if (partials)
         hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, (int)FIN_AX,
                            (const double *)partials, (int)grid, st);
@@ -561,7 +572,8 @@ hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const v
 
 template <typename GS>
 hipError_t ax_dispatch(sem_ctx c, int prec, const void *u, void *y, int in_local, int out_mode,
-                       double *partials, CgState *st, const AxTile &t, hipStream_t s) {
+                       double *partials, CgState *st, const AxTile &t, hipStream_t s,
+                       bool vec64) {
     const void *G = c->ws + c->L.G[prec];
     const float *gsc = dptr<float>(c, c->L.gscale[prec]);
     const bool f64 = prec == SEM_FP64;
@@ -570,7 +582,7 @@ hipError_t ax_dispatch(sem_ctx c, int prec, const void *u, void *y, int in_local
 #define SEM_AXN(n)                                                                         \
     case n:                                                                                \
         return ax_dispatch_n<n, GS>(c, G, gsc, D, DT, u, y, in_local, out_mode, partials, st, \
-                                    t, s);
+                                    t, s, vec64);
     switch (c->n1) {
         SEM_AXN(2) SEM_AXN(3) SEM_AXN(4) SEM_AXN(5) SEM_AXN(6) SEM_AXN(7) SEM_AXN(8)
         SEM_AXN(9) SEM_AXN(10) SEM_AXN(11) SEM_AXN(12) SEM_AXN(13) SEM_AXN(14)
@@ -1132,6 +1144,20 @@ __global__ void __launch_bounds__(256) k_finish_batch(BatchArgs A, int site) {
     }
 }
 
+// r.z and r.r of the current residual (after an FP64 residual replacement).
+__global__ void k_rz_rr(int64_t n, const double *__restrict__ r, const double *__restrict__ dinv,
+                        double *partials) {
+    double rz = 0, rr = 0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const double rq = r[q];
+        rz += rq * (dinv[q] * rq);
+        rr += rq * rq;
+    }
+    double v[2] = {rz, rr};
+    block_partial<2>(v, partials);
+}
+
 inline unsigned vec_grid(int64_t n) {
     int64_t g = (n + kVecBlock - 1) / kVecBlock;
     if (g > kMaxPartials) g = kMaxPartials;
@@ -1221,14 +1247,16 @@ hipError_t launch_rhs(sem_ctx c, const double *fL, const double *f, double *b, h
 }
 
 hipError_t launch_ax(sem_ctx c, int prec, const void *u, void *y, int in_local, int out_mode,
-                     double *partials, CgState *st, const AxTile &t, hipStream_t s) {
+                     double *partials, CgState *st, const AxTile &t, hipStream_t s, bool vec64) {
     switch (prec) {
-        case SEM_FP64: return ax_dispatch<double>(c, prec, u, y, in_local, out_mode, partials, st, t, s);
-        case SEM_FP32: return ax_dispatch<float>(c, prec, u, y, in_local, out_mode, partials, st, t, s);
+        case SEM_FP64:
+            return ax_dispatch<double>(c, prec, u, y, in_local, out_mode, partials, st, t, s, vec64);
+        case SEM_FP32:
+            return ax_dispatch<float>(c, prec, u, y, in_local, out_mode, partials, st, t, s, vec64);
         case SEM_FP16_SCALED:
-            return ax_dispatch<_Float16>(c, prec, u, y, in_local, out_mode, partials, st, t, s);
+            return ax_dispatch<_Float16>(c, prec, u, y, in_local, out_mode, partials, st, t, s, vec64);
         case SEM_BF16_SCALED:
-            return ax_dispatch<bf16_t>(c, prec, u, y, in_local, out_mode, partials, st, t, s);
+            return ax_dispatch<bf16_t>(c, prec, u, y, in_local, out_mode, partials, st, t, s, vec64);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1308,15 +1336,17 @@ hipError_t launch_cg_iteration(sem_ctx c, int level, int prec, void *x, void *r,
     const Layout &L = c->L;
     const int64_t n = c->n_unique;
     hipError_t e;
-    if (deterministic) {
+    const bool vec64 = level == 0;     // level 0: FP64 vectors (any operator precision)
+    if (deterministic && (prec == SEM_FP64 || !vec64)) {
         e = launch_ax(c, prec, p, w, 0, OUT_COMPACT, partials_site(c, 0), st, c->tile[prec], s);
         if (e != hipSuccess) return e;
         e = launch_gather_sum(c, prec, c->ws + L.wb, w, s);
     } else {
-        e = launch_ax(c, prec, p, w, 0, OUT_ATOMIC, partials_site(c, 0), st, c->tile[prec], s);
+        e = launch_ax(c, prec, p, w, 0, OUT_ATOMIC, partials_site(c, 0), st, c->tile[prec], s,
+                      vec64);
     }
     if (e != hipSuccess) return e;
-    if (prec == SEM_FP64) {
+    if (vec64) {
         hipLaunchKernelGGL(k_cg_update<double>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n,
                            (double *)x, (double *)r, (const double *)p, (const double *)w,
                            dptr<double>(c, L.dinv64), partials_site(c, 2), st);
@@ -1353,6 +1383,15 @@ hipError_t launch_ir_update(sem_ctx c, double *x, const float *d, CgState *outer
     const int64_t n = c->n_unique;
     hipLaunchKernelGGL(k_ir_update, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n, x, d,
                        (const CgState *)outer, scaled);
+    return hipGetLastError();
+}
+
+hipError_t launch_rz_rr(sem_ctx c, const double *r, CgState *st, hipStream_t s) {
+    const int64_t n = c->n_unique;
+    hipLaunchKernelGGL(k_rz_rr, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n, r,
+                       dptr<double>(c, c->L.dinv64), partials_site(c, 1));
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, (int)FIN_RESET,
+                       (const double *)partials_site(c, 1), (int)vec_grid(n), st);
     return hipGetLastError();
 }
 

@@ -164,15 +164,18 @@ def test_solve_unit_cube_manufactured(precision):
         assert abs(info["iterations"] - oinfo["iterations"]) <= 0.25 * oinfo["iterations"] + 5
 
 
-@pytest.mark.parametrize("delta", [0.0, 0.1, 0.5])
+@pytest.mark.parametrize("delta,v64", [(0.0, False), (0.1, False), (0.5, False), (0.1, True),
+                                       (0.01, True)])
 @pytest.mark.parametrize("precision", ["fp32", "fp16", "bf16"])
-def test_refinement_variants(precision, delta):
-    """Restarted refinement (delta = 0) and reliable updates (delta > 0)
-    both reach a true FP64 residual of 1e-10 on a curvilinear mesh."""
+def test_refinement_variants(precision, delta, v64):
+    """Restarted refinement (delta = 0), reliable updates (delta > 0) and
+    FP64 vectors with a reduced-precision operator all reach a true FP64
+    residual of 1e-10 on a curvilinear mesh."""
     p = pair("deformed3_N7")
     b = p.ora.rhs_unique(F.random_unique(p.op.n_unique, 21))
     xc, info, true_rel = _solve_case(p, b, 1e-10, precision, reliable_delta=delta,
-                                     inner_tol=1e-4 if precision == "fp32" else 1e-2)
+                                     inner_tol=1e-4 if precision == "fp32" else 1e-2,
+                                     fp64_vectors=v64)
     assert info["status"] == "SEM_OK", info
     assert true_rel <= 1.01e-10, (true_rel, info)
     xo, _ = p.ora.pcg(b, 1e-12)
@@ -193,6 +196,16 @@ def test_solve_deterministic_repeatable():
     x1, i1 = p.op.solve(b, tol=1e-10, deterministic=True)
     x2, i2 = p.op.solve(b, tol=1e-10, deterministic=True)
     assert torch.equal(x1, x2) and i1["iterations"] == i2["iterations"]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_fp64_vector_solve_warm_start_ogrid(precision):
+    p = pair("ogrid_N3")
+    b = p.ora.rhs_unique(F.random_unique(p.op.n_unique, 31))
+    x0 = p.to_dev(1e-3 * F.random_unique(p.op.n_unique, 32) * (p.dmask == 0))
+    x, info = p.op.solve(p.to_dev(b), x=x0, tol=1e-10, precision=precision, fp64_vectors=True)
+    assert info["status"] == "SEM_OK"
+    assert p.ora.true_residual(p.from_dev(x), b) <= 1.01e-10
 
 
 def test_solve_warm_start_and_restart():
