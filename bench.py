@@ -192,9 +192,10 @@ def main():
     tune = {}
     if not args.no_tune:
         best, table = op.autotune("fp64", reps=10, cache_path=args.tune_cache)
-        tune["fp64"] = {"best": best, "candidates": [[t["elements_per_block"], t["grid_cap"],
-                                                      t["xcd_remap"], round(ms, 4)]
-                                                     for t, ms in table]}
+        tune["fp64"] = {"best": best,
+                        "candidates (epb, grid, xcd, pipeline, ms)": [
+                            [t["elements_per_block"], t["grid_cap"], t["xcd_remap"], t["pipeline"],
+                             round(ms, 4)] for t, ms in table]}
         log("autotune fp64:", best, "best %.4f ms" % min(ms for _, ms in table))
     for _ in range(args.warmup):
         op.ax(u, y)

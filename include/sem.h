@@ -201,6 +201,9 @@ typedef struct {
                                      otherwise persistent workgroups, a
                                      multiple of 8                          */
     int xcd_remap;                /* 1: contiguous element ranges per XCD    */
+    int pipeline;                 /* 0: each element requests all planes of
+                                     its factors at once; 1: two planes in
+                                     flight (fewer registers, more waves)    */
 } sem_tile;
 
 typedef struct {
@@ -213,7 +216,7 @@ sem_status sem_set_tile(sem_ctx ctx, sem_precision prec, const sem_tile *tile);
 
 /* Autotuner: times the fused assembled operator of precision `prec` for
  * every candidate tile (elements per workgroup, persistent grid size, XCD
- * remapping) on this context's mesh with hipEvents on `stream`, keeps the
+ * remapping, factor pipelining) on this context's mesh with hipEvents on `stream`, keeps the
  * fastest for later calls and returns it.  Uses the solver work vectors as
  * scratch (needs opts.solver = 1); their contents are overwritten.
  * cache_path (may be NULL): a text file of earlier results keyed by

@@ -53,11 +53,11 @@ class _Info(ctypes.Structure):
 
 class Tile(ctypes.Structure):
     _fields_ = [("elements_per_block", ctypes.c_int), ("grid_cap", ctypes.c_int),
-                ("xcd_remap", ctypes.c_int)]
+                ("xcd_remap", ctypes.c_int), ("pipeline", ctypes.c_int)]
 
     def as_dict(self):
         return {"elements_per_block": self.elements_per_block, "grid_cap": self.grid_cap,
-                "xcd_remap": self.xcd_remap}
+                "xcd_remap": self.xcd_remap, "pipeline": self.pipeline}
 
 
 class TuneResult(ctypes.Structure):
@@ -361,8 +361,9 @@ class Operator:
         self._check(lib().sem_get_tile(self._ctx, PRECISIONS[precision], ctypes.byref(t)))
         return t.as_dict()
 
-    def set_tile(self, precision: str = "fp64", elements_per_block=1, grid_cap=0, xcd_remap=1):
-        t = Tile(elements_per_block, grid_cap, xcd_remap)
+    def set_tile(self, precision: str = "fp64", elements_per_block=1, grid_cap=0, xcd_remap=1,
+                 pipeline=0):
+        t = Tile(elements_per_block, grid_cap, xcd_remap, pipeline)
         self._check(lib().sem_set_tile(self._ctx, PRECISIONS[precision], ctypes.byref(t)))
 
     def autotune(self, precision: str = "fp64", reps: int = 10, cache_path: Optional[str] = None):
@@ -423,7 +424,7 @@ class Batch:
             pass
 
     def set_tile(self, threads=256, grid_cap=0):
-        t = Tile(threads, grid_cap, 0)
+        t = Tile(threads, grid_cap, 0, 0)
         self._check(lib().sem_batch_set_tile(self._b, ctypes.byref(t), _stream_handle()))
 
     def autotune(self, reps: int = 5):

@@ -219,12 +219,12 @@ extern "C" sem_status sem_batch_autotune(sem_batch b, int reps, sem_tile *best, 
     SEM_HIP(nullptr, hipEventCreate(&e1));
     const int ncu = b->ctxs[0]->num_cus;
     double bms = INFINITY;
-    sem_tile bt{b->threads, b->grid_cap, 0};
+    sem_tile bt{b->threads, b->grid_cap, 0, 0};
     reps = std::max(1, reps);
     for (int thr = 64; thr <= 256; thr += 64) {
         if (thr < b->max_c || batch_lds_bytes(thr, b->max_n1) > b->ctxs[0]->max_lds) continue;
         for (int cap : {0, 2 * ncu, 4 * ncu, 8 * ncu}) {
-            sem_tile t{thr, cap, 0};
+            sem_tile t{thr, cap, 0, 0};
             sem_status st = sem_batch_set_tile(b, &t, stream);
             if (st) return st;
             for (int r = 0; r < 2; ++r) SEM_HIP(nullptr, launch_batch_ax_only(b->bl, s));

@@ -703,6 +703,7 @@ extern "C" sem_status sem_get_tile(sem_ctx c, sem_precision prec, sem_tile *t) {
     t->elements_per_block = c->tile[prec].epb;
     t->grid_cap = c->tile[prec].grid_cap;
     t->xcd_remap = c->tile[prec].xcd;
+    t->pipeline = c->tile[prec].pipeline;
     return SEM_OK;
 }
 
@@ -710,6 +711,7 @@ static bool tile_valid(sem_ctx c, int prec, const sem_tile &t) {
     const int C = c->n1 * c->n1;
     if (t.elements_per_block < 1 || t.elements_per_block * C > 256) return false;
     if (t.grid_cap < 0 || (t.grid_cap % 8) != 0) return false;
+    if (t.pipeline < 0 || t.pipeline > 1 || t.xcd_remap < 0 || t.xcd_remap > 1) return false;
     const size_t sz = prec == SEM_FP64 ? 8 : 4;
     const int threads = ((t.elements_per_block * C + 63) / 64) * 64;
     const int nslots = (threads + C - 1) / C;
@@ -723,6 +725,7 @@ extern "C" sem_status sem_set_tile(sem_ctx c, sem_precision prec, const sem_tile
     c->tile[prec].epb = t->elements_per_block;
     c->tile[prec].grid_cap = t->grid_cap;
     c->tile[prec].xcd = t->xcd_remap;
+    c->tile[prec].pipeline = t->pipeline;
     for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
     c->graphs.clear();
     return SEM_OK;
@@ -758,8 +761,9 @@ extern "C" sem_status sem_autotune(sem_ctx c, sem_precision prec, int reps, cons
                 const char *rest = line + std::strlen(key);
                 sem_tile t;
                 double ms;
-                if (sscanf(rest, " : epb=%d grid=%d xcd=%d ms=%lf", &t.elements_per_block,
-                           &t.grid_cap, &t.xcd_remap, &ms) == 4 && tile_valid(c, prec, t)) {
+                if (sscanf(rest, " : epb=%d grid=%d xcd=%d pipe=%d ms=%lf", &t.elements_per_block,
+                           &t.grid_cap, &t.xcd_remap, &t.pipeline, &ms) == 5 &&
+                    tile_valid(c, prec, t)) {
                     fclose(f);
                     sem_set_tile(c, prec, &t);
                     if (best) *best = t;
@@ -799,15 +803,17 @@ extern "C" sem_status sem_autotune(sem_ctx c, sem_precision prec, int reps, cons
     AxTile best_t = saved;
     int nres = 0;
     reps = std::max(1, reps);
+    for (int pipe = 0; pipe < 2; ++pipe)
     for (int epb : epbs)
         for (int cap : caps)
             for (int xcd = 0; xcd < 2; ++xcd) {
-                sem_tile t{epb, (cap / 8) * 8, xcd};
+                sem_tile t{epb, (cap / 8) * 8, xcd, pipe};
                 if (!tile_valid(c, prec, t)) continue;
                 AxTile at;
                 at.epb = epb;
                 at.grid_cap = t.grid_cap;
                 at.xcd = xcd;
+                at.pipeline = pipe;
                 hipError_t he = hipSuccess;
                 for (int r = 0; r < 2 && he == hipSuccess; ++r)
                     he = launch_ax(c, prec, u, y, 0, OUT_ATOMIC, nullptr, nullptr, at, s);
@@ -836,12 +842,12 @@ extern "C" sem_status sem_autotune(sem_ctx c, sem_precision prec, int reps, cons
     c->tile[prec] = best_t;
     for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
     c->graphs.clear();
-    if (best) *best = sem_tile{best_t.epb, best_t.grid_cap, best_t.xcd};
+    if (best) *best = sem_tile{best_t.epb, best_t.grid_cap, best_t.xcd, best_t.pipeline};
     if (cache && std::isfinite(best_ms)) {
         FILE *f = fopen(cache, "a");
         if (f) {
-            fprintf(f, "%s : epb=%d grid=%d xcd=%d ms=%.6f\n", key, best_t.epb, best_t.grid_cap,
-                    best_t.xcd, best_ms);
+            fprintf(f, "%s : epb=%d grid=%d xcd=%d pipe=%d ms=%.6f\n", key, best_t.epb,
+                    best_t.grid_cap, best_t.xcd, best_t.pipeline, best_ms);
             fclose(f);
         }
     }

@@ -50,6 +50,7 @@ struct AxTile {
     int epb = 1;          // elements per workgroup
     int grid_cap = 0;     // max workgroups (0: one per element group)
     int xcd = 1;          // XCD-aware element chunking
+    int pipeline = 0;     // 0: all factor planes in flight; 1: a ring of 2 planes
 };
 
 // Offset, in values, of factor component q (0..5 = 11,22,33,12,13,23) of

@@ -271,11 +271,16 @@ __device__ __forceinline__ void load_g6(const bf16_t *plane, int col, float (&g)
 }
 
 // Waves per SIMD the compiler must allow for: bounds the register budget.
-template <int N1, typename GS>
+template <int N1, typename GS, int PF = N1>
 struct AxOcc {
-    static constexpr int value =
-        sizeof(typename GT<GS>::T) == 8 ? (N1 <= 3 ? 4 : (N1 <= 5 ? 3 : (N1 <= 9 ? 2 : 1)))
-                                        : (N1 <= 6 ? 4 : (N1 <= 9 ? 3 : (N1 <= 12 ? 2 : 1)));
+    static constexpr bool F64 = sizeof(typename GT<GS>::T) == 8;
+    static constexpr int all_planes =
+        F64 ? (N1 <= 3 ? 4 : (N1 <= 5 ? 3 : (N1 <= 9 ? 2 : 1)))
+            : (N1 <= 6 ? 4 : (N1 <= 9 ? 3 : (N1 <= 12 ? 2 : 1)));
+    static constexpr int ring =
+        F64 ? (N1 <= 5 ? 4 : (N1 <= 7 ? 3 : (N1 <= 11 ? 2 : 1)))
+            : (N1 <= 7 ? 4 : (N1 <= 11 ? 3 : 2));
+    static constexpr int value = PF >= N1 ? all_planes : ring;
 };
 
 // Per-workgroup geometry of the element loop: lane -> (slot, column i,j).
@@ -341,7 +346,11 @@ __device__ __forceinline__ const T *uniform_ptr(const T *p) {
 
 enum { MODE_ATOMIC = 0, MODE_COMPACT = 1, MODE_LOCAL = 2 };
 
-template <int N1, typename GS, int MODE, typename VT = typename GT<GS>::T>
+// PF: planes of factors in flight.  PF >= N1 requests every plane at the
+// start of the element (most bytes in flight, most registers); a smaller PF
+// keeps a ring of PF+1 planes, requesting plane k+PF while plane k is
+// computed (fewer registers, so more waves per SIMD).
+template <int N1, typename GS, int MODE, typename VT = typename GT<GS>::T, int PF = N1>
 __device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename GT<GS>::T *Dg,
                                            const typename GT<GS>::T *DTg,
                                            const typename GT<GS>::T *Dl, const Lane<N1> &L,
@@ -368,10 +377,12 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename G
     VT *__restrict__ WB = reinterpret_cast<VT *>(M.wb);
 
     // ---- request the factors of every plane
-    T g[N1][6];
+    constexpr bool ALL = PF >= N1;
+    constexpr int NS = ALL ? N1 : PF + 1;
+    T g[NS][6];
     const GS *Ge = M.G + (size_t)ec * NP * 6;
 #pragma unroll
-    for (int k = 0; k < N1; ++k) load_g6<C>(Ge + (size_t)k * C * 6, col, g[k]);
+    for (int k = 0; k < (ALL ? N1 : PF); ++k) load_g6<C>(Ge + (size_t)k * C * 6, col, g[k % NS]);
 
     // ---- gather u_e = (Q M u)_e
     T u[N1];
@@ -409,6 +420,9 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename G
     }
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
+        if (!ALL && k + PF < N1)
+            load_g6<C>(Ge + (size_t)(k + PF) * C * 6, col, g[(k + PF) % NS]);
+        const T *gk = g[k % NS];
         T ur = 0, us = 0, ut = 0;
 #pragma unroll
         for (int m = 0; m < N1; ++m) {
@@ -416,9 +430,9 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename G
             us += Dj[m] * S0[k * PLANE + m * PITCH + i];
             ut += Dk[k * N1 + m] * u[m];
         }
-        const T wr = g[k][0] * ur + g[k][3] * us + g[k][4] * ut;
-        const T ws = g[k][3] * ur + g[k][1] * us + g[k][5] * ut;
-        wt[k] = g[k][4] * ur + g[k][5] * us + g[k][2] * ut;
+        const T wr = gk[0] * ur + gk[3] * us + gk[4] * ut;
+        const T ws = gk[3] * ur + gk[1] * us + gk[5] * ut;
+        wt[k] = gk[4] * ur + gk[5] * us + gk[2] * ut;
         S1[k * PLANE + j * PITCH + i] = wr;
         S2[k * PLANE + j * PITCH + i] = ws;
         if (want_dot) edot += (double)(ur * wr + us * ws + ut * wt[k]);
@@ -471,9 +485,9 @@ __device__ __forceinline__ void fill_dl(T *Dl, const T *Dg) {
 // of all planes and the gathered u are requested together (the element's
 // map entries were fetched while the previous element was computed), so a
 // wave waits about one memory latency per element.
-template <int N1, typename GS, int MODE, typename VT>
+template <int N1, typename GS, int MODE, typename VT, int PF = N1>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, 256),
-                               amdgpu_waves_per_eu(AxOcc<N1, GS>::value)))
+                               amdgpu_waves_per_eu(AxOcc<N1, GS, PF>::value)))
 k_ax(AxParams<N1, GS> P) {
     using T = typename GT<GS>::T;
     constexpr int C = N1 * N1, BUF = N1 * N1 * (N1 + 1);
@@ -504,8 +518,8 @@ k_ax(AxParams<N1, GS> P) {
         bool active, act_n;
         const int64_t ec = elem_of(git, active);
         const int64_t en = git + gridDim.x < P.ngroups ? elem_of(git + gridDim.x, act_n) : -1;
-        ax_element<N1, GS, MODE, VT>(M, P.D, P.DT, Dl, L, S0, ec, active, en, bm,
-                                     P.partials != nullptr, dot);
+        ax_element<N1, GS, MODE, VT, PF>(M, P.D, P.DT, Dl, L, S0, ec, active, en, bm,
+                                         P.partials != nullptr, dot);
     }
     if (P.partials) {
         double v[1] = {dot};
@@ -550,15 +564,23 @@ hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const v
     if (grid > cap) grid = std::max<int64_t>(8, (cap / 8) * 8);
     if (grid > P.ngroups) grid = P.ngroups;
     if (P.xcd && grid < P.ngroups && (grid & 7)) P.xcd = 0;
+    const bool ring = t.pipeline != 0;       // factor planes in flight: 2 instead of all
     if (vec64 && !std::is_same<T, double>::value) {
         if (in_local || out_mode != OUT_ATOMIC) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_ax<N1, GS, MODE_ATOMIC, double>), dim3((unsigned)grid), dim3(threads),
-                           lds, s, P);
+        if (ring)
+            hipLaunchKernelGGL((k_ax<N1, GS, MODE_ATOMIC, double, 2>), dim3((unsigned)grid),
+                               dim3(threads), lds, s, P);
+        else
+            hipLaunchKernelGGL((k_ax<N1, GS, MODE_ATOMIC, double>), dim3((unsigned)grid),
+                               dim3(threads), lds, s, P);
     } else if (in_local) {
         hipLaunchKernelGGL((k_ax<N1, GS, MODE_LOCAL, T>), dim3((unsigned)grid), dim3(threads), lds,
                            s, P);
     } else if (out_mode == OUT_COMPACT) {
         hipLaunchKernelGGL((k_ax<N1, GS, MODE_COMPACT, T>), dim3((unsigned)grid), dim3(threads),
+                           lds, s, P);
+    } else if (ring) {
+        hipLaunchKernelGGL((k_ax<N1, GS, MODE_ATOMIC, T, 2>), dim3((unsigned)grid), dim3(threads),
                            lds, s, P);
     } else {
         hipLaunchKernelGGL((k_ax<N1, GS, MODE_ATOMIC, T>), dim3((unsigned)grid), dim3(threads),
