@@ -203,7 +203,10 @@ typedef struct {
     int xcd_remap;                /* 1: contiguous element ranges per XCD    */
     int pipeline;                 /* 0: each element requests all planes of
                                      its factors at once; 1: two planes in
-                                     flight (fewer registers, more waves)    */
+                                     flight (fewer registers, more waves);
+                                     2: all planes, and the next element's
+                                     loads are issued while the current one
+                                     finishes (atomic summation only)        */
 } sem_tile;
 
 typedef struct {

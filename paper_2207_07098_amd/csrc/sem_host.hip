@@ -711,7 +711,7 @@ static bool tile_valid(sem_ctx c, int prec, const sem_tile &t) {
     const int C = c->n1 * c->n1;
     if (t.elements_per_block < 1 || t.elements_per_block * C > 256) return false;
     if (t.grid_cap < 0 || (t.grid_cap % 8) != 0) return false;
-    if (t.pipeline < 0 || t.pipeline > 1 || t.xcd_remap < 0 || t.xcd_remap > 1) return false;
+    if (t.pipeline < 0 || t.pipeline > 2 || t.xcd_remap < 0 || t.xcd_remap > 1) return false;
     const size_t sz = prec == SEM_FP64 ? 8 : 4;
     const int threads = ((t.elements_per_block * C + 63) / 64) * 64;
     const int nslots = (threads + C - 1) / C;
@@ -803,7 +803,7 @@ extern "C" sem_status sem_autotune(sem_ctx c, sem_precision prec, int reps, cons
     AxTile best_t = saved;
     int nres = 0;
     reps = std::max(1, reps);
-    for (int pipe = 0; pipe < 2; ++pipe)
+    for (int pipe = 0; pipe < 3; ++pipe)
     for (int epb : epbs)
         for (int cap : caps)
             for (int xcd = 0; xcd < 2; ++xcd) {

@@ -278,9 +278,11 @@ struct AxOcc {
         F64 ? (N1 <= 3 ? 4 : (N1 <= 5 ? 3 : (N1 <= 9 ? 2 : 1)))
             : (N1 <= 6 ? 4 : (N1 <= 9 ? 3 : (N1 <= 12 ? 2 : 1)));
     static constexpr int ring =
-        F64 ? (N1 <= 5 ? 4 : (N1 <= 7 ? 3 : (N1 <= 11 ? 2 : 1)))
+        F64 ? (N1 <= 3 ? 4 : (N1 <= 5 ? 3 : (N1 <= 10 ? 2 : 1)))
             : (N1 <= 7 ? 4 : (N1 <= 11 ? 3 : 2));
     static constexpr int value = PF >= N1 ? all_planes : ring;
+    // two elements in flight hold about twice the factor registers
+    static constexpr int pipe = all_planes > 1 ? all_planes - 1 : 1;
 };
 
 // Per-workgroup geometry of the element loop: lane -> (slot, column i,j).
@@ -407,10 +409,19 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename G
 
 #pragma unroll
     for (int k = 0; k < N1; ++k) S0[k * PLANE + j * PITCH + i] = u[k];
+    // ---- t-derivative first (register-local), so that u is dead before the
+    // r/s part; wt[k] holds u_t until it is replaced by its G-weighted value
+    T wt[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        T ut = 0;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) ut += Dk[k * N1 + m] * u[m];
+        wt[k] = ut;
+    }
     __syncthreads();
 
-    // ---- D u, then G (D u): r/s parts to LDS, t part kept in registers
-    T wt[N1];
+    // ---- r/s derivatives, then G (D u): r/s parts to LDS, t part in registers
     double edot = 0.0;
     T Di[N1], Dj[N1];
 #pragma unroll
@@ -423,12 +434,12 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename G
         if (!ALL && k + PF < N1)
             load_g6<C>(Ge + (size_t)(k + PF) * C * 6, col, g[(k + PF) % NS]);
         const T *gk = g[k % NS];
-        T ur = 0, us = 0, ut = 0;
+        T ur = 0, us = 0;
+        const T ut = wt[k];
 #pragma unroll
         for (int m = 0; m < N1; ++m) {
             ur += Di[m] * S0[k * PLANE + j * PITCH + m];
             us += Dj[m] * S0[k * PLANE + m * PITCH + i];
-            ut += Dk[k * N1 + m] * u[m];
         }
         const T wr = gk[0] * ur + gk[3] * us + gk[4] * ut;
         const T ws = gk[3] * ur + gk[1] * us + gk[5] * ut;
@@ -472,6 +483,176 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename G
             }
         }
         __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <int N1, typename T>
+__device__ __forceinline__ void fill_dl(T *Dl, const T *Dg);
+
+// ---- pieces of the element operator used by the cross-element pipeline
+template <int N1, typename GS>
+__device__ __forceinline__ void load_all_planes(const GS *G, int64_t ec, int col,
+                                                typename GT<GS>::T (&g)[N1][6]) {
+    constexpr int C = N1 * N1, NP = C * N1;
+    const GS *Ge = G + (size_t)ec * NP * 6;
+#pragma unroll
+    for (int k = 0; k < N1; ++k) load_g6<C>(Ge + (size_t)k * C * 6, col, g[k]);
+}
+
+template <int N1, typename GS, typename VT>
+__device__ __forceinline__ void gather_u(const AxMesh<GS> &M, const Lane<N1> &L, int64_t ec,
+                                         bool active, const int32_t (&bm)[N1],
+                                         typename GT<GS>::T (&u)[N1], int32_t (&bidx)[N1]) {
+    using T = typename GT<GS>::T;
+    constexpr int N = N1 - 1;
+    const VT *__restrict__ U = reinterpret_cast<const VT *>(M.u);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        bidx[k] = -1;
+        if (L.bpt(k)) {
+            const int32_t m = bm[k];
+            const T v = (T)U[m & 0x7fffffff];
+            const bool take = active && m >= 0;
+            bidx[k] = take ? m : -1;
+            u[k] = take ? v : T(0);
+        } else {
+            u[k] = (T)U[interior_index(M.n_bnd, ec, L.i, L.j, k, N)];
+        }
+    }
+}
+
+// Element loop with the next element's factors and gathered u requested
+// right after the current element's G-weighting (its factor and u
+// registers are dead by then), so that their latency overlaps the
+// transposed derivatives and the summation of the current element.
+template <int N1, typename GS, typename VT>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, 256),
+                               amdgpu_waves_per_eu(AxOcc<N1, GS>::pipe)))
+k_ax_pipe(AxParams<N1, GS> P) {
+    using T = typename GT<GS>::T;
+    constexpr int N = N1 - 1, C = N1 * N1;
+    constexpr int PITCH = N1 + 1, PLANE = N1 * PITCH, BUF = N1 * PLANE;
+    constexpr bool SCALED = sizeof(GS) == 2;
+    CgState *st = P.st;
+    if (st && st->done) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Lane<N1> L(threadIdx.x);
+    const int nslots = (blockDim.x + C - 1) / C;
+    T *S0 = reinterpret_cast<T *>(smem_raw) + (size_t)L.slot * 3 * BUF;
+    T *S1 = S0 + BUF;
+    T *S2 = S1 + BUF;
+    T *Dl = reinterpret_cast<T *>(smem_raw) + (size_t)nslots * 3 * BUF;
+    fill_dl<N1, T>(Dl, P.D);
+    AxMesh<GS> M{P.u, P.y, P.wb, P.G, P.gscale, P.bmap, P.E, P.n_bnd, 0, OUT_ATOMIC};
+    VT *__restrict__ Y = reinterpret_cast<VT *>(P.y);
+    const int i = L.i, j = L.j;
+    auto elem_of = [&](int64_t git, bool &act) {
+        const int64_t g = P.xcd ? xcd_remap(git, P.ngroups) : git;
+        const int64_t e = g * P.epb + L.slot;
+        act = (L.slot < P.epb) && (e < P.E);
+        return act ? e : (int64_t)0;     // inactive lanes read element 0
+    };
+    const int64_t stride = gridDim.x;
+    int32_t bm[N1], bidx[N1];
+    T g[N1][6], u[N1];
+    if ((int64_t)blockIdx.x < P.ngroups) {
+        bool a0;
+        const int64_t e0 = elem_of(blockIdx.x, a0);
+        load_map<N1>(P.bmap, L, e0, bm);
+        load_all_planes<N1, GS>(P.G, e0, L.col, g);
+        gather_u<N1, GS, VT>(M, L, e0, a0, bm, u, bidx);
+        if ((int64_t)blockIdx.x + stride < P.ngroups) {
+            bool a1;
+            load_map<N1>(P.bmap, L, elem_of(blockIdx.x + stride, a1), bm);
+        }
+    }
+    double dot = 0.0;
+    for (int64_t git = blockIdx.x; git < P.ngroups; git += stride) {
+        const T *Dg = uniform_ptr(P.D), *DTg = uniform_ptr(P.DT);
+        asm volatile("" : "+s"(Dg), "+s"(DTg));
+        cptr<T> Dk = (cptr<T>)Dg;
+        cptr<T> DTk = (cptr<T>)DTg;
+        bool active;
+        const int64_t ec = elem_of(git, active);
+#pragma unroll
+        for (int k = 0; k < N1; ++k) S0[k * PLANE + j * PITCH + i] = u[k];
+        __syncthreads();
+        // ---- D u, then G (D u)
+        T wt[N1];
+        double edot = 0.0;
+        {
+            T Di[N1], Dj[N1];
+#pragma unroll
+            for (int m = 0; m < N1; ++m) {
+                Di[m] = Dl[i * N1 + m];
+                Dj[m] = Dl[j * N1 + m];
+            }
+#pragma unroll
+            for (int k = 0; k < N1; ++k) {
+                T ur = 0, us = 0, ut = 0;
+#pragma unroll
+                for (int m = 0; m < N1; ++m) {
+                    ur += Di[m] * S0[k * PLANE + j * PITCH + m];
+                    us += Dj[m] * S0[k * PLANE + m * PITCH + i];
+                    ut += Dk[k * N1 + m] * u[m];
+                }
+                const T wr = g[k][0] * ur + g[k][3] * us + g[k][4] * ut;
+                const T ws = g[k][3] * ur + g[k][1] * us + g[k][5] * ut;
+                wt[k] = g[k][4] * ur + g[k][5] * us + g[k][2] * ut;
+                S1[k * PLANE + j * PITCH + i] = wr;
+                S2[k * PLANE + j * PITCH + i] = ws;
+                if (P.partials) edot += (double)(ur * wr + us * ws + ut * wt[k]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // ---- request the next element while this one finishes
+        int32_t bcur[N1];
+#pragma unroll
+        for (int k = 0; k < N1; ++k) bcur[k] = bidx[k];
+        if (git + stride < P.ngroups) {
+            bool an;
+            const int64_t en = elem_of(git + stride, an);
+            load_all_planes<N1, GS>(P.G, en, L.col, g);
+            gather_u<N1, GS, VT>(M, L, en, an, bm, u, bidx);
+            if (git + 2 * stride < P.ngroups) {
+                bool a2;
+                load_map<N1>(P.bmap, L, elem_of(git + 2 * stride, a2), bm);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        __syncthreads();
+        // ---- D^T (G D u) and the summation into y
+        const T sc = SCALED ? (T)P.gscale[ec] : T(1);
+        if (P.partials && active) dot += SCALED ? edot * (double)sc : edot;
+        T Di[N1], Dj[N1];
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+            Di[m] = Dl[m * N1 + i];
+            Dj[m] = Dl[m * N1 + j];
+        }
+#pragma unroll
+        for (int k = 0; k < N1; ++k) {
+            T w = 0;
+#pragma unroll
+            for (int m = 0; m < N1; ++m) {
+                w += Di[m] * S1[k * PLANE + j * PITCH + m];
+                w += Dj[m] * S2[k * PLANE + m * PITCH + i];
+                w += DTk[k * N1 + m] * wt[m];
+            }
+            if (SCALED) w *= sc;
+            if (active) {
+                if (L.bpt(k)) {
+                    if (bcur[k] >= 0) unsafeAtomicAdd(Y + bcur[k], (VT)w);
+                } else {
+                    Y[interior_index(P.n_bnd, ec, i, j, k, N)] = (VT)w;
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    if (P.partials) {
+        double v[1] = {dot};
+        block_partial<1>(v, P.partials);
     }
 }
 
@@ -564,8 +745,16 @@ hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const v
     if (grid > cap) grid = std::max<int64_t>(8, (cap / 8) * 8);
     if (grid > P.ngroups) grid = P.ngroups;
     if (P.xcd && grid < P.ngroups && (grid & 7)) P.xcd = 0;
-    const bool ring = t.pipeline != 0;       // factor planes in flight: 2 instead of all
-    if (vec64 && !std::is_same<T, double>::value) {
+    const bool ring = t.pipeline == 1;       // factor planes in flight: 2 instead of all
+    const bool pipe = t.pipeline == 2;       // next element requested during this one
+    if (pipe && !in_local && out_mode == OUT_ATOMIC) {
+        if (vec64)
+            hipLaunchKernelGGL((k_ax_pipe<N1, GS, double>), dim3((unsigned)grid), dim3(threads), lds,
+                               s, P);
+        else
+            hipLaunchKernelGGL((k_ax_pipe<N1, GS, T>), dim3((unsigned)grid), dim3(threads), lds, s,
+                               P);
+    } else if (vec64 && !std::is_same<T, double>::value) {
         if (in_local || out_mode != OUT_ATOMIC) return hipErrorInvalidValue;
         if (ring)
             hipLaunchKernelGGL((k_ax<N1, GS, MODE_ATOMIC, double, 2>), dim3((unsigned)grid),

@@ -130,6 +130,56 @@ def test_reduced_precision_operator(name, prec, fmt, dtype):
     assert err < 4 * emul + 2e-6, (err, emul)
 
 
+def _tiles(N):
+    emax = max(1, 256 // (N + 1) ** 2)
+    for pipe in (0, 1, 2):
+        for epb in sorted({1, emax}):
+            for xcd, cap in ((0, 0), (1, 0), (1, 8), (0, 16)):
+                yield dict(elements_per_block=epb, grid_cap=cap, xcd_remap=xcd, pipeline=pipe)
+
+
+@pytest.mark.parametrize("name", ["cube4_N5", "deformed3_N7", "ogrid_N3", "stretched_N9", "box2_N2"])
+def test_every_tile_matches_oracle(name):
+    """Each launch shape (elements per block, grid cap, XCD remap, factor
+    pipelining) gives the oracle's operator: FP64 to 1e-12, FP32 equal to the
+    default tile's result up to summation order."""
+    p = pair(name)
+    u = F.random_unique(p.op.n_unique, 2)
+    ref = p.ora.apply(u)
+    u64, u32 = p.to_dev(u), p.to_dev(u, torch.float32)
+    saved = {pr: p.op.get_tile(pr) for pr in ("fp64", "fp32")}
+    y32_ref = p.from_dev(p.op.ax(u32, precision="fp32"))
+    try:
+        for t in _tiles(p.N):
+            for det in (False, True):
+                p.op.set_tile("fp64", **t)
+                y = p.from_dev(p.op.ax(u64, deterministic=det))
+                assert relerr(y, ref) < TOL64, (t, det)
+                p.op.set_tile("fp32", **t)
+                y = p.from_dev(p.op.ax(u32, precision="fp32", deterministic=det))
+                assert relerr(y, y32_ref) < 2e-6, (t, det)
+    finally:
+        for pr, t in saved.items():
+            p.op.set_tile(pr, **t)
+
+
+@pytest.mark.parametrize("pipeline", [0, 1, 2])
+def test_solves_under_each_pipeline(pipeline):
+    p = pair("deformed3_N7")
+    b = p.ora.rhs_unique(F.random_unique(p.op.n_unique, 12))
+    saved = {pr: p.op.get_tile(pr) for pr in ("fp64", "fp32")}
+    try:
+        for pr in saved:
+            p.op.set_tile(pr, elements_per_block=2, grid_cap=0, xcd_remap=1, pipeline=pipeline)
+        for prec, v64 in (("fp64", False), ("fp32", False), ("fp32", True)):
+            x, info = p.op.solve(p.to_dev(b), tol=1e-10, precision=prec, fp64_vectors=v64)
+            assert info["status"] == "SEM_OK", (prec, v64, info)
+            assert p.ora.true_residual(p.from_dev(x), b) <= 1.01e-10, (prec, v64, info)
+    finally:
+        for pr, t in saved.items():
+            p.op.set_tile(pr, **t)
+
+
 def test_deterministic_operator_is_bitwise_repeatable():
     p = pair("deformed3_N7")
     u = p.to_dev(F.random_unique(p.op.n_unique, 7))
