@@ -45,6 +45,37 @@ def bytes_ax_gs(n_local, n_unique, s=8):
     return n_local * (6 * s + 4) + 2 * s * n_unique
 
 
+def kernel_name(tile, N, vec="double", fac="double"):
+    n1 = N + 1
+    return "k_ax<%d,%s,ATOMIC,%s,%d>" % (n1, fac, vec, 2 if tile["pipeline"] == 1 else n1)
+
+
+def source_digest():
+    """SHA-256 of the kernel source: ties a counter record to the code it measured."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_2207_07098_amd", "csrc", "sem_kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def recorded_traffic(workload, kernel, tile):
+    """HBM bytes per launch from the committed counter summaries (FETCH_SIZE
+    and WRITE_SIZE passes, scaled by the copy-kernel calibration), or None
+    when no record matches this kernel source, workload, kernel and tile."""
+    import glob
+    digest = source_digest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                if not line.startswith("traffic-record:"):
+                    continue
+                r = json.loads(line.split(":", 1)[1])
+                if (r.get("source_sha256") == digest and r.get("workload") == workload
+                        and r.get("kernel") == kernel and r.get("tile") == tile):
+                    return r["hbm_bytes_per_launch"], os.path.relpath(path, ROOT)
+    return None, None
+
+
 def cpu_baseline(K=24, N=7, min_seconds=10.0):
     import fixtures as F
     import oracle
@@ -224,6 +255,10 @@ def main():
     k_ms = float(kms.mean())
 
     B = bytes_ax_gs(op.n_local, op.n_unique)
+    tile = op.get_tile("fp64")
+    kname = kernel_name(tile, N)
+    wl_tag = ("box%d_N%d" % (K, N)) if K else ("ogrid_N%d" % N)
+    traffic, traffic_src = recorded_traffic(wl_tag, kname, tile)
     gdofs = op.n_unique / (ms_step * 1e-3) / 1e9
     achieved = B / (k_ms * 1e-3) / 1e9
     log("Ax+gs: %.3f ms/call, kernel %.3f ms (std %.3f), %.1f GDOF/s, %.0f GB/s alg (%.1f%%)" %
@@ -240,11 +275,14 @@ def main():
                               "stretching 1.05, periodic azimuth and span), N=%d" % N),
                    "elements": op.E, "N": N, "n_unique": op.n_unique, "n_local": op.n_local},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                     "kernel": "k_ax<8,double> (fused Ax+gs, atomic summation)",
-                     "kernel_ms": k_ms, "bytes_per_launch": B},
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch", "traffic_source": traffic_src,
+                     "traffic_over_algorithmic": traffic / B if traffic else None,
+                     "kernel": kname + " (fused Ax+gs, atomic summation)",
+                     "kernel_ms": k_ms, "bytes_per_launch": B,
+                     "source_sha256": source_digest()},
         "local_points_per_s": op.n_local / (ms_step * 1e-3),
-        "tile": op.get_tile("fp64"),
+        "tile": tile,
     }
     if tune:
         result["autotune"] = tune

@@ -175,15 +175,20 @@ sem_status sem_scatter(sem_ctx ctx, const double *w_L, double *y,
 #define SEM_AX_Y_ZEROED      2u   /* caller guarantees y[0:n_boundary) == 0 on
                                      entry (e.g. cleared by a fused preceding
                                      kernel); skips the clearing pass        */
+#define SEM_AX_FP64_VECTORS  4u   /* reduced-precision operator (FP32, FP16 or
+                                     BF16 factors and arithmetic) applied to
+                                     FP64 u and y; atomic summation only     */
 
 /* Assembled operator on unique vectors: y = M Q^T A_L Q M u (Eqs. (11)-(12)
  * with the mask), fused in one pass over the elements.  u and y are device
- * vectors of n_unique entries (solver order), double for SEM_FP64 and float
- * otherwise; u and y must not overlap.  With SEM_AX_DETERMINISTIC the
+ * vectors of n_unique entries (solver order), double for SEM_FP64 or with
+ * SEM_AX_FP64_VECTORS, float otherwise; u and y must not overlap.  With SEM_AX_DETERMINISTIC the
  * summation of element contributions runs in a fixed order (bit-identical
  * repeats); by default contributions to shared nodes are added with device
  * atomics into y, whose element-boundary block is cleared first unless
- * SEM_AX_Y_ZEROED is given.  Stream-ordered, asynchronous. */
+ * SEM_AX_Y_ZEROED is given.  SEM_AX_FP64_VECTORS with SEM_FP64 or with
+ * SEM_AX_DETERMINISTIC returns SEM_ERR_INVALID.  Stream-ordered,
+ * asynchronous. */
 sem_status sem_ax(sem_ctx ctx, const void *u, void *y, sem_precision prec,
                   unsigned flags, sem_stream stream);
 
@@ -203,10 +208,7 @@ typedef struct {
     int xcd_remap;                /* 1: contiguous element ranges per XCD    */
     int pipeline;                 /* 0: each element requests all planes of
                                      its factors at once; 1: two planes in
-                                     flight (fewer registers, more waves);
-                                     2: all planes, and the next element's
-                                     loads are issued while the current one
-                                     finishes (atomic summation only)        */
+                                     flight (fewer registers, more waves)    */
 } sem_tile;
 
 typedef struct {

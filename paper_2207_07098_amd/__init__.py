@@ -22,6 +22,7 @@ FP64, FP32, FP16_SCALED, BF16_SCALED = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16_SCALED, "bf16": BF16_SCALED}
 AX_DETERMINISTIC = 1
 AX_Y_ZEROED = 2
+AX_FP64_VECTORS = 4
 
 STATUS = {0: "SEM_OK", 1: "SEM_ERR_INVALID", 2: "SEM_ERR_MESH", 3: "SEM_ERR_DEVICE",
           4: "SEM_ERR_OOM", 5: "SEM_ERR_NOT_CONVERGED", 6: "SEM_ERR_BREAKDOWN",
@@ -280,11 +281,13 @@ class Operator:
                            dtype=dtype or torch.float64, device=self.device)
 
     def ax(self, u, y=None, precision: str = "fp64", deterministic: bool = False,
-           y_zeroed: bool = False):
-        """y = M Q^T A_L Q M u on unique (solver order) vectors."""
+           y_zeroed: bool = False, fp64_vectors: bool = False):
+        """y = M Q^T A_L Q M u on unique (solver order) vectors.  With
+        fp64_vectors a reduced-precision operator takes and returns FP64."""
         if y is None:
             y = self.vector(u.dtype)
-        flags = (AX_DETERMINISTIC if deterministic else 0) | (AX_Y_ZEROED if y_zeroed else 0)
+        flags = ((AX_DETERMINISTIC if deterministic else 0) | (AX_Y_ZEROED if y_zeroed else 0)
+                 | (AX_FP64_VECTORS if fp64_vectors else 0))
         self._check(lib().sem_ax(self._ctx, _dptr(u), _dptr(y), PRECISIONS[precision], flags,
                                  _stream_handle()))
         return y

@@ -648,7 +648,15 @@ extern "C" sem_status sem_ax(sem_ctx c, const void *u, void *y, sem_precision pr
     if (u == y) return fail(c, SEM_ERR_INVALID, "u and y must not alias");
     if (!aligned16(u) || !aligned16(y)) return fail(c, SEM_ERR_INVALID, "vectors must be 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
-    if (flags & SEM_AX_DETERMINISTIC) {
+    const bool v64 = (flags & SEM_AX_FP64_VECTORS) != 0;
+    if (v64 && (prec == SEM_FP64 || (flags & SEM_AX_DETERMINISTIC)))
+        return fail(c, SEM_ERR_INVALID,
+                    "SEM_AX_FP64_VECTORS needs a reduced precision and atomic summation");
+    if (v64) {
+        if (!(flags & SEM_AX_Y_ZEROED)) SEM_HIP(c, launch_fill((double *)y, c->n_bnd, 0.0, s));
+        SEM_HIP(c, launch_ax(c, prec, u, y, 0, OUT_ATOMIC, nullptr, nullptr, c->tile[prec], s,
+                             true));
+    } else if (flags & SEM_AX_DETERMINISTIC) {
         SEM_HIP(c, launch_ax(c, prec, u, y, 0, OUT_COMPACT, nullptr, nullptr, c->tile[prec], s));
         SEM_HIP(c, launch_gather_sum(c, prec, c->ws + c->L.wb, y, s));
     } else {
@@ -711,7 +719,7 @@ static bool tile_valid(sem_ctx c, int prec, const sem_tile &t) {
     const int C = c->n1 * c->n1;
     if (t.elements_per_block < 1 || t.elements_per_block * C > 256) return false;
     if (t.grid_cap < 0 || (t.grid_cap % 8) != 0) return false;
-    if (t.pipeline < 0 || t.pipeline > 2 || t.xcd_remap < 0 || t.xcd_remap > 1) return false;
+    if (t.pipeline < 0 || t.pipeline > 1 || t.xcd_remap < 0 || t.xcd_remap > 1) return false;
     const size_t sz = prec == SEM_FP64 ? 8 : 4;
     const int threads = ((t.elements_per_block * C + 63) / 64) * 64;
     const int nslots = (threads + C - 1) / C;
@@ -803,7 +811,7 @@ extern "C" sem_status sem_autotune(sem_ctx c, sem_precision prec, int reps, cons
     AxTile best_t = saved;
     int nres = 0;
     reps = std::max(1, reps);
-    for (int pipe = 0; pipe < 3; ++pipe)
+    for (int pipe = 0; pipe < 2; ++pipe)
     for (int epb : epbs)
         for (int cap : caps)
             for (int xcd = 0; xcd < 2; ++xcd) {

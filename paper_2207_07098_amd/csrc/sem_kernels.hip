@@ -281,8 +281,6 @@ struct AxOcc {
         F64 ? (N1 <= 3 ? 4 : (N1 <= 5 ? 3 : (N1 <= 10 ? 2 : 1)))
             : (N1 <= 7 ? 4 : (N1 <= 11 ? 3 : 2));
     static constexpr int value = PF >= N1 ? all_planes : ring;
-    // two elements in flight hold about twice the factor registers
-    static constexpr int pipe = all_planes > 1 ? all_planes - 1 : 1;
 };
 
 // Per-workgroup geometry of the element loop: lane -> (slot, column i,j).
@@ -378,32 +376,41 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename G
     VT *__restrict__ Y = reinterpret_cast<VT *>(M.y);
     VT *__restrict__ WB = reinterpret_cast<VT *>(M.wb);
 
-    // ---- request the factors of every plane
     constexpr bool ALL = PF >= N1;
     constexpr int NS = ALL ? N1 : PF + 1;
     T g[NS][6];
     const GS *Ge = M.G + (size_t)ec * NP * 6;
-#pragma unroll
-    for (int k = 0; k < (ALL ? N1 : PF); ++k) load_g6<C>(Ge + (size_t)k * C * 6, col, g[k % NS]);
-
-    // ---- gather u_e = (Q M u)_e
+    // ---- gather u_e = (Q M u)_e first: memory counters retire in issue
+    // order, so the derivatives can start while the factors still arrive
     T u[N1];
     int32_t bidx[N1];
+    if (IN_LOCAL) {
 #pragma unroll
-    for (int k = 0; k < N1; ++k) {
-        bidx[k] = -1;
-        if (IN_LOCAL) {
+        for (int k = 0; k < N1; ++k) {
+            bidx[k] = -1;
             u[k] = (T)U[ec * NP + k * C + col];
-        } else if (L.bpt(k)) {
-            const int32_t m = bm[k];            // a valid entry for every lane
-            const T v = (T)U[m & 0x7fffffff];
-            const bool take = active && m >= 0;
-            bidx[k] = take ? m : -1;
-            u[k] = take ? v : T(0);
-        } else {
-            u[k] = (T)U[interior_index(M.n_bnd, ec, i, j, k, N)];
+        }
+    } else {
+        // one unconditional load per plane from a selected address (map
+        // entry or interior index), masked afterwards: loads under divergent
+        // branches would each be waited for before the next is issued
+        VT raw[N1];
+#pragma unroll
+        for (int k = 0; k < N1; ++k) {
+            const int64_t a = L.bpt(k) ? (int64_t)(bm[k] & 0x7fffffff)
+                                       : interior_index(M.n_bnd, ec, i, j, k, N);
+            raw[k] = U[a];                     // every lane holds a valid address
+        }
+#pragma unroll
+        for (int k = 0; k < N1; ++k) {
+            const bool take = !L.bpt(k) || (active && bm[k] >= 0);
+            bidx[k] = L.bpt(k) && take ? bm[k] : -1;
+            u[k] = take ? (T)raw[k] : T(0);
         }
     }
+    // ---- then the factors of the first planes (all of them, or the ring)
+#pragma unroll
+    for (int k = 0; k < (ALL ? N1 : PF); ++k) load_g6<C>(Ge + (size_t)k * C * 6, col, g[k % NS]);
     // ---- map entries of the next element
     if (!IN_LOCAL && next_e >= 0) load_map<N1>(M.bmap, L, next_e, bm);
 
@@ -521,141 +528,6 @@ __device__ __forceinline__ void gather_u(const AxMesh<GS> &M, const Lane<N1> &L,
     }
 }
 
-// Element loop with the next element's factors and gathered u requested
-// right after the current element's G-weighting (its factor and u
-// registers are dead by then), so that their latency overlaps the
-// transposed derivatives and the summation of the current element.
-template <int N1, typename GS, typename VT>
-__global__ void __attribute__((amdgpu_flat_work_group_size(1, 256),
-                               amdgpu_waves_per_eu(AxOcc<N1, GS>::pipe)))
-k_ax_pipe(AxParams<N1, GS> P) {
-    using T = typename GT<GS>::T;
-    constexpr int N = N1 - 1, C = N1 * N1;
-    constexpr int PITCH = N1 + 1, PLANE = N1 * PITCH, BUF = N1 * PLANE;
-    constexpr bool SCALED = sizeof(GS) == 2;
-    CgState *st = P.st;
-    if (st && st->done) return;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const Lane<N1> L(threadIdx.x);
-    const int nslots = (blockDim.x + C - 1) / C;
-    T *S0 = reinterpret_cast<T *>(smem_raw) + (size_t)L.slot * 3 * BUF;
-    T *S1 = S0 + BUF;
-    T *S2 = S1 + BUF;
-    T *Dl = reinterpret_cast<T *>(smem_raw) + (size_t)nslots * 3 * BUF;
-    fill_dl<N1, T>(Dl, P.D);
-    AxMesh<GS> M{P.u, P.y, P.wb, P.G, P.gscale, P.bmap, P.E, P.n_bnd, 0, OUT_ATOMIC};
-    VT *__restrict__ Y = reinterpret_cast<VT *>(P.y);
-    const int i = L.i, j = L.j;
-    auto elem_of = [&](int64_t git, bool &act) {
-        const int64_t g = P.xcd ? xcd_remap(git, P.ngroups) : git;
-        const int64_t e = g * P.epb + L.slot;
-        act = (L.slot < P.epb) && (e < P.E);
-        return act ? e : (int64_t)0;     // inactive lanes read element 0
-    };
-    const int64_t stride = gridDim.x;
-    int32_t bm[N1], bidx[N1];
-    T g[N1][6], u[N1];
-    if ((int64_t)blockIdx.x < P.ngroups) {
-        bool a0;
-        const int64_t e0 = elem_of(blockIdx.x, a0);
-        load_map<N1>(P.bmap, L, e0, bm);
-        load_all_planes<N1, GS>(P.G, e0, L.col, g);
-        gather_u<N1, GS, VT>(M, L, e0, a0, bm, u, bidx);
-        if ((int64_t)blockIdx.x + stride < P.ngroups) {
-            bool a1;
-            load_map<N1>(P.bmap, L, elem_of(blockIdx.x + stride, a1), bm);
-        }
-    }
-    double dot = 0.0;
-    for (int64_t git = blockIdx.x; git < P.ngroups; git += stride) {
-        const T *Dg = uniform_ptr(P.D), *DTg = uniform_ptr(P.DT);
-        asm volatile("" : "+s"(Dg), "+s"(DTg));
-        cptr<T> Dk = (cptr<T>)Dg;
-        cptr<T> DTk = (cptr<T>)DTg;
-        bool active;
-        const int64_t ec = elem_of(git, active);
-#pragma unroll
-        for (int k = 0; k < N1; ++k) S0[k * PLANE + j * PITCH + i] = u[k];
-        __syncthreads();
-        // ---- D u, then G (D u)
-        T wt[N1];
-        double edot = 0.0;
-        {
-            T Di[N1], Dj[N1];
-#pragma unroll
-            for (int m = 0; m < N1; ++m) {
-                Di[m] = Dl[i * N1 + m];
-                Dj[m] = Dl[j * N1 + m];
-            }
-#pragma unroll
-            for (int k = 0; k < N1; ++k) {
-                T ur = 0, us = 0, ut = 0;
-#pragma unroll
-                for (int m = 0; m < N1; ++m) {
-                    ur += Di[m] * S0[k * PLANE + j * PITCH + m];
-                    us += Dj[m] * S0[k * PLANE + m * PITCH + i];
-                    ut += Dk[k * N1 + m] * u[m];
-                }
-                const T wr = g[k][0] * ur + g[k][3] * us + g[k][4] * ut;
-                const T ws = g[k][3] * ur + g[k][1] * us + g[k][5] * ut;
-                wt[k] = g[k][4] * ur + g[k][5] * us + g[k][2] * ut;
-                S1[k * PLANE + j * PITCH + i] = wr;
-                S2[k * PLANE + j * PITCH + i] = ws;
-                if (P.partials) edot += (double)(ur * wr + us * ws + ut * wt[k]);
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        }
-        // ---- request the next element while this one finishes
-        int32_t bcur[N1];
-#pragma unroll
-        for (int k = 0; k < N1; ++k) bcur[k] = bidx[k];
-        if (git + stride < P.ngroups) {
-            bool an;
-            const int64_t en = elem_of(git + stride, an);
-            load_all_planes<N1, GS>(P.G, en, L.col, g);
-            gather_u<N1, GS, VT>(M, L, en, an, bm, u, bidx);
-            if (git + 2 * stride < P.ngroups) {
-                bool a2;
-                load_map<N1>(P.bmap, L, elem_of(git + 2 * stride, a2), bm);
-            }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        __syncthreads();
-        // ---- D^T (G D u) and the summation into y
-        const T sc = SCALED ? (T)P.gscale[ec] : T(1);
-        if (P.partials && active) dot += SCALED ? edot * (double)sc : edot;
-        T Di[N1], Dj[N1];
-#pragma unroll
-        for (int m = 0; m < N1; ++m) {
-            Di[m] = Dl[m * N1 + i];
-            Dj[m] = Dl[m * N1 + j];
-        }
-#pragma unroll
-        for (int k = 0; k < N1; ++k) {
-            T w = 0;
-#pragma unroll
-            for (int m = 0; m < N1; ++m) {
-                w += Di[m] * S1[k * PLANE + j * PITCH + m];
-                w += Dj[m] * S2[k * PLANE + m * PITCH + i];
-                w += DTk[k * N1 + m] * wt[m];
-            }
-            if (SCALED) w *= sc;
-            if (active) {
-                if (L.bpt(k)) {
-                    if (bcur[k] >= 0) unsafeAtomicAdd(Y + bcur[k], (VT)w);
-                } else {
-                    Y[interior_index(P.n_bnd, ec, i, j, k, N)] = (VT)w;
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    }
-    if (P.partials) {
-        double v[1] = {dot};
-        block_partial<1>(v, P.partials);
-    }
-}
-
 template <int N1, typename T>
 __device__ __forceinline__ void fill_dl(T *Dl, const T *Dg) {
     constexpr int C = N1 * N1;
@@ -746,15 +618,7 @@ hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const v
     if (grid > P.ngroups) grid = P.ngroups;
     if (P.xcd && grid < P.ngroups && (grid & 7)) P.xcd = 0;
     const bool ring = t.pipeline == 1;       // factor planes in flight: 2 instead of all
-    const bool pipe = t.pipeline == 2;       // next element requested during this one
-    if (pipe && !in_local && out_mode == OUT_ATOMIC) {
-        if (vec64)
-            hipLaunchKernelGGL((k_ax_pipe<N1, GS, double>), dim3((unsigned)grid), dim3(threads), lds,
-                               s, P);
-        else
-            hipLaunchKernelGGL((k_ax_pipe<N1, GS, T>), dim3((unsigned)grid), dim3(threads), lds, s,
-                               P);
-    } else if (vec64 && !std::is_same<T, double>::value) {
+    if (vec64 && !std::is_same<T, double>::value) {
         if (in_local || out_mode != OUT_ATOMIC) return hipErrorInvalidValue;
         if (ring)
             hipLaunchKernelGGL((k_ax<N1, GS, MODE_ATOMIC, double, 2>), dim3((unsigned)grid),

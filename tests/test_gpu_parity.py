@@ -132,7 +132,7 @@ def test_reduced_precision_operator(name, prec, fmt, dtype):
 
 def _tiles(N):
     emax = max(1, 256 // (N + 1) ** 2)
-    for pipe in (0, 1, 2):
+    for pipe in (0, 1):
         for epb in sorted({1, emax}):
             for xcd, cap in ((0, 0), (1, 0), (1, 8), (0, 16)):
                 yield dict(elements_per_block=epb, grid_cap=cap, xcd_remap=xcd, pipeline=pipe)
@@ -158,12 +158,15 @@ def test_every_tile_matches_oracle(name):
                 p.op.set_tile("fp32", **t)
                 y = p.from_dev(p.op.ax(u32, precision="fp32", deterministic=det))
                 assert relerr(y, y32_ref) < 2e-6, (t, det)
+            # FP32 operator on FP64 vectors (the operator of the FP64-vector solve)
+            y = p.from_dev(p.op.ax(u64, precision="fp32", fp64_vectors=True))
+            assert relerr(y, y32_ref) < 2e-6, (t, "fp64 vectors")
     finally:
         for pr, t in saved.items():
             p.op.set_tile(pr, **t)
 
 
-@pytest.mark.parametrize("pipeline", [0, 1, 2])
+@pytest.mark.parametrize("pipeline", [0, 1])
 def test_solves_under_each_pipeline(pipeline):
     p = pair("deformed3_N7")
     b = p.ora.rhs_unique(F.random_unique(p.op.n_unique, 12))
@@ -178,6 +181,15 @@ def test_solves_under_each_pipeline(pipeline):
     finally:
         for pr, t in saved.items():
             p.op.set_tile(pr, **t)
+
+
+def test_fp64_vector_flag_rejections():
+    p = pair("cube4_N5")
+    u = p.to_dev(F.random_unique(p.op.n_unique, 3))
+    with pytest.raises(sem.SemError):
+        p.op.ax(u, precision="fp64", fp64_vectors=True)
+    with pytest.raises(sem.SemError):
+        p.op.ax(u, precision="fp32", fp64_vectors=True, deterministic=True)
 
 
 def test_deterministic_operator_is_bitwise_repeatable():

@@ -35,6 +35,14 @@ def test_library_exports_every_declared_symbol():
     assert sorted(sem.EXPORTS) == declared
 
 
+def test_binding_flag_values_match_header():
+    src = open(os.path.join(ROOT, "include", "sem.h")).read()
+    defs = dict(re.findall(r"#define SEM_(AX_\w+)\s+(\d+)u", src))
+    assert set(defs) == {"AX_DETERMINISTIC", "AX_Y_ZEROED", "AX_FP64_VECTORS"}
+    for name, val in defs.items():
+        assert getattr(sem, name) == int(val), name
+
+
 def test_library_is_for_gfx950():
     out = subprocess.run(["/opt/rocm/bin/roc-obj-ls", sem.LIB_PATH], capture_output=True,
                          text=True)
