@@ -214,13 +214,14 @@ extern "C" sem_status sem_batch_autotune(sem_batch b, int reps, sem_tile *best, 
     std::memset(zero.data(), 0, sizeof(CgState) * zero.size());
     SEM_HIP(nullptr, hipMemcpyAsync(b->ws + b->off_st, zero.data(), sizeof(CgState) * zero.size(),
                                     hipMemcpyHostToDevice, s));
-    hipEvent_t e0, e1;
-    SEM_HIP(nullptr, hipEventCreate(&e0));
-    SEM_HIP(nullptr, hipEventCreate(&e1));
+    // As in the solve, every timed operator pass follows other kernels (here
+    // the clearing of each problem's summed block, as the p-update does).
+    reps = std::max(1, std::min(reps, 64));
+    std::vector<hipEvent_t> ev(2 * reps);
+    for (auto &e : ev) SEM_HIP(nullptr, hipEventCreate(&e));
     const int ncu = b->ctxs[0]->num_cus;
     double bms = INFINITY;
     sem_tile bt{b->threads, b->grid_cap, 0, 0};
-    reps = std::max(1, reps);
     for (int thr = 64; thr <= 256; thr += 64) {
         if (thr < b->max_c || batch_lds_bytes(thr, b->max_n1) > b->ctxs[0]->max_lds) continue;
         for (int cap : {0, 2 * ncu, 4 * ncu, 8 * ncu}) {
@@ -228,20 +229,27 @@ extern "C" sem_status sem_batch_autotune(sem_batch b, int reps, sem_tile *best, 
             sem_status st = sem_batch_set_tile(b, &t, stream);
             if (st) return st;
             for (int r = 0; r < 2; ++r) SEM_HIP(nullptr, launch_batch_ax_only(b->bl, s));
-            SEM_HIP(nullptr, hipEventRecord(e0, s));
-            for (int r = 0; r < reps; ++r) SEM_HIP(nullptr, launch_batch_ax_only(b->bl, s));
-            SEM_HIP(nullptr, hipEventRecord(e1, s));
-            SEM_HIP(nullptr, hipEventSynchronize(e1));
-            float ms = 0.f;
-            SEM_HIP(nullptr, hipEventElapsedTime(&ms, e0, e1));
+            for (int r = 0; r < reps; ++r) {
+                for (const BatchProb &pb : b->probs)
+                    SEM_HIP(nullptr, launch_fill(pb.w, pb.n_bnd, 0.0, s));
+                SEM_HIP(nullptr, hipEventRecord(ev[2 * r], s));
+                SEM_HIP(nullptr, launch_batch_ax_only(b->bl, s));
+                SEM_HIP(nullptr, hipEventRecord(ev[2 * r + 1], s));
+            }
+            SEM_HIP(nullptr, hipEventSynchronize(ev[2 * reps - 1]));
+            double ms = 0.0;
+            for (int r = 0; r < reps; ++r) {
+                float m = 0.f;
+                SEM_HIP(nullptr, hipEventElapsedTime(&m, ev[2 * r], ev[2 * r + 1]));
+                ms += m;
+            }
             if (ms / reps < bms) {
                 bms = ms / reps;
                 bt = t;
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (auto &e : ev) (void)hipEventDestroy(e);
     sem_status st = sem_batch_set_tile(b, &bt, stream);
     if (st) return st;
     if (best) *best = bt;

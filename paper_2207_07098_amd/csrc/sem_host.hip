@@ -803,14 +803,21 @@ extern "C" sem_status sem_autotune(sem_ctx c, sem_precision prec, int reps, cons
     for (int e = 1; e <= max_epb; ++e)
         if (max_epb <= 8 || e == 1 || e == 2 || e == 4 || e == 8 || e == max_epb) epbs.push_back(e);
     const int caps[4] = {0, 2 * c->num_cus, 4 * c->num_cus, 8 * c->num_cus};
-    hipEvent_t e0, e1;
-    SEM_HIP(c, hipEventCreate(&e0));
-    SEM_HIP(c, hipEventCreate(&e1));
+    // Each timed launch is preceded by the clearing of the summed block, as
+    // in the CG iteration (the p-update kernel clears it right before the
+    // operator): back-to-back launches of the operator alone favour
+    // persistent grids that are slower once another kernel runs in between.
+    reps = std::max(1, std::min(reps, 64));
+    std::vector<hipEvent_t> ev(2 * reps);
+    for (auto &e : ev) SEM_HIP(c, hipEventCreate(&e));
+    auto clear_y = [&]() {
+        return prec == SEM_FP64 ? launch_fill((double *)y, c->n_bnd, 0.0, s)
+                                : launch_fill32((float *)y, c->n_bnd, 0.0f, s);
+    };
     const AxTile saved = c->tile[prec];
     double best_ms = INFINITY;
     AxTile best_t = saved;
     int nres = 0;
-    reps = std::max(1, reps);
     for (int pipe = 0; pipe < 2; ++pipe)
     for (int epb : epbs)
         for (int cap : caps)
@@ -826,14 +833,20 @@ extern "C" sem_status sem_autotune(sem_ctx c, sem_precision prec, int reps, cons
                 for (int r = 0; r < 2 && he == hipSuccess; ++r)
                     he = launch_ax(c, prec, u, y, 0, OUT_ATOMIC, nullptr, nullptr, at, s);
                 if (he != hipSuccess) continue;
-                SEM_HIP(c, hipEventRecord(e0, s));
-                for (int r = 0; r < reps; ++r)
+                for (int r = 0; r < reps; ++r) {
+                    SEM_HIP(c, clear_y());
+                    SEM_HIP(c, hipEventRecord(ev[2 * r], s));
                     SEM_HIP(c, launch_ax(c, prec, u, y, 0, OUT_ATOMIC, nullptr, nullptr, at, s));
-                SEM_HIP(c, hipEventRecord(e1, s));
-                SEM_HIP(c, hipEventSynchronize(e1));
-                float ms = 0.f;
-                SEM_HIP(c, hipEventElapsedTime(&ms, e0, e1));
-                const double per = ms / reps;
+                    SEM_HIP(c, hipEventRecord(ev[2 * r + 1], s));
+                }
+                SEM_HIP(c, hipEventSynchronize(ev[2 * reps - 1]));
+                double total = 0.0;
+                for (int r = 0; r < reps; ++r) {
+                    float ms = 0.f;
+                    SEM_HIP(c, hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]));
+                    total += ms;
+                }
+                const double per = total / reps;
                 if (results && nres < max_results) {
                     results[nres].tile = t;
                     results[nres].ms = per;
@@ -844,8 +857,7 @@ extern "C" sem_status sem_autotune(sem_ctx c, sem_precision prec, int reps, cons
                     best_t = at;
                 }
             }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (auto &e : ev) (void)hipEventDestroy(e);
     if (n_results) *n_results = std::min(nres, max_results);
     c->tile[prec] = best_t;
     for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);

@@ -12,7 +12,13 @@
 namespace sem {
 
 constexpr int kMaxN1 = 16;           // N <= 15
-constexpr int kMaxPartials = 8192;   // per-block partial sums of one reduction
+constexpr int kMaxPartials = 1 << 17;  // per-block partial sums of one reduction (the
+                                       // operator runs one workgroup per element group)
+#ifndef SEM_VEC_MAX_BLOCKS
+#define SEM_VEC_MAX_BLOCKS 32768
+#endif
+constexpr int kVecMaxBlocks = SEM_VEC_MAX_BLOCKS;  // grid of the grid-stride vector kernels
+static_assert(kVecMaxBlocks <= kMaxPartials, "vector partials exceed the partials buffer");
 constexpr int kNumPrec = 4;
 
 // Device-resident CG scalars.  One instance per solver level.

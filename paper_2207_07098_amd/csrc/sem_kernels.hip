@@ -128,6 +128,8 @@ __device__ void block_partial(const double (&v)[NV], double *partials) {
     }
 }
 
+typedef double d4v __attribute__((ext_vector_type(4)));
+
 enum { FIN_AX = 0, FIN_BEGIN = 1, FIN_UPDATE = 2, FIN_RESID = 3, FIN_RESET = 4 };
 
 // Grid-wide sums of the partials of the preceding kernel and the scalar
@@ -136,10 +138,29 @@ __global__ void __launch_bounds__(1024) k_finish(int site, const double *__restr
                                                  int nblocks, CgState *st) {
     if ((site == FIN_AX || site == FIN_UPDATE) && st->done) return;
     __shared__ double red[16];
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (int q = threadIdx.x; q < nblocks; q += blockDim.x)
+    // four independent chains per thread keep several loads in flight; the
+    // summation order is fixed for a given nblocks
+    double acc4[4][3] = {};
+    const d4v *P4 = reinterpret_cast<const d4v *>(partials);
+    int q = threadIdx.x;
+    for (; q + 3 * (int)blockDim.x < nblocks; q += 4 * blockDim.x) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) acc[a] += partials[(size_t)q * 4 + a];
+        for (int c = 0; c < 4; ++c) {
+            const d4v v = P4[q + c * blockDim.x];
+            acc4[c][0] += v.x;
+            acc4[c][1] += v.y;
+            acc4[c][2] += v.z;
+        }
+    }
+    for (; q < nblocks; q += blockDim.x) {
+        const d4v v = P4[q];
+        acc4[0][0] += v.x;
+        acc4[0][1] += v.y;
+        acc4[0][2] += v.z;
+    }
+    double acc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) acc[a] = (acc4[0][a] + acc4[1][a]) + (acc4[2][a] + acc4[3][a]);
     double out[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) out[a] = block_sum(acc[a], red);
@@ -235,6 +256,9 @@ typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f2v __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
+// 12-byte vector with 4-byte alignment (six 16-bit factors of one point)
+typedef uint32_t u3v __attribute__((ext_vector_type(3), aligned(4)));
+
 template <int C>
 __device__ __forceinline__ void load_g6(const double *plane, int col, double (&g)[6]) {
     const d2v *q = reinterpret_cast<const d2v *>(plane) + col;
@@ -251,22 +275,21 @@ __device__ __forceinline__ void load_g6(const float *plane, int col, float (&g)[
 }
 template <int C>
 __device__ __forceinline__ void load_g6(const _Float16 *plane, int col, float (&g)[6]) {
-    const uint32_t *q = reinterpret_cast<const uint32_t *>(plane + (size_t)col * 6);
+    // the six 16-bit values of a point are 12 contiguous bytes: one load
+    const u3v w = __builtin_nontemporal_load(reinterpret_cast<const u3v *>(plane + (size_t)col * 6));
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const uint32_t w = __builtin_nontemporal_load(q + a);
-        g[2 * a] = (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
-        g[2 * a + 1] = (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+        g[2 * a] = (float)__builtin_bit_cast(_Float16, (uint16_t)(w[a] & 0xffffu));
+        g[2 * a + 1] = (float)__builtin_bit_cast(_Float16, (uint16_t)(w[a] >> 16));
     }
 }
 template <int C>
 __device__ __forceinline__ void load_g6(const bf16_t *plane, int col, float (&g)[6]) {
-    const uint32_t *q = reinterpret_cast<const uint32_t *>(plane + (size_t)col * 6);
+    const u3v w = __builtin_nontemporal_load(reinterpret_cast<const u3v *>(plane + (size_t)col * 6));
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const uint32_t w = __builtin_nontemporal_load(q + a);
-        g[2 * a] = __uint_as_float(w << 16);
-        g[2 * a + 1] = __uint_as_float(w & 0xffff0000u);
+        g[2 * a] = __uint_as_float(w[a] << 16);
+        g[2 * a + 1] = __uint_as_float(w[a] & 0xffff0000u);
     }
 }
 
@@ -1235,7 +1258,7 @@ __global__ void k_rz_rr(int64_t n, const double *__restrict__ r, const double *_
 
 inline unsigned vec_grid(int64_t n) {
     int64_t g = (n + kVecBlock - 1) / kVecBlock;
-    if (g > kMaxPartials) g = kMaxPartials;
+    if (g > kVecMaxBlocks) g = kVecMaxBlocks;
     if (g < 1) g = 1;
     return (unsigned)g;
 }
