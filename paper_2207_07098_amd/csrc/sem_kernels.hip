@@ -519,38 +519,6 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename G
 template <int N1, typename T>
 __device__ __forceinline__ void fill_dl(T *Dl, const T *Dg);
 
-// ---- pieces of the element operator used by the cross-element pipeline
-template <int N1, typename GS>
-__device__ __forceinline__ void load_all_planes(const GS *G, int64_t ec, int col,
-                                                typename GT<GS>::T (&g)[N1][6]) {
-    constexpr int C = N1 * N1, NP = C * N1;
-    const GS *Ge = G + (size_t)ec * NP * 6;
-#pragma unroll
-    for (int k = 0; k < N1; ++k) load_g6<C>(Ge + (size_t)k * C * 6, col, g[k]);
-}
-
-template <int N1, typename GS, typename VT>
-__device__ __forceinline__ void gather_u(const AxMesh<GS> &M, const Lane<N1> &L, int64_t ec,
-                                         bool active, const int32_t (&bm)[N1],
-                                         typename GT<GS>::T (&u)[N1], int32_t (&bidx)[N1]) {
-    using T = typename GT<GS>::T;
-    constexpr int N = N1 - 1;
-    const VT *__restrict__ U = reinterpret_cast<const VT *>(M.u);
-#pragma unroll
-    for (int k = 0; k < N1; ++k) {
-        bidx[k] = -1;
-        if (L.bpt(k)) {
-            const int32_t m = bm[k];
-            const T v = (T)U[m & 0x7fffffff];
-            const bool take = active && m >= 0;
-            bidx[k] = take ? m : -1;
-            u[k] = take ? v : T(0);
-        } else {
-            u[k] = (T)U[interior_index(M.n_bnd, ec, L.i, L.j, k, N)];
-        }
-    }
-}
-
 template <int N1, typename T>
 __device__ __forceinline__ void fill_dl(T *Dl, const T *Dg) {
     constexpr int C = N1 * N1;
