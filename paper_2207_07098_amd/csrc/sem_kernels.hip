@@ -344,7 +344,10 @@ __device__ __forceinline__ void load_map(const int32_t *bmap, const Lane<N1> &L,
                                          int32_t (&bm)[N1]) {
     constexpr int N = N1 - 1, NP = N1 * N1 * N1, NB = NP - (N - 1) * (N - 1) * (N - 1);
 #pragma unroll
-    for (int k = 0; k < N1; ++k) bm[k] = L.bpt(k) ? bmap[e * NB + L.bpos(k)] : -1;
+    // streamed once per application: non-temporal, so that it does not evict
+    // the u and y lines that neighbouring elements reuse
+    for (int k = 0; k < N1; ++k)
+        bm[k] = L.bpt(k) ? __builtin_nontemporal_load(bmap + e * NB + L.bpos(k)) : -1;
 }
 
 // One element per lane slot: w_e = D^T G_e D u_e with gather/mask/summation.
@@ -509,7 +512,8 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename G
                     WB[ec * NB + L.bpos(k)] = (VT)w;
                 }
             } else {
-                Y[interior_index(M.n_bnd, ec, i, j, k, N)] = (VT)w;
+                // written once, read by the next kernel: non-temporal
+                __builtin_nontemporal_store((VT)w, Y + interior_index(M.n_bnd, ec, i, j, k, N));
             }
         }
         __builtin_amdgcn_sched_barrier(0);
