@@ -940,6 +940,22 @@ struct Vec<float> {
 
 // x += alpha p; r -= alpha w; reduces r.r and r.z (z = dinv r); updates beta
 // and the convergence state.  16-byte accesses; n % W entries in a tail.
+// Streaming accesses of the vector kernels (each vector is touched once per
+// kernel); SEM_VEC_NT selects non-temporal hints.
+#ifndef SEM_VEC_NT
+#define SEM_VEC_NT 1
+#endif
+template <typename V>
+__device__ __forceinline__ V vld(const V *p) {
+    if (SEM_VEC_NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+template <typename V>
+__device__ __forceinline__ void vst(V v, V *p) {
+    if (SEM_VEC_NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 template <typename T>
 __global__ void k_cg_update(int64_t n, T *__restrict__ x, T *__restrict__ r,
                             const T *__restrict__ p, const T *__restrict__ w,
@@ -952,15 +968,15 @@ __global__ void k_cg_update(int64_t n, T *__restrict__ x, T *__restrict__ r,
     const int64_t nv = n / W, stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t v = t0; v < nv; v += stride) {
-        V xv = reinterpret_cast<V *>(x)[v];
-        V rv = reinterpret_cast<V *>(r)[v];
-        const V pv = reinterpret_cast<const V *>(p)[v];
-        const V wv = reinterpret_cast<const V *>(w)[v];
-        const V dv = reinterpret_cast<const V *>(dinv)[v];
+        V xv = vld(reinterpret_cast<V *>(x) + v);
+        V rv = vld(reinterpret_cast<V *>(r) + v);
+        const V pv = vld(reinterpret_cast<const V *>(p) + v);
+        const V wv = vld(reinterpret_cast<const V *>(w) + v);
+        const V dv = vld(reinterpret_cast<const V *>(dinv) + v);
         xv += alpha * pv;
         rv -= alpha * wv;
-        reinterpret_cast<V *>(x)[v] = xv;
-        reinterpret_cast<V *>(r)[v] = rv;
+        vst(xv, reinterpret_cast<V *>(x) + v);
+        vst(rv, reinterpret_cast<V *>(r) + v);
 #pragma unroll
         for (int c = 0; c < W; ++c) {
             rr += (double)rv[c] * (double)rv[c];
@@ -990,12 +1006,12 @@ __global__ void k_cg_p(int64_t n, int64_t n_bnd, const T *__restrict__ r, T *__r
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nbv = n_bnd / W;            // whole vectors inside the boundary block
     for (int64_t v = t0; v < nv; v += stride) {
-        const V rv = reinterpret_cast<const V *>(r)[v];
-        const V dv = reinterpret_cast<const V *>(dinv)[v];
-        V pv = reinterpret_cast<V *>(p)[v];
+        const V rv = vld(reinterpret_cast<const V *>(r) + v);
+        const V dv = vld(reinterpret_cast<const V *>(dinv) + v);
+        V pv = vld(reinterpret_cast<V *>(p) + v);
         pv = dv * rv + beta * pv;
-        reinterpret_cast<V *>(p)[v] = pv;
-        if (v < nbv) reinterpret_cast<V *>(w)[v] = V(0);
+        vst(pv, reinterpret_cast<V *>(p) + v);
+        if (v < nbv) vst(V(0), reinterpret_cast<V *>(w) + v);
     }
     for (int64_t q = nbv * W + t0; q < n_bnd; q += stride) w[q] = 0;
     for (int64_t q = nv * W + t0; q < n; q += stride) p[q] = dinv[q] * r[q] + beta * p[q];
