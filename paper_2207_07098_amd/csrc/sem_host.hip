@@ -719,11 +719,15 @@ static bool tile_valid(sem_ctx c, int prec, const sem_tile &t) {
     const int C = c->n1 * c->n1;
     if (t.elements_per_block < 1 || t.elements_per_block * C > 256) return false;
     if (t.grid_cap < 0 || (t.grid_cap % 8) != 0) return false;
-    if (t.pipeline < 0 || t.pipeline > 1 || t.xcd_remap < 0 || t.xcd_remap > 1) return false;
+    if (t.pipeline < 0 || t.pipeline > 2 || t.xcd_remap < 0 || t.xcd_remap > 1) return false;
+    // 2: matrix-core element operator, for 16-bit factors at N = 7
+    if (t.pipeline == 2 && !(c->n1 == 8 && (prec == SEM_FP16_SCALED || prec == SEM_BF16_SCALED)))
+        return false;
     const size_t sz = prec == SEM_FP64 ? 8 : 4;
     const int threads = ((t.elements_per_block * C + 63) / 64) * 64;
     const int nslots = (threads + C - 1) / C;
-    const size_t lds = ((size_t)nslots * 2 * c->n1 * c->n1 * (c->n1 + 1) + C) * sz;
+    // three LDS buffers per element slot plus D (the operator kernels' layout)
+    const size_t lds = ((size_t)nslots * 3 * c->n1 * c->n1 * (c->n1 + 1) + C) * sz;
     return lds <= c->max_lds;
 }
 
@@ -818,7 +822,7 @@ extern "C" sem_status sem_autotune(sem_ctx c, sem_precision prec, int reps, cons
     double best_ms = INFINITY;
     AxTile best_t = saved;
     int nres = 0;
-    for (int pipe = 0; pipe < 2; ++pipe)
+    for (int pipe = 0; pipe < 3; ++pipe)
     for (int epb : epbs)
         for (int cap : caps)
             for (int xcd = 0; xcd < 2; ++xcd) {

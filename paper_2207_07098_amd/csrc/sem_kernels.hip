@@ -350,6 +350,32 @@ __device__ __forceinline__ void load_map(const int32_t *bmap, const Lane<N1> &L,
         bm[k] = L.bpt(k) ? __builtin_nontemporal_load(bmap + e * NB + L.bpos(k)) : -1;
 }
 
+// u_e = (Q M u)_e for one lane's column of element e: one unconditional load
+// per plane from a selected address (map entry or interior index), masked
+// afterwards.  Loads under divergent branches would each be waited for
+// before the next is issued.  bidx receives the summation targets (-1: none).
+template <int N1, typename GS, typename VT>
+__device__ __forceinline__ void gather_u(const AxMesh<GS> &M, const Lane<N1> &L, int64_t e,
+                                         bool active, const int32_t (&bm)[N1],
+                                         typename GT<GS>::T (&u)[N1], int32_t (&bidx)[N1]) {
+    using T = typename GT<GS>::T;
+    constexpr int N = N1 - 1;
+    const VT *__restrict__ U = reinterpret_cast<const VT *>(M.u);
+    VT raw[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        const int64_t a = L.bpt(k) ? (int64_t)(bm[k] & 0x7fffffff)
+                                   : interior_index(M.n_bnd, e, L.i, L.j, k, N);
+        raw[k] = U[a];                         // every lane holds a valid address
+    }
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        const bool take = !L.bpt(k) || (active && bm[k] >= 0);
+        bidx[k] = L.bpt(k) && take ? bm[k] : -1;
+        u[k] = take ? (T)raw[k] : T(0);
+    }
+}
+
 // One element per lane slot: w_e = D^T G_e D u_e with gather/mask/summation.
 // `bm` holds the map entries of element ec (fetched earlier); when
 // `next_e >= 0` the entries of element next_e are fetched into it after the
@@ -575,6 +601,201 @@ k_ax(AxParams<N1, GS> P) {
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Element operator on matrix cores (16-bit factors, N = 7): one element per
+// wave.  The derivative contractions of Eq. (9) are 8x8 by 8x64 products per
+// direction; two of them share one 16x16x16 MFMA through a block-diagonal
+// A = diag(D, D), so each direction takes two MFMAs forward and two
+// backward.  u is divided by a per-element power of two (its largest
+// magnitude rounded up) before it is rounded to 16 bits; the G-weighted
+// derivatives are rounded to 16 bits unscaled (they stay far below the
+// 16-bit range); products accumulate in FP32.  The operands are staged in
+// LDS in three layouts (contraction index fastest for r, s and t), so every
+// lane fetches its four consecutive operand values with one 8-byte read.
+// ---------------------------------------------------------------------------
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+typedef short s4v __attribute__((ext_vector_type(4)));
+
+template <typename GS>
+struct MF;
+template <>
+struct MF<_Float16> {
+    using E = _Float16;
+    using V = h4v;
+    static __device__ __forceinline__ E cvt(float f) { return (_Float16)f; }
+    static __device__ __forceinline__ f4v mma(V a, V b, f4v c) {
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct MF<bf16_t> {
+    using E = uint16_t;
+    using V = s4v;
+    static __device__ __forceinline__ E cvt(float f) { return f32_to_bf16_rne(f); }
+    static __device__ __forceinline__ f4v mma(V a, V b, f4v c) {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    }
+};
+
+template <typename GS>
+__device__ __forceinline__ typename MF<GS>::V pack4(typename MF<GS>::E a, typename MF<GS>::E b,
+                                                    typename MF<GS>::E c, typename MF<GS>::E d) {
+    typename MF<GS>::V v;
+    v[0] = a;
+    v[1] = b;
+    v[2] = c;
+    v[3] = d;
+    return v;
+}
+
+constexpr int kMfmaSlotBytes = 3 * 512 * 2 + 3 * 512 * 4;   // 16-bit operands + FP32 outputs
+
+// One direction of the block-diagonal contraction: out = diag(M, M) * B over
+// the 64 columns of an element, B read from `src` (layout: contraction index
+// fastest within groups of 8), FP32 result written to `dst` in the same
+// layout.  Column index c in 0..63 addresses the group at c * 8.
+template <typename GS>
+__device__ __forceinline__ void mfma_dir(typename MF<GS>::V a, const typename MF<GS>::E *src,
+                                         float *dst, int lane) {
+    using V = typename MF<GS>::V;
+    const int q = lane >> 4, grp = q >> 1, m0 = 4 * (q & 1);
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+        const int colidx = 16 * n + (lane & 15) + 32 * grp;
+        const V b = *reinterpret_cast<const V *>(src + colidx * 8 + m0);
+        const f4v acc = MF<GS>::mma(a, b, f4v{0.f, 0.f, 0.f, 0.f});
+        *reinterpret_cast<f4v *>(dst + colidx * 8 + m0) = acc;
+    }
+}
+
+template <typename GS, typename VT>
+__global__ void __launch_bounds__(256) k_ax_mfma(AxParams<8, GS> P) {
+    constexpr int N1 = 8, N = 7, C = 64, NP = 512, NB = NP - 216;
+    using E = typename MF<GS>::E;
+    using V = typename MF<GS>::V;
+    CgState *st = P.st;
+    if (st && st->done) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Lane<N1> L(threadIdx.x);
+    const int lane = threadIdx.x & 63;
+    // per wave: operands in layouts R [k][j][i], S [k][i][j], T [(i,j)][k]
+    E *UR = reinterpret_cast<E *>(smem_raw + (size_t)L.slot * kMfmaSlotBytes);
+    E *US = UR + NP;
+    E *UT = US + NP;
+    float *FR = reinterpret_cast<float *>(UT + NP);
+    float *FS = FR + NP;
+    float *FT = FS + NP;
+    // A operands diag(D, D) and diag(D^T, D^T): lane holds row lane%16,
+    // contraction entries 4*(lane/16) .. +3
+    V aF, aB;
+    {
+        const int row = lane & 15, q = lane >> 4;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int kk = 4 * q + t;
+            const bool blk = (row >> 3) == (kk >> 3);
+            aF[t] = MF<GS>::cvt(blk ? (float)P.D[(row & 7) * N1 + (kk & 7)] : 0.f);
+            aB[t] = MF<GS>::cvt(blk ? (float)P.D[(kk & 7) * N1 + (row & 7)] : 0.f);
+        }
+    }
+    AxMesh<GS> M{P.u, P.y, P.wb, P.G, P.gscale, P.bmap, P.E, P.n_bnd, 0, OUT_ATOMIC};
+    VT *__restrict__ Y = reinterpret_cast<VT *>(P.y);
+    const int i = L.i, j = L.j, col = L.col;
+    double dot = 0.0;
+    for (int64_t git = blockIdx.x; git < P.ngroups; git += gridDim.x) {
+        const int64_t e = git * P.epb + L.slot;
+        const bool active = (L.slot < P.epb) && (e < P.E);
+        const int64_t ec = active ? e : 0;      // inactive waves work on element 0
+        int32_t bm[N1], bidx[N1];
+        float u[N1], g[N1][6];
+        load_map<N1>(P.bmap, L, ec, bm);
+        gather_u<N1, GS, VT>(M, L, ec, active, bm, u, bidx);
+        const GS *Ge = P.G + (size_t)ec * NP * 6;
+#pragma unroll
+        for (int k = 0; k < N1; ++k) load_g6<C>(Ge + (size_t)k * C * 6, col, g[k]);
+        // per-element power-of-two scale of u
+        float mx = 0.f;
+#pragma unroll
+        for (int k = 0; k < N1; ++k) mx = fmaxf(mx, fabsf(u[k]));
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+        int ex = 0;
+        (void)frexpf(mx, &ex);
+        const float inv = mx > 0.f ? ldexpf(1.f, -ex) : 1.f;
+        const float sig = mx > 0.f ? ldexpf(1.f, ex) : 1.f;
+        {
+            E h[N1];
+#pragma unroll
+            for (int k = 0; k < N1; ++k) {
+                h[k] = MF<GS>::cvt(u[k] * inv);
+                UR[k * C + j * N1 + i] = h[k];
+                US[k * C + i * N1 + j] = h[k];
+            }
+            *reinterpret_cast<V *>(UT + col * N1) = pack4<GS>(h[0], h[1], h[2], h[3]);
+            *reinterpret_cast<V *>(UT + col * N1 + 4) = pack4<GS>(h[4], h[5], h[6], h[7]);
+        }
+        __syncthreads();
+        mfma_dir<GS>(aF, UR, FR, lane);
+        mfma_dir<GS>(aF, US, FS, lane);
+        mfma_dir<GS>(aF, UT, FT, lane);
+        __syncthreads();
+        // G-weighting at the lane's own column
+        double edot = 0.0;
+        {
+            const f4v t0 = *reinterpret_cast<const f4v *>(FT + col * N1);
+            const f4v t1 = *reinterpret_cast<const f4v *>(FT + col * N1 + 4);
+            const float utv[N1] = {t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z, t1.w};
+            E hw[N1];
+#pragma unroll
+            for (int k = 0; k < N1; ++k) {
+                const float ur = FR[k * C + j * N1 + i];
+                const float us = FS[k * C + i * N1 + j];
+                const float ut = utv[k];
+                const float *gk = g[k];
+                const float wr = gk[0] * ur + gk[3] * us + gk[4] * ut;
+                const float ws = gk[3] * ur + gk[1] * us + gk[5] * ut;
+                const float wt = gk[4] * ur + gk[5] * us + gk[2] * ut;
+                if (P.partials) edot += (double)(ur * wr + us * ws + ut * wt);
+                UR[k * C + j * N1 + i] = MF<GS>::cvt(wr);
+                US[k * C + i * N1 + j] = MF<GS>::cvt(ws);
+                hw[k] = MF<GS>::cvt(wt);
+            }
+            *reinterpret_cast<V *>(UT + col * N1) = pack4<GS>(hw[0], hw[1], hw[2], hw[3]);
+            *reinterpret_cast<V *>(UT + col * N1 + 4) = pack4<GS>(hw[4], hw[5], hw[6], hw[7]);
+        }
+        __syncthreads();
+        mfma_dir<GS>(aB, UR, FR, lane);
+        mfma_dir<GS>(aB, US, FS, lane);
+        mfma_dir<GS>(aB, UT, FT, lane);
+        __syncthreads();
+        const float sc = P.gscale[ec];
+        if (P.partials && active) dot += edot * (double)sc * (double)sig * (double)sig;
+        const float outs = sc * sig;
+        {
+            const f4v t0 = *reinterpret_cast<const f4v *>(FT + col * N1);
+            const f4v t1 = *reinterpret_cast<const f4v *>(FT + col * N1 + 4);
+            const float wtv[N1] = {t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z, t1.w};
+#pragma unroll
+            for (int k = 0; k < N1; ++k) {
+                const float w = (FR[k * C + j * N1 + i] + FS[k * C + i * N1 + j] + wtv[k]) * outs;
+                if (active) {
+                    if (L.bpt(k)) {
+                        if (bidx[k] >= 0) unsafeAtomicAdd(Y + bidx[k], (VT)w);
+                    } else {
+                        __builtin_nontemporal_store((VT)w, Y + interior_index(P.n_bnd, ec, i, j, k, N));
+                    }
+                }
+            }
+        }
+        __syncthreads();                        // LDS is rewritten by the next element
+    }
+    if (P.partials) {
+        double v[1] = {dot};
+        block_partial<1>(v, P.partials);
+    }
+}
+
 template <int N1, typename GS>
 hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const void *Dp,
                          const void *DTp, const void *u, void *y, int in_local, int out_mode,
@@ -586,7 +807,11 @@ hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const v
     int epb = std::max(1, std::min(t.epb, 256 / C));
     const int threads = ((epb * C + 63) / 64) * 64;
     const int nslots = (threads + C - 1) / C;      // padding lanes get a slot too
-    const size_t lds = ((size_t)nslots * 3 * BUF + C) * sizeof(T);
+    // matrix-core variant: 16-bit factors, N = 7, atomic summation
+    constexpr bool MFMA_OK = N1 == 8 && sizeof(GS) == 2;
+    const bool mfma = MFMA_OK && t.pipeline == 2 && !in_local && out_mode == OUT_ATOMIC;
+    const size_t lds = mfma ? (size_t)nslots * kMfmaSlotBytes
+                            : ((size_t)nslots * 3 * BUF + C) * sizeof(T);
     if (lds > c->max_lds) return hipErrorInvalidConfiguration;
     AxParams<N1, GS> P;
     P.u = u;
@@ -613,6 +838,20 @@ hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const v
     if (grid > P.ngroups) grid = P.ngroups;
     if (P.xcd && grid < P.ngroups && (grid & 7)) P.xcd = 0;
     const bool ring = t.pipeline == 1;       // factor planes in flight: 2 instead of all
+    if constexpr (MFMA_OK) {
+        if (mfma) {
+            if (vec64)
+                hipLaunchKernelGGL((k_ax_mfma<GS, double>), dim3((unsigned)grid), dim3(threads),
+                                   lds, s, P);
+            else
+                hipLaunchKernelGGL((k_ax_mfma<GS, float>), dim3((unsigned)grid), dim3(threads),
+                                   lds, s, P);
+            if (partials)
+                hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, (int)FIN_AX,
+                                   (const double *)partials, (int)grid, st);
+            return hipGetLastError();
+        }
+    }
     if (vec64 && !std::is_same<T, double>::value) {
         if (in_local || out_mode != OUT_ATOMIC) return hipErrorInvalidValue;
         if (ring)

@@ -29,6 +29,7 @@ def _meshes():
         "cube4_N5": (F.box(4), 5),
         "deformed3_N7": (F.box(3, hi=(2 * np.pi,) * 3, deform=0.05), 7),
         "reoriented_N4": (F.box((3, 2, 2), hi=(2.0, 1.0, 1.5), reorient_seed=3), 4),
+        "reoriented_N7": (F.box((2, 2, 3), hi=(1.0, 1.5, 2.0), deform=0.05, reorient_seed=5), 7),
         "ogrid_N3": (F.ogrid(8, 3, 4), 3),
         "stretched_N9": (F.box(2, hi=(3.0, 1.0, 2.0), widths=[[0.5, 2.0], [1.0, 1.7], [0.6, 0.9]]), 9),
         "single_N1": (F.box(1, dirichlet=(0,) * 6), 1),
@@ -164,6 +165,56 @@ def test_every_tile_matches_oracle(name):
     finally:
         for pr, t in saved.items():
             p.op.set_tile(pr, **t)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("name", ["deformed3_N7", "reoriented_N7"])
+def test_matrix_core_operator(name, prec):
+    """The MFMA element operator (16-bit factors, N = 7; u and the weighted
+    derivatives rounded to 16 bits as well) against the FP64 oracle, for
+    several workgroup shapes, on FP32 and FP64 vectors."""
+    p = pair(name)
+    u = F.random_unique(p.op.n_unique, 4)
+    ref = p.ora.apply(u)
+    emul = relerr(oracle.Problem(**{**p.ora.__dict__, "G": oracle.quantize_G(p.ora.G, prec)})
+                  .apply(u), ref)
+    u32, u64 = p.to_dev(u, torch.float32), p.to_dev(u)
+    saved = p.op.get_tile(prec)
+    bound = {"fp16": 8 * emul + 2e-3, "bf16": 8 * emul + 3e-2}[prec]
+    try:
+        for epb in (1, 2, 4):
+            p.op.set_tile(prec, elements_per_block=epb, grid_cap=0, xcd_remap=0, pipeline=2)
+            y32 = p.from_dev(p.op.ax(u32, precision=prec))
+            err = relerr(y32, ref)
+            print("mfma", name, prec, epb, "err %.3g emul %.3g" % (err, emul))
+            assert err < bound, (epb, err, emul)
+            y64 = p.from_dev(p.op.ax(u64, precision=prec, fp64_vectors=True))
+            assert relerr(y64, y32) < 2e-6
+    finally:
+        p.op.set_tile(prec, **saved)
+
+
+def test_matrix_core_tile_rules():
+    p = pair("cube4_N5")
+    with pytest.raises(sem.SemError):
+        p.op.set_tile("fp16", elements_per_block=1, pipeline=2)      # N = 5
+    q = pair("deformed3_N7")
+    with pytest.raises(sem.SemError):
+        q.op.set_tile("fp32", elements_per_block=1, pipeline=2)      # FP32 factors
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_matrix_core_refined_solve(prec):
+    p = pair("deformed3_N7")
+    b = p.ora.rhs_unique(F.random_unique(p.op.n_unique, 13))
+    saved = p.op.get_tile(prec)
+    try:
+        p.op.set_tile(prec, elements_per_block=2, grid_cap=0, xcd_remap=0, pipeline=2)
+        x, info = p.op.solve(p.to_dev(b), tol=1e-10, precision=prec)
+        assert info["status"] == "SEM_OK", info
+        assert p.ora.true_residual(p.from_dev(x), b) <= 1.01e-10, info
+    finally:
+        p.op.set_tile(prec, **saved)
 
 
 @pytest.mark.parametrize("pipeline", [0, 1])
