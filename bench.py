@@ -76,6 +76,47 @@ def recorded_traffic(workload, kernel, tile):
     return None, None
 
 
+def kernel_ms(op, prec, u, y, nb, stream, reps=20):
+    """Mean per-launch time of the fused operator, each launch after the
+    clearing of the summed block (as in the CG loop)."""
+    import torch
+    ev = []
+    for r in range(reps + 3):
+        y[:nb].zero_()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        op.ax(u, y, precision=prec, y_zeroed=True)
+        b.record(stream)
+        if r >= 3:
+            ev.append((a, b))
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+
+def mfma_compare(op, u32, nb, stream):
+    """16-bit operator on matrix cores (tile pipeline 2) against the tuned
+    SIMT tile: kernel times and algorithmic GB/s (1.21 GB per application at
+    48^3, N = 7)."""
+    import torch
+    y = torch.zeros_like(u32)
+    B = op.n_local * (6 * 2 + 4) + 2 * 4 * op.n_unique                 # FP32 vectors
+    out = {}
+    for prec in ("fp16", "bf16"):
+        tuned = op.get_tile(prec)
+        simt = kernel_ms(op, prec, u32, y, nb, stream)
+        best = None
+        for epb in (1, 2, 4):
+            op.set_tile(prec, elements_per_block=epb, grid_cap=0, xcd_remap=0, pipeline=2)
+            ms = kernel_ms(op, prec, u32, y, nb, stream)
+            if best is None or ms < best[1]:
+                best = (epb, ms)
+        op.set_tile(prec, **tuned)
+        out[prec] = {"simt_ms": simt, "mfma_ms": best[1], "mfma_elements_per_block": best[0],
+                     "simt_GBps": B / simt / 1e6, "mfma_GBps": B / best[1] / 1e6}
+        log("mfma", prec, out[prec])
+    return out
+
+
 def cpu_baseline(K=24, N=7, min_seconds=10.0):
     import fixtures as F
     import oracle
@@ -320,6 +361,8 @@ def main():
                 best, table = op.autotune(prec, reps=10, cache_path=args.tune_cache)
                 log("autotune", prec, best, "%.4f ms" % min(ms for _, ms in table))
                 tune[prec] = {"best": best, "best_ms": min(ms for _, ms in table)}
+            if N == 7:
+                result["mfma_16bit"] = mfma_compare(op, u.float(), nb, stream)
         solves = {}
         x64 = None
         for prec in args.solve_precisions.split(","):

@@ -208,7 +208,12 @@ typedef struct {
     int xcd_remap;                /* 1: contiguous element ranges per XCD    */
     int pipeline;                 /* 0: each element requests all planes of
                                      its factors at once; 1: two planes in
-                                     flight (fewer registers, more waves)    */
+                                     flight (fewer registers, more waves);
+                                     2: matrix-core (MFMA) element operator,
+                                     FP16/BF16 factors at N = 7 only; it also
+                                     rounds u (scaled per element) and the
+                                     weighted derivatives to 16 bits, so it
+                                     is never chosen by sem_autotune         */
 } sem_tile;
 
 typedef struct {

@@ -822,7 +822,10 @@ extern "C" sem_status sem_autotune(sem_ctx c, sem_precision prec, int reps, cons
     double best_ms = INFINITY;
     AxTile best_t = saved;
     int nres = 0;
-    for (int pipe = 0; pipe < 3; ++pipe)
+    // the matrix-core variant (pipeline 2) also rounds u and the weighted
+    // derivatives to 16 bits; that rounding is not linear in u and costs the
+    // refined solves their convergence, so it is only used when set explicitly
+    for (int pipe = 0; pipe < 2; ++pipe)
     for (int epb : epbs)
         for (int cap : caps)
             for (int xcd = 0; xcd < 2; ++xcd) {
