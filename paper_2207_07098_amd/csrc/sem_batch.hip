@@ -79,6 +79,14 @@ static void fill_launch(sem_batch b) {
     bl.threads = b->threads;
     const int ncu = b->ctxs[0]->num_cus;
     bl.ax_grid = b->grid_cap > 0 ? std::min(b->grid_cap, bl.n_ax) : bl.n_ax;
+    bl.grid_cap = b->grid_cap;
+    // items are ordered by decreasing order: one contiguous range per order
+    for (int n1 = 0; n1 <= sem::kMaxN1; ++n1) bl.ax_lo[n1] = bl.ax_hi[n1] = 0;
+    for (int w = 0; w < bl.n_ax; ++w) {
+        const int n1 = b->ctxs[b->ax[w].prob]->n1;
+        if (bl.ax_lo[n1] == bl.ax_hi[n1]) bl.ax_lo[n1] = w;
+        bl.ax_hi[n1] = w + 1;
+    }
     bl.vec_grid = std::min(bl.n_vec, 8 * ncu);
     bl.max_n1 = b->max_n1;
 }

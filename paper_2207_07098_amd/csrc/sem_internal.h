@@ -189,6 +189,8 @@ struct BatchLaunch {             // host-side description of one batch launch
     int n_ax, n_vec, nprob;
     double *ax_partials, *vec_partials;
     int threads, ax_grid, vec_grid, max_n1;
+    int grid_cap;
+    int ax_lo[sem::kMaxN1 + 1], ax_hi[sem::kMaxN1 + 1];   // operator items of each order
 };
 constexpr int kBatchMaxN1 = 10;
 size_t batch_lds_bytes(int threads, int max_n1);

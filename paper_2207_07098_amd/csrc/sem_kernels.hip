@@ -1337,32 +1337,25 @@ __device__ __forceinline__ void batch_group(const BatchArgs &A, const BatchProb 
                                         dot);
 }
 
-__global__ void __attribute__((amdgpu_flat_work_group_size(1, 256), amdgpu_waves_per_eu(1)))
-k_ax_batch(BatchArgs A) {
+// Operator pass over the work items [lo, hi) of the problems of one order:
+// one launch per order present, so that each order gets its own register
+// budget (a single kernel for all orders would run every order at the
+// occupancy of the largest).
+template <int N1>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, 256),
+                               amdgpu_waves_per_eu(AxOcc<N1, double>::value)))
+k_ax_batch(BatchArgs A, int lo, int hi) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double *lds = reinterpret_cast<double *>(smem_raw);
-    for (int w = blockIdx.x; w < A.n_ax; w += gridDim.x) {
+    for (int w = lo + blockIdx.x; w < hi; w += gridDim.x) {
         const BatchAxItem it = A.ax_items[w];
         const BatchProb &pb = A.probs[it.prob];
         double dot = 0.0;
-        if (!pb.st->done) {
-            switch (pb.n1) {
-                case 2: batch_group<2>(A, pb, it.group, lds, dot); break;
-                case 3: batch_group<3>(A, pb, it.group, lds, dot); break;
-                case 4: batch_group<4>(A, pb, it.group, lds, dot); break;
-                case 5: batch_group<5>(A, pb, it.group, lds, dot); break;
-                case 6: batch_group<6>(A, pb, it.group, lds, dot); break;
-                case 7: batch_group<7>(A, pb, it.group, lds, dot); break;
-                case 8: batch_group<8>(A, pb, it.group, lds, dot); break;
-                case 9: batch_group<9>(A, pb, it.group, lds, dot); break;
-                case 10: batch_group<10>(A, pb, it.group, lds, dot); break;
-                default: break;
-            }
-        }
+        if (!pb.st->done) batch_group<N1>(A, pb, it.group, lds, dot);
         __shared__ double red[16];
         const double sdot = block_sum(dot, red);
         if (threadIdx.x == 0) A.ax_partials[(size_t)w * 4] = sdot;
-        __syncthreads();                 // LDS layout changes with the next item's order
+        __syncthreads();                 // LDS is rewritten by the next item
     }
 }
 
@@ -1745,20 +1738,40 @@ static BatchArgs batch_args(const BatchLaunch &bl) {
     return A;
 }
 
+static size_t batch_lds_bytes_n1(int threads, int n1) {
+    const int C = n1 * n1;
+    const int nslots = (threads + C - 1) / C;
+    return ((size_t)nslots * 3 * n1 * n1 * (n1 + 1) + C) * sizeof(double);
+}
+
 size_t batch_lds_bytes(int threads, int max_n1) {
     size_t best = 0;
-    for (int n1 = 2; n1 <= max_n1; ++n1) {
-        const int C = n1 * n1;
-        const int nslots = (threads + C - 1) / C;
-        best = std::max(best, ((size_t)nslots * 3 * n1 * n1 * (n1 + 1) + C) * sizeof(double));
-    }
+    for (int n1 = 2; n1 <= max_n1; ++n1) best = std::max(best, batch_lds_bytes_n1(threads, n1));
     return best;
+}
+
+static void launch_batch_operator(const BatchLaunch &bl, const BatchArgs &A, hipStream_t s) {
+    for (int n1 = kBatchMaxN1; n1 >= 2; --n1) {
+        const int lo = bl.ax_lo[n1], hi = bl.ax_hi[n1];
+        if (hi <= lo) continue;
+        const int grid = bl.grid_cap > 0 ? std::min(bl.grid_cap, hi - lo) : hi - lo;
+        const size_t lds = batch_lds_bytes_n1(bl.threads, n1);
+        switch (n1) {
+#define SEM_BAXN(n)                                                                        \
+    case n:                                                                                \
+        hipLaunchKernelGGL(k_ax_batch<n>, dim3(grid), dim3(bl.threads), lds, s, A, lo, hi); \
+        break;
+            SEM_BAXN(2) SEM_BAXN(3) SEM_BAXN(4) SEM_BAXN(5) SEM_BAXN(6) SEM_BAXN(7) SEM_BAXN(8)
+            SEM_BAXN(9) SEM_BAXN(10)
+#undef SEM_BAXN
+            default: break;
+        }
+    }
 }
 
 hipError_t launch_batch_iteration(const BatchLaunch &bl, hipStream_t s) {
     BatchArgs A = batch_args(bl);
-    const size_t lds = batch_lds_bytes(bl.threads, bl.max_n1);
-    hipLaunchKernelGGL(k_ax_batch, dim3(bl.ax_grid), dim3(bl.threads), lds, s, A);
+    launch_batch_operator(bl, A, s);
     hipLaunchKernelGGL(k_finish_batch, dim3(bl.nprob), dim3(256), 0, s, A, (int)FIN_AX);
     hipLaunchKernelGGL(k_vec_batch, dim3(bl.vec_grid), dim3(256), 0, s, A, 1);
     hipLaunchKernelGGL(k_finish_batch, dim3(bl.nprob), dim3(256), 0, s, A, (int)FIN_UPDATE);
@@ -1775,8 +1788,7 @@ hipError_t launch_batch_begin(const BatchLaunch &bl, hipStream_t s) {
 
 hipError_t launch_batch_ax_only(const BatchLaunch &bl, hipStream_t s) {
     BatchArgs A = batch_args(bl);
-    const size_t lds = batch_lds_bytes(bl.threads, bl.max_n1);
-    hipLaunchKernelGGL(k_ax_batch, dim3(bl.ax_grid), dim3(bl.threads), lds, s, A);
+    launch_batch_operator(bl, A, s);
     return hipGetLastError();
 }
 
