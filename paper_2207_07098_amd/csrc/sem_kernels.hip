@@ -1316,6 +1316,11 @@ struct BatchArgs {
     double *vec_partials;    // [n_vec][4]
 };
 
+// factor planes in flight in the batched operator: a ring of two for the
+// largest orders keeps them at two waves per SIMD
+template <int N1>
+constexpr int kBatchPF = N1 >= 9 ? 2 : N1;
+
 template <int N1>
 __device__ __forceinline__ void batch_group(const BatchArgs &A, const BatchProb &pb,
                                             int64_t group, double *lds, double &dot) {
@@ -1333,8 +1338,8 @@ __device__ __forceinline__ void batch_group(const BatchArgs &A, const BatchProb 
     int32_t bm[N1];
     load_map<N1>(pb.bmap, L, ec, bm);
     __syncthreads();
-    ax_element<N1, double, MODE_ATOMIC>(M, pb.D, pb.DT, Dl, L, S0, ec, active, -1, bm, true,
-                                        dot);
+    ax_element<N1, double, MODE_ATOMIC, double, kBatchPF<N1>>(M, pb.D, pb.DT, Dl, L, S0, ec, active,
+                                                              -1, bm, true, dot);
 }
 
 // Operator pass over the work items [lo, hi) of the problems of one order:
@@ -1343,7 +1348,7 @@ __device__ __forceinline__ void batch_group(const BatchArgs &A, const BatchProb 
 // occupancy of the largest).
 template <int N1>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, 256),
-                               amdgpu_waves_per_eu(AxOcc<N1, double>::value)))
+                               amdgpu_waves_per_eu(AxOcc<N1, double, kBatchPF<N1>>::value)))
 k_ax_batch(BatchArgs A, int lo, int hi) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double *lds = reinterpret_cast<double *>(smem_raw);
