@@ -189,6 +189,30 @@ def bench_batch(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_operator(args):
+    """Only the fused operator of one precision on the 48^3, N=7 box, with a
+    given tile: per-launch kernel times (each launch after the clearing of
+    the summed block)."""
+    import torch
+    import fixtures as F
+    import paper_2207_07098_amd as sem
+    w = F.periodic_box_deformed(args.K, args.N, tol=1e-10)
+    op = sem.Operator(w.mesh, args.N, precisions=("fp64", args.operator), solver=True)
+    if args.tile:
+        e, g, x, p = (int(v) for v in args.tile.split(":"))
+        op.set_tile(args.operator, elements_per_block=e, grid_cap=g, xcd_remap=x, pipeline=p)
+    else:
+        op.autotune(args.operator, reps=10, cache_path=args.tune_cache)
+    u = torch.from_numpy(F.random_unique(op.n_unique, 0)).cuda()
+    if args.operator != "fp64":
+        u = u.float()
+    y = torch.zeros_like(u)
+    ms = kernel_ms(op, args.operator, u, y, op.n_boundary, torch.cuda.current_stream(),
+                   reps=args.steps)
+    print(json.dumps({"operator": args.operator, "tile": op.get_tile(args.operator),
+                      "kernel_ms": ms, "steps": args.steps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +232,10 @@ def main():
                     help="box: 48^3 N=7 deformed box (default line); batch: 64 mixed problems; "
                          "ogrid: 256x64x32 O-grid around a cylinder")
     ap.add_argument("--nprob", type=int, default=64)
+    ap.add_argument("--operator", default=None, choices=["fp64", "fp32", "fp16", "bf16"],
+                    help="time only the fused operator in this precision (for counter runs)")
+    ap.add_argument("--tile", default=None,
+                    help="with --operator: elements_per_block:grid_cap:xcd_remap:pipeline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of 1 GiB (for counter scaling) and exit")
     args = ap.parse_args()
@@ -240,6 +268,8 @@ def main():
         return
     if args.workload == "batch":
         return bench_batch(args)
+    if args.operator:
+        return bench_operator(args)
     N, K = args.N, args.K
     if args.workload == "ogrid":
         w = F.cylinder_ogrid(N=N)
