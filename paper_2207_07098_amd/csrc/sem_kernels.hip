@@ -112,8 +112,9 @@ __device__ double block_sum(double v, double *red) {
     return s;
 }
 
-// Per-block partial sums of up to 4 values, written with plain stores to
-// partials[blockIdx][0..NV); the grid-wide sum is formed by k_finish in a
+// Per-block partial sums of NV (1..3) values, written with plain stores to
+// partials[blockIdx * NV + 0..NV) (packed: the finishing kernel reads
+// NV * 8 bytes per block); the grid-wide sum is formed by k_finish in a
 // fixed order after the kernel ends (the kernel boundary orders the
 // stores, so no device-scope fence is needed inside the streaming kernels).
 template <int NV>
@@ -124,7 +125,41 @@ __device__ void block_partial(const double (&v)[NV], double *partials) {
     for (int a = 0; a < NV; ++a) s[a] = block_sum(v[a], red);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int a = 0; a < NV; ++a) partials[(size_t)blockIdx.x * 4 + a] = s[a];
+        for (int a = 0; a < NV; ++a) partials[(size_t)blockIdx.x * NV + a] = s[a];
+    }
+}
+
+// Sum of the packed partials of nblocks blocks (NV values each) by one
+// workgroup: UF independent chains per thread keep that many loads in
+// flight; the order is fixed for a given nblocks.
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double *__restrict__ partials, int nblocks,
+                                             double (&acc)[3]) {
+    constexpr int UF = 8;
+    double accu[UF][NV] = {};
+    int q = threadIdx.x;
+    for (; q + (UF - 1) * (int)blockDim.x < nblocks; q += UF * blockDim.x) {
+        double v[UF][NV];
+#pragma unroll
+        for (int c = 0; c < UF; ++c)
+#pragma unroll
+            for (int a = 0; a < NV; ++a) v[c][a] = partials[(size_t)(q + c * blockDim.x) * NV + a];
+#pragma unroll
+        for (int c = 0; c < UF; ++c)
+#pragma unroll
+            for (int a = 0; a < NV; ++a) accu[c][a] += v[c][a];
+    }
+    for (; q < nblocks; q += blockDim.x)
+#pragma unroll
+        for (int a = 0; a < NV; ++a) accu[0][a] += partials[(size_t)q * NV + a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double t = 0.0;
+        if (a < NV) {
+#pragma unroll
+            for (int c = 0; c < UF; ++c) t += accu[c][a < NV ? a : 0];
+        }
+        acc[a] = t;
     }
 }
 
@@ -138,29 +173,10 @@ __global__ void __launch_bounds__(1024) k_finish(int site, const double *__restr
                                                  int nblocks, CgState *st) {
     if ((site == FIN_AX || site == FIN_UPDATE) && st->done) return;
     __shared__ double red[16];
-    // four independent chains per thread keep several loads in flight; the
-    // summation order is fixed for a given nblocks
-    double acc4[4][3] = {};
-    const d4v *P4 = reinterpret_cast<const d4v *>(partials);
-    int q = threadIdx.x;
-    for (; q + 3 * (int)blockDim.x < nblocks; q += 4 * blockDim.x) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const d4v v = P4[q + c * blockDim.x];
-            acc4[c][0] += v.x;
-            acc4[c][1] += v.y;
-            acc4[c][2] += v.z;
-        }
-    }
-    for (; q < nblocks; q += blockDim.x) {
-        const d4v v = P4[q];
-        acc4[0][0] += v.x;
-        acc4[0][1] += v.y;
-        acc4[0][2] += v.z;
-    }
     double acc[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) acc[a] = (acc4[0][a] + acc4[1][a]) + (acc4[2][a] + acc4[3][a]);
+    if (site == FIN_AX) sum_partials<1>(partials, nblocks, acc);
+    else if (site == FIN_BEGIN) sum_partials<3>(partials, nblocks, acc);
+    else sum_partials<2>(partials, nblocks, acc);
     double out[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) out[a] = block_sum(acc[a], red);
