@@ -724,8 +724,7 @@ static bool tile_valid(sem_ctx c, int prec, const sem_tile &t) {
     if (t.pipeline == 2 && !(c->n1 == 8 && (prec == SEM_FP16_SCALED || prec == SEM_BF16_SCALED)))
         return false;
     const size_t sz = prec == SEM_FP64 ? 8 : 4;
-    const int threads = ((t.elements_per_block * C + 63) / 64) * 64;
-    const int nslots = (threads + C - 1) / C;
+    const int nslots = t.elements_per_block;        // one LDS slot per element
     // three LDS buffers per element slot plus D (the operator kernels' layout)
     const size_t lds = ((size_t)nslots * 3 * c->n1 * c->n1 * (c->n1 + 1) + C) * sz;
     return lds <= c->max_lds;

@@ -94,16 +94,22 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t n) {
     return x * q + (x < r ? x : r) + idx;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
+// Sum over the wave; `nl` lanes are present (the last wave of a workgroup
+// whose size is not a multiple of 64 is partial: absent lanes count as 0).
+__device__ __forceinline__ double wave_sum(double v, int nl = 64) {
+    const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off, 64);
+        v += ((lane ^ off) < nl) ? o : 0.0;
+    }
     return v;
 }
 
 // Fixed-order block sum; every thread gets the result.
 __device__ double block_sum(double v, double *red) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-    v = wave_sum(v);
+    v = wave_sum(v, min(64, (int)blockDim.x - wv * 64));
     __syncthreads();
     if (lane == 0) red[wv] = v;
     __syncthreads();
@@ -318,7 +324,7 @@ struct AxOcc {
             : (N1 <= 6 ? 4 : (N1 <= 9 ? 3 : (N1 <= 12 ? 2 : 1)));
     static constexpr int ring =
         F64 ? (N1 <= 3 ? 4 : (N1 <= 5 ? 3 : (N1 <= 10 ? 2 : 1)))
-            : (N1 <= 7 ? 4 : (N1 <= 11 ? 3 : 2));
+            : (N1 <= 7 ? 4 : (N1 <= 10 ? 3 : 2));
     static constexpr int value = PF >= N1 ? all_planes : ring;
 };
 
@@ -584,10 +590,11 @@ k_ax(AxParams<N1, GS> P) {
     CgState *st = P.st;
     if (st && st->done) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    // one LDS slot per element of the group (the workgroup has exactly
+    // epb * (N+1)^2 lanes; its last wave may be partial)
     const Lane<N1> L(threadIdx.x);
-    const int nslots = (blockDim.x + C - 1) / C;
     T *S0 = reinterpret_cast<T *>(smem_raw) + (size_t)L.slot * 3 * BUF;
-    T *Dl = reinterpret_cast<T *>(smem_raw) + (size_t)nslots * 3 * BUF;
+    T *Dl = reinterpret_cast<T *>(smem_raw) + (size_t)P.epb * 3 * BUF;
     fill_dl<N1, T>(Dl, P.D);
     AxMesh<GS> M{P.u, P.y, P.wb, P.G, P.gscale, P.bmap, P.E, P.n_bnd, P.in_local, P.out_mode};
     auto elem_of = [&](int64_t git, bool &act) {
@@ -821,8 +828,8 @@ hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const v
     constexpr int C = N1 * N1;
     constexpr size_t BUF = (size_t)N1 * N1 * (N1 + 1);
     int epb = std::max(1, std::min(t.epb, 256 / C));
-    const int threads = ((epb * C + 63) / 64) * 64;
-    const int nslots = (threads + C - 1) / C;      // padding lanes get a slot too
+    const int threads = epb * C;                   // exactly one slot per element
+    const int nslots = epb;
     // matrix-core variant: 16-bit factors, N = 7, atomic summation
     constexpr bool MFMA_OK = N1 == 8 && sizeof(GS) == 2;
     const bool mfma = MFMA_OK && t.pipeline == 2 && !in_local && out_mode == OUT_ATOMIC;
@@ -1342,9 +1349,8 @@ __device__ __forceinline__ void batch_group(const BatchArgs &A, const BatchProb 
                                             int64_t group, double *lds, double &dot) {
     constexpr int C = N1 * N1, BUF = N1 * N1 * (N1 + 1);
     const Lane<N1> L(threadIdx.x);
-    const int nslots = (blockDim.x + C - 1) / C;
     double *S0 = lds + (size_t)L.slot * 3 * BUF;
-    double *Dl = lds + (size_t)nslots * 3 * BUF;
+    double *Dl = lds + (size_t)pb.epb * 3 * BUF;
     fill_dl<N1, double>(Dl, pb.D);
     const int64_t e = group * pb.epb + L.slot;
     const bool active = L.slot < pb.epb && e < pb.E;
@@ -1761,7 +1767,7 @@ static BatchArgs batch_args(const BatchLaunch &bl) {
 
 static size_t batch_lds_bytes_n1(int threads, int n1) {
     const int C = n1 * n1;
-    const int nslots = (threads + C - 1) / C;
+    const int nslots = std::max(1, threads / C);    // the problems' elements per group
     return ((size_t)nslots * 3 * n1 * n1 * (n1 + 1) + C) * sizeof(double);
 }
 
@@ -1777,10 +1783,11 @@ static void launch_batch_operator(const BatchLaunch &bl, const BatchArgs &A, hip
         if (hi <= lo) continue;
         const int grid = bl.grid_cap > 0 ? std::min(bl.grid_cap, hi - lo) : hi - lo;
         const size_t lds = batch_lds_bytes_n1(bl.threads, n1);
+        const int threads = std::max(1, bl.threads / (n1 * n1)) * n1 * n1;   // epb slots
         switch (n1) {
-#define SEM_BAXN(n)                                                                        \
-    case n:                                                                                \
-        hipLaunchKernelGGL(k_ax_batch<n>, dim3(grid), dim3(bl.threads), lds, s, A, lo, hi); \
+#define SEM_BAXN(n)                                                                       \
+    case n:                                                                               \
+        hipLaunchKernelGGL(k_ax_batch<n>, dim3(grid), dim3(threads), lds, s, A, lo, hi);  \
         break;
             SEM_BAXN(2) SEM_BAXN(3) SEM_BAXN(4) SEM_BAXN(5) SEM_BAXN(6) SEM_BAXN(7) SEM_BAXN(8)
             SEM_BAXN(9) SEM_BAXN(10)

@@ -167,6 +167,30 @@ def test_every_tile_matches_oracle(name):
             p.op.set_tile(pr, **t)
 
 
+@pytest.mark.parametrize("N", [6, 8, 10, 11, 12, 13, 14, 15])
+def test_every_order_up_to_the_maximum(N):
+    """Orders the other meshes do not reach, up to the largest supported
+    (N = 15: one workgroup of 256 lanes per element): geometry, the element
+    operator, the assembled operator (atomic and fixed order) and a solve."""
+    m = F.box((2, 1, 1), hi=(2.0, 1.0, 1.0), deform=0.03, reorient_seed=N)
+    p = Pair(m, N, precisions=("fp64", "fp32"))
+    G, B, dinv = p.op.geometry()
+    assert relerr(G, p.ora.G) < TOL64
+    rng = np.random.default_rng(N)
+    uL = rng.uniform(-1, 1, (p.op.E, (N + 1) ** 3))
+    w = p.op.ax_local(p.local_to_dev(uL)).cpu().numpy().reshape(uL.shape)
+    assert relerr(w, oracle.ax_local(N, p.ora.G, uL)) < TOL64
+    u = F.random_unique(p.op.n_unique, N)
+    for det in (False, True):
+        y = p.from_dev(p.op.ax(p.to_dev(u), deterministic=det))
+        assert relerr(y, p.ora.apply(u)) < TOL64
+    y32 = p.from_dev(p.op.ax(p.to_dev(u, torch.float32), precision="fp32"))
+    assert relerr(y32, p.ora.apply(u)) < 1e-5
+    b = p.ora.rhs_unique(F.random_unique(p.op.n_unique, 100 + N))
+    x, info = p.op.solve(p.to_dev(b), tol=1e-10)
+    assert p.ora.true_residual(p.from_dev(x), b) <= 1.01e-10, info
+
+
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
 @pytest.mark.parametrize("name", ["deformed3_N7", "reoriented_N7"])
 def test_matrix_core_operator(name, prec):
