@@ -22,8 +22,10 @@
  *   sem_export_numbering() gives the canonical first-appearance numbering
  *   and the permutation between the two orders.
  *   Geometric factors: [E][6][n_p], components (11,22,33,12,13,23).
- *   Device pointers must be 256-byte aligned device memory of the current
- *   HIP device; host pointers are ordinary host memory.
+ *   Device pointers are device memory of the current HIP device: the
+ *   workspace 256-byte aligned, the vectors of sem_ax and the solves 16-byte
+ *   aligned (SEM_ERR_INVALID otherwise); host pointers are ordinary host
+ *   memory.
  *
  * Errors: every call returns a sem_status; nothing aborts or throws across
  * the ABI.  sem_last_error(ctx) (or NULL for errors without a context)
@@ -182,13 +184,13 @@ sem_status sem_scatter(sem_ctx ctx, const double *w_L, double *y,
 /* Assembled operator on unique vectors: y = M Q^T A_L Q M u (Eqs. (11)-(12)
  * with the mask), fused in one pass over the elements.  u and y are device
  * vectors of n_unique entries (solver order), double for SEM_FP64 or with
- * SEM_AX_FP64_VECTORS, float otherwise; u and y must not overlap.  With SEM_AX_DETERMINISTIC the
- * summation of element contributions runs in a fixed order (bit-identical
- * repeats); by default contributions to shared nodes are added with device
- * atomics into y, whose element-boundary block is cleared first unless
- * SEM_AX_Y_ZEROED is given.  SEM_AX_FP64_VECTORS with SEM_FP64 or with
- * SEM_AX_DETERMINISTIC returns SEM_ERR_INVALID.  Stream-ordered,
- * asynchronous. */
+ * SEM_AX_FP64_VECTORS, float otherwise; u and y must not overlap.  With
+ * SEM_AX_DETERMINISTIC the summation of element contributions runs in a
+ * fixed order (bit-identical repeats); by default contributions to shared
+ * nodes are added with device atomics into y, whose element-boundary block
+ * is cleared first unless SEM_AX_Y_ZEROED is given.  SEM_AX_FP64_VECTORS
+ * with SEM_FP64 or with SEM_AX_DETERMINISTIC returns SEM_ERR_INVALID.
+ * Stream-ordered, asynchronous. */
 sem_status sem_ax(sem_ctx ctx, const void *u, void *y, sem_precision prec,
                   unsigned flags, sem_stream stream);
 
@@ -201,7 +203,8 @@ sem_status sem_rhs(sem_ctx ctx, const double *f_L, const double *f,
 /* Launch shape of the element operator for one precision. */
 typedef struct {
     int elements_per_block;       /* elements per workgroup (one lane per
-                                     (i,j) column of an element)            */
+                                     (i,j) column of an element; the
+                                     workgroup has exactly that many lanes)  */
     int grid_cap;                 /* 0: one workgroup per element group;
                                      otherwise persistent workgroups, a
                                      multiple of 8                          */
@@ -226,8 +229,9 @@ sem_status sem_set_tile(sem_ctx ctx, sem_precision prec, const sem_tile *tile);
 
 /* Autotuner: times the fused assembled operator of precision `prec` for
  * every candidate tile (elements per workgroup, persistent grid size, XCD
- * remapping, factor pipelining) on this context's mesh with hipEvents on `stream`, keeps the
- * fastest for later calls and returns it.  Uses the solver work vectors as
+ * remapping, factor pipelining) on this context's mesh with hipEvents on
+ * `stream`, each launch after a clearing kernel as in the CG iteration,
+ * keeps the fastest for later calls and returns it.  Uses the solver work vectors as
  * scratch (needs opts.solver = 1); their contents are overwritten.
  * cache_path (may be NULL): a text file of earlier results keyed by
  * architecture, N, precision and element count; a hit skips the timing,
@@ -294,11 +298,13 @@ sem_status sem_cg_solve(sem_ctx ctx, const double *b, double *x,
  * Batched solve: many independent Poisson problems (meshes of different
  * sizes and orders N <= 9, each set up as its own context with geometry and
  * opts.solver = 1) solved together by Jacobi-PCG in FP64.  Every CG phase
- * of all problems is one persistent launch over a table of work items
- * (problem, element group) or (problem, node range); per-problem scalars and
- * convergence flags stay on the device and converged problems turn their
- * items into no-ops; the iteration is captured once in a hipGraph.  The
- * contexts must outlive the batch and their work vectors are used by it.
+ * of all problems is one launch over a table of work items (problem,
+ * element group) or (problem, node range) -- the operator phase one launch
+ * per polynomial order present, each compiled for its own register budget;
+ * per-problem scalars and convergence flags stay on the device and
+ * converged problems turn their items into no-ops; the iteration is
+ * captured once in a hipGraph.  The contexts must outlive the batch and
+ * their work vectors are used by it.
  * ------------------------------------------------------------------------- */
 typedef struct sem_batch_s *sem_batch;
 
@@ -309,9 +315,10 @@ const char *sem_batch_last_error(sem_batch batch);
 sem_status sem_batch_workspace_size(sem_batch batch, size_t *bytes);
 sem_status sem_batch_bind_workspace(sem_batch batch, void *dev_ptr, size_t bytes,
                                     sem_stream stream);
-/* Tile of the batched operator: elements_per_block carries the threads per
- * workgroup (a multiple of 64, at least the largest (N+1)^2; each problem
- * gets threads/(N+1)^2 elements per workgroup), grid_cap as for sem_tile. */
+/* Tile of the batched operator: elements_per_block carries a thread budget
+ * per workgroup (a multiple of 64, at least the largest (N+1)^2); a problem
+ * of order N gets threads/(N+1)^2 elements per workgroup and workgroups of
+ * exactly that many elements' lanes.  grid_cap as for sem_tile. */
 sem_status sem_batch_set_tile(sem_batch batch, const sem_tile *tile, sem_stream stream);
 /* Times every admissible batch tile (hipEvents) and keeps the fastest. */
 sem_status sem_batch_autotune(sem_batch batch, int reps, sem_tile *best, double *best_ms,
