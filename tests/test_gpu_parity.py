@@ -396,13 +396,21 @@ def test_full_size_sampled_parity(K):
     configuration: the fused operator at 4096 sampled unique nodes against
     the oracle evaluated on the elements around them."""
     w = F.periodic_box_deformed(K, 7)
-    op = sem.Operator(w.mesh, 7, precisions=("fp64",), solver=False)
+    op = sem.Operator(w.mesh, 7, precisions=("fp64",), solver=True)
     gid, pos, dmask, mult = op.numbering()
     u = F.random_unique(op.n_unique, 0)
     uv = np.empty_like(u)
     uv[pos] = u
-    y = op.ax(torch.from_numpy(uv).cuda()).cpu().numpy()[pos]
+    ud = torch.from_numpy(uv).cuda()
     rng = np.random.default_rng(K)
     nodes = np.unique(rng.integers(0, op.n_unique, 4096))
     ref = sampled_apply(w.mesh, 7, u, nodes, gid)
-    assert relerr(y[nodes], ref) < TOL64
+    best, _ = op.autotune("fp64", reps=3)          # the tile the benchmark would time
+    tiles = [best, dict(elements_per_block=2, grid_cap=0, xcd_remap=0, pipeline=0),
+             dict(elements_per_block=1, grid_cap=0, xcd_remap=0, pipeline=1),
+             dict(elements_per_block=4, grid_cap=1024, xcd_remap=1, pipeline=0)]
+    for t in tiles:
+        op.set_tile("fp64", **t)
+        for det in (False, True):
+            y = op.ax(ud, deterministic=det).cpu().numpy()[pos]
+            assert relerr(y[nodes], ref) < TOL64, (t, det)
