@@ -1152,13 +1152,13 @@ static sem_status solve_reliable(sem_ctx c, const double *b, double *x,
         info->outer_iterations += 1;
         if (!std::isfinite(rel)) return SEM_ERR_NAN;
         if (rel <= o.tol) return SEM_OK;
-        if (bad) return fallback();
+        if (bad) return fallback(rel);
         if (hi.status == 1 || info->iterations >= o.max_iter) return SEM_ERR_NOT_CONVERGED;
         if (hi.done) {
             // inner recurrence met the target but the true residual did not:
             // allow a few replacements, then finish in FP64
             stalls = rel > 0.5 * last_rel ? stalls + 1 : 0;
-            if (stalls >= 2 || info->outer_iterations >= o.max_outer) return fallback();
+            if (stalls >= 2 || info->outer_iterations >= o.max_outer) return fallback(rel);
         }
         last_rel = rel;
         SEM_HIP(c, launch_reliable_reset(c, r, (float *)lv.r, (float *)lv.x, st_in, s));
@@ -1196,10 +1196,14 @@ static sem_status solve_approx_op(sem_ctx c, const double *b, double *x,
     }
     double rmax = std::sqrt(h.rr), last_rel = rmax / std::sqrt(bb);
     int stalls = 0;
-    auto fallback = [&]() {
+    // FP64 CG from zero, unless the iterate is already close: after a stall
+    // its error tends to sit in the slowest (smallest-eigenvalue) modes, from
+    // which FP64 CG needs many more iterations than from zero
+    auto fallback = [&](double rel) {
         sem_solve_options o64 = o;
         o64.precision = SEM_FP64;
-        return solve_fp64(c, b, x, o64, info, s, o.max_iter, false);
+        const bool restart = !(rel < 1e-6);
+        return solve_fp64(c, b, x, o64, info, s, o.max_iter, restart);
     };
     for (;;) {
         CgState hc;
@@ -1217,11 +1221,11 @@ static sem_status solve_approx_op(sem_ctx c, const double *b, double *x,
         info->outer_iterations += 1;
         if (!std::isfinite(rel)) return SEM_ERR_NAN;
         if (rel <= o.tol) return SEM_OK;
-        if (bad) return fallback();
+        if (bad) return fallback(rel);
         if (hc.status == 1 || info->iterations >= o.max_iter) return SEM_ERR_NOT_CONVERGED;
         if (hc.done) {
             stalls = rel > 0.5 * last_rel ? stalls + 1 : 0;
-            if (stalls >= 2 || info->outer_iterations >= o.max_outer) return fallback();
+            if (stalls >= 2 || info->outer_iterations >= o.max_outer) return fallback(rel);
         }
         last_rel = rel;
         SEM_HIP(c, launch_rz_rr(c, r, st, s));

@@ -301,6 +301,23 @@ def test_solve_unit_cube_manufactured(precision):
         assert abs(info["iterations"] - oinfo["iterations"]) <= 0.25 * oinfo["iterations"] + 5
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_solve_deformed_box_16(precision):
+    """[0,2pi]^3, 16^3 deformed elements, N=7, f = 3 sin x sin y sin z, PCG to
+    1e-8: the true residual of the GPU solution evaluated by the oracle, and
+    the error against sin x sin y sin z at the GLL points."""
+    w = F.periodic_box_deformed(16, 7)
+    p = Pair(w.mesh, 7, precisions=("fp64", "fp32"))
+    xyz = p.ora.xyz
+    b = p.ora.rhs_local(w.f_local(xyz))
+    xc, info, true_rel = _solve_case(p, b, 1e-8, precision)
+    assert info["status"] == "SEM_OK", info
+    assert true_rel <= 1e-8 * 1.01, (true_rel, info)
+    ue = np.zeros(p.op.n_unique)
+    ue[p.gid.ravel()] = w.u_exact(xyz).ravel()
+    assert np.max(np.abs(xc - ue)) < 1e-7           # discretisation error at N=7, K=16
+
+
 @pytest.mark.parametrize("delta,v64", [(0.0, False), (0.1, False), (0.5, False), (0.1, True),
                                        (0.01, True)])
 @pytest.mark.parametrize("precision", ["fp32", "fp16", "bf16"])
