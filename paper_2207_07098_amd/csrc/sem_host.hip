@@ -1130,10 +1130,12 @@ static sem_status solve_reliable(sem_ctx c, const double *b, double *x,
     double rmax = std::sqrt(h.rr);
     double last_rel = rel;
     int stalls = 0;
-    auto fallback = [&]() {
+    // FP64 CG from zero, unless the iterate is already close (see
+    // solve_approx_op)
+    auto fallback = [&](double rel_now) {
         sem_solve_options o64 = o;
         o64.precision = SEM_FP64;
-        return solve_fp64(c, b, x, o64, info, s, o.max_iter, false);
+        return solve_fp64(c, b, x, o64, info, s, o.max_iter, !(rel_now < 1e-6));
     };
     for (;;) {
         CgState hi;
