@@ -144,7 +144,7 @@ extern "C" sem_status sem_batch_create(const sem_ctx *ctxs, int nprob, sem_batch
         pb.n_u = c->n_unique;
         pb.n1 = c->n1;
     }
-    b->threads = b->max_c > 128 ? 256 : 256;
+    b->threads = 256;                      // thread budget per workgroup (tunable)
     // capacities: one element per group is the largest possible table
     int64_t nax = 0, nvec = 0;
     for (int p = 0; p < nprob; ++p) {
