@@ -1399,8 +1399,8 @@ __global__ void __launch_bounds__(256) k_vec_batch(BatchArgs A, int mode) {
             double *x = pb.x, *r = pb.r, *p = pb.p, *wv = pb.w;
             const double *b = pb.b, *dinv = pb.dinv;
             const double alpha = pb.st->alpha, beta = pb.st->beta;
-            for (int64_t q = it.begin + threadIdx.x; q < it.end; q += blockDim.x) {
-                if (mode == 0) {
+            for (int64_t q = it.begin + threadIdx.x; mode == 0 && q < it.end; q += blockDim.x) {
+                {
                     const double bq = b[q], zq = dinv[q] * bq;
                     x[q] = 0.0;
                     r[q] = bq;
@@ -1409,15 +1409,48 @@ __global__ void __launch_bounds__(256) k_vec_batch(BatchArgs A, int mode) {
                     s0 += bq * zq;
                     s1 += bq * bq;
                     s2 += bq * bq;
-                } else if (mode == 1) {
+                }
+            }
+            if (mode == 1) {
+                // 16-byte streaming accesses over whole pairs (items start at
+                // even nodes), the odd last node of a problem separately
+                const int64_t ve = it.end >> 1;
+                for (int64_t v = (it.begin >> 1) + threadIdx.x; v < ve; v += blockDim.x) {
+                    d2v xv = vld(reinterpret_cast<const d2v *>(x) + v);
+                    d2v rv = vld(reinterpret_cast<const d2v *>(r) + v);
+                    const d2v pv = vld(reinterpret_cast<const d2v *>(p) + v);
+                    const d2v wq = vld(reinterpret_cast<const d2v *>(wv) + v);
+                    const d2v dv = vld(reinterpret_cast<const d2v *>(dinv) + v);
+                    xv += alpha * pv;
+                    rv -= alpha * wq;
+                    vst(xv, reinterpret_cast<d2v *>(x) + v);
+                    vst(rv, reinterpret_cast<d2v *>(r) + v);
+                    s0 += rv.x * rv.x + rv.y * rv.y;
+                    s1 += rv.x * (dv.x * rv.x) + rv.y * (dv.y * rv.y);
+                }
+                if ((it.end & 1) && threadIdx.x == 0) {
+                    const int64_t q = it.end - 1;
                     x[q] += alpha * p[q];
                     const double rq = r[q] - alpha * wv[q];
                     r[q] = rq;
                     s0 += rq * rq;
                     s1 += rq * (dinv[q] * rq);
-                } else {
+                }
+            } else if (mode == 2) {
+                const int64_t ve = it.end >> 1, nb = pb.n_bnd;
+                for (int64_t v = (it.begin >> 1) + threadIdx.x; v < ve; v += blockDim.x) {
+                    const d2v rv = vld(reinterpret_cast<const d2v *>(r) + v);
+                    const d2v dv = vld(reinterpret_cast<const d2v *>(dinv) + v);
+                    d2v pv = vld(reinterpret_cast<const d2v *>(p) + v);
+                    pv = dv * rv + beta * pv;
+                    vst(pv, reinterpret_cast<d2v *>(p) + v);
+                    if (2 * v + 1 < nb) vst(d2v{0.0, 0.0}, reinterpret_cast<d2v *>(wv) + v);
+                    else if (2 * v < nb) wv[2 * v] = 0.0;
+                }
+                if ((it.end & 1) && threadIdx.x == 0) {
+                    const int64_t q = it.end - 1;
                     p[q] = dinv[q] * r[q] + beta * p[q];
-                    if (q < pb.n_bnd) wv[q] = 0.0;
+                    if (q < nb) wv[q] = 0.0;
                 }
             }
         }
