@@ -275,7 +275,10 @@ typedef struct {
     sem_status status;
     int64_t    iterations;        /* CG iterations, all levels               */
     int        outer_iterations;  /* refinement steps (0 for plain PCG)      */
-    int        restarts;
+    int        restarts;          /* FP64 PCG restarts after a missed true-
+                                     residual check, plus search-direction
+                                     restarts of a reduced-precision PCG
+                                     whose recurrence stopped halving        */
     double     true_rel_residual; /* FP64 ||b - A x|| / ||b|| at exit        */
     double     rel_residual;      /* last recurrence residual estimate       */
     double     seconds;           /* wall time of the call                   */
@@ -288,7 +291,9 @@ void sem_default_solve_options(sem_solve_options *opts);
  * until convergence or failure; the only device-to-host traffic is one
  * status poll every check_every iterations.  Returns SEM_OK on convergence,
  * else SEM_ERR_NOT_CONVERGED / SEM_ERR_BREAKDOWN / SEM_ERR_NAN with *info
- * filled in either case.  Needs opts.solver = 1 at set-up and, for a
+ * filled in either case.  A reduced-precision solve finishes with FP64 PCG
+ * when its inner PCG breaks down or when two FP64 corrections in a row
+ * fail to halve the true residual.  Needs opts.solver = 1 at set-up and, for a
  * reduced-precision solve, that precision among opts.precisions. */
 sem_status sem_cg_solve(sem_ctx ctx, const double *b, double *x,
                         const sem_solve_options *opts, sem_solve_info *info,

@@ -1097,6 +1097,32 @@ static sem_status solve_refined(sem_ctx c, const double *b, double *x,
     }
 }
 
+// Stretches of the recurrence between residual replacements.  When the
+// recurrence residual has not halved for longer than twice the longest
+// earlier stretch (and kMin iterations), the PCG has lost the conjugacy
+// that keeping the search direction relies on (the operator's rounding
+// perturbs every product): the stretch ends with a replacement that also
+// restarts the direction from the preconditioned FP64 residual.  Slow but
+// steady convergence keeps halving and is left alone.
+struct Stretches {
+    static constexpr int64_t kMin = 200;
+    int64_t start = 0, longest = 0, last_gain = 0;
+    double mark;
+    explicit Stretches(double r0) : mark(r0) {}
+    bool stalled(int64_t it, double r) {
+        if (r < 0.5 * mark) {
+            mark = r;
+            last_gain = it;
+        }
+        return it - last_gain > std::max(kMin, 2 * longest);
+    }
+    void close(int64_t it, bool forced, double r) {
+        if (!forced) longest = std::max(longest, it - start);
+        start = last_gain = it;
+        mark = r;
+    }
+};
+
 // Refinement with reliable updates: the reduced-precision PCG runs without
 // restarts; whenever its recurrence residual has dropped by `delta` since
 // the last replacement (or it reports convergence), its iterate is added to
@@ -1130,6 +1156,8 @@ static sem_status solve_reliable(sem_ctx c, const double *b, double *x,
     double rmax = std::sqrt(h.rr);
     double last_rel = rel;
     int stalls = 0;
+    int64_t base = 0;       // iterations before the last direction restart
+    Stretches seg(rmax);
     // FP64 CG from zero, unless the iterate is already close (see
     // solve_approx_op)
     auto fallback = [&](double rel_now) {
@@ -1141,10 +1169,13 @@ static sem_status solve_reliable(sem_ctx c, const double *b, double *x,
         CgState hi;
         e = run_cg(c, lv, o, o.max_iter, &hi, s, true);
         if (e) return e;
-        info->iterations = hi.iter;
+        const int64_t it = base + hi.iter;
+        info->iterations = it;
         info->rel_residual = bb > 0 ? std::sqrt(hi.rr / bb) : 0.0;
         const bool bad = hi.status == 2 || hi.status == 3;
-        if (!(hi.done || std::sqrt(hi.rr) < o.reliable_delta * rmax || bad)) continue;
+        const bool reached = hi.done || std::sqrt(hi.rr) < o.reliable_delta * rmax;
+        const bool forced = !reached && !bad && seg.stalled(it, std::sqrt(hi.rr));
+        if (!(reached || bad || forced)) continue;
         // reliable update: x += x_in, FP64 residual
         if (!bad) SEM_HIP(c, launch_ir_update(c, x, (const float *)lv.x, nullptr, 0, s));
         e = residual64(c, b, x, y, r, nullptr, 1, o.deterministic, s, &h);
@@ -1156,17 +1187,28 @@ static sem_status solve_reliable(sem_ctx c, const double *b, double *x,
         if (rel <= o.tol) return SEM_OK;
         if (bad) return fallback(rel);
         if (hi.status == 1 || info->iterations >= o.max_iter) return SEM_ERR_NOT_CONVERGED;
-        if (hi.done) {
-            // inner recurrence met the target but the true residual did not:
-            // allow a few replacements, then finish in FP64
-            stalls = rel > 0.5 * last_rel ? stalls + 1 : 0;
-            if (stalls >= 2 || info->outer_iterations >= o.max_outer) return fallback(rel);
-        }
+        // the recurrence residual fell by delta (or met the target) but the
+        // true residual fell by less than half, twice in a row: the
+        // operator's rounding dominates, finish in FP64
+        stalls = rel > 0.5 * last_rel ? stalls + 1 : 0;
+        if (stalls >= 2 || (hi.done && info->outer_iterations >= o.max_outer))
+            return fallback(rel);
         last_rel = rel;
-        SEM_HIP(c, launch_reliable_reset(c, r, (float *)lv.r, (float *)lv.x, st_in, s));
-        // the p kernel is skipped in the iteration that reports convergence,
-        // so the boundary block of w may not have been cleared
-        SEM_HIP(c, launch_fill32((float *)lv.w, c->n_bnd, 0.0f, s));
+        seg.close(it, forced, std::sqrt(h.rr));
+        if (forced) {
+            // new inner PCG on the FP64 residual: x_in = 0, p = z
+            info->restarts += 1;
+            base = it;
+            init.tol2 = (o.tol * o.tol) * bb / h.rr;
+            init.max_iter = std::max<int64_t>(1, o.max_iter - it);
+            SEM_HIP(c, hipMemcpyAsync(st_in, &init, sizeof(init), hipMemcpyHostToDevice, s));
+            SEM_HIP(c, launch_cg_begin(c, 2, r, lv.x, lv.r, lv.p, lv.w, 1, st_in, s, 0));
+        } else {
+            SEM_HIP(c, launch_reliable_reset(c, r, (float *)lv.r, (float *)lv.x, st_in, s));
+            // the p kernel is skipped in the iteration that reports
+            // convergence, so the boundary block of w may not have been cleared
+            SEM_HIP(c, launch_fill32((float *)lv.w, c->n_bnd, 0.0f, s));
+        }
         rmax = std::sqrt(h.rr);
     }
 }
@@ -1198,6 +1240,8 @@ static sem_status solve_approx_op(sem_ctx c, const double *b, double *x,
     }
     double rmax = std::sqrt(h.rr), last_rel = rmax / std::sqrt(bb);
     int stalls = 0;
+    int64_t base = 0;       // iterations before the last direction restart
+    Stretches seg(rmax);
     // FP64 CG from zero, unless the iterate is already close: after a stall
     // its error tends to sit in the slowest (smallest-eigenvalue) modes, from
     // which FP64 CG needs many more iterations than from zero
@@ -1211,10 +1255,13 @@ static sem_status solve_approx_op(sem_ctx c, const double *b, double *x,
         CgState hc;
         sem_status e = run_cg(c, lv, o, o.max_iter, &hc, s, true);
         if (e) return e;
-        info->iterations = hc.iter;
+        const int64_t it = base + hc.iter;
+        info->iterations = it;
         info->rel_residual = std::sqrt(hc.rr / bb);
         const bool bad = hc.status == 2 || hc.status == 3;
-        if (!(hc.done || std::sqrt(hc.rr) < o.reliable_delta * rmax || bad)) continue;
+        const bool reached = hc.done || std::sqrt(hc.rr) < o.reliable_delta * rmax;
+        const bool forced = !reached && !bad && seg.stalled(it, std::sqrt(hc.rr));
+        if (!(reached || bad || forced)) continue;
         CgState hr;
         e = residual64(c, b, x, dptr<double>(c, L.z64), r, nullptr, 1, o.deterministic, s, &hr);
         if (e) return e;
@@ -1225,13 +1272,23 @@ static sem_status solve_approx_op(sem_ctx c, const double *b, double *x,
         if (rel <= o.tol) return SEM_OK;
         if (bad) return fallback(rel);
         if (hc.status == 1 || info->iterations >= o.max_iter) return SEM_ERR_NOT_CONVERGED;
-        if (hc.done) {
-            stalls = rel > 0.5 * last_rel ? stalls + 1 : 0;
-            if (stalls >= 2 || info->outer_iterations >= o.max_outer) return fallback(rel);
-        }
+        stalls = rel > 0.5 * last_rel ? stalls + 1 : 0;     // as in solve_reliable
+        if (stalls >= 2 || (hc.done && info->outer_iterations >= o.max_outer))
+            return fallback(rel);
         last_rel = rel;
-        SEM_HIP(c, launch_rz_rr(c, r, st, s));
-        SEM_HIP(c, launch_fill(w, c->n_bnd, 0.0, s));
+        seg.close(it, forced, std::sqrt(hr.rr));
+        if (forced) {
+            // restart from the current x: r = b - A x in FP64, p = z
+            info->restarts += 1;
+            base = it;
+            init.tol2 = o.tol * o.tol;
+            init.max_iter = std::max<int64_t>(1, o.max_iter - it);
+            SEM_HIP(c, hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, s));
+            SEM_HIP(c, launch_cg_begin(c, 0, b, x, r, lv.p, w, 0, st, s));
+        } else {
+            SEM_HIP(c, launch_rz_rr(c, r, st, s));
+            SEM_HIP(c, launch_fill(w, c->n_bnd, 0.0, s));
+        }
         rmax = std::sqrt(hr.rr);
     }
 }
