@@ -269,6 +269,13 @@ typedef struct {
                                      applications, with FP64 residual
                                      replacement every delta reduction
                                      (needs reliable_delta in (0,1))         */
+    int           stall_window;   /* reliable-update variants: when the
+                                     recurrence residual has not halved for
+                                     more than max(stall_window, twice the
+                                     longest earlier stretch between
+                                     replacements) iterations, the next
+                                     replacement also restarts the search
+                                     direction; 0 = never; default 200      */
 } sem_solve_options;
 
 typedef struct {

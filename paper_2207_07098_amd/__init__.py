@@ -71,7 +71,8 @@ class SolveOptions(ctypes.Structure):
                 ("max_outer", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("zero_guess", ctypes.c_int),
                 ("deterministic", ctypes.c_int), ("max_restart", ctypes.c_int),
-                ("reliable_delta", ctypes.c_double), ("fp64_vectors", ctypes.c_int)]
+                ("reliable_delta", ctypes.c_double), ("fp64_vectors", ctypes.c_int),
+                ("stall_window", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -329,7 +330,8 @@ class Operator:
               max_iter: int = 100000, inner_tol: Optional[float] = None,
               check_every: int = 50, use_graph: bool = True, deterministic: bool = False,
               max_outer: int = 50, max_restart: int = 3, raise_on_error: bool = True,
-              reliable_delta: Optional[float] = None, fp64_vectors: bool = False):
+              reliable_delta: Optional[float] = None, fp64_vectors: bool = False,
+              stall_window: Optional[int] = None):
         """Jacobi-PCG (fp64) or FP64 iterative refinement around a reduced-
         precision PCG.  Returns (x, info dict)."""
         o = SolveOptions()
@@ -347,6 +349,8 @@ class Operator:
         if reliable_delta is not None:
             o.reliable_delta = reliable_delta
         o.fp64_vectors = 1 if fp64_vectors else 0
+        if stall_window is not None:
+            o.stall_window = stall_window
         o.zero_guess = 1 if x is None else 0
         if x is None:
             x = self.vector()

@@ -897,6 +897,7 @@ extern "C" void sem_default_solve_options(sem_solve_options *o) {
     o->max_restart = 3;
     o->reliable_delta = 0.1;
     o->fp64_vectors = 0;
+    o->stall_window = 200;
 }
 
 namespace {
@@ -1025,7 +1026,11 @@ static sem_status solve_fp64(sem_ctx c, const double *b, double *x, const sem_so
         if (e) return e;
         info->iterations += h.iter;
         info->rel_residual = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
-        if (h.status != 0) { result = status_from_state(h); break; }
+        if (h.status != 0) {
+            result = status_from_state(h);
+            if (result == SEM_ERR_NAN) fail(c, result, "FP64 PCG met a non-finite value");
+            break;
+        }
         // true residual in FP64
         CgState hr;
         e = residual64(c, b, x, dptr<double>(c, L.w64), dptr<double>(c, L.z64), nullptr, 1,
@@ -1056,6 +1061,7 @@ static sem_status solve_refined(sem_ctx c, const double *b, double *x,
     CgState *st_in = dptr<CgState>(c, L.state) + 2;
     Level lv{2, (int)o.precision, c->ws + L.d32, r32, c->ws + L.p32, c->ws + L.w32};
     if (o.zero_guess) SEM_HIP(c, launch_fill(x, c->n_unique, 0.0, s));
+    double *xsave = dptr<double>(c, L.r64);   // x before the last correction
     double prev = INFINITY, prev2 = INFINITY;
     for (int outer = 0;; ++outer) {
         CgState h;
@@ -1064,7 +1070,15 @@ static sem_status solve_refined(sem_ctx c, const double *b, double *x,
         double rel = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
         info->true_rel_residual = rel;
         info->outer_iterations = outer;
-        if (!std::isfinite(rel)) return SEM_ERR_NAN;
+        if (!std::isfinite(rel)) {
+            if (outer == 0) return fail(c, SEM_ERR_NAN, "non-finite initial residual");
+            // a non-finite correction: back to the last finite x, finish in FP64
+            SEM_HIP(c, hipMemcpyAsync(x, xsave, sizeof(double) * c->n_unique,
+                                      hipMemcpyDeviceToDevice, s));
+            sem_solve_options o64 = o;
+            o64.precision = SEM_FP64;
+            return solve_fp64(c, b, x, o64, info, s, o.max_iter, !(prev < 1e-6));
+        }
         if (rel <= o.tol) return SEM_OK;
         // stagnation: less than a factor 2 over two refinement steps -> FP64 CG
         if (outer >= o.max_outer || info->iterations >= o.max_iter ||
@@ -1093,28 +1107,29 @@ static sem_status solve_refined(sem_ctx c, const double *b, double *x,
             o64.precision = SEM_FP64;
             return solve_fp64(c, b, x, o64, info, s, o.max_iter, false);
         }
+        SEM_HIP(c, hipMemcpyAsync(xsave, x, sizeof(double) * c->n_unique,
+                                  hipMemcpyDeviceToDevice, s));
         SEM_HIP(c, launch_ir_update(c, x, (const float *)lv.x, dptr<CgState>(c, L.state) + 1, 1, s));
     }
 }
 
 // Stretches of the recurrence between residual replacements.  When the
 // recurrence residual has not halved for longer than twice the longest
-// earlier stretch (and kMin iterations), the PCG has lost the conjugacy
+// earlier stretch (and the stall window), the PCG has lost the conjugacy
 // that keeping the search direction relies on (the operator's rounding
 // perturbs every product): the stretch ends with a replacement that also
 // restarts the direction from the preconditioned FP64 residual.  Slow but
-// steady convergence keeps halving and is left alone.
+// steady convergence keeps halving and is left alone.  Window 0: never.
 struct Stretches {
-    static constexpr int64_t kMin = 200;
-    int64_t start = 0, longest = 0, last_gain = 0;
+    int64_t window, start = 0, longest = 0, last_gain = 0;
     double mark;
-    explicit Stretches(double r0) : mark(r0) {}
+    Stretches(int64_t w, double r0) : window(w), mark(r0) {}
     bool stalled(int64_t it, double r) {
         if (r < 0.5 * mark) {
             mark = r;
             last_gain = it;
         }
-        return it - last_gain > std::max(kMin, 2 * longest);
+        return window > 0 && it - last_gain > std::max(window, 2 * longest);
     }
     void close(int64_t it, bool forced, double r) {
         if (!forced) longest = std::max(longest, it - start);
@@ -1145,8 +1160,9 @@ static sem_status solve_reliable(sem_ctx c, const double *b, double *x,
     const double bb = h.bb;
     double rel = bb > 0 ? std::sqrt(h.rr / bb) : 0.0;
     info->true_rel_residual = rel;
-    if (!std::isfinite(rel)) return SEM_ERR_NAN;
+    if (!std::isfinite(rel)) return fail(c, SEM_ERR_NAN, "non-finite initial residual");
     if (rel <= o.tol) return SEM_OK;
+    double *xsave = dptr<double>(c, L.r64);   // x before the last reliable update
     CgState init;
     std::memset(&init, 0, sizeof(init));
     init.tol2 = (o.tol * o.tol) * bb / h.rr;     // absolute target (tol ||b||)^2 after begin
@@ -1157,7 +1173,7 @@ static sem_status solve_reliable(sem_ctx c, const double *b, double *x,
     double last_rel = rel;
     int stalls = 0;
     int64_t base = 0;       // iterations before the last direction restart
-    Stretches seg(rmax);
+    Stretches seg(o.stall_window, rmax);
     // FP64 CG from zero, unless the iterate is already close (see
     // solve_approx_op)
     auto fallback = [&](double rel_now) {
@@ -1177,13 +1193,23 @@ static sem_status solve_reliable(sem_ctx c, const double *b, double *x,
         const bool forced = !reached && !bad && seg.stalled(it, std::sqrt(hi.rr));
         if (!(reached || bad || forced)) continue;
         // reliable update: x += x_in, FP64 residual
-        if (!bad) SEM_HIP(c, launch_ir_update(c, x, (const float *)lv.x, nullptr, 0, s));
+        if (!bad) {
+            SEM_HIP(c, hipMemcpyAsync(xsave, x, sizeof(double) * c->n_unique,
+                                      hipMemcpyDeviceToDevice, s));
+            SEM_HIP(c, launch_ir_update(c, x, (const float *)lv.x, nullptr, 0, s));
+        }
         e = residual64(c, b, x, y, r, nullptr, 1, o.deterministic, s, &h);
         if (e) return e;
         rel = std::sqrt(h.rr / bb);
         info->true_rel_residual = rel;
         info->outer_iterations += 1;
-        if (!std::isfinite(rel)) return SEM_ERR_NAN;
+        if (!std::isfinite(rel)) {
+            if (bad) return fail(c, SEM_ERR_NAN, "non-finite FP64 residual");
+            // a non-finite inner iterate: back to the last finite x, finish in FP64
+            SEM_HIP(c, hipMemcpyAsync(x, xsave, sizeof(double) * c->n_unique,
+                                      hipMemcpyDeviceToDevice, s));
+            return fallback(last_rel);
+        }
         if (rel <= o.tol) return SEM_OK;
         if (bad) return fallback(rel);
         if (hi.status == 1 || info->iterations >= o.max_iter) return SEM_ERR_NOT_CONVERGED;
@@ -1241,7 +1267,7 @@ static sem_status solve_approx_op(sem_ctx c, const double *b, double *x,
     double rmax = std::sqrt(h.rr), last_rel = rmax / std::sqrt(bb);
     int stalls = 0;
     int64_t base = 0;       // iterations before the last direction restart
-    Stretches seg(rmax);
+    Stretches seg(o.stall_window, rmax);
     // FP64 CG from zero, unless the iterate is already close: after a stall
     // its error tends to sit in the slowest (smallest-eigenvalue) modes, from
     // which FP64 CG needs many more iterations than from zero
@@ -1268,7 +1294,7 @@ static sem_status solve_approx_op(sem_ctx c, const double *b, double *x,
         const double rel = std::sqrt(hr.rr / bb);
         info->true_rel_residual = rel;
         info->outer_iterations += 1;
-        if (!std::isfinite(rel)) return SEM_ERR_NAN;
+        if (!std::isfinite(rel)) return fail(c, SEM_ERR_NAN, "non-finite FP64 residual");
         if (rel <= o.tol) return SEM_OK;
         if (bad) return fallback(rel);
         if (hc.status == 1 || info->iterations >= o.max_iter) return SEM_ERR_NOT_CONVERGED;
@@ -1309,6 +1335,7 @@ extern "C" sem_status sem_cg_solve(sem_ctx c, const double *b, double *x,
     sem_solve_options o;
     if (opts) o = *opts; else sem_default_solve_options(&o);
     if (!(o.tol > 0) || o.max_iter < 1) return info->status = fail(c, SEM_ERR_INVALID, "bad tolerance or cap");
+    if (o.stall_window < 0) return info->status = fail(c, SEM_ERR_INVALID, "negative stall window");
     if (o.precision != SEM_FP64) {
         st = check_ready(c, o.precision);
         if (st) return info->status = st;

@@ -336,6 +336,33 @@ def test_refinement_variants(precision, delta, v64):
     assert relerr(xc, xo) < 1e-7
 
 
+@pytest.mark.parametrize("v64", [False, True])
+def test_direction_restarts_keep_the_answer(v64):
+    """BF16 factors on matrix cores make the reliable-update PCG lose
+    conjugacy on this mesh, so the default stall window restarts its search
+    direction (the count is printed); with window 0 the rule is off.  Both
+    runs meet the FP64 tolerance and the oracle's solution; a negative
+    window is rejected."""
+    p = pair("deformed3_N7")
+    b = p.ora.rhs_unique(F.random_unique(p.op.n_unique, 13))
+    xo, _ = p.ora.pcg(b, 1e-12)
+    saved = p.op.get_tile("bf16")
+    try:
+        p.op.set_tile("bf16", elements_per_block=2, grid_cap=0, xcd_remap=0, pipeline=2)
+        for window in (None, 0):
+            xc, info, true_rel = _solve_case(p, b, 1e-10, "bf16", fp64_vectors=v64,
+                                             stall_window=window, raise_on_error=False)
+            print("stall window", window, "v64", v64, info, flush=True)
+            assert info["status"] == "SEM_OK", (window, info)
+            assert true_rel <= 1.01e-10, (window, true_rel, info)
+            assert relerr(xc, xo) < 1e-7
+    finally:
+        p.op.set_tile("bf16", **saved)
+    x, info = p.op.solve(p.to_dev(b), tol=1e-10, precision="bf16", stall_window=-1,
+                         raise_on_error=False)
+    assert info["status"] == "SEM_ERR_INVALID"
+
+
 @pytest.mark.parametrize("graph", [True, False])
 def test_solve_graph_and_eager_agree(graph):
     p = pair("deformed3_N7")

@@ -43,6 +43,22 @@ def test_binding_flag_values_match_header():
         assert getattr(sem, name) == int(val), name
 
 
+def test_default_solve_options_through_the_binding():
+    """The library fills the binding's options struct field by field: every
+    documented default lands in its own field (a missing or misplaced field
+    in the binding shifts the later ones)."""
+    o = sem.SolveOptions()
+    sem.lib().sem_default_solve_options(ctypes.byref(o))
+    assert (o.tol, o.max_iter, o.precision, o.inner_tol) == (1e-10, 100000, 0, 1e-4)
+    assert (o.max_outer, o.check_every, o.use_graph, o.zero_guess) == (50, 50, 1, 1)
+    assert (o.deterministic, o.max_restart, o.reliable_delta) == (0, 3, 0.1)
+    assert (o.fp64_vectors, o.stall_window) == (0, 200)
+    src = open(os.path.join(ROOT, "include", "sem.h")).read()
+    body = src[src.index("typedef struct {\n    double        tol;"):src.index("} sem_solve_options;")]
+    names = re.findall(r"^\s+\w+\s+(\w+);", body, re.M)
+    assert names == [f[0] for f in sem.SolveOptions._fields_]
+
+
 def test_library_is_for_gfx950():
     out = subprocess.run(["/opt/rocm/bin/roc-obj-ls", sem.LIB_PATH], capture_output=True,
                          text=True)
