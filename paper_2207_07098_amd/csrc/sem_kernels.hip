@@ -325,7 +325,10 @@ struct AxOcc {
     static constexpr int ring =
         F64 ? (N1 <= 3 ? 4 : (N1 <= 5 ? 3 : (N1 <= 10 ? 2 : 1)))
             : (N1 <= 7 ? 4 : (N1 <= 10 ? 3 : 2));
-    static constexpr int value = PF >= N1 ? all_planes : ring;
+    // 16-bit factors at N = 7: four waves (a few spilled registers) beat
+    // three by 6% per application; FP32 factors lose 4% at four
+    static constexpr int value = (sizeof(GS) == 2 && N1 == 8) ? 4
+                                 : (PF >= N1 ? all_planes : ring);
 };
 
 // Per-workgroup geometry of the element loop: lane -> (slot, column i,j).
