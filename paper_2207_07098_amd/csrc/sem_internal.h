@@ -15,7 +15,7 @@ constexpr int kMaxN1 = 16;           // N <= 15
 constexpr int kMaxPartials = 1 << 17;  // per-block partial sums of one reduction (the
                                        // operator runs one workgroup per element group)
 #ifndef SEM_VEC_MAX_BLOCKS
-#define SEM_VEC_MAX_BLOCKS 32768
+#define SEM_VEC_MAX_BLOCKS 16384
 #endif
 constexpr int kVecMaxBlocks = SEM_VEC_MAX_BLOCKS;  // grid of the grid-stride vector kernels
 static_assert(kVecMaxBlocks <= kMaxPartials, "vector partials exceed the partials buffer");

@@ -31,7 +31,7 @@ namespace sem {
 
 namespace {
 
-constexpr int kVecBlock = 256;
+constexpr int kVecBlock = 512;
 
 struct bf16_t {
     uint16_t v;
