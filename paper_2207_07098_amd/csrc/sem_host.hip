@@ -1163,9 +1163,15 @@ static sem_status solve_reliable(sem_ctx c, const double *b, double *x,
     if (!std::isfinite(rel)) return fail(c, SEM_ERR_NAN, "non-finite initial residual");
     if (rel <= o.tol) return SEM_OK;
     double *xsave = dptr<double>(c, L.r64);   // x before the last reliable update
+    // The inner PCG pauses on the device after the iteration in which its
+    // recurrence residual has dropped by delta since the last replacement,
+    // so no iterations run past a replacement point between polls.
+    const double delta2 = o.reliable_delta * o.reliable_delta;
+    double pause2_host = 0.0;
     CgState init;
     std::memset(&init, 0, sizeof(init));
     init.tol2 = (o.tol * o.tol) * bb / h.rr;     // absolute target (tol ||b||)^2 after begin
+    init.pause2 = delta2 * h.rr;
     init.max_iter = o.max_iter;
     SEM_HIP(c, hipMemcpyAsync(st_in, &init, sizeof(init), hipMemcpyHostToDevice, s));
     SEM_HIP(c, launch_cg_begin(c, 2, r, lv.x, lv.r, lv.p, lv.w, 1, st_in, s, 0));
@@ -1221,11 +1227,16 @@ static sem_status solve_reliable(sem_ctx c, const double *b, double *x,
             return fallback(rel);
         last_rel = rel;
         seg.close(it, forced, std::sqrt(h.rr));
-        if (forced) {
+        // A recurrence that met the final target (done = 1, not a pause)
+        // has skipped its last direction update: keeping that stale
+        // direction would repeat a search already made, so the direction
+        // restarts then as well.
+        if (forced || hi.done == 1) {
             // new inner PCG on the FP64 residual: x_in = 0, p = z
-            info->restarts += 1;
+            info->restarts += forced ? 1 : 0;
             base = it;
             init.tol2 = (o.tol * o.tol) * bb / h.rr;
+            init.pause2 = delta2 * h.rr;
             init.max_iter = std::max<int64_t>(1, o.max_iter - it);
             SEM_HIP(c, hipMemcpyAsync(st_in, &init, sizeof(init), hipMemcpyHostToDevice, s));
             SEM_HIP(c, launch_cg_begin(c, 2, r, lv.x, lv.r, lv.p, lv.w, 1, st_in, s, 0));
@@ -1234,6 +1245,9 @@ static sem_status solve_reliable(sem_ctx c, const double *b, double *x,
             // the p kernel is skipped in the iteration that reports
             // convergence, so the boundary block of w may not have been cleared
             SEM_HIP(c, launch_fill32((float *)lv.w, c->n_bnd, 0.0f, s));
+            pause2_host = delta2 * h.rr;
+            SEM_HIP(c, hipMemcpyAsync(&st_in->pause2, &pause2_host, sizeof(double),
+                                      hipMemcpyHostToDevice, s));
         }
         rmax = std::sqrt(h.rr);
     }
@@ -1265,6 +1279,10 @@ static sem_status solve_approx_op(sem_ctx c, const double *b, double *x,
         return SEM_OK;
     }
     double rmax = std::sqrt(h.rr), last_rel = rmax / std::sqrt(bb);
+    // pause at each replacement point (see solve_reliable)
+    const double delta2 = o.reliable_delta * o.reliable_delta;
+    double pause2_host = delta2 * h.rr;
+    SEM_HIP(c, hipMemcpyAsync(&st->pause2, &pause2_host, sizeof(double), hipMemcpyHostToDevice, s));
     int stalls = 0;
     int64_t base = 0;       // iterations before the last direction restart
     Stretches seg(o.stall_window, rmax);
@@ -1303,17 +1321,21 @@ static sem_status solve_approx_op(sem_ctx c, const double *b, double *x,
             return fallback(rel);
         last_rel = rel;
         seg.close(it, forced, std::sqrt(hr.rr));
-        if (forced) {
+        if (forced || hc.done == 1) {  // a met target skipped the direction update
             // restart from the current x: r = b - A x in FP64, p = z
-            info->restarts += 1;
+            info->restarts += forced ? 1 : 0;
             base = it;
             init.tol2 = o.tol * o.tol;
+            init.pause2 = delta2 * hr.rr;
             init.max_iter = std::max<int64_t>(1, o.max_iter - it);
             SEM_HIP(c, hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, s));
             SEM_HIP(c, launch_cg_begin(c, 0, b, x, r, lv.p, w, 0, st, s));
         } else {
             SEM_HIP(c, launch_rz_rr(c, r, st, s));
             SEM_HIP(c, launch_fill(w, c->n_bnd, 0.0, s));
+            pause2_host = delta2 * hr.rr;
+            SEM_HIP(c, hipMemcpyAsync(&st->pause2, &pause2_host, sizeof(double),
+                                      hipMemcpyHostToDevice, s));
         }
         rmax = std::sqrt(hr.rr);
     }

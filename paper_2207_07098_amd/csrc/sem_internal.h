@@ -36,7 +36,11 @@ struct CgState {
     int done;         // 1: converged, failed or capped -> kernels are no-ops
     int status;       // 0 running/converged, 1 cap, 2 breakdown, 3 nan
     unsigned counter[4];  // last-block-done tickets
-    double pad[4];
+    double pause2;    // replacement point: r.r at or below it pauses the CG
+                      // after the iteration's direction update (0: never)
+    int pause;        // set with that update; the next iteration then stops
+    int pad_i;
+    double pad[2];
 };
 
 // Byte offsets of every array inside the caller's workspace.

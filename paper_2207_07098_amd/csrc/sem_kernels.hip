@@ -178,6 +178,10 @@ enum { FIN_AX = 0, FIN_BEGIN = 1, FIN_UPDATE = 2, FIN_RESID = 3, FIN_RESET = 4 }
 __global__ void __launch_bounds__(1024) k_finish(int site, const double *__restrict__ partials,
                                                  int nblocks, CgState *st) {
     if ((site == FIN_AX || site == FIN_UPDATE) && st->done) return;
+    if (site == FIN_AX && st->pause) {          // the operator skipped this iteration
+        if (threadIdx.x == 0) st->done = 2;
+        return;
+    }
     __shared__ double red[16];
     double acc[3];
     if (site == FIN_AX) sum_partials<1>(partials, nblocks, acc);
@@ -210,6 +214,7 @@ __global__ void __launch_bounds__(1024) k_finish(int site, const double *__restr
             st->iter = 0;
             st->status = 0;
             st->done = 0;
+            st->pause = 0;
             if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
                 st->status = 3;
                 st->done = 1;
@@ -231,6 +236,8 @@ __global__ void __launch_bounds__(1024) k_finish(int site, const double *__restr
             } else if (st->iter >= st->max_iter) {
                 st->status = 1;
                 st->done = 1;
+            } else if (out[0] <= st->pause2) {
+                st->pause = 1;                   // k_cg_p still runs
             }
             break;
         }
@@ -242,6 +249,7 @@ __global__ void __launch_bounds__(1024) k_finish(int site, const double *__restr
             st->rz = out[0];
             st->rr = out[1];
             st->done = 0;
+            st->pause = 0;
             st->status = 0;
             if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
                 st->status = 3;
@@ -591,7 +599,7 @@ k_ax(AxParams<N1, GS> P) {
     using T = typename GT<GS>::T;
     constexpr int C = N1 * N1, BUF = N1 * N1 * (N1 + 1);
     CgState *st = P.st;
-    if (st && st->done) return;
+    if (st && (st->done || st->pause)) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     // one LDS slot per element of the group (the workgroup has exactly
     // epb * (N+1)^2 lanes; its last wave may be partial)
@@ -701,7 +709,7 @@ __global__ void __launch_bounds__(256) k_ax_mfma(AxParams<8, GS> P) {
     using E = typename MF<GS>::E;
     using V = typename MF<GS>::V;
     CgState *st = P.st;
-    if (st && st->done) return;
+    if (st && (st->done || st->pause)) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const Lane<N1> L(threadIdx.x);
     const int lane = threadIdx.x & 63;
