@@ -337,6 +337,28 @@ def test_refinement_variants(precision, delta, v64):
 
 
 @pytest.mark.parametrize("v64", [False, True])
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_replacement_points_do_not_depend_on_polling(precision, v64):
+    """The reliable-update PCG pauses on the device where its recurrence
+    residual has dropped by delta, so how often the host polls does not
+    change the iteration: on a problem FP64 PCG solves in ~30 iterations,
+    polls every 50 or every 7 iterations give the same count, a small
+    multiple of the FP64 one."""
+    p = pair("cube4_N5")
+    w = F.unit_cube(4, 5)
+    b = p.ora.rhs_local(w.f_local(p.ora.xyz))
+    _, i64, _ = _solve_case(p, b, 1e-10, "fp64")
+    its = []
+    for every in (50, 7):
+        xc, info, true_rel = _solve_case(p, b, 1e-10, precision, fp64_vectors=v64,
+                                         inner_tol=1e-2, check_every=every)
+        assert info["status"] == "SEM_OK" and true_rel <= 1.01e-10, (every, info)
+        its.append(info["iterations"])
+    assert abs(its[0] - its[1]) <= 3, (its, i64)
+    assert its[0] <= 4 * i64["iterations"], (its, i64)
+
+
+@pytest.mark.parametrize("v64", [False, True])
 def test_direction_restarts_keep_the_answer(v64):
     """BF16 factors on matrix cores make the reliable-update PCG lose
     conjugacy on this mesh, so the default stall window restarts its search
