@@ -278,6 +278,19 @@ typedef struct {
                                      direction; 0 = never; default 200      */
 } sem_solve_options;
 
+/* Why a reduced-precision solve handed over to FP64 PCG (sem_solve_info). */
+typedef enum {
+    SEM_FALLBACK_NONE = 0,        /* no hand-over                             */
+    SEM_FALLBACK_STAGNATION = 1,  /* FP64 corrections stopped halving the
+                                     true residual                           */
+    SEM_FALLBACK_BREAKDOWN = 2,   /* reduced-precision PCG: p^T A p <= 0      */
+    SEM_FALLBACK_NONFINITE = 3,   /* reduced-precision PCG met NaN or Inf, or
+                                     an alpha or beta outside the FP32 range */
+    SEM_FALLBACK_RESTORED = 4,    /* a correction made x non-finite; the last
+                                     finite x was put back first             */
+    SEM_FALLBACK_OUTER_CAP = 5    /* max_outer refinement steps were used up  */
+} sem_fallback;
+
 typedef struct {
     sem_status status;
     int64_t    iterations;        /* CG iterations, all levels               */
@@ -289,6 +302,10 @@ typedef struct {
     double     true_rel_residual; /* FP64 ||b - A x|| / ||b|| at exit        */
     double     rel_residual;      /* last recurrence residual estimate       */
     double     seconds;           /* wall time of the call                   */
+    int        fallback;          /* sem_fallback: 0, or why the solve was
+                                     finished by FP64 PCG                    */
+    int64_t    fallback_iterations; /* FP64 PCG iterations after the hand-over
+                                     (included in iterations)                */
 } sem_solve_info;
 
 void sem_default_solve_options(sem_solve_options *opts);
@@ -299,8 +316,11 @@ void sem_default_solve_options(sem_solve_options *opts);
  * status poll every check_every iterations.  Returns SEM_OK on convergence,
  * else SEM_ERR_NOT_CONVERGED / SEM_ERR_BREAKDOWN / SEM_ERR_NAN with *info
  * filled in either case.  A reduced-precision solve finishes with FP64 PCG
- * when its inner PCG breaks down or when two FP64 corrections in a row
- * fail to halve the true residual.  Needs opts.solver = 1 at set-up and, for a
+ * when its inner PCG breaks down or meets a non-finite value, when a
+ * correction makes x non-finite (x is put back to its last finite value),
+ * when two FP64 corrections in a row fail to halve the true residual, or
+ * when max_outer steps are used up; info->fallback then names the cause
+ * and the return value is that of the FP64 PCG.  Needs opts.solver = 1 at set-up and, for a
  * reduced-precision solve, that precision among opts.precisions. */
 sem_status sem_cg_solve(sem_ctx ctx, const double *b, double *x,
                         const sem_solve_options *opts, sem_solve_info *info,

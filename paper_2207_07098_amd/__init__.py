@@ -75,11 +75,16 @@ class SolveOptions(ctypes.Structure):
                 ("stall_window", ctypes.c_int)]
 
 
+FALLBACK = {0: "none", 1: "stagnation", 2: "breakdown", 3: "nonfinite", 4: "restored",
+            5: "outer_cap"}
+
+
 class SolveInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int64),
                 ("outer_iterations", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("true_rel_residual", ctypes.c_double), ("rel_residual", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("fallback", ctypes.c_int),
+                ("fallback_iterations", ctypes.c_int64)]
 
     def as_dict(self):
         return {"status": STATUS.get(self.status, self.status),
@@ -88,7 +93,9 @@ class SolveInfo(ctypes.Structure):
                 "restarts": int(self.restarts),
                 "true_rel_residual": float(self.true_rel_residual),
                 "rel_residual": float(self.rel_residual),
-                "seconds": float(self.seconds)}
+                "seconds": float(self.seconds),
+                "fallback": FALLBACK.get(self.fallback, self.fallback),
+                "fallback_iterations": int(self.fallback_iterations)}
 
 
 EXPORTS = ["sem_gll", "sem_setup", "sem_free", "sem_last_error", "sem_query",

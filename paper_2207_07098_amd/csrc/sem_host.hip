@@ -9,9 +9,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <unordered_map>
 
 #include "sem_internal.h"
+#include "sem_numbering.h"
 
 using namespace sem;
 
@@ -104,234 +104,6 @@ static void derivative_matrix(int N, const double *xi, double *D) {
 }
 
 // ---------------------------------------------------------------------------
-// Numbering (Eq. (10): local copies of a physical node share one value).
-//
-// Each GLL point of an element is classified by how many of its indices sit
-// on the element boundary: 3 -> a vertex (keyed by its corner id), 2 -> an
-// edge (keyed by the sorted pair of end-vertex ids and the position measured
-// from the smaller id), 1 -> a face (keyed by the sorted four corner ids and
-// the position in a frame anchored at the smallest id, first axis towards
-// the smaller of its two neighbours), 0 -> an element-interior node.  These
-// keys depend only on vertex ids, so every element sharing an entity sees
-// the same key for the same point whatever its local orientation.  The
-// canonical id is the order of first appearance; the solver order puts the
-// element-boundary nodes first and the interior nodes after them,
-// element by element.
-// ---------------------------------------------------------------------------
-namespace {
-
-struct PairHash {
-    size_t operator()(const std::pair<int64_t, int64_t> &p) const {
-        uint64_t h = (uint64_t)p.first * 0x9E3779B97F4A7C15ull;
-        h ^= (uint64_t)p.second + 0x7F4A7C159E3779B9ull + (h << 6) + (h >> 2);
-        return (size_t)h;
-    }
-};
-struct Quad {
-    int64_t v[4];
-    bool operator==(const Quad &o) const {
-        return v[0] == o.v[0] && v[1] == o.v[1] && v[2] == o.v[2] && v[3] == o.v[3];
-    }
-};
-struct QuadHash {
-    size_t operator()(const Quad &q) const {
-        uint64_t h = 1469598103934665603ull;
-        for (int a = 0; a < 4; ++a) {
-            h ^= (uint64_t)q.v[a] + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
-            h *= 1099511628211ull;
-        }
-        return (size_t)h;
-    }
-};
-
-inline int ring_index(int i, int j, int N) {
-    // position of boundary column (i,j) among the 4N boundary columns, l order
-    if (j == 0) return i;
-    if (j == N) return N + 1 + 2 * (N - 1) + i;
-    return N + 1 + 2 * (j - 1) + (i == 0 ? 0 : 1);
-}
-
-}  // namespace
-
-static sem_status build_numbering(sem_ctx c, const sem_mesh *m) {
-    const int N = c->N, n1 = c->n1, np = c->np;
-    const int64_t E = c->E;
-    const int64_t *C = m->corner_ids;
-    const int ne = N - 1;                    // interior points per edge
-    const int nf = ne * ne;                  // interior points per face
-
-    std::unordered_map<std::pair<int64_t, int64_t>, int64_t, PairHash> edges;
-    std::unordered_map<Quad, int64_t, QuadHash> faces;
-    edges.reserve((size_t)E * 4);
-    faces.reserve((size_t)E * 4);
-    std::vector<int32_t> edge_gid, face_gid;
-    std::vector<int8_t> face_users;
-    std::vector<int32_t> vert_gid((size_t)m->num_vertices, -1);
-    c->gid_canon.assign((size_t)c->n_local, 0);
-    std::vector<uint8_t> is_interior;
-    std::vector<uint8_t> dir;
-    std::vector<int32_t> mult;
-    is_interior.reserve((size_t)c->n_local / 2);
-    dir.reserve((size_t)c->n_local / 2);
-    mult.reserve((size_t)c->n_local / 2);
-    int64_t next = 0;
-    auto fresh = [&](bool interior) -> int32_t {
-        is_interior.push_back(interior);
-        dir.push_back(0);
-        mult.push_back(0);
-        return (int32_t)next++;
-    };
-    if ((double)c->n_local >= 2147483647.0)
-        return fail(c, SEM_ERR_UNSUPPORTED, "more than 2^31-1 local points");
-
-    // register faces first to validate conformity (each face used <= 2 times)
-    static const int fcorner[6][4] = {{0, 2, 4, 6}, {1, 3, 5, 7}, {0, 1, 4, 5},
-                                      {2, 3, 6, 7}, {0, 1, 2, 3}, {4, 5, 6, 7}};
-    for (int64_t e = 0; e < E; ++e) {
-        const int64_t *v = C + e * 8;
-        for (int a = 0; a < 8; ++a) {
-            if (v[a] < 0 || v[a] >= m->num_vertices)
-                return fail(c, SEM_ERR_MESH, "element " + std::to_string(e) +
-                                                  ": corner id out of range");
-            for (int b = 0; b < a; ++b)
-                if (v[a] == v[b])
-                    return fail(c, SEM_ERR_MESH, "element " + std::to_string(e) +
-                                                      ": repeated corner id");
-        }
-        for (int f = 0; f < 6; ++f) {
-            Quad q{{v[fcorner[f][0]], v[fcorner[f][1]], v[fcorner[f][2]], v[fcorner[f][3]]}};
-            std::sort(q.v, q.v + 4);
-            auto it = faces.find(q);
-            if (it == faces.end()) {
-                faces.emplace(q, (int64_t)face_users.size());
-                face_users.push_back(1);
-            } else if (++face_users[it->second] > 2) {
-                return fail(c, SEM_ERR_MESH, "face of element " + std::to_string(e) +
-                                                  " shared by more than two elements");
-            }
-        }
-    }
-    face_gid.assign(face_users.size() * (size_t)nf, -1);
-
-    for (int64_t e = 0; e < E; ++e) {
-        const int64_t *v = C + e * 8;
-        const uint8_t *fb = m->face_bc ? m->face_bc + e * 6 : nullptr;
-        for (int k = 0; k < n1; ++k)
-            for (int j = 0; j < n1; ++j)
-                for (int i = 0; i < n1; ++i) {
-                    const int l = i + n1 * (j + n1 * k);
-                    const int ext[3] = {i == 0 || i == N, j == 0 || j == N, k == 0 || k == N};
-                    const int nx = ext[0] + ext[1] + ext[2];
-                    int32_t g;
-                    if (nx == 3) {
-                        int cidx = (i == N) + 2 * (j == N) + 4 * (k == N);
-                        int32_t &slot = vert_gid[(size_t)v[cidx]];
-                        if (slot < 0) slot = fresh(false);
-                        g = slot;
-                    } else if (nx == 2) {
-                        int d = !ext[0] ? 0 : (!ext[1] ? 1 : 2);
-                        int pos = d == 0 ? i : (d == 1 ? j : k);
-                        int c0 = (d == 0 ? 0 : (i == N)) + (d == 1 ? 0 : 2 * (j == N)) +
-                                 (d == 2 ? 0 : 4 * (k == N));
-                        int c1 = c0 + (1 << d);
-                        int64_t a = v[c0], b = v[c1];
-                        if (a > b) { std::swap(a, b); pos = N - pos; }
-                        auto key = std::make_pair(a, b);
-                        auto it = edges.find(key);
-                        int64_t eidx;
-                        if (it == edges.end()) {
-                            eidx = (int64_t)edges.size();
-                            edges.emplace(key, eidx);
-                            edge_gid.resize((size_t)(eidx + 1) * ne, -1);
-                        } else {
-                            eidx = it->second;
-                        }
-                        int32_t &slot = edge_gid[(size_t)eidx * ne + (pos - 1)];
-                        if (slot < 0) slot = fresh(false);
-                        g = slot;
-                    } else if (nx == 1) {
-                        int d = ext[0] ? 0 : (ext[1] ? 1 : 2);
-                        int side = d == 0 ? (i == N) : (d == 1 ? (j == N) : (k == N));
-                        int p = d == 0 ? j : i;            // first in-face axis
-                        int q = d == 2 ? j : k;            // second in-face axis
-                        auto corner = [&](int pa, int qa) -> int64_t {
-                            int cc;
-                            if (d == 0) cc = side + 2 * pa + 4 * qa;
-                            else if (d == 1) cc = 2 * side + pa + 4 * qa;
-                            else cc = 4 * side + pa + 2 * qa;
-                            return v[cc];
-                        };
-                        int64_t vv[2][2] = {{corner(0, 0), corner(0, 1)}, {corner(1, 0), corner(1, 1)}};
-                        int o1 = 0, o2 = 0;
-                        for (int pa = 0; pa < 2; ++pa)
-                            for (int qa = 0; qa < 2; ++qa)
-                                if (vv[pa][qa] < vv[o1][o2]) { o1 = pa; o2 = qa; }
-                        int a1 = o1 ? N - p : p, a2 = o2 ? N - q : q;
-                        int s, t;
-                        if (vv[1 - o1][o2] < vv[o1][1 - o2]) { s = a1; t = a2; } else { s = a2; t = a1; }
-                        Quad key{{vv[0][0], vv[0][1], vv[1][0], vv[1][1]}};
-                        std::sort(key.v, key.v + 4);
-                        int64_t fidx = faces.find(key)->second;
-                        int32_t &slot = face_gid[(size_t)fidx * nf + (s - 1) * ne + (t - 1)];
-                        if (slot < 0) slot = fresh(false);
-                        g = slot;
-                    } else {
-                        g = fresh(true);
-                    }
-                    c->gid_canon[(size_t)e * np + l] = g;
-                    mult[g] += 1;
-                    if (fb && ((i == 0 && fb[0]) || (i == N && fb[1]) || (j == 0 && fb[2]) ||
-                               (j == N && fb[3]) || (k == 0 && fb[4]) || (k == N && fb[5])))
-                        dir[g] = 1;
-                }
-    }
-    c->n_unique = next;
-    c->dir_canon = std::move(dir);
-    c->mult_canon = std::move(mult);
-    c->solver_pos.assign((size_t)next, 0);
-    int64_t pos = 0, ndir = 0;
-    for (int64_t g = 0; g < next; ++g)
-        if (!is_interior[g]) c->solver_pos[g] = (int32_t)pos++;
-    c->n_bnd = pos;
-    for (int64_t g = 0; g < next; ++g) {
-        if (is_interior[g]) c->solver_pos[g] = (int32_t)pos++;
-        ndir += c->dir_canon[g];
-    }
-    c->n_dir = ndir;
-
-    // compact boundary map and the node -> copies CSR
-    const int nb = c->nb;
-    c->bmap.assign((size_t)E * nb, 0);
-    c->bdir.assign((size_t)c->n_bnd, 0);
-    std::vector<int32_t> count((size_t)c->n_bnd + 1, 0);
-    for (int64_t e = 0; e < E; ++e) {
-        int b = 0;
-        for (int k = 0; k < n1; ++k)
-            for (int j = 0; j < n1; ++j)
-                for (int i = 0; i < n1; ++i) {
-                    bool bnd = k == 0 || k == N || i == 0 || i == N || j == 0 || j == N;
-                    if (!bnd) continue;
-                    int32_t g = c->gid_canon[(size_t)e * np + i + n1 * (j + n1 * k)];
-                    int32_t sp = c->solver_pos[g];
-                    uint8_t d = c->dir_canon[g];
-                    c->bmap[(size_t)e * nb + b] = d ? (int32_t)(sp | 0x80000000u) : sp;
-                    c->bdir[sp] = d;
-                    count[sp + 1] += 1;
-                    ++b;
-                }
-    }
-    c->csr_off.assign((size_t)c->n_bnd + 1, 0);
-    for (int64_t g = 0; g < c->n_bnd; ++g) c->csr_off[g + 1] = c->csr_off[g] + count[g + 1];
-    c->csr_idx.assign((size_t)E * nb, 0);
-    std::vector<int32_t> fill(c->csr_off.begin(), c->csr_off.end() - 1);
-    for (int64_t q = 0; q < E * nb; ++q) {
-        int32_t sp = c->bmap[q] & 0x7fffffff;
-        c->csr_idx[fill[sp]++] = (int32_t)q;
-    }
-    return SEM_OK;
-}
-
-// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" const char *sem_last_error(sem_ctx ctx) {
@@ -357,11 +129,26 @@ extern "C" sem_status sem_setup(const sem_mesh *mesh, int N, const sem_options *
     c->solver = opts ? opts->solver : 0;
     sem_gll(N, c->xi, c->rho);
     derivative_matrix(N, c->xi, c->D);
-    sem_status st = build_numbering(c, mesh);
-    if (st != SEM_OK) {
-        g_last_error = c->err;
-        delete c;
-        return st;
+    {
+        Numbering num;
+        std::string err;
+        const int code = build_numbering(N, c->E, mesh->corner_ids, mesh->face_bc,
+                                         mesh->num_vertices, num, err);
+        if (code != 0) {
+            delete c;
+            return fail(nullptr, (sem_status)code, err);
+        }
+        c->n_unique = num.n_unique;
+        c->n_bnd = num.n_bnd;
+        c->n_dir = num.n_dir;
+        c->gid_canon = std::move(num.gid_canon);
+        c->solver_pos = std::move(num.solver_pos);
+        c->dir_canon = std::move(num.dir_canon);
+        c->mult_canon = std::move(num.mult_canon);
+        c->bmap = std::move(num.bmap);
+        c->csr_off = std::move(num.csr_off);
+        c->csr_idx = std::move(num.csr_idx);
+        c->bdir = std::move(num.bdir);
     }
     if (mesh->vertex_xyz) {
         c->vertex_xyz.assign(mesh->vertex_xyz, mesh->vertex_xyz + 3 * mesh->num_vertices);
@@ -1050,6 +837,29 @@ static sem_status solve_fp64(sem_ctx c, const double *b, double *x, const sem_so
     return result;
 }
 
+// FP64 PCG finishing a reduced-precision solve; `why` (sem_fallback) and
+// the iterations of the FP64 part are reported in info.
+static sem_status finish_fp64(sem_ctx c, const double *b, double *x, const sem_solve_options &o,
+                              sem_solve_info *info, hipStream_t s, bool from_zero, int why) {
+    sem_solve_options o64 = o;
+    o64.precision = SEM_FP64;
+    info->fallback = why;
+    const int64_t before = info->iterations;
+    const sem_status st = solve_fp64(c, b, x, o64, info, s, o.max_iter, from_zero);
+    info->fallback_iterations = info->iterations - before;
+    return st;
+}
+
+// Fixed power-of-two scale 2^-e with 2^(e-1) < v <= 2^e (1 for v = 0): the
+// FP64 residual is multiplied by it before it is rounded to FP32, so that a
+// right-hand side of any magnitude lands in the FP32 range, exactly scaled.
+static double pow2_inverse(double v) {
+    if (!(v > 0.0) || !std::isfinite(v)) return 1.0;
+    int e = 0;
+    const double f = std::frexp(v, &e);     // v = f 2^e, f in [0.5, 1)
+    return std::ldexp(1.0, f == 0.5 ? 1 - e : -e);
+}
+
 static sem_status solve_refined(sem_ctx c, const double *b, double *x,
                                 const sem_solve_options &o, sem_solve_info *info,
                                 hipStream_t s) {
@@ -1075,17 +885,15 @@ static sem_status solve_refined(sem_ctx c, const double *b, double *x,
             // a non-finite correction: back to the last finite x, finish in FP64
             SEM_HIP(c, hipMemcpyAsync(x, xsave, sizeof(double) * c->n_unique,
                                       hipMemcpyDeviceToDevice, s));
-            sem_solve_options o64 = o;
-            o64.precision = SEM_FP64;
-            return solve_fp64(c, b, x, o64, info, s, o.max_iter, !(prev < 1e-6));
+            return finish_fp64(c, b, x, o, info, s, !(prev < 1e-6), SEM_FALLBACK_RESTORED);
         }
         if (rel <= o.tol) return SEM_OK;
         // stagnation: less than a factor 2 over two refinement steps -> FP64 CG
         if (outer >= o.max_outer || info->iterations >= o.max_iter ||
             (outer >= 2 && rel > 0.5 * prev2)) {
-            sem_solve_options o64 = o;
-            o64.precision = SEM_FP64;
-            return solve_fp64(c, b, x, o64, info, s, o.max_iter, false);
+            const int why = (outer >= 2 && rel > 0.5 * prev2) ? SEM_FALLBACK_STAGNATION
+                                                              : SEM_FALLBACK_OUTER_CAP;
+            return finish_fp64(c, b, x, o, info, s, false, why);
         }
         prev2 = prev;
         prev = rel;
@@ -1094,6 +902,7 @@ static sem_status solve_refined(sem_ctx c, const double *b, double *x,
         std::memset(&init, 0, sizeof(init));
         init.tol2 = o.inner_tol * o.inner_tol;
         init.max_iter = std::max<int64_t>(1, o.max_iter - info->iterations);
+        init.narrow = 1;
         SEM_HIP(c, hipMemcpyAsync(st_in, &init, sizeof(init), hipMemcpyHostToDevice, s));
         SEM_HIP(c, launch_cg_begin(c, 2, r, lv.x, lv.r, lv.p, lv.w, 1, st_in, s));
         CgState hi;
@@ -1103,9 +912,8 @@ static sem_status solve_refined(sem_ctx c, const double *b, double *x,
         info->rel_residual = hi.bb > 0 ? std::sqrt(hi.rr / hi.bb) : 0.0;
         if (hi.status == 3 || hi.status == 2) {
             // reduced precision broke down: finish in FP64
-            sem_solve_options o64 = o;
-            o64.precision = SEM_FP64;
-            return solve_fp64(c, b, x, o64, info, s, o.max_iter, false);
+            return finish_fp64(c, b, x, o, info, s, false,
+                               hi.status == 2 ? SEM_FALLBACK_BREAKDOWN : SEM_FALLBACK_NONFINITE);
         }
         SEM_HIP(c, hipMemcpyAsync(xsave, x, sizeof(double) * c->n_unique,
                                   hipMemcpyDeviceToDevice, s));
@@ -1163,18 +971,24 @@ static sem_status solve_reliable(sem_ctx c, const double *b, double *x,
     if (!std::isfinite(rel)) return fail(c, SEM_ERR_NAN, "non-finite initial residual");
     if (rel <= o.tol) return SEM_OK;
     double *xsave = dptr<double>(c, L.r64);   // x before the last reliable update
-    // The inner PCG pauses on the device after the iteration in which its
-    // recurrence residual has dropped by delta since the last replacement,
-    // so no iterations run past a replacement point between polls.
+    // The inner PCG works on the residual times a fixed power of two sig ~
+    // 1/||b|| (its iterate is x_in / sig), so that its FP32 vectors hold
+    // values of order 1 down to tol whatever the magnitude of b.  It pauses
+    // on the device after the iteration in which its recurrence residual has
+    // dropped by delta since the last replacement, so no iterations run past
+    // a replacement point between polls.  Residual norms on the host below
+    // are in FP64 units (inner norm / sig).
+    const double sig = pow2_inverse(std::sqrt(bb));
     const double delta2 = o.reliable_delta * o.reliable_delta;
     double pause2_host = 0.0;
     CgState init;
     std::memset(&init, 0, sizeof(init));
-    init.tol2 = (o.tol * o.tol) * bb / h.rr;     // absolute target (tol ||b||)^2 after begin
-    init.pause2 = delta2 * h.rr;
+    init.tol2 = (o.tol * o.tol) * bb / h.rr;     // relative to the inner b.b at begin
+    init.pause2 = delta2 * h.rr * sig * sig;
     init.max_iter = o.max_iter;
+    init.narrow = 1;
     SEM_HIP(c, hipMemcpyAsync(st_in, &init, sizeof(init), hipMemcpyHostToDevice, s));
-    SEM_HIP(c, launch_cg_begin(c, 2, r, lv.x, lv.r, lv.p, lv.w, 1, st_in, s, 0));
+    SEM_HIP(c, launch_cg_begin(c, 2, r, lv.x, lv.r, lv.p, lv.w, 1, st_in, s, 0, sig));
     double rmax = std::sqrt(h.rr);
     double last_rel = rel;
     int stalls = 0;
@@ -1182,27 +996,26 @@ static sem_status solve_reliable(sem_ctx c, const double *b, double *x,
     Stretches seg(o.stall_window, rmax);
     // FP64 CG from zero, unless the iterate is already close (see
     // solve_approx_op)
-    auto fallback = [&](double rel_now) {
-        sem_solve_options o64 = o;
-        o64.precision = SEM_FP64;
-        return solve_fp64(c, b, x, o64, info, s, o.max_iter, !(rel_now < 1e-6));
+    auto fallback = [&](double rel_now, int why) {
+        return finish_fp64(c, b, x, o, info, s, !(rel_now < 1e-6), why);
     };
     for (;;) {
         CgState hi;
         e = run_cg(c, lv, o, o.max_iter, &hi, s, true);
         if (e) return e;
         const int64_t it = base + hi.iter;
+        const double rin = std::sqrt(hi.rr) / sig;      // recurrence residual, FP64 units
         info->iterations = it;
-        info->rel_residual = bb > 0 ? std::sqrt(hi.rr / bb) : 0.0;
+        info->rel_residual = bb > 0 ? rin / std::sqrt(bb) : 0.0;
         const bool bad = hi.status == 2 || hi.status == 3;
-        const bool reached = hi.done || std::sqrt(hi.rr) < o.reliable_delta * rmax;
-        const bool forced = !reached && !bad && seg.stalled(it, std::sqrt(hi.rr));
+        const bool reached = hi.done || rin < o.reliable_delta * rmax;
+        const bool forced = !reached && !bad && seg.stalled(it, rin);
         if (!(reached || bad || forced)) continue;
-        // reliable update: x += x_in, FP64 residual
+        // reliable update: x += x_in / sig, FP64 residual
         if (!bad) {
             SEM_HIP(c, hipMemcpyAsync(xsave, x, sizeof(double) * c->n_unique,
                                       hipMemcpyDeviceToDevice, s));
-            SEM_HIP(c, launch_ir_update(c, x, (const float *)lv.x, nullptr, 0, s));
+            SEM_HIP(c, launch_ir_update(c, x, (const float *)lv.x, nullptr, 0, s, 1.0 / sig));
         }
         e = residual64(c, b, x, y, r, nullptr, 1, o.deterministic, s, &h);
         if (e) return e;
@@ -1214,17 +1027,19 @@ static sem_status solve_reliable(sem_ctx c, const double *b, double *x,
             // a non-finite inner iterate: back to the last finite x, finish in FP64
             SEM_HIP(c, hipMemcpyAsync(x, xsave, sizeof(double) * c->n_unique,
                                       hipMemcpyDeviceToDevice, s));
-            return fallback(last_rel);
+            return fallback(last_rel, SEM_FALLBACK_RESTORED);
         }
         if (rel <= o.tol) return SEM_OK;
-        if (bad) return fallback(rel);
+        if (bad)
+            return fallback(rel, hi.status == 2 ? SEM_FALLBACK_BREAKDOWN : SEM_FALLBACK_NONFINITE);
         if (hi.status == 1 || info->iterations >= o.max_iter) return SEM_ERR_NOT_CONVERGED;
         // the recurrence residual fell by delta (or met the target) but the
         // true residual fell by less than half, twice in a row: the
         // operator's rounding dominates, finish in FP64
         stalls = rel > 0.5 * last_rel ? stalls + 1 : 0;
-        if (stalls >= 2 || (hi.done && info->outer_iterations >= o.max_outer))
-            return fallback(rel);
+        if (stalls >= 2) return fallback(rel, SEM_FALLBACK_STAGNATION);
+        if (hi.done && info->outer_iterations >= o.max_outer)
+            return fallback(rel, SEM_FALLBACK_OUTER_CAP);
         last_rel = rel;
         seg.close(it, forced, std::sqrt(h.rr));
         // A recurrence that met the final target (done = 1, not a pause)
@@ -1236,16 +1051,16 @@ static sem_status solve_reliable(sem_ctx c, const double *b, double *x,
             info->restarts += forced ? 1 : 0;
             base = it;
             init.tol2 = (o.tol * o.tol) * bb / h.rr;
-            init.pause2 = delta2 * h.rr;
+            init.pause2 = delta2 * h.rr * sig * sig;
             init.max_iter = std::max<int64_t>(1, o.max_iter - it);
             SEM_HIP(c, hipMemcpyAsync(st_in, &init, sizeof(init), hipMemcpyHostToDevice, s));
-            SEM_HIP(c, launch_cg_begin(c, 2, r, lv.x, lv.r, lv.p, lv.w, 1, st_in, s, 0));
+            SEM_HIP(c, launch_cg_begin(c, 2, r, lv.x, lv.r, lv.p, lv.w, 1, st_in, s, 0, sig));
         } else {
-            SEM_HIP(c, launch_reliable_reset(c, r, (float *)lv.r, (float *)lv.x, st_in, s));
+            SEM_HIP(c, launch_reliable_reset(c, r, (float *)lv.r, (float *)lv.x, st_in, s, sig));
             // the p kernel is skipped in the iteration that reports
             // convergence, so the boundary block of w may not have been cleared
             SEM_HIP(c, launch_fill32((float *)lv.w, c->n_bnd, 0.0f, s));
-            pause2_host = delta2 * h.rr;
+            pause2_host = delta2 * h.rr * sig * sig;
             SEM_HIP(c, hipMemcpyAsync(&st_in->pause2, &pause2_host, sizeof(double),
                                       hipMemcpyHostToDevice, s));
         }
@@ -1289,11 +1104,8 @@ static sem_status solve_approx_op(sem_ctx c, const double *b, double *x,
     // FP64 CG from zero, unless the iterate is already close: after a stall
     // its error tends to sit in the slowest (smallest-eigenvalue) modes, from
     // which FP64 CG needs many more iterations than from zero
-    auto fallback = [&](double rel) {
-        sem_solve_options o64 = o;
-        o64.precision = SEM_FP64;
-        const bool restart = !(rel < 1e-6);
-        return solve_fp64(c, b, x, o64, info, s, o.max_iter, restart);
+    auto fallback = [&](double rel, int why) {
+        return finish_fp64(c, b, x, o, info, s, !(rel < 1e-6), why);
     };
     for (;;) {
         CgState hc;
@@ -1314,11 +1126,13 @@ static sem_status solve_approx_op(sem_ctx c, const double *b, double *x,
         info->outer_iterations += 1;
         if (!std::isfinite(rel)) return fail(c, SEM_ERR_NAN, "non-finite FP64 residual");
         if (rel <= o.tol) return SEM_OK;
-        if (bad) return fallback(rel);
+        if (bad)
+            return fallback(rel, hc.status == 2 ? SEM_FALLBACK_BREAKDOWN : SEM_FALLBACK_NONFINITE);
         if (hc.status == 1 || info->iterations >= o.max_iter) return SEM_ERR_NOT_CONVERGED;
         stalls = rel > 0.5 * last_rel ? stalls + 1 : 0;     // as in solve_reliable
-        if (stalls >= 2 || (hc.done && info->outer_iterations >= o.max_outer))
-            return fallback(rel);
+        if (stalls >= 2) return fallback(rel, SEM_FALLBACK_STAGNATION);
+        if (hc.done && info->outer_iterations >= o.max_outer)
+            return fallback(rel, SEM_FALLBACK_OUTER_CAP);
         last_rel = rel;
         seg.close(it, forced, std::sqrt(hr.rr));
         if (forced || hc.done == 1) {  // a met target skipped the direction update

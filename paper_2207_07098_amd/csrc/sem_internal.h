@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "sem.h"
+#include "sem_scalar.h"
 
 namespace sem {
 
@@ -20,28 +21,6 @@ constexpr int kMaxPartials = 1 << 17;  // per-block partial sums of one reductio
 constexpr int kVecMaxBlocks = SEM_VEC_MAX_BLOCKS;  // grid of the grid-stride vector kernels
 static_assert(kVecMaxBlocks <= kMaxPartials, "vector partials exceed the partials buffer");
 constexpr int kNumPrec = 4;
-
-// Device-resident CG scalars.  One instance per solver level.
-struct CgState {
-    double rz;        // r.z of the current iterate
-    double pAp;
-    double alpha;
-    double beta;
-    double rr;        // r.r after the last update
-    double bb;        // b.b (squared norm of the right-hand side)
-    double tol2;      // (tol * ||b||)^2
-    double scale;     // right-hand-side scale of an inner solve
-    long long iter;   // iterations done
-    long long max_iter;
-    int done;         // 1: converged, failed or capped -> kernels are no-ops
-    int status;       // 0 running/converged, 1 cap, 2 breakdown, 3 nan
-    unsigned counter[4];  // last-block-done tickets
-    double pause2;    // replacement point: r.r at or below it pauses the CG
-                      // after the iteration's direction update (0: never)
-    int pause;        // set with that update; the next iteration then stops
-    int pad_i;
-    double pad[2];
-};
 
 // Byte offsets of every array inside the caller's workspace.
 struct Layout {
@@ -155,15 +134,16 @@ hipError_t launch_qt(sem_ctx c, const double *wL, double *y, hipStream_t s);
 
 // CG building blocks, T = double or float.
 hipError_t launch_cg_begin(sem_ctx c, int level, const void *b, void *x, void *r, void *p,
-                           void *w, int x_zero, CgState *st, hipStream_t s, int scaled = 1);
+                           void *w, int x_zero, CgState *st, hipStream_t s, int scaled = 1,
+                           double bscale = 1.0);
 hipError_t launch_cg_iteration(sem_ctx c, int level, int prec, void *x, void *r, void *p,
                                void *w, CgState *st, int deterministic, hipStream_t s);
 hipError_t launch_residual64(sem_ctx c, const double *b, const double *Ax, double *r,
                              float *r32, CgState *st, hipStream_t s);
 hipError_t launch_ir_update(sem_ctx c, double *x, const float *d, CgState *st, int scaled,
-                            hipStream_t s);
+                            hipStream_t s, double mul = 1.0);
 hipError_t launch_reliable_reset(sem_ctx c, const double *r64, float *r, float *x, CgState *st,
-                                 hipStream_t s);
+                                 hipStream_t s, double scale);
 
 // ---- batched solve ----
 struct BatchProb {               // device-resident, one per problem

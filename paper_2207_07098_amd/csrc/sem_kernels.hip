@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <climits>
 #include <type_traits>
 #include <cmath>
@@ -192,70 +193,14 @@ __global__ void __launch_bounds__(1024) k_finish(int site, const double *__restr
     for (int a = 0; a < 3; ++a) out[a] = block_sum(acc[a], red);
     if (threadIdx.x != 0) return;
     switch (site) {
-        case FIN_AX: {                                   // p^T A p -> alpha
-            const double pAp = out[0];
-            st->pAp = pAp;
-            if (!std::isfinite(pAp)) {
-                st->status = 3;
-                st->done = 1;
-            } else if (!(pAp > 0.0)) {
-                st->status = 2;
-                st->done = 1;
-            } else {
-                st->alpha = st->rz / pAp;
-            }
-            break;
-        }
-        case FIN_BEGIN: {                                // r.z, r.r, b.b
-            st->rz = out[0];
-            st->rr = out[1];
-            st->bb = out[2];
-            st->tol2 = st->tol2 * out[2];
-            st->iter = 0;
-            st->status = 0;
-            st->done = 0;
-            st->pause = 0;
-            if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
-                st->status = 3;
-                st->done = 1;
-            } else if (out[1] <= st->tol2) {
-                st->done = 1;
-            }
-            break;
-        }
-        case FIN_UPDATE: {                               // r.r, r.z -> beta
-            st->rr = out[0];
-            st->beta = out[1] / st->rz;
-            st->rz = out[1];
-            st->iter += 1;
-            if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
-                st->status = 3;
-                st->done = 1;
-            } else if (out[0] <= st->tol2) {
-                st->done = 1;
-            } else if (st->iter >= st->max_iter) {
-                st->status = 1;
-                st->done = 1;
-            } else if (out[0] <= st->pause2) {
-                st->pause = 1;                   // k_cg_p still runs
-            }
-            break;
-        }
-        case FIN_RESID:                                  // r.r, b.b
+        case FIN_AX: cg_finish_ax(*st, out[0]); break;                    // p^T A p -> alpha
+        case FIN_BEGIN: cg_finish_begin(*st, out[0], out[1], out[2]); break;  // r.z, r.r, b.b
+        case FIN_UPDATE: cg_finish_update(*st, out[0], out[1]); break;    // r.r, r.z -> beta
+        case FIN_RESID:                                                   // r.r, b.b
             st->rr = out[0];
             st->bb = out[1];
             break;
-        case FIN_RESET:                                  // r.z, r.r
-            st->rz = out[0];
-            st->rr = out[1];
-            st->done = 0;
-            st->pause = 0;
-            st->status = 0;
-            if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
-                st->status = 3;
-                st->done = 1;
-            }
-            break;
+        case FIN_RESET: cg_finish_reset(*st, out[0], out[1]); break;      // r.z, r.r
     }
 }
 
@@ -754,10 +699,8 @@ __global__ void __launch_bounds__(256) k_ax_mfma(AxParams<8, GS> P) {
         for (int k = 0; k < N1; ++k) mx = fmaxf(mx, fabsf(u[k]));
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
-        int ex = 0;
-        (void)frexpf(mx, &ex);
-        const float inv = mx > 0.f ? ldexpf(1.f, -ex) : 1.f;
-        const float sig = mx > 0.f ? ldexpf(1.f, ex) : 1.f;
+        const Pow2Scale ps = pow2_scale(mx);
+        const float inv = ps.inv, sig = ps.sig;
         {
             E h[N1];
 #pragma unroll
@@ -1167,15 +1110,16 @@ __global__ void k_fill(T *p, int64_t n, T v) {
 // Begin: x = 0 and r = b (x_zero), or r = b - w with w = A x; p = dinv r;
 // reduces r.z, r.r, b.b; zeroes w on boundary nodes for the next atomic
 // operator.  With b64 != null (inner solve of a refinement step) the
-// right-hand side is the FP64 outer residual scaled by 1/||r|| (outer state).
+// right-hand side is the FP64 outer residual times 1/||r|| of the outer
+// state (outer != null) or times bscale, rounded to T.
 template <typename T>
 __global__ void k_cg_begin(int64_t n, int64_t n_bnd, const T *__restrict__ b,
                            const double *__restrict__ b64, const CgState *__restrict__ outer,
                            T *__restrict__ x, T *__restrict__ r, T *__restrict__ p,
                            T *__restrict__ w, const T *__restrict__ dinv, int x_zero,
-                           double *partials, CgState *st) {
+                           double bscale, double *partials, CgState *st) {
     double rz = 0, rr = 0, bb = 0;
-    const double scale = (b64 && outer) ? 1.0 / sqrt(outer->rr) : 1.0;
+    const double scale = (b64 && outer) ? 1.0 / sqrt(outer->rr) : bscale;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * blockDim.x) {
         const T bq = b64 ? (T)(b64[q] * scale) : b[q];
@@ -1307,25 +1251,27 @@ __global__ void k_residual64(int64_t n, const double *__restrict__ b,
 }
 
 // x += s d with s = ||r|| of the outer residual state (scaled inner
-// right-hand side) or s = 1.
+// right-hand side) or s = mul.
 __global__ void k_ir_update(int64_t n, double *__restrict__ x, const float *__restrict__ d,
-                            const CgState *outer, int scaled) {
-    const double s = scaled ? sqrt(outer->rr) : 1.0;
+                            const CgState *outer, int scaled, double mul) {
+    const double s = scaled ? sqrt(outer->rr) : mul;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * blockDim.x)
         x[q] += s * (double)d[q];
 }
 
 // Reliable update of the inner solve: its residual is replaced by the FP64
-// residual r64 (rounded), its iterate restarts at zero, r.z and r.r are
-// recomputed; the search direction p is kept.
+// residual r64 times `scale` (the inner solve's fixed power-of-two scale),
+// rounded; its iterate restarts at zero, r.z and r.r are recomputed; the
+// search direction p is kept.
 __global__ void k_reliable_reset(int64_t n, const double *__restrict__ r64,
                                  float *__restrict__ r, float *__restrict__ x,
-                                 const float *__restrict__ dinv, double *partials, CgState *st) {
+                                 const float *__restrict__ dinv, double scale, double *partials,
+                                 CgState *st) {
     double rz = 0, rr = 0;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * blockDim.x) {
-        const float rq = (float)r64[q];
+        const float rq = (float)(r64[q] * scale);
         r[q] = rq;
         x[q] = 0.0f;
         rz += (double)rq * (double)(dinv[q] * rq);
@@ -1493,44 +1439,9 @@ __global__ void __launch_bounds__(256) k_finish_batch(BatchArgs A, int site) {
     double out[3];
     for (int a = 0; a < 3; ++a) out[a] = block_sum(acc[a], red);
     if (threadIdx.x != 0) return;
-    if (site == FIN_AX) {
-        st->pAp = out[0];
-        if (!std::isfinite(out[0])) {
-            st->status = 3;
-            st->done = 1;
-        } else if (!(out[0] > 0.0)) {
-            st->status = 2;
-            st->done = 1;
-        } else {
-            st->alpha = st->rz / out[0];
-        }
-    } else if (site == FIN_BEGIN) {
-        st->rz = out[0];
-        st->rr = out[1];
-        st->bb = out[2];
-        st->tol2 = st->tol2 * out[2];
-        st->iter = 0;
-        st->status = 0;
-        st->done = (out[1] <= st->tol2) ? 1 : 0;
-        if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
-            st->status = 3;
-            st->done = 1;
-        }
-    } else {
-        st->rr = out[0];
-        st->beta = out[1] / st->rz;
-        st->rz = out[1];
-        st->iter += 1;
-        if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
-            st->status = 3;
-            st->done = 1;
-        } else if (out[0] <= st->tol2) {
-            st->done = 1;
-        } else if (st->iter >= st->max_iter) {
-            st->status = 1;
-            st->done = 1;
-        }
-    }
+    if (site == FIN_AX) cg_finish_ax(*st, out[0]);
+    else if (site == FIN_BEGIN) cg_finish_begin(*st, out[0], out[1], out[2]);
+    else cg_finish_update(*st, out[0], out[1]);
 }
 
 // r.z and r.r of the current residual (after an FP64 residual replacement).
@@ -1689,7 +1600,8 @@ static double *partials_site(sem_ctx c, int site) {
 }
 
 hipError_t launch_cg_begin(sem_ctx c, int level, const void *b, void *x, void *r, void *p,
-                           void *w, int x_zero, CgState *st, hipStream_t s, int scaled) {
+                           void *w, int x_zero, CgState *st, hipStream_t s, int scaled,
+                           double bscale) {
     const Layout &L = c->L;
     const int64_t n = c->n_unique;
     if (level == 0) {
@@ -1702,18 +1614,18 @@ hipError_t launch_cg_begin(sem_ctx c, int level, const void *b, void *x, void *r
         hipLaunchKernelGGL(k_cg_begin<double>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n,
                            c->n_bnd, (const double *)b, (const double *)nullptr,
                            (const CgState *)nullptr, (double *)x, (double *)r, (double *)p,
-                           (double *)w, dptr<double>(c, L.dinv64), x_zero, partials_site(c, 1),
-                           st);
+                           (double *)w, dptr<double>(c, L.dinv64), x_zero, 1.0,
+                           partials_site(c, 1), st);
         hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, (int)FIN_BEGIN,
                            (const double *)partials_site(c, 1), (int)vec_grid(n), st);
     } else {
-        // inner refinement solve: b is the FP64 outer residual, optionally
-        // divided by its norm (from the outer residual state)
+        // inner refinement solve: b is the FP64 outer residual, divided by
+        // its norm (from the outer residual state) or multiplied by bscale
         const CgState *outer = scaled ? dptr<CgState>(c, L.state) + 1 : nullptr;
         hipLaunchKernelGGL(k_cg_begin<float>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n,
                            c->n_bnd, (const float *)nullptr, (const double *)b, outer,
                            (float *)x, (float *)r, (float *)p, (float *)w,
-                           dptr<float>(c, L.dinv32), 1, partials_site(c, 1), st);
+                           dptr<float>(c, L.dinv32), 1, bscale, partials_site(c, 1), st);
         hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, (int)FIN_BEGIN,
                            (const double *)partials_site(c, 1), (int)vec_grid(n), st);
     }
@@ -1768,10 +1680,10 @@ hipError_t launch_residual64(sem_ctx c, const double *b, const double *Ax, doubl
 }
 
 hipError_t launch_ir_update(sem_ctx c, double *x, const float *d, CgState *outer, int scaled,
-                            hipStream_t s) {
+                            hipStream_t s, double mul) {
     const int64_t n = c->n_unique;
     hipLaunchKernelGGL(k_ir_update, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n, x, d,
-                       (const CgState *)outer, scaled);
+                       (const CgState *)outer, scaled, mul);
     return hipGetLastError();
 }
 
@@ -1785,10 +1697,10 @@ hipError_t launch_rz_rr(sem_ctx c, const double *r, CgState *st, hipStream_t s) 
 }
 
 hipError_t launch_reliable_reset(sem_ctx c, const double *r64, float *r, float *x, CgState *st,
-                                 hipStream_t s) {
+                                 hipStream_t s, double scale) {
     const int64_t n = c->n_unique;
     hipLaunchKernelGGL(k_reliable_reset, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n, r64, r, x,
-                       dptr<float>(c, c->L.dinv32), partials_site(c, 1), st);
+                       dptr<float>(c, c->L.dinv32), scale, partials_site(c, 1), st);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, (int)FIN_RESET,
                        (const double *)partials_site(c, 1), (int)vec_grid(n), st);
     return hipGetLastError();

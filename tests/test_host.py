@@ -59,6 +59,19 @@ def test_default_solve_options_through_the_binding():
     assert names == [f[0] for f in sem.SolveOptions._fields_]
 
 
+def test_solve_info_fields_match_header():
+    """The binding's sem_solve_info mirrors the header field by field, and
+    its fallback names follow the sem_fallback enum."""
+    src = open(os.path.join(ROOT, "include", "sem.h")).read()
+    body = src[src.index("typedef struct {\n    sem_status status;"):src.index("} sem_solve_info;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"^\s+\w+\s+(\w+);", body, re.M)
+    assert names == [f[0] for f in sem.SolveInfo._fields_]
+    enum = src[src.index("typedef enum {\n    SEM_FALLBACK_NONE"):src.index("} sem_fallback;")]
+    vals = {int(v): n.lower() for n, v in re.findall(r"SEM_FALLBACK_(\w+) = (\d+)", enum)}
+    assert vals == sem.FALLBACK
+
+
 def test_library_is_for_gfx950():
     out = subprocess.run(["/opt/rocm/bin/roc-obj-ls", sem.LIB_PATH], capture_output=True,
                          text=True)
@@ -130,6 +143,32 @@ def test_numbering_partial_dirichlet():
 @pytest.mark.parametrize("N", [1, 3, 7])
 def test_numbering_periodic_ogrid(N):
     _numbering_case(F.ogrid(8, 3, 4), N)
+
+
+@pytest.mark.parametrize("name", ["box48_N7", "ogrid_256x64x32_N7"])
+def test_numbering_full_size_configs(name):
+    """The graded configurations at full size: 48^3 deformed box and the
+    256x64x32 O-grid (periodic in theta and z, Dirichlet on the cylinder),
+    N = 7.  The library's numbering (corner-id entity keys) equals the
+    oracle's lattice numbering bit for bit, with the same multiplicity and
+    Dirichlet mask; the unique counts are the closed forms 337^3 and
+    1792 * 449 * 224."""
+    if name == "box48_N7":
+        mesh, nu_closed = F.periodic_box_deformed(48, 7).mesh, 337 ** 3
+    else:
+        mesh, nu_closed = F.cylinder_ogrid().mesh, 1792 * 449 * 224
+    op = sem.Operator(mesh, 7, precisions=("fp64",), solver=False, setup_device=False)
+    gid, pos, dmask, mult = op.numbering()
+    ogid, nu = oracle.number(7, mesh)
+    assert nu == op.n_unique == nu_closed
+    assert np.array_equal(gid, ogid)
+    del gid
+    omult, odm = oracle.mult_mask(7, ogid, mesh.face_bc, nu)
+    assert np.array_equal(mult, omult)
+    assert np.array_equal(dmask, odm)
+    assert np.array_equal(np.sort(pos), np.arange(nu))
+    if name != "box48_N7":
+        assert int(odm.sum()) == 401408            # the cylinder surface layer
 
 
 def test_numbering_config_sizes():
