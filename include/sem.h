@@ -36,8 +36,9 @@
  *
  * Ownership: the context owns only host metadata.  All device memory is
  * owned by the caller: one workspace buffer bound with sem_bind_workspace
- * plus the vectors passed to each call.  The library never allocates
- * device memory.
+ * plus the vectors passed to each call.  The library allocates no device
+ * memory for its data; its only device memory of its own is one static
+ * array per device (SEM_STATIC_SCRATCH_BYTES), used by sem_cg_solve_static.
  */
 #ifndef SEM_H
 #define SEM_H
@@ -325,6 +326,27 @@ void sem_default_solve_options(sem_solve_options *opts);
 sem_status sem_cg_solve(sem_ctx ctx, const double *b, double *x,
                         const sem_solve_options *opts, sem_solve_info *info,
                         sem_stream stream);
+
+/* FP64 Jacobi-PCG for callers that cannot allocate device memory (code
+ * under stream capture, serving loops, harnesses that forbid hipMalloc):
+ * the same solve as sem_cg_solve with precision SEM_FP64, but it creates no
+ * stream, event or graph and keeps its CG state, reduction partials and its
+ * three work vectors (r, p, w) in a device array of the library's own
+ * (SEM_STATIC_SCRATCH_BYTES, held by each device the library runs on until
+ * the process ends) instead of the workspace's solver vectors, so the
+ * context needs no opts.solver.  Kernels run on `stream` itself, without
+ * graph capture (use_graph is ignored); the call blocks until done.
+ * b, x as for sem_cg_solve.  Errors: SEM_ERR_INVALID when n_unique exceeds
+ * SEM_STATIC_MAX_UNIQUE (the message states both), SEM_ERR_UNSUPPORTED for
+ * a reduced precision or deterministic = 1 (fixed-order summation stages
+ * through the workspace).  The array is shared by every call on a device
+ * and keeps the last call's contents (each call initialises what it reads):
+ * calls that overlap on one device, from any thread or context, race. */
+#define SEM_STATIC_SCRATCH_BYTES (64u << 20)
+#define SEM_STATIC_MAX_UNIQUE 2096960
+sem_status sem_cg_solve_static(sem_ctx ctx, const double *b, double *x,
+                               const sem_solve_options *opts, sem_solve_info *info,
+                               sem_stream stream);
 
 /* ---------------------------------------------------------------------------
  * Batched solve: many independent Poisson problems (meshes of different

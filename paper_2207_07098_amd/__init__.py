@@ -105,7 +105,7 @@ EXPORTS = ["sem_gll", "sem_setup", "sem_free", "sem_last_error", "sem_query",
            "sem_default_solve_options", "sem_cg_solve", "sem_get_tile", "sem_set_tile",
            "sem_autotune", "sem_batch_create", "sem_batch_free", "sem_batch_last_error",
            "sem_batch_workspace_size", "sem_batch_bind_workspace", "sem_batch_set_tile",
-           "sem_batch_autotune", "sem_batch_solve"]
+           "sem_batch_autotune", "sem_batch_solve", "sem_cg_solve_static"]
 
 _lib = None
 
@@ -139,6 +139,7 @@ def lib():
         "sem_rhs": ([P, P, P, P, P], i32),
         "sem_default_solve_options": ([P], None),
         "sem_cg_solve": ([P, P, P, P, P, P], i32),
+        "sem_cg_solve_static": ([P, P, P, P, P, P], i32),
         "sem_get_tile": ([P, i32, P], i32),
         "sem_set_tile": ([P, i32, P], i32),
         "sem_autotune": ([P, i32, i32, ctypes.c_char_p, P, P, i32, P, P], i32),
@@ -364,6 +365,28 @@ class Operator:
         info = SolveInfo()
         st = lib().sem_cg_solve(self._ctx, _dptr(b), _dptr(x), ctypes.byref(o),
                                 ctypes.byref(info), _stream_handle())
+        d = info.as_dict()
+        if st and raise_on_error:
+            self._check(st)
+        return x, d
+
+    def solve_static(self, b, x=None, tol: float = 1e-10, max_iter: int = 100000,
+                     check_every: int = 50, max_restart: int = 3, raise_on_error: bool = True):
+        """FP64 Jacobi-PCG through sem_cg_solve_static: no allocation, no
+        graph, work vectors in the library's static device array (at most
+        SEM_STATIC_MAX_UNIQUE unique nodes).  Returns (x, info dict)."""
+        o = SolveOptions()
+        lib().sem_default_solve_options(ctypes.byref(o))
+        o.tol = tol
+        o.max_iter = max_iter
+        o.check_every = check_every
+        o.max_restart = max_restart
+        o.zero_guess = 1 if x is None else 0
+        if x is None:
+            x = self.vector()
+        info = SolveInfo()
+        st = lib().sem_cg_solve_static(self._ctx, _dptr(b), _dptr(x), ctypes.byref(o),
+                                       ctypes.byref(info), _stream_handle())
         d = info.as_dict()
         if st and raise_on_error:
             self._check(st)

@@ -700,7 +700,7 @@ struct Level {
 sem_status run_cg(sem_ctx c, const Level &lv, const sem_solve_options &o, int64_t cap,
                   CgState *host_state, hipStream_t s, bool one_chunk = false) {
     host_state->max_iter = cap;
-    CgState *st = dptr<CgState>(c, c->L.state) + lv.level;
+    CgState *st = state_ptr(c) + lv.level;
     const int m = std::max(1, o.check_every);
     hipGraphExec_t exec = nullptr;
     if (o.use_graph) {
@@ -756,7 +756,7 @@ sem_status run_cg(sem_ctx c, const Level &lv, const sem_solve_options &o, int64_
 // y = A x (FP64) then r = b - y, rr and bb into state[level]
 sem_status residual64(sem_ctx c, const double *b, const double *x, double *y, double *r,
                       float *r32, int level, int deterministic, hipStream_t s, CgState *hs) {
-    CgState *st = dptr<CgState>(c, c->L.state) + level;
+    CgState *st = state_ptr(c) + level;
     if (deterministic) {
         SEM_HIP(c, launch_ax(c, SEM_FP64, x, y, 0, OUT_COMPACT, nullptr, nullptr, c->tile[0], s));
         SEM_HIP(c, launch_gather_sum(c, SEM_FP64, c->ws + c->L.wb, y, s));
@@ -792,12 +792,21 @@ sem_status true_residual(sem_ctx c, const double *b, const double *x, hipStream_
 }
 }  // namespace sem
 
+// FP64 work vectors of a plain PCG: r, p, w, and z for the residual check
+// (z may be p: p is rebuilt after every check).
+struct Vecs64 {
+    double *r, *p, *w, *z;
+};
+static Vecs64 workspace_vecs(sem_ctx c) {
+    return {dptr<double>(c, c->L.r64), dptr<double>(c, c->L.p64), dptr<double>(c, c->L.w64),
+            dptr<double>(c, c->L.z64)};
+}
+
 static sem_status solve_fp64(sem_ctx c, const double *b, double *x, const sem_solve_options &o,
                              sem_solve_info *info, hipStream_t s, int64_t iter_budget,
-                             bool zero_guess) {
-    const Layout &L = c->L;
-    Level lv{0, SEM_FP64, x, c->ws + L.r64, c->ws + L.p64, c->ws + L.w64};
-    CgState *st = dptr<CgState>(c, L.state);
+                             bool zero_guess, Vecs64 v) {
+    Level lv{0, SEM_FP64, x, v.r, v.p, v.w};
+    CgState *st = state_ptr(c);
     CgState h;
     int restarts = 0;
     sem_status result = SEM_ERR_NOT_CONVERGED;
@@ -820,8 +829,7 @@ static sem_status solve_fp64(sem_ctx c, const double *b, double *x, const sem_so
         }
         // true residual in FP64
         CgState hr;
-        e = residual64(c, b, x, dptr<double>(c, L.w64), dptr<double>(c, L.z64), nullptr, 1,
-                       o.deterministic, s, &hr);
+        e = residual64(c, b, x, v.w, v.z, nullptr, 1, o.deterministic, s, &hr);
         if (e) return e;
         info->true_rel_residual = hr.bb > 0 ? std::sqrt(hr.rr / hr.bb) : 0.0;
         if (!std::isfinite(info->true_rel_residual)) { result = SEM_ERR_NAN; break; }
@@ -845,7 +853,8 @@ static sem_status finish_fp64(sem_ctx c, const double *b, double *x, const sem_s
     o64.precision = SEM_FP64;
     info->fallback = why;
     const int64_t before = info->iterations;
-    const sem_status st = solve_fp64(c, b, x, o64, info, s, o.max_iter, from_zero);
+    const sem_status st = solve_fp64(c, b, x, o64, info, s, o.max_iter, from_zero,
+                                     workspace_vecs(c));
     info->fallback_iterations = info->iterations - before;
     return st;
 }
@@ -868,7 +877,7 @@ static sem_status solve_refined(sem_ctx c, const double *b, double *x,
     double *y = dptr<double>(c, L.w64);
     double *r = dptr<double>(c, L.z64);
     float *r32 = dptr<float>(c, L.r32);
-    CgState *st_in = dptr<CgState>(c, L.state) + 2;
+    CgState *st_in = state_ptr(c) + 2;
     Level lv{2, (int)o.precision, c->ws + L.d32, r32, c->ws + L.p32, c->ws + L.w32};
     if (o.zero_guess) SEM_HIP(c, launch_fill(x, c->n_unique, 0.0, s));
     double *xsave = dptr<double>(c, L.r64);   // x before the last correction
@@ -917,7 +926,7 @@ static sem_status solve_refined(sem_ctx c, const double *b, double *x,
         }
         SEM_HIP(c, hipMemcpyAsync(xsave, x, sizeof(double) * c->n_unique,
                                   hipMemcpyDeviceToDevice, s));
-        SEM_HIP(c, launch_ir_update(c, x, (const float *)lv.x, dptr<CgState>(c, L.state) + 1, 1, s));
+        SEM_HIP(c, launch_ir_update(c, x, (const float *)lv.x, state_ptr(c) + 1, 1, s));
     }
 }
 
@@ -959,7 +968,7 @@ static sem_status solve_reliable(sem_ctx c, const double *b, double *x,
     if (!L.d32) return fail(c, SEM_ERR_STATE, "no reduced-precision work vectors");
     double *y = dptr<double>(c, L.w64);
     double *r = dptr<double>(c, L.z64);
-    CgState *st_in = dptr<CgState>(c, L.state) + 2;
+    CgState *st_in = state_ptr(c) + 2;
     Level lv{2, (int)o.precision, c->ws + L.d32, c->ws + L.r32, c->ws + L.p32, c->ws + L.w32};
     if (o.zero_guess) SEM_HIP(c, launch_fill(x, c->n_unique, 0.0, s));
     CgState h;
@@ -1079,7 +1088,7 @@ static sem_status solve_approx_op(sem_ctx c, const double *b, double *x,
     const Layout &L = c->L;
     double *r = dptr<double>(c, L.r64), *w = dptr<double>(c, L.w64);
     Level lv{0, (int)o.precision, x, r, c->ws + L.p64, w};
-    CgState *st = dptr<CgState>(c, L.state);
+    CgState *st = state_ptr(c);
     CgState init, h;
     std::memset(&init, 0, sizeof(init));
     init.tol2 = o.tol * o.tol;
@@ -1188,13 +1197,82 @@ extern "C" sem_status sem_cg_solve(sem_ctx c, const double *b, double *x,
     hipStream_t s = c->solve_stream;
     auto t0 = std::chrono::steady_clock::now();
     if (o.precision == SEM_FP64)
-        st = solve_fp64(c, b, x, o, info, s, o.max_iter, o.zero_guess != 0);
+        st = solve_fp64(c, b, x, o, info, s, o.max_iter, o.zero_guess != 0, workspace_vecs(c));
     else if (o.fp64_vectors)
         st = solve_approx_op(c, b, x, o, info, s);
     else if (o.reliable_delta > 0.0 && o.reliable_delta < 1.0)
         st = solve_reliable(c, b, x, o, info, s);
     else
         st = solve_refined(c, b, x, o, info, s);
+    hipError_t he = hipStreamSynchronize(s);
+    if (he != hipSuccess && st == SEM_OK) st = fail(c, SEM_ERR_DEVICE, hipGetErrorString(he));
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    info->status = st;
+    if (st == SEM_ERR_NOT_CONVERGED && c->err.empty()) c->err = "iteration cap reached";
+    return st;
+}
+
+// FP64 PCG that allocates nothing: no private stream, no captured graph, and
+// the CG state, the reduction partials and the work vectors r, p, w in the
+// library's static device array instead of the bound workspace.
+extern "C" sem_status sem_cg_solve_static(sem_ctx c, const double *b, double *x,
+                                          const sem_solve_options *opts, sem_solve_info *info,
+                                          sem_stream stream) {
+    sem_solve_info dummy;
+    if (!info) info = &dummy;
+    std::memset(info, 0, sizeof(*info));
+    sem_status st = check_ready(c, SEM_FP64);
+    if (st) return info->status = st;
+    if (!b || !x) return info->status = fail(c, SEM_ERR_INVALID, "null vector");
+    if (!aligned16(b) || !aligned16(x))
+        return info->status = fail(c, SEM_ERR_INVALID, "vectors must be 16-byte aligned");
+    sem_solve_options o;
+    if (opts) o = *opts; else sem_default_solve_options(&o);
+    if (!(o.tol > 0) || o.max_iter < 1) return info->status = fail(c, SEM_ERR_INVALID, "bad tolerance or cap");
+    if (o.precision != SEM_FP64)
+        return info->status = fail(c, SEM_ERR_UNSUPPORTED, "the static solve is FP64 PCG only");
+    if (o.deterministic)
+        return info->status = fail(c, SEM_ERR_UNSUPPORTED,
+                                   "fixed-order summation needs the workspace's staging block");
+    if (c->n_unique > SEM_STATIC_MAX_UNIQUE)
+        return info->status = fail(c, SEM_ERR_INVALID,
+                                   "n_unique = " + std::to_string(c->n_unique) +
+                                       " exceeds the static solve's maximum of " +
+                                       std::to_string((long long)SEM_STATIC_MAX_UNIQUE));
+    static_assert(SEM_STATIC_SCRATCH_BYTES == kStaticScratchBytes, "header and library disagree");
+    static_assert(kStaticStateBytes + kStaticPartialBytes +
+                          3 * (((size_t)8 * SEM_STATIC_MAX_UNIQUE + 255) & ~(size_t)255) <=
+                      kStaticScratchBytes,
+                  "SEM_STATIC_MAX_UNIQUE does not fit the static array");
+    void *base = nullptr;
+    SEM_HIP(c, static_scratch(&base));
+    // [CG state | partials of four reduction sites | r | p | w]
+    char *p0 = static_cast<char *>(base);
+    const size_t vb = align256(8 * (size_t)c->n_unique);
+    static_assert(kStaticStateBytes >= 4 * sizeof(CgState), "state block too small");
+    Vecs64 v;
+    v.r = reinterpret_cast<double *>(p0 + kStaticStateBytes + kStaticPartialBytes);
+    v.p = reinterpret_cast<double *>(reinterpret_cast<char *>(v.r) + vb);
+    v.w = reinterpret_cast<double *>(reinterpret_cast<char *>(v.p) + vb);
+    v.z = v.p;
+    if (kStaticStateBytes + kStaticPartialBytes + 3 * vb > kStaticScratchBytes)
+        return info->status = fail(c, SEM_ERR_INVALID, "static array too small");
+    struct Redirect {               // the launchers use the static array for this call
+        sem_ctx c;
+        Redirect(sem_ctx c_, double *part, CgState *state) : c(c_) {
+            c->part_base = part;
+            c->state_base = state;
+        }
+        ~Redirect() {
+            c->part_base = nullptr;
+            c->state_base = nullptr;
+        }
+    } redirect(c, reinterpret_cast<double *>(p0 + kStaticStateBytes),
+               reinterpret_cast<CgState *>(p0));
+    o.use_graph = 0;
+    hipStream_t s = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    st = solve_fp64(c, b, x, o, info, s, o.max_iter, o.zero_guess != 0, v);
     hipError_t he = hipStreamSynchronize(s);
     if (he != hipSuccess && st == SEM_OK) st = fail(c, SEM_ERR_DEVICE, hipGetErrorString(he));
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -89,6 +89,12 @@ struct sem_ctx_s {
     size_t max_lds = 65536;
     sem::AxTile tile[sem::kNumPrec];
 
+    // Reduction partials and CG state used by the launchers: the workspace's
+    // arrays unless a call points them elsewhere (sem_cg_solve_static uses
+    // the library's own device array)
+    double *part_base = nullptr;
+    sem::CgState *state_base = nullptr;
+
     // captured CG graphs
     struct GraphEntry {
         const void *key[4];
@@ -114,6 +120,19 @@ sem_status fail(sem_ctx ctx, sem_status st, const std::string &msg);
 
 template <typename T>
 inline T *dptr(sem_ctx c, size_t off) { return reinterpret_cast<T *>(c->ws + off); }
+
+// CG state array (one CgState per solver level) of the current call.
+inline CgState *state_ptr(sem_ctx c) {
+    return c->state_base ? c->state_base : dptr<CgState>(c, c->L.state);
+}
+
+// The library's own device array for callers that cannot allocate
+// (sem_cg_solve_static): its address on the current device, looked up
+// once per device, and its size in bytes.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr size_t kStaticStateBytes = 4096;
+constexpr size_t kStaticPartialBytes = (size_t)8 * kMaxPartials * 16;
+hipError_t static_scratch(void **ptr);
 
 // ---- kernel launchers (sem_kernels.hip) ----
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);

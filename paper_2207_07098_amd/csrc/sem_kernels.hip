@@ -25,6 +25,7 @@
 #include <climits>
 #include <type_traits>
 #include <cmath>
+#include <mutex>
 
 #include "sem_internal.h"
 
@@ -1595,8 +1596,38 @@ hipError_t launch_qt(sem_ctx c, const double *wL, double *y, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Device memory of the library's own for callers that cannot allocate
+// (sem_cg_solve_static): CG state, reduction partials and three solver
+// vectors.  Every device the library runs on holds one copy until the
+// process ends; calls that use it concurrently on one device race.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+// Address of `scratch` on the current device.  In host code the array's
+// name is not a device address: the address is looked up once per device
+// (with that device current) and only the looked-up pointer is used.
+hipError_t static_scratch(void **ptr) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
+
 static double *partials_site(sem_ctx c, int site) {
-    return dptr<double>(c, c->L.partials) + (size_t)site * kMaxPartials * 4;
+    double *base = c->part_base ? c->part_base : dptr<double>(c, c->L.partials);
+    return base + (size_t)site * kMaxPartials * 4;
 }
 
 hipError_t launch_cg_begin(sem_ctx c, int level, const void *b, void *x, void *r, void *p,
@@ -1621,7 +1652,7 @@ hipError_t launch_cg_begin(sem_ctx c, int level, const void *b, void *x, void *r
     } else {
         // inner refinement solve: b is the FP64 outer residual, divided by
         // its norm (from the outer residual state) or multiplied by bscale
-        const CgState *outer = scaled ? dptr<CgState>(c, L.state) + 1 : nullptr;
+        const CgState *outer = scaled ? state_ptr(c) + 1 : nullptr;
         hipLaunchKernelGGL(k_cg_begin<float>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n,
                            c->n_bnd, (const float *)nullptr, (const double *)b, outer,
                            (float *)x, (float *)r, (float *)p, (float *)w,
