@@ -214,10 +214,11 @@ typedef struct {
                                      its factors at once; 1: two planes in
                                      flight (fewer registers, more waves);
                                      2: matrix-core (MFMA) element operator,
-                                     FP16/BF16 factors at N = 7 only; it also
-                                     rounds u (scaled per element) and the
-                                     weighted derivatives to 16 bits, so it
-                                     is never chosen by sem_autotune         */
+                                     FP16/BF16 factors at N = 7 only; u
+                                     (scaled per element), D and the
+                                     weighted derivatives enter as pairs of
+                                     16-bit numbers (hi + lo), products
+                                     accumulate in FP32                      */
 } sem_tile;
 
 typedef struct {

@@ -513,7 +513,9 @@ static bool tile_valid(sem_ctx c, int prec, const sem_tile &t) {
     const size_t sz = prec == SEM_FP64 ? 8 : 4;
     const int nslots = t.elements_per_block;        // one LDS slot per element
     // three LDS buffers per element slot plus D (the operator kernels' layout)
-    const size_t lds = ((size_t)nslots * 3 * c->n1 * c->n1 * (c->n1 + 1) + C) * sz;
+    const size_t lds = t.pipeline == 2
+                           ? (size_t)nslots * kMfmaSlotBytes
+                           : ((size_t)nslots * 3 * c->n1 * c->n1 * (c->n1 + 1) + C) * sz;
     return lds <= c->max_lds;
 }
 
@@ -608,10 +610,9 @@ extern "C" sem_status sem_autotune(sem_ctx c, sem_precision prec, int reps, cons
     double best_ms = INFINITY;
     AxTile best_t = saved;
     int nres = 0;
-    // the matrix-core variant (pipeline 2) also rounds u and the weighted
-    // derivatives to 16 bits; that rounding is not linear in u and costs the
-    // refined solves their convergence, so it is only used when set explicitly
-    for (int pipe = 0; pipe < 2; ++pipe)
+    // pipeline 2 (matrix cores) is a candidate wherever it is valid: 16-bit
+    // factors at N = 7
+    for (int pipe = 0; pipe < 3; ++pipe)
     for (int epb : epbs)
         for (int cap : caps)
             for (int xcd = 0; xcd < 2; ++xcd) {

@@ -34,6 +34,10 @@ struct Layout {
     size_t total;
 };
 
+// LDS bytes per element slot of the matrix-core operator (N = 7): hi and
+// lo 16-bit operands in three layouts plus three FP32 result blocks.
+constexpr size_t kMfmaSlotBytes = 12288;
+
 // Launch shape of the element operator.
 struct AxTile {
     int epb = 1;          // elements per workgroup

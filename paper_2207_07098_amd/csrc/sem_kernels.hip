@@ -586,13 +586,18 @@ k_ax(AxParams<N1, GS> P) {
 // Element operator on matrix cores (16-bit factors, N = 7): one element per
 // wave.  The derivative contractions of Eq. (9) are 8x8 by 8x64 products per
 // direction; two of them share one 16x16x16 MFMA through a block-diagonal
-// A = diag(D, D), so each direction takes two MFMAs forward and two
-// backward.  u is divided by a per-element power of two (its largest
-// magnitude rounded up) before it is rounded to 16 bits; the G-weighted
-// derivatives are rounded to 16 bits unscaled (they stay far below the
-// 16-bit range); products accumulate in FP32.  The operands are staged in
-// LDS in three layouts (contraction index fastest for r, s and t), so every
-// lane fetches its four consecutive operand values with one 8-byte read.
+// A = diag(D, D).  Every MFMA operand is carried as a pair of 16-bit
+// numbers, hi + lo with lo the rounding error of hi, and every product is
+// formed as lo*hi + hi*lo + hi*hi accumulated in FP32 (three MFMAs), so the
+// contractions keep about 22 (FP16) or 17 (BF16) significant bits: the
+// operator's error is set by the 16-bit factors G, as in the SIMT kernel,
+// and it stays linear in u to that accuracy (rounding u to one 16-bit
+// number made the refined solves stall).  u is divided by a per-element
+// power of two first (its largest magnitude rounded up) so that its pair
+// spans the 16-bit range; the G-weighted derivatives are split unscaled.
+// The operands are staged in LDS in three layouts (contraction index
+// fastest for r, s and t), so every lane fetches its four consecutive
+// operand values of each part with one 8-byte read.
 // ---------------------------------------------------------------------------
 typedef _Float16 h4v __attribute__((ext_vector_type(4)));
 typedef short s4v __attribute__((ext_vector_type(4)));
@@ -604,6 +609,7 @@ struct MF<_Float16> {
     using E = _Float16;
     using V = h4v;
     static __device__ __forceinline__ E cvt(float f) { return (_Float16)f; }
+    static __device__ __forceinline__ float tof(E e) { return (float)e; }
     static __device__ __forceinline__ f4v mma(V a, V b, f4v c) {
         return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
     }
@@ -613,45 +619,61 @@ struct MF<bf16_t> {
     using E = uint16_t;
     using V = s4v;
     static __device__ __forceinline__ E cvt(float f) { return f32_to_bf16_rne(f); }
+    static __device__ __forceinline__ float tof(E e) { return __uint_as_float((uint32_t)e << 16); }
     static __device__ __forceinline__ f4v mma(V a, V b, f4v c) {
         return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
     }
 };
 
+// v = hi + lo to 16-bit precision twice over (round to nearest even both times)
 template <typename GS>
-__device__ __forceinline__ typename MF<GS>::V pack4(typename MF<GS>::E a, typename MF<GS>::E b,
-                                                    typename MF<GS>::E c, typename MF<GS>::E d) {
+__device__ __forceinline__ void split16(float v, typename MF<GS>::E &hi, typename MF<GS>::E &lo) {
+    hi = MF<GS>::cvt(v);
+    lo = MF<GS>::cvt(v - MF<GS>::tof(hi));
+}
+
+template <typename GS>
+__device__ __forceinline__ typename MF<GS>::V pack4(const typename MF<GS>::E *e) {
     typename MF<GS>::V v;
-    v[0] = a;
-    v[1] = b;
-    v[2] = c;
-    v[3] = d;
+    v[0] = e[0];
+    v[1] = e[1];
+    v[2] = e[2];
+    v[3] = e[3];
     return v;
 }
 
-constexpr int kMfmaSlotBytes = 3 * 512 * 2 + 3 * 512 * 4;   // 16-bit operands + FP32 outputs
+// Per wave: the hi and lo parts of the operands in layouts R [k][j][i],
+// S [k][i][j] and T [(i,j)][k] (16-bit), then the FP32 results R, S, T.
+constexpr int kMfmaPart = 512;                                  // values per layout
+static_assert(kMfmaSlotBytes == 6 * kMfmaPart * 2 + 3 * kMfmaPart * 4, "MFMA slot layout");
 
 // One direction of the block-diagonal contraction: out = diag(M, M) * B over
-// the 64 columns of an element, B read from `src` (layout: contraction index
-// fastest within groups of 8), FP32 result written to `dst` in the same
-// layout.  Column index c in 0..63 addresses the group at c * 8.
+// the 64 columns of an element, M and B as hi/lo pairs, B read from
+// srch/srcl (layout: contraction index fastest within groups of 8), the FP32
+// result written to `dst` in the same layout.  Column c (0..63) addresses
+// the group at c * 8.
 template <typename GS>
-__device__ __forceinline__ void mfma_dir(typename MF<GS>::V a, const typename MF<GS>::E *src,
-                                         float *dst, int lane) {
+__device__ __forceinline__ void mfma_dir(typename MF<GS>::V ah, typename MF<GS>::V al,
+                                         const typename MF<GS>::E *srch,
+                                         const typename MF<GS>::E *srcl, float *dst, int lane) {
     using V = typename MF<GS>::V;
     const int q = lane >> 4, grp = q >> 1, m0 = 4 * (q & 1);
 #pragma unroll
     for (int n = 0; n < 2; ++n) {
         const int colidx = 16 * n + (lane & 15) + 32 * grp;
-        const V b = *reinterpret_cast<const V *>(src + colidx * 8 + m0);
-        const f4v acc = MF<GS>::mma(a, b, f4v{0.f, 0.f, 0.f, 0.f});
+        const V bh = *reinterpret_cast<const V *>(srch + colidx * 8 + m0);
+        const V bl = *reinterpret_cast<const V *>(srcl + colidx * 8 + m0);
+        f4v acc = MF<GS>::mma(al, bh, f4v{0.f, 0.f, 0.f, 0.f});
+        acc = MF<GS>::mma(ah, bl, acc);
+        acc = MF<GS>::mma(ah, bh, acc);
         *reinterpret_cast<f4v *>(dst + colidx * 8 + m0) = acc;
     }
 }
 
 template <typename GS, typename VT>
 __global__ void __launch_bounds__(256) k_ax_mfma(AxParams<8, GS> P) {
-    constexpr int N1 = 8, N = 7, C = 64, NP = 512, NB = NP - 216;
+    constexpr int N1 = 8, N = 7, C = 64, NP = 512;
+    static_assert(NP == kMfmaPart, "one element per MFMA slot");
     using E = typename MF<GS>::E;
     using V = typename MF<GS>::V;
     CgState *st = P.st;
@@ -659,24 +681,31 @@ __global__ void __launch_bounds__(256) k_ax_mfma(AxParams<8, GS> P) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const Lane<N1> L(threadIdx.x);
     const int lane = threadIdx.x & 63;
-    // per wave: operands in layouts R [k][j][i], S [k][i][j], T [(i,j)][k]
-    E *UR = reinterpret_cast<E *>(smem_raw + (size_t)L.slot * kMfmaSlotBytes);
-    E *US = UR + NP;
-    E *UT = US + NP;
-    float *FR = reinterpret_cast<float *>(UT + NP);
+    E *URh = reinterpret_cast<E *>(smem_raw + (size_t)L.slot * kMfmaSlotBytes);
+    E *URl = URh + NP;
+    E *USh = URl + NP;
+    E *USl = USh + NP;
+    E *UTh = USl + NP;
+    E *UTl = UTh + NP;
+    float *FR = reinterpret_cast<float *>(UTl + NP);
     float *FS = FR + NP;
     float *FT = FS + NP;
-    // A operands diag(D, D) and diag(D^T, D^T): lane holds row lane%16,
-    // contraction entries 4*(lane/16) .. +3
-    V aF, aB;
+    // A operands diag(D, D) and diag(D^T, D^T) as hi/lo pairs: the lane holds
+    // row lane%16, contraction entries 4*(lane/16) .. +3
+    V aFh, aFl, aBh, aBl;
     {
         const int row = lane & 15, q = lane >> 4;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int kk = 4 * q + t;
             const bool blk = (row >> 3) == (kk >> 3);
-            aF[t] = MF<GS>::cvt(blk ? (float)P.D[(row & 7) * N1 + (kk & 7)] : 0.f);
-            aB[t] = MF<GS>::cvt(blk ? (float)P.D[(kk & 7) * N1 + (row & 7)] : 0.f);
+            E h, l;
+            split16<GS>(blk ? (float)P.D[(row & 7) * N1 + (kk & 7)] : 0.f, h, l);
+            aFh[t] = h;
+            aFl[t] = l;
+            split16<GS>(blk ? (float)P.D[(kk & 7) * N1 + (row & 7)] : 0.f, h, l);
+            aBh[t] = h;
+            aBl[t] = l;
         }
     }
     AxMesh<GS> M{P.u, P.y, P.wb, P.G, P.gscale, P.bmap, P.E, P.n_bnd, 0, OUT_ATOMIC};
@@ -703,20 +732,24 @@ __global__ void __launch_bounds__(256) k_ax_mfma(AxParams<8, GS> P) {
         const Pow2Scale ps = pow2_scale(mx);
         const float inv = ps.inv, sig = ps.sig;
         {
-            E h[N1];
+            E h[N1], l[N1];
 #pragma unroll
             for (int k = 0; k < N1; ++k) {
-                h[k] = MF<GS>::cvt(u[k] * inv);
-                UR[k * C + j * N1 + i] = h[k];
-                US[k * C + i * N1 + j] = h[k];
+                split16<GS>(u[k] * inv, h[k], l[k]);
+                URh[k * C + j * N1 + i] = h[k];
+                URl[k * C + j * N1 + i] = l[k];
+                USh[k * C + i * N1 + j] = h[k];
+                USl[k * C + i * N1 + j] = l[k];
             }
-            *reinterpret_cast<V *>(UT + col * N1) = pack4<GS>(h[0], h[1], h[2], h[3]);
-            *reinterpret_cast<V *>(UT + col * N1 + 4) = pack4<GS>(h[4], h[5], h[6], h[7]);
+            *reinterpret_cast<V *>(UTh + col * N1) = pack4<GS>(h);
+            *reinterpret_cast<V *>(UTh + col * N1 + 4) = pack4<GS>(h + 4);
+            *reinterpret_cast<V *>(UTl + col * N1) = pack4<GS>(l);
+            *reinterpret_cast<V *>(UTl + col * N1 + 4) = pack4<GS>(l + 4);
         }
         __syncthreads();
-        mfma_dir<GS>(aF, UR, FR, lane);
-        mfma_dir<GS>(aF, US, FS, lane);
-        mfma_dir<GS>(aF, UT, FT, lane);
+        mfma_dir<GS>(aFh, aFl, URh, URl, FR, lane);
+        mfma_dir<GS>(aFh, aFl, USh, USl, FS, lane);
+        mfma_dir<GS>(aFh, aFl, UTh, UTl, FT, lane);
         __syncthreads();
         // G-weighting at the lane's own column
         double edot = 0.0;
@@ -724,7 +757,7 @@ __global__ void __launch_bounds__(256) k_ax_mfma(AxParams<8, GS> P) {
             const f4v t0 = *reinterpret_cast<const f4v *>(FT + col * N1);
             const f4v t1 = *reinterpret_cast<const f4v *>(FT + col * N1 + 4);
             const float utv[N1] = {t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z, t1.w};
-            E hw[N1];
+            E hw[N1], lw[N1];
 #pragma unroll
             for (int k = 0; k < N1; ++k) {
                 const float ur = FR[k * C + j * N1 + i];
@@ -735,17 +768,24 @@ __global__ void __launch_bounds__(256) k_ax_mfma(AxParams<8, GS> P) {
                 const float ws = gk[3] * ur + gk[1] * us + gk[5] * ut;
                 const float wt = gk[4] * ur + gk[5] * us + gk[2] * ut;
                 if (P.partials) edot += (double)(ur * wr + us * ws + ut * wt);
-                UR[k * C + j * N1 + i] = MF<GS>::cvt(wr);
-                US[k * C + i * N1 + j] = MF<GS>::cvt(ws);
-                hw[k] = MF<GS>::cvt(wt);
+                E h, l;
+                split16<GS>(wr, h, l);
+                URh[k * C + j * N1 + i] = h;
+                URl[k * C + j * N1 + i] = l;
+                split16<GS>(ws, h, l);
+                USh[k * C + i * N1 + j] = h;
+                USl[k * C + i * N1 + j] = l;
+                split16<GS>(wt, hw[k], lw[k]);
             }
-            *reinterpret_cast<V *>(UT + col * N1) = pack4<GS>(hw[0], hw[1], hw[2], hw[3]);
-            *reinterpret_cast<V *>(UT + col * N1 + 4) = pack4<GS>(hw[4], hw[5], hw[6], hw[7]);
+            *reinterpret_cast<V *>(UTh + col * N1) = pack4<GS>(hw);
+            *reinterpret_cast<V *>(UTh + col * N1 + 4) = pack4<GS>(hw + 4);
+            *reinterpret_cast<V *>(UTl + col * N1) = pack4<GS>(lw);
+            *reinterpret_cast<V *>(UTl + col * N1 + 4) = pack4<GS>(lw + 4);
         }
         __syncthreads();
-        mfma_dir<GS>(aB, UR, FR, lane);
-        mfma_dir<GS>(aB, US, FS, lane);
-        mfma_dir<GS>(aB, UT, FT, lane);
+        mfma_dir<GS>(aBh, aBl, URh, URl, FR, lane);
+        mfma_dir<GS>(aBh, aBl, USh, USl, FS, lane);
+        mfma_dir<GS>(aBh, aBl, UTh, UTl, FT, lane);
         __syncthreads();
         const float sc = P.gscale[ec];
         if (P.partials && active) dot += edot * (double)sc * (double)sig * (double)sig;
