@@ -201,6 +201,18 @@ sem_status sem_ax(sem_ctx ctx, const void *u, void *y, sem_precision prec,
 sem_status sem_rhs(sem_ctx ctx, const double *f_L, const double *f,
                    double *b, sem_stream stream);
 
+/* Helmholtz operator H = h1 A + h2 B, with B = blockdiag(rho_i rho_j rho_k J)
+ * the GLL-lumped mass (Sec. II-A, last paragraph: the velocity equations
+ * are solved the same way; Sec. II-B: by P-CG).  From this call on, sem_ax,
+ * sem_autotune and the solves of this context apply M Q^T (h1 A_L + h2 B_L)
+ * Q M, and the Jacobi preconditioner is the inverse diagonal of H.  Needs
+ * finite h1 > 0 and h2 >= 0 (SEM_ERR_INVALID otherwise) and geometry set
+ * (SEM_ERR_STATE); (1, 0) is the Poisson operator again.  While another
+ * pair is set, 16-bit precisions, sem_ax_local, SEM_AX_DETERMINISTIC,
+ * SEM_AX_FP64_VECTORS, deterministic or FP64-vector solves and batching
+ * return SEM_ERR_UNSUPPORTED.  Synchronises `stream`. */
+sem_status sem_set_helmholtz(sem_ctx ctx, double h1, double h2, sem_stream stream);
+
 /* Launch shape of the element operator for one precision. */
 typedef struct {
     int elements_per_block;       /* elements per workgroup (one lane per

@@ -63,6 +63,11 @@ def lib():
         L.ora_rhs.argtypes = [i64, P, P, P, i64, P, P]
         L.ora_pcg.argtypes = [i32, i64, P, P, P, i64, P, P, P, P,
                               ctypes.c_double, i64, i32, P, P]
+        d = ctypes.c_double
+        L.ora_apply_helmholtz.argtypes = [i32, i64, P, P, P, d, d, P, i64, P, P, P]
+        L.ora_jacobi_helmholtz.argtypes = [i32, i64, P, P, P, d, d, P, i64, P, P, P]
+        L.ora_pcg_helmholtz.argtypes = [i32, i64, P, P, P, d, d, P, i64, P, P, P, P,
+                                        d, i64, i32, P, P]
         _lib = L
     return _lib
 
@@ -217,6 +222,48 @@ class Problem:
         if history:
             info["history"] = hist[:int(out[0]) + 1].copy()
         return x, info
+
+    def true_residual(self, x: np.ndarray, b: np.ndarray) -> float:
+        r = b - self.apply(x)
+        return float(np.linalg.norm(r) / np.linalg.norm(b))
+
+
+@dataclass
+class Helmholtz:
+    """The Helmholtz operator h1 A + h2 B of the velocity solve (Sec. II-A,
+    last paragraph; B the GLL-lumped mass) on an oracle Problem, with its
+    Jacobi preconditioner and PCG (Sec. II-B)."""
+    P: Problem
+    h1: float
+    h2: float
+
+    def __post_init__(self):
+        P = self.P
+        self.diag = np.empty(P.n_u)
+        self.dinv = np.empty(P.n_u)
+        lib().ora_jacobi_helmholtz(P.N, P.E, _p(P.D), _p(P.G), _p(P.B), self.h1, self.h2,
+                                   _p(P.gid), P.n_u, _p(P.dirichlet), _p(self.diag),
+                                   _p(self.dinv))
+
+    def apply(self, u: np.ndarray) -> np.ndarray:
+        """y = M Q^T (h1 A_L + h2 B_L) Q M u."""
+        P = self.P
+        y = np.empty(P.n_u)
+        lib().ora_apply_helmholtz(P.N, P.E, _p(P.D), _p(P.G), _p(P.B), self.h1, self.h2,
+                                  _p(P.gid), P.n_u, _p(P.dirichlet),
+                                  _p(np.ascontiguousarray(u, dtype=np.float64)), _p(y))
+        return y
+
+    def pcg(self, b: np.ndarray, tol: float, max_iter: int = 100000, max_restart: int = 5):
+        P = self.P
+        x = np.zeros(P.n_u)
+        out = np.zeros(4)
+        st = lib().ora_pcg_helmholtz(P.N, P.E, _p(P.D), _p(P.G), _p(P.B), self.h1, self.h2,
+                                     _p(P.gid), P.n_u, _p(P.dirichlet), _p(self.dinv),
+                                     _p(np.ascontiguousarray(b, dtype=np.float64)), _p(x),
+                                     tol, max_iter, max_restart, _p(out), None)
+        return x, {"status": int(st), "iterations": int(out[0]),
+                   "true_rel_residual": float(out[1]), "restarts": int(out[2])}
 
     def true_residual(self, x: np.ndarray, b: np.ndarray) -> float:
         r = b - self.apply(x)

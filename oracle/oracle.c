@@ -365,6 +365,54 @@ void ora_jacobi(int N, int64_t E, const double *D, const double *G,
         dinv[g] = dirichlet[g] ? 0.0 : 1.0 / diag[g];
 }
 
+/*
+ * Helmholtz operator of the velocity solve (Sec. II-A, last paragraph: the
+ * same discretization is applied to the Helmholtz equation; the mass matrix
+ * B is the GLL-lumped one, B = rho_i rho_j rho_k J per point):
+ *   y = M Q^T (h1 A_L + h2 B_L) Q M u.
+ * h1 = 1, h2 = 0 gives ora_apply's operator.
+ */
+void ora_apply_helmholtz(int N, int64_t E, const double *D, const double *G,
+                         const double *B, double h1, double h2,
+                         const int32_t *gid, int64_t n_unique,
+                         const uint8_t *dirichlet, const double *u, double *y)
+{
+    int n1 = N + 1;
+    int64_t nl = E * n1 * n1 * n1;
+    double *um = (double *)malloc(sizeof(double) * n_unique);
+    double *uL = (double *)malloc(sizeof(double) * nl);
+    double *wL = (double *)malloc(sizeof(double) * nl);
+    memcpy(um, u, sizeof(double) * n_unique);
+    ora_mask(n_unique, dirichlet, um);
+    ora_q(nl, gid, um, uL);
+    ora_ax_local(N, E, D, G, uL, wL);
+    for (int64_t p = 0; p < nl; ++p) wL[p] = h1 * wL[p] + h2 * B[p] * uL[p];
+    ora_qt(nl, gid, n_unique, wL, y);
+    ora_mask(n_unique, dirichlet, y);
+    free(um); free(uL); free(wL);
+}
+
+/*
+ * Jacobi preconditioner of the Helmholtz operator: d = h1 Q^T diag(A_L)
+ * + h2 Q^T B_L (the lumped mass is diagonal), dinv = 1/d off the mask.
+ */
+void ora_jacobi_helmholtz(int N, int64_t E, const double *D, const double *G,
+                          const double *B, double h1, double h2,
+                          const int32_t *gid, int64_t n_unique,
+                          const uint8_t *dirichlet, double *diag, double *dinv)
+{
+    int n1 = N + 1;
+    int64_t nl = E * n1 * n1 * n1;
+    double *bm = (double *)malloc(sizeof(double) * n_unique);
+    ora_jacobi(N, E, D, G, gid, n_unique, dirichlet, diag, dinv);
+    ora_qt(nl, gid, n_unique, B, bm);
+    for (int64_t g = 0; g < n_unique; ++g) {
+        diag[g] = h1 * diag[g] + h2 * bm[g];
+        dinv[g] = dirichlet[g] ? 0.0 : 1.0 / diag[g];
+    }
+    free(bm);
+}
+
 /* O10: right-hand side b = M Q^T (B_L f_L) with the GLL-lumped mass B. */
 void ora_rhs(int64_t nl, const double *B, const double *fL, const int32_t *gid,
              int64_t n_unique, const uint8_t *dirichlet, double *b)
@@ -381,6 +429,16 @@ static double dot(int64_t n, const double *a, const double *b)
     return s;
 }
 
+/* The operator PCG iterates with: Poisson (B == NULL) or Helmholtz. */
+static void apply_op(int N, int64_t E, const double *D, const double *G,
+                     const double *B, double h1, double h2, const int32_t *gid,
+                     int64_t n_unique, const uint8_t *dirichlet, const double *u,
+                     double *y)
+{
+    if (B) ora_apply_helmholtz(N, E, D, G, B, h1, h2, gid, n_unique, dirichlet, u, y);
+    else ora_apply(N, E, D, G, gid, n_unique, dirichlet, u, y);
+}
+
 /*
  * O11: Jacobi-preconditioned conjugate gradients on A x = b (Sec. II-B
  * names P-CG; the preconditioner here is the exact point diagonal).
@@ -394,11 +452,15 @@ static double dot(int64_t n, const double *a, const double *b)
  * out[3] = recurrence relative residual.  hist (optional, max_iter+1
  * entries) receives the recurrence relative residual per iteration.
  * Returns 0 when converged, 1 when max_iter was reached, 2 on breakdown.
+ * ora_pcg_helmholtz runs the same iteration on h1 A + h2 B (B != NULL; the
+ * velocity solve of Sec. II-B) with dinv from ora_jacobi_helmholtz;
+ * ora_pcg is the Poisson case.
  */
-int ora_pcg(int N, int64_t E, const double *D, const double *G,
-            const int32_t *gid, int64_t n_unique, const uint8_t *dirichlet,
-            const double *dinv, const double *b, double *x, double tol,
-            int64_t max_iter, int max_restart, double *out, double *hist)
+int ora_pcg_helmholtz(int N, int64_t E, const double *D, const double *G,
+                      const double *B, double h1, double h2,
+                      const int32_t *gid, int64_t n_unique, const uint8_t *dirichlet,
+                      const double *dinv, const double *b, double *x, double tol,
+                      int64_t max_iter, int max_restart, double *out, double *hist)
 {
     int64_t n = n_unique;
     double *r = (double *)malloc(sizeof(double) * n);
@@ -415,7 +477,7 @@ int ora_pcg(int N, int64_t E, const double *D, const double *G,
         goto done;
     }
     for (;;) {
-        ora_apply(N, E, D, G, gid, n, dirichlet, x, w);
+        apply_op(N, E, D, G, B, h1, h2, gid, n, dirichlet, x, w);
         for (int64_t q = 0; q < n; ++q) r[q] = dirichlet[q] ? 0.0 : b[q] - w[q];
         rel = sqrt(dot(n, r, r)) / bnorm;
         if (hist && it == 0) hist[0] = rel;
@@ -424,7 +486,7 @@ int ora_pcg(int N, int64_t E, const double *D, const double *G,
         double rz = dot(n, r, z);
         int hit = 0;
         while (it < max_iter) {
-            ora_apply(N, E, D, G, gid, n, dirichlet, p, w);
+            apply_op(N, E, D, G, B, h1, h2, gid, n, dirichlet, p, w);
             double pw = dot(n, p, w);
             if (!(pw > 0.0)) { status = 2; goto finish; }
             double alpha = rz / pw;
@@ -441,7 +503,7 @@ int ora_pcg(int N, int64_t E, const double *D, const double *G,
         }
         if (!hit) { status = 1; break; }
         /* true residual check */
-        ora_apply(N, E, D, G, gid, n, dirichlet, x, w);
+        apply_op(N, E, D, G, B, h1, h2, gid, n, dirichlet, x, w);
         for (int64_t q = 0; q < n; ++q) r[q] = dirichlet[q] ? 0.0 : b[q] - w[q];
         true_rel = sqrt(dot(n, r, r)) / bnorm;
         if (true_rel <= tol) { status = 0; break; }
@@ -450,7 +512,7 @@ int ora_pcg(int N, int64_t E, const double *D, const double *G,
     }
 finish:
     if (status != 0 || true_rel == 0.0) {
-        ora_apply(N, E, D, G, gid, n, dirichlet, x, w);
+        apply_op(N, E, D, G, B, h1, h2, gid, n, dirichlet, x, w);
         for (int64_t q = 0; q < n; ++q) r[q] = dirichlet[q] ? 0.0 : b[q] - w[q];
         true_rel = sqrt(dot(n, r, r)) / bnorm;
     }
@@ -458,4 +520,13 @@ done:
     if (out) { out[0] = (double)it; out[1] = true_rel; out[2] = restarts; out[3] = rel; }
     free(r); free(z); free(p); free(w);
     return status;
+}
+
+int ora_pcg(int N, int64_t E, const double *D, const double *G,
+            const int32_t *gid, int64_t n_unique, const uint8_t *dirichlet,
+            const double *dinv, const double *b, double *x, double tol,
+            int64_t max_iter, int max_restart, double *out, double *hist)
+{
+    return ora_pcg_helmholtz(N, E, D, G, NULL, 1.0, 0.0, gid, n_unique, dirichlet, dinv, b,
+                             x, tol, max_iter, max_restart, out, hist);
 }

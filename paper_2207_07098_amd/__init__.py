@@ -105,7 +105,8 @@ EXPORTS = ["sem_gll", "sem_setup", "sem_free", "sem_last_error", "sem_query",
            "sem_default_solve_options", "sem_cg_solve", "sem_get_tile", "sem_set_tile",
            "sem_autotune", "sem_batch_create", "sem_batch_free", "sem_batch_last_error",
            "sem_batch_workspace_size", "sem_batch_bind_workspace", "sem_batch_set_tile",
-           "sem_batch_autotune", "sem_batch_solve", "sem_cg_solve_static"]
+           "sem_batch_autotune", "sem_batch_solve", "sem_cg_solve_static",
+           "sem_set_helmholtz"]
 
 _lib = None
 
@@ -140,6 +141,7 @@ def lib():
         "sem_default_solve_options": ([P], None),
         "sem_cg_solve": ([P, P, P, P, P, P], i32),
         "sem_cg_solve_static": ([P, P, P, P, P, P], i32),
+        "sem_set_helmholtz": ([P, ctypes.c_double, ctypes.c_double, P], i32),
         "sem_get_tile": ([P, i32, P], i32),
         "sem_set_tile": ([P, i32, P], i32),
         "sem_autotune": ([P, i32, i32, ctypes.c_char_p, P, P, i32, P, P], i32),
@@ -391,6 +393,11 @@ class Operator:
         if st and raise_on_error:
             self._check(st)
         return x, d
+
+    def set_helmholtz(self, h1: float = 1.0, h2: float = 0.0):
+        """Operator h1 A + h2 B (B the lumped mass) for later applications and
+        solves; (1, 0) is the Poisson operator."""
+        self._check(lib().sem_set_helmholtz(self._ctx, float(h1), float(h2), _stream_handle()))
 
     # -- launch shapes -----------------------------------------------------
     def get_tile(self, precision: str = "fp64"):

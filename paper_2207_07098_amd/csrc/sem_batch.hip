@@ -127,6 +127,11 @@ extern "C" sem_status sem_batch_create(const sem_ctx *ctxs, int nprob, sem_batch
             delete b;
             return fail(nullptr, SEM_ERR_UNSUPPORTED, "batched solve supports N <= 9");
         }
+        if (c->helm) {
+            delete b;
+            return fail(nullptr, SEM_ERR_UNSUPPORTED,
+                        "problem " + std::to_string(p) + ": the batched solve is for the Poisson operator");
+        }
         b->max_n1 = std::max(b->max_n1, c->n1);
         b->max_c = std::max(b->max_c, c->n1 * c->n1);
         BatchProb &pb = b->probs[p];

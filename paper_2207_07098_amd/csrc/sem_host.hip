@@ -417,9 +417,40 @@ static sem_status check_ready(sem_ctx c, int prec) {
     return SEM_OK;
 }
 
+// Operations the Helmholtz operator (h1, h2) != (1, 0) does not offer.
+static sem_status helm_unsupported(sem_ctx c, int prec, bool local, bool deterministic,
+                                   bool vec64) {
+    if (!c->helm) return SEM_OK;
+    if (prec != SEM_FP64 && prec != SEM_FP32)
+        return fail(c, SEM_ERR_UNSUPPORTED, "the Helmholtz operator has FP64 and FP32 factors only");
+    if (local || deterministic || vec64)
+        return fail(c, SEM_ERR_UNSUPPORTED,
+                    "the Helmholtz operator runs on unique vectors with atomic summation only");
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_set_helmholtz(sem_ctx c, double h1, double h2, sem_stream stream) {
+    if (!c) return fail(c, SEM_ERR_INVALID, "null context");
+    if (!c->geometry_ready) return fail(c, SEM_ERR_STATE, "geometry not set");
+    if (!(h1 > 0.0) || !(h2 >= 0.0) || !std::isfinite(h1) || !std::isfinite(h2))
+        return fail(c, SEM_ERR_INVALID, "need finite h1 > 0 and h2 >= 0");
+    c->h1 = h1;
+    c->h2 = h2;
+    c->helm = !(h1 == 1.0 && h2 == 0.0);
+    hipStream_t s = (hipStream_t)stream;
+    SEM_HIP(c, launch_dinv(c, s));
+    SEM_HIP(c, hipStreamSynchronize(s));
+    // captured iterations hold the previous operator's kernels and arguments
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+    return SEM_OK;
+}
+
 extern "C" sem_status sem_ax_local(sem_ctx c, const void *uL, void *wL, sem_precision prec,
                                    sem_stream stream) {
     sem_status st = check_ready(c, prec);
+    if (st) return st;
+    st = helm_unsupported(c, prec, true, false, false);
     if (st) return st;
     if (!uL || !wL) return fail(c, SEM_ERR_INVALID, "null vector");
     SEM_HIP(c, launch_ax(c, prec, uL, wL, 1, OUT_LOCAL, nullptr, nullptr, c->tile[prec],
@@ -436,6 +467,8 @@ extern "C" sem_status sem_ax(sem_ctx c, const void *u, void *y, sem_precision pr
     if (!aligned16(u) || !aligned16(y)) return fail(c, SEM_ERR_INVALID, "vectors must be 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     const bool v64 = (flags & SEM_AX_FP64_VECTORS) != 0;
+    st = helm_unsupported(c, prec, false, (flags & SEM_AX_DETERMINISTIC) != 0, v64);
+    if (st) return st;
     if (v64 && (prec == SEM_FP64 || (flags & SEM_AX_DETERMINISTIC)))
         return fail(c, SEM_ERR_INVALID,
                     "SEM_AX_FP64_VECTORS needs a reduced precision and atomic summation");
@@ -545,6 +578,8 @@ extern "C" sem_status sem_autotune(sem_ctx c, sem_precision prec, int reps, cons
                                    sem_tile *best, sem_tune_result *results, int max_results,
                                    int *n_results, sem_stream stream) {
     sem_status st = check_ready(c, prec);
+    if (st) return st;
+    st = helm_unsupported(c, prec, false, false, false);
     if (st) return st;
     if (!c->L.p64) return fail(c, SEM_ERR_STATE, "autotune needs the solver work vectors");
     if (n_results) *n_results = 0;
@@ -1186,6 +1221,8 @@ extern "C" sem_status sem_cg_solve(sem_ctx c, const double *b, double *x,
         st = check_ready(c, o.precision);
         if (st) return info->status = st;
     }
+    st = helm_unsupported(c, o.precision, false, o.deterministic != 0, o.fp64_vectors != 0);
+    if (st) return info->status = st;
     // Solves run on a private stream ordered after the caller's stream, so
     // that the iteration can be captured even when the caller uses the null
     // stream.

@@ -99,6 +99,10 @@ struct sem_ctx_s {
     double *part_base = nullptr;
     sem::CgState *state_base = nullptr;
 
+    // Operator h1 A + h2 B (Helmholtz); (1, 0) is the Poisson operator
+    double h1 = 1.0, h2 = 0.0;
+    bool helm = false;
+
     // captured CG graphs
     struct GraphEntry {
         const void *key[4];
@@ -145,6 +149,7 @@ hipError_t launch_geometry(sem_ctx c, const double *xyz_dev, int64_t e0, int64_t
                            int *errflag, hipStream_t s);
 hipError_t launch_lowprec_factors(sem_ctx c, hipStream_t s);
 hipError_t launch_diag(sem_ctx c, hipStream_t s);
+hipError_t launch_dinv(sem_ctx c, hipStream_t s);
 hipError_t launch_rhs(sem_ctx c, const double *fL, const double *f, double *b, hipStream_t s);
 hipError_t launch_ax(sem_ctx c, int prec, const void *u, void *y, int in_local, int out_mode,
                      double *dot_partials, CgState *st, const AxTile &t, hipStream_t s,

@@ -64,10 +64,9 @@ struct GT<bf16_t> {
     }
 };
 
+// Round to nearest even (gfx950 converts in hardware: v_cvt_pk_bf16_f32).
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 
 __device__ __forceinline__ int ring_index(int i, int j, int N) {
@@ -223,6 +222,8 @@ struct AxParams {
     CgState *st;
     const T *D;                  // D[i][m] row-major, and its transpose, in
     const T *DT;                 // device memory (read with scalar loads)
+    const double *B;             // Helmholtz: lumped mass [E][n_p] and the
+    double h1, h2;               // coefficients of h1 A + h2 B
 };
 
 // Factor loads of one lane for one k-plane (layout of goff()): 3 x 16 B
@@ -316,6 +317,8 @@ struct AxMesh {
     const int32_t *bmap;
     int64_t E, n_bnd;
     int in_local, out_mode;
+    const double *B;             // Helmholtz only (see AxParams)
+    double h1, h2;
 };
 
 template <int N1>
@@ -381,7 +384,11 @@ enum { MODE_ATOMIC = 0, MODE_COMPACT = 1, MODE_LOCAL = 2 };
 // start of the element (most bytes in flight, most registers); a smaller PF
 // keeps a ring of PF+1 planes, requesting plane k+PF while plane k is
 // computed (fewer registers, so more waves per SIMD).
-template <int N1, typename GS, int MODE, typename VT = typename GT<GS>::T, int PF = N1>
+// HELM: the Helmholtz operator h1 D^T G D + h2 B of the velocity solve
+// (Sec. II-A, last paragraph): the element's mass values are streamed with
+// its factors, u is read back from LDS at the output.
+template <int N1, typename GS, int MODE, typename VT = typename GT<GS>::T, int PF = N1,
+          bool HELM = false>
 __device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename GT<GS>::T *Dg,
                                            const typename GT<GS>::T *DTg,
                                            const typename GT<GS>::T *Dl, const Lane<N1> &L,
@@ -442,6 +449,12 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename G
     // ---- then the factors of the first planes (all of them, or the ring)
 #pragma unroll
     for (int k = 0; k < (ALL ? N1 : PF); ++k) load_g6<C>(Ge + (size_t)k * C * 6, col, g[k % NS]);
+    double bl[HELM ? N1 : 1];
+    if constexpr (HELM) {
+#pragma unroll
+        for (int k = 0; k < N1; ++k)
+            bl[k] = __builtin_nontemporal_load(M.B + (size_t)ec * NP + k * C + col);
+    }
     // ---- map entries of the next element
     if (!IN_LOCAL && next_e >= 0) load_map<N1>(M.bmap, L, next_e, bm);
 
@@ -491,7 +504,8 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename G
 
     // ---- D^T (G D u)
     const T sc = SCALED ? (T)M.gscale[ec] : T(1);
-    if (want_dot && active) dot += SCALED ? edot * (double)sc : edot;
+    if (want_dot && active) dot += HELM ? M.h1 * edot : (SCALED ? edot * (double)sc : edot);
+    double hdot = 0.0;
 #pragma unroll
     for (int m = 0; m < N1; ++m) {
         Di[m] = Dl[m * N1 + i];
@@ -507,6 +521,11 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename G
             w += DTk[k * N1 + m] * wt[m];
         }
         if (SCALED) w *= sc;
+        if constexpr (HELM) {
+            const T uk = S0[k * PLANE + j * PITCH + i];
+            w = (T)M.h1 * w + (T)M.h2 * (T)bl[k] * uk;
+            if (want_dot) hdot += bl[k] * (double)uk * (double)uk;
+        }
         if (active) {
             if (MODE == MODE_LOCAL) {
                 Y[ec * NP + k * C + col] = (VT)w;
@@ -523,6 +542,7 @@ __device__ __forceinline__ void ax_element(const AxMesh<GS> &M, const typename G
         }
         __builtin_amdgcn_sched_barrier(0);
     }
+    if (HELM && want_dot && active) dot += M.h2 * hdot;
 }
 
 template <int N1, typename T>
@@ -538,7 +558,7 @@ __device__ __forceinline__ void fill_dl(T *Dl, const T *Dg) {
 // of all planes and the gathered u are requested together (the element's
 // map entries were fetched while the previous element was computed), so a
 // wave waits about one memory latency per element.
-template <int N1, typename GS, int MODE, typename VT, int PF = N1>
+template <int N1, typename GS, int MODE, typename VT, int PF = N1, bool HELM = false>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, 256),
                                amdgpu_waves_per_eu(AxOcc<N1, GS, PF>::value)))
 k_ax(AxParams<N1, GS> P) {
@@ -553,7 +573,8 @@ k_ax(AxParams<N1, GS> P) {
     T *S0 = reinterpret_cast<T *>(smem_raw) + (size_t)L.slot * 3 * BUF;
     T *Dl = reinterpret_cast<T *>(smem_raw) + (size_t)P.epb * 3 * BUF;
     fill_dl<N1, T>(Dl, P.D);
-    AxMesh<GS> M{P.u, P.y, P.wb, P.G, P.gscale, P.bmap, P.E, P.n_bnd, P.in_local, P.out_mode};
+    AxMesh<GS> M{P.u, P.y, P.wb, P.G, P.gscale, P.bmap, P.E, P.n_bnd, P.in_local, P.out_mode,
+                 P.B, P.h1, P.h2};
     auto elem_of = [&](int64_t git, bool &act) {
         const int64_t g = P.xcd ? xcd_remap(git, P.ngroups) : git;
         const int64_t e = g * P.epb + L.slot;
@@ -572,8 +593,8 @@ k_ax(AxParams<N1, GS> P) {
         bool active, act_n;
         const int64_t ec = elem_of(git, active);
         const int64_t en = git + gridDim.x < P.ngroups ? elem_of(git + gridDim.x, act_n) : -1;
-        ax_element<N1, GS, MODE, VT, PF>(M, P.D, P.DT, Dl, L, S0, ec, active, en, bm,
-                                         P.partials != nullptr, dot);
+        ax_element<N1, GS, MODE, VT, PF, HELM>(M, P.D, P.DT, Dl, L, S0, ec, active, en, bm,
+                                               P.partials != nullptr, dot);
     }
     if (P.partials) {
         double v[1] = {dot};
@@ -708,7 +729,8 @@ __global__ void __launch_bounds__(256) k_ax_mfma(AxParams<8, GS> P) {
             aBl[t] = l;
         }
     }
-    AxMesh<GS> M{P.u, P.y, P.wb, P.G, P.gscale, P.bmap, P.E, P.n_bnd, 0, OUT_ATOMIC};
+    AxMesh<GS> M{P.u, P.y, P.wb, P.G, P.gscale, P.bmap, P.E, P.n_bnd, 0, OUT_ATOMIC,
+                 nullptr, 1.0, 0.0};
     VT *__restrict__ Y = reinterpret_cast<VT *>(P.y);
     const int i = L.i, j = L.j, col = L.col;
     double dot = 0.0;
@@ -849,6 +871,9 @@ hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const v
     P.xcd = t.xcd;
     P.partials = partials;
     P.st = st;
+    P.B = dptr<double>(c, c->L.B);
+    P.h1 = c->h1;
+    P.h2 = c->h2;
     int64_t grid = P.ngroups;
     int64_t cap = t.grid_cap > 0 ? t.grid_cap : INT_MAX;
     if (partials) cap = std::min<int64_t>(cap, kMaxPartials);
@@ -856,6 +881,26 @@ hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const v
     if (grid > P.ngroups) grid = P.ngroups;
     if (P.xcd && grid < P.ngroups && (grid & 7)) P.xcd = 0;
     const bool ring = t.pipeline == 1;       // factor planes in flight: 2 instead of all
+    if (c->helm) {
+        // Helmholtz: FP64/FP32 factors, atomic summation on unique vectors
+        if constexpr (sizeof(GS) >= 4) {
+            // (FP64 vectors are the operator's own for FP64 factors)
+            if (in_local || out_mode != OUT_ATOMIC || (vec64 && !std::is_same<T, double>::value))
+                return hipErrorInvalidValue;
+            if (ring)
+                hipLaunchKernelGGL((k_ax<N1, GS, MODE_ATOMIC, T, 2, true>), dim3((unsigned)grid),
+                                   dim3(threads), lds, s, P);
+            else
+                hipLaunchKernelGGL((k_ax<N1, GS, MODE_ATOMIC, T, N1, true>), dim3((unsigned)grid),
+                                   dim3(threads), lds, s, P);
+            if (partials)
+                hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, (int)FIN_AX,
+                                   (const double *)partials, (int)grid, st);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     if constexpr (MFMA_OK) {
         if (mfma) {
             if (vec64)
@@ -1014,7 +1059,7 @@ __global__ void k_lowprec(const double *__restrict__ G, int n1, float *G32, _Flo
 
 // Per-point value -> interior entries of y directly, boundary entries into
 // the compact buffer wb (then k_gather_sum).  mode 0: exact Jacobi diagonal
-// of D^T G D; mode 1: B * f_L; mode 2: B * (Q f).
+// of D^T G D; mode 1: B * f_L; mode 2: B * (Q f); mode 3: B.
 __global__ void k_local_values(int mode, int64_t E, int n1, int64_t n_bnd,
                                const double *__restrict__ D, const double *__restrict__ G,
                                const double *__restrict__ B, const double *__restrict__ f,
@@ -1045,6 +1090,8 @@ __global__ void k_local_values(int mode, int64_t E, int n1, int64_t n_bnd,
             v = s;
         } else if (mode == 1) {
             v = B[q] * f[q];
+        } else if (mode == 3) {
+            v = B[q];
         } else {
             double fv;
             if (bpt) fv = f[bmap[e * nb + bp] & 0x7fffffff];
@@ -1126,13 +1173,16 @@ __global__ void k_q_or_qt_int(int mode, int64_t E, int n1, int64_t n_bnd,
     }
 }
 
+// Jacobi inverse diagonal of h1 A + h2 B: d64 holds the assembled mass on
+// entry when h2 != 0 (read before it is overwritten), diag that of A.
 __global__ void k_dinv(int64_t n_u, int64_t n_bnd, const uint8_t *__restrict__ bdir,
-                       const double *__restrict__ diag, double *__restrict__ d64,
-                       float *__restrict__ d32) {
+                       const double *__restrict__ diag, double h1, double h2,
+                       double *__restrict__ d64, float *__restrict__ d32) {
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_u;
          g += (int64_t)gridDim.x * blockDim.x) {
         const bool masked = g < n_bnd && bdir[g];
-        const double v = masked ? 0.0 : 1.0 / diag[g];
+        const double dg = h1 * diag[g] + (h2 != 0.0 ? h2 * d64[g] : 0.0);
+        const double v = masked ? 0.0 : 1.0 / dg;
         d64[g] = v;
         if (d32) d32[g] = (float)v;
     }
@@ -1354,7 +1404,7 @@ __device__ __forceinline__ void batch_group(const BatchArgs &A, const BatchProb 
     const bool active = L.slot < pb.epb && e < pb.E;
     const int64_t ec = active ? e : 0;
     AxMesh<double> M{pb.p, pb.w, nullptr, reinterpret_cast<const double *>(pb.G), nullptr,
-                     pb.bmap, pb.E, pb.n_bnd, 0, OUT_ATOMIC};
+                     pb.bmap, pb.E, pb.n_bnd, 0, OUT_ATOMIC, nullptr, 1.0, 0.0};
     int32_t bm[N1];
     load_map<N1>(pb.bmap, L, ec, bm);
     __syncthreads();
@@ -1570,9 +1620,27 @@ hipError_t launch_diag(sem_ctx c, hipStream_t s) {
     if (e != hipSuccess) return e;
     e = launch_gather_sum(c, SEM_FP64, c->ws + L.wb, diag, s);
     if (e != hipSuccess) return e;
+    return launch_dinv(c, s);
+}
+
+hipError_t launch_dinv(sem_ctx c, hipStream_t s) {
+    const Layout &L = c->L;
+    double *d64 = dptr<double>(c, L.dinv64);
+    if (c->h2 != 0.0) {
+        // assembled mass Q^T B_L into d64 first (masked entries 0)
+        hipLaunchKernelGGL(k_local_values, dim3(vec_grid(c->n_local)), dim3(kVecBlock), 0, s, 3,
+                           c->E, c->n1, c->n_bnd, dptr<double>(c, L.dhat64),
+                           dptr<double>(c, L.G[0]), dptr<double>(c, L.B),
+                           (const double *)nullptr, dptr<int32_t>(c, L.bmap), d64,
+                           dptr<double>(c, L.wb));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = launch_gather_sum(c, SEM_FP64, c->ws + L.wb, d64, s);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_dinv, dim3(vec_grid(c->n_unique)), dim3(kVecBlock), 0, s, c->n_unique,
-                       c->n_bnd, dptr<uint8_t>(c, L.bdir), diag, dptr<double>(c, L.dinv64),
-                       L.dinv32 ? dptr<float>(c, L.dinv32) : nullptr);
+                       c->n_bnd, dptr<uint8_t>(c, L.bdir), dptr<double>(c, L.diag), c->h1, c->h2,
+                       d64, L.dinv32 ? dptr<float>(c, L.dinv32) : nullptr);
     return hipGetLastError();
 }
 

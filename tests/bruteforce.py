@@ -88,3 +88,38 @@ def assemble(xyz: np.ndarray, N: int):
         g = gid[e]
         A[np.ix_(g, g)] += Ae[e]
     return A, gid
+
+
+def mass_matrices(xyz: np.ndarray, xi: np.ndarray, w: np.ndarray):
+    """Dense element mass matrices [E, np, np] by quadrature at the GLL nodes
+    (sum_q w_q |J_q| phi_a(x_q) phi_b(x_q); the basis is nodal there)."""
+    n1 = xi.size
+    D = deriv_matrix_numpy(xi)
+    I = np.eye(n1)
+    Dr = np.kron(I, np.kron(I, D))
+    Ds = np.kron(I, np.kron(D, I))
+    Dt = np.kron(D, np.kron(I, I))
+    W = np.kron(w, np.kron(w, w))
+    npt = W.size
+    Phi = np.eye(npt)                               # phi_a at node q
+    E = xyz.shape[0]
+    X = xyz.reshape(E, 3, -1)
+    out = []
+    for e in range(E):
+        J = np.stack([np.stack([Dr @ X[e, l], Ds @ X[e, l], Dt @ X[e, l]], -1)
+                      for l in range(3)], 1)
+        detJ = np.linalg.det(J)
+        out.append(np.einsum("q,qa,qb->ab", W * detJ, Phi, Phi))
+    return np.array(out)
+
+
+def assemble_helmholtz(xyz: np.ndarray, N: int, h1: float, h2: float):
+    """Dense assembled h1 A + h2 M (no mask) in coordinate numbering."""
+    xi, w = gll_numpy(N)
+    He = h1 * element_matrices(xyz, xi, w) + h2 * mass_matrices(xyz, xi, w)
+    gid, n = coordinate_numbering(xyz)
+    H = np.zeros((n, n))
+    for e in range(He.shape[0]):
+        g = gid[e]
+        H[np.ix_(g, g)] += He[e]
+    return H, gid

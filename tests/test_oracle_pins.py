@@ -362,3 +362,87 @@ def test_quantized_G_error_levels():
         Pq = oracle.Problem(**{**P.__dict__, "G": Gq})
         err = np.max(np.abs(Pq.apply(u) - y)) / np.max(np.abs(y))
         assert lo < err < hi, (fmt, err)
+
+
+# ---------------------------------------------------------------- Helmholtz
+# Sec. II-A (last paragraph): the velocity equations use the same
+# discretization; their operator is h1 A + h2 B with B the lumped mass.
+def _dense_helm(H, n):
+    return np.stack([H.apply(e) for e in np.eye(n)], axis=1)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_helmholtz_against_dense_bruteforce(seed):
+    """Oracle h1 A + h2 B against the numpy quadrature assembly of stiffness
+    and (nodal-quadrature) mass on a deformed, re-oriented mesh."""
+    N, h1, h2 = 3, 0.7, 2.5
+    m = F.box(2, hi=(2 * np.pi,) * 3, deform=0.15, reorient_seed=seed, dirichlet=(0,) * 6)
+    P = oracle.setup(m, N)
+    Ho = _dense_helm(oracle.Helmholtz(P, h1, h2), P.n_u)
+    xi_np, _ = BF.gll_numpy(N)
+    Hb, gid_b = BF.assemble_helmholtz(m.coords(xi_np), N, h1, h2)
+    perm = np.full(P.n_u, -1)
+    perm[P.gid.ravel()] = gid_b.ravel()
+    np.testing.assert_allclose(Ho, Hb[np.ix_(perm, perm)], atol=1e-11 * np.abs(Hb).max())
+
+
+def test_helmholtz_constant_mode_and_spd():
+    """Without Dirichlet conditions A 1 = 0, so H 1 = h2 Q^T B_L and
+    1^T H 1 = h2 * volume; H is SPD with smallest eigenvalue at least h2
+    times the smallest assembled mass entry."""
+    N, h1, h2 = 4, 1.3, 0.8
+    m = F.box((2, 1, 2), hi=(2.0, 1.0, 1.5), dirichlet=(0,) * 6)
+    P = oracle.setup(m, N)
+    H = oracle.Helmholtz(P, h1, h2)
+    one = np.ones(P.n_u)
+    y = H.apply(one)
+    assert abs(one @ y - h2 * 3.0) < 1e-12 * h2 * 3.0        # volume 2 * 1 * 1.5
+    bm = oracle.qt(P.gid, P.B, P.n_u)
+    np.testing.assert_allclose(y, h2 * bm, rtol=1e-11, atol=1e-12 * h2 * bm.max())
+    Hd = _dense_helm(H, P.n_u)
+    assert np.abs(Hd - Hd.T).max() < 1e-13 * np.abs(Hd).max()
+    np.linalg.cholesky(Hd)
+    assert np.linalg.eigvalsh(Hd)[0] >= h2 * bm.min() * (1 - 1e-10)
+
+
+def test_helmholtz_jacobi_and_pcg_against_dense():
+    N, h1, h2 = 3, 0.4, 5.0
+    m = F.box(2, hi=(2 * np.pi,) * 3, deform=0.1, reorient_seed=3)
+    P = oracle.setup(m, N)
+    H = oracle.Helmholtz(P, h1, h2)
+    Hd = _dense_helm(H, P.n_u)
+    keep = P.dirichlet == 0
+    np.testing.assert_allclose(H.diag[keep], np.diag(Hd)[keep], rtol=1e-12)
+    assert (H.dinv[~keep] == 0).all()
+    b = P.rhs_unique(F.random_unique(P.n_u, 9))
+    x, info = H.pcg(b, 1e-12)
+    assert info["status"] == 0 and info["true_rel_residual"] <= 1e-12
+    xs = np.zeros(P.n_u)
+    xs[keep] = np.linalg.solve(Hd[np.ix_(keep, keep)], b[keep])
+    kappa = np.linalg.cond(Hd[np.ix_(keep, keep)])
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < kappa * 1e-12 * 10
+    # h1 = 1, h2 = 0 is the Poisson operator
+    u = F.random_unique(P.n_u, 2)
+    assert np.array_equal(oracle.Helmholtz(P, 1.0, 0.0).apply(u), P.apply(u))
+
+
+def _helmholtz_manufactured_error(K, N, h1, h2):
+    """(-h1 lap + h2) u = f on [0, 2pi]^3, u = sin x sin y sin z (zero on
+    the boundary), f = (3 h1 + h2) u: max nodal error of the discrete solution."""
+    m = F.box(K, hi=(2 * np.pi,) * 3)
+    P = oracle.setup(m, N)
+    ue_L = np.sin(P.xyz[:, 0]) * np.sin(P.xyz[:, 1]) * np.sin(P.xyz[:, 2])
+    b = P.rhs_local((3 * h1 + h2) * ue_L)
+    x, info = oracle.Helmholtz(P, h1, h2).pcg(b, 1e-13)
+    ue = np.zeros(P.n_u)
+    ue[P.gid.ravel()] = ue_L.reshape(K ** 3, -1).ravel()
+    return np.max(np.abs(x - ue))
+
+
+def test_helmholtz_manufactured_spectral_convergence():
+    """Exponential decay in N for two (h1, h2) pairs: a dropped or misweighted
+    mass term leaves an O(1) error instead."""
+    for h1, h2 in ((1.0, 10.0), (0.05, 1.0)):
+        errs = [_helmholtz_manufactured_error(2, N, h1, h2) for N in (3, 5, 7)]
+        assert errs[1] < errs[0] / 20 and errs[2] < errs[1] / 20, (h1, h2, errs)
+        assert errs[-1] < 1e-5
