@@ -362,6 +362,39 @@ sem_status sem_cg_solve_static(sem_ctx ctx, const double *b, double *x,
                                sem_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * Projection onto previous solutions (successive right-hand sides, Sec. II-B:
+ * the solution of a time step is projected on earlier solution vectors to
+ * lower the Krylov start residual; Sec. VI-A: on GPUs the space is reset
+ * every 20 steps).  A projection space of one context keeps up to
+ * max_vectors (1..32) A-orthonormal vectors X and A X (A the context's
+ * operator, Poisson or Helmholtz, in FP64) in a caller-owned device
+ * workspace.  sem_proj_solve(b, x): x_bar = X X^T b (the A-norm best
+ * approximation in span X), r0 = b - (A X) X^T b, then the context's solver
+ * (opts as for sem_cg_solve, any precision) computes the correction d with
+ * ||r0 - A d|| <= tol ||b||, x = x_bar + d; d, A-orthogonalised against X
+ * twice (classical Gram-Schmidt), is appended.  When the space is full it is
+ * reset and restarts from the new solution.  *start_rel_residual (may be
+ * NULL) receives ||r0|| / ||b||; info->true_rel_residual is that of x for b
+ * (recomputed in FP64).  The context needs opts.solver = 1; b and x are
+ * device unique vectors (solver order, FP64, 16-byte aligned); x is output.
+ * Returns the solver's status (SEM_ERR_NOT_CONVERGED also when the final
+ * true residual misses tol; the space is then not updated).
+ * ------------------------------------------------------------------------- */
+typedef struct sem_proj_s *sem_proj;
+
+sem_status sem_proj_create(sem_ctx ctx, int max_vectors, sem_proj *out);
+void       sem_proj_free(sem_proj proj);
+const char *sem_proj_last_error(sem_proj proj);
+sem_status sem_proj_workspace_size(sem_proj proj, size_t *bytes);
+sem_status sem_proj_bind_workspace(sem_proj proj, void *dev_ptr, size_t bytes,
+                                   sem_stream stream);
+sem_status sem_proj_reset(sem_proj proj);                 /* empty the space  */
+sem_status sem_proj_size(sem_proj proj, int *n_vectors);  /* vectors held     */
+sem_status sem_proj_solve(sem_proj proj, const double *b, double *x,
+                          const sem_solve_options *opts, sem_solve_info *info,
+                          double *start_rel_residual, sem_stream stream);
+
+/* ---------------------------------------------------------------------------
  * Batched solve: many independent Poisson problems (meshes of different
  * sizes and orders N <= 9, each set up as its own context with geometry and
  * opts.solver = 1) solved together by Jacobi-PCG in FP64.  Every CG phase

@@ -270,6 +270,68 @@ class Helmholtz:
         return float(np.linalg.norm(r) / np.linalg.norm(b))
 
 
+class Projection:
+    """Projection of successive solutions (Sec. II-B: the solution of the
+    current time step is projected on previous solution vectors to lower the
+    start residual; the scheme of the reference cited there, Fischer 1998;
+    Sec. VI-A: the GPU code resets the space every 20 steps).
+
+    ``op`` is a Problem (Poisson) or a Helmholtz: it provides apply(u) and
+    pcg(b, tol).  The space holds A-orthonormal vectors X (columns) and
+    A X; each solve returns x = x_bar + d with x_bar = X X^T b and d from
+    PCG on r0 = b - A x_bar to ||r0 - A d|| <= tol ||b||; d is then
+    A-orthogonalised against X (Gram-Schmidt in the A inner product, twice)
+    and appended, after a reset of a full space the whole x instead."""
+
+    def __init__(self, op, max_vectors: int = 20):
+        self.op = op
+        self.max_vectors = max_vectors
+        self.X = []
+        self.AX = []
+
+    def solve(self, b: np.ndarray, tol: float):
+        b = np.asarray(b, dtype=np.float64)
+        bnorm = np.linalg.norm(b)
+        xbar = np.zeros_like(b)
+        Axbar = np.zeros_like(b)
+        for xi, axi in zip(self.X, self.AX):
+            c = xi @ b                   # x_i^T A x* = x_i^T b
+            xbar += c * xi
+            Axbar += c * axi
+        r0 = b - Axbar
+        rel0 = np.linalg.norm(r0) / bnorm if bnorm > 0 else 0.0
+        info = {"start_rel_residual": float(rel0), "iterations": 0}
+        if bnorm == 0 or rel0 <= tol:
+            info["true_rel_residual"] = float(np.linalg.norm(b - self.op.apply(xbar)) / bnorm) \
+                if bnorm > 0 else 0.0
+            return xbar, info
+        d, pinfo = self.op.pcg(r0, tol / rel0)
+        info["iterations"] = pinfo["iterations"]
+        x = xbar + d
+        info["true_rel_residual"] = float(np.linalg.norm(b - self.op.apply(x)) / bnorm)
+        if len(self.X) == self.max_vectors:
+            self.X, self.AX = [], []
+            d = x.copy()
+        self._append(d)
+        return x, info
+
+    def _append(self, v: np.ndarray):
+        v = v.copy()
+        av = self.op.apply(v)
+        before = v @ av
+        for _ in range(2):
+            for xi, axi in zip(self.X, self.AX):
+                c = xi @ av
+                v -= c * xi
+                av -= c * axi
+        nrm2 = v @ av
+        if not (nrm2 > 1e-24 * before) or not (nrm2 > 0):
+            return
+        s = 1.0 / np.sqrt(nrm2)
+        self.X.append(v * s)
+        self.AX.append(av * s)
+
+
 def setup(mesh, N: int, xyz=None) -> Problem:
     """Oracle set-up of a mesh at order N: GLL, D, G, B, numbering, Jacobi."""
     xi, rho = gll(N)

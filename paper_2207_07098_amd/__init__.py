@@ -106,7 +106,9 @@ EXPORTS = ["sem_gll", "sem_setup", "sem_free", "sem_last_error", "sem_query",
            "sem_autotune", "sem_batch_create", "sem_batch_free", "sem_batch_last_error",
            "sem_batch_workspace_size", "sem_batch_bind_workspace", "sem_batch_set_tile",
            "sem_batch_autotune", "sem_batch_solve", "sem_cg_solve_static",
-           "sem_set_helmholtz"]
+           "sem_set_helmholtz", "sem_proj_create", "sem_proj_free", "sem_proj_last_error",
+           "sem_proj_workspace_size", "sem_proj_bind_workspace", "sem_proj_reset",
+           "sem_proj_size", "sem_proj_solve"]
 
 _lib = None
 
@@ -142,6 +144,14 @@ def lib():
         "sem_cg_solve": ([P, P, P, P, P, P], i32),
         "sem_cg_solve_static": ([P, P, P, P, P, P], i32),
         "sem_set_helmholtz": ([P, ctypes.c_double, ctypes.c_double, P], i32),
+        "sem_proj_create": ([P, i32, P], i32),
+        "sem_proj_free": ([P], None),
+        "sem_proj_last_error": ([P], ctypes.c_char_p),
+        "sem_proj_workspace_size": ([P, P], i32),
+        "sem_proj_bind_workspace": ([P, P, ctypes.c_size_t, P], i32),
+        "sem_proj_reset": ([P], i32),
+        "sem_proj_size": ([P, P], i32),
+        "sem_proj_solve": ([P, P, P, P, P, P, P], i32),
         "sem_get_tile": ([P, i32, P], i32),
         "sem_set_tile": ([P, i32, P], i32),
         "sem_autotune": ([P, i32, i32, ctypes.c_char_p, P, P, i32, P, P], i32),
@@ -434,6 +444,66 @@ class Operator:
         if pos is None:
             pos = self.numbering()[1]
         return v_solver[pos]
+
+
+class Projection:
+    """Projection space of an Operator (successive right-hand sides): each
+    solve starts from the A-norm best approximation in the span of earlier
+    solution corrections (up to ``max_vectors``, reset when full)."""
+
+    def __init__(self, op, max_vectors: int = 20):
+        torch = _torch()
+        self.op = op
+        self._p = ctypes.c_void_p()
+        op._check(lib().sem_proj_create(op._ctx, max_vectors, ctypes.byref(self._p)))
+        nb = ctypes.c_size_t()
+        self._check(lib().sem_proj_workspace_size(self._p, ctypes.byref(nb)))
+        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=op.device)
+        self._check(lib().sem_proj_bind_workspace(self._p, _dptr(self.workspace), nb.value,
+                                                  _stream_handle()))
+
+    def _check(self, st):
+        if st:
+            raise SemError(st, lib().sem_proj_last_error(self._p).decode())
+
+    def __del__(self):
+        try:
+            if self._p:
+                lib().sem_proj_free(self._p)
+                self._p = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    def size(self) -> int:
+        n = ctypes.c_int()
+        self._check(lib().sem_proj_size(self._p, ctypes.byref(n)))
+        return n.value
+
+    def reset(self):
+        self._check(lib().sem_proj_reset(self._p))
+
+    def solve(self, b, x=None, tol: float = 1e-10, precision: str = "fp64",
+              max_iter: int = 100000, inner_tol: Optional[float] = None,
+              raise_on_error: bool = True):
+        """Returns (x, info dict with 'start_rel_residual')."""
+        o = SolveOptions()
+        lib().sem_default_solve_options(ctypes.byref(o))
+        o.tol = tol
+        o.max_iter = max_iter
+        o.precision = PRECISIONS[precision]
+        if inner_tol is not None:
+            o.inner_tol = inner_tol
+        if x is None:
+            x = self.op.vector()
+        info = SolveInfo()
+        rel0 = ctypes.c_double()
+        st = lib().sem_proj_solve(self._p, _dptr(b), _dptr(x), ctypes.byref(o),
+                                  ctypes.byref(info), ctypes.byref(rel0), _stream_handle())
+        d = info.as_dict()
+        d["start_rel_residual"] = rel0.value
+        if st and raise_on_error:
+            self._check(st)
+        return x, d
 
 
 class Batch:

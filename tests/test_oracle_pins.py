@@ -446,3 +446,78 @@ def test_helmholtz_manufactured_spectral_convergence():
         errs = [_helmholtz_manufactured_error(2, N, h1, h2) for N in (3, 5, 7)]
         assert errs[1] < errs[0] / 20 and errs[2] < errs[1] / 20, (h1, h2, errs)
         assert errs[-1] < 1e-5
+
+
+# ---------------------------------------------------------------- projection
+# Sec. II-B: projection of the solution on previous solutions (successive
+# right-hand sides); Sec. VI-A: the GPU variant resets the space every 20 steps.
+def _proj_problem():
+    m = F.box(2, hi=(2 * np.pi,) * 3, deform=0.1, reorient_seed=2)
+    P = oracle.setup(m, 4)
+    keep = P.dirichlet == 0
+    return P, keep
+
+
+def test_projection_optimal_in_a_norm_and_orthonormal():
+    """x_bar is the A-norm best approximation of A^-1 b in span X, found
+    independently by a dense least-squares solve; X is A-orthonormal."""
+    P, keep = _proj_problem()
+    A = _dense(P)[np.ix_(keep, keep)]
+    pr = oracle.Projection(P, max_vectors=8)
+    for k in range(5):
+        pr.solve(P.rhs_unique(F.random_unique(P.n_u, 100 + k)), 1e-12)
+    X = np.stack(pr.X, axis=1)[keep]
+    np.testing.assert_allclose(X.T @ A @ X, np.eye(X.shape[1]), atol=1e-10)
+    b = P.rhs_unique(F.random_unique(P.n_u, 7))
+    xs = np.linalg.solve(A, b[keep])
+    # minimise ||xs - X c||_A: with A = L L^T, least squares on L^T X c = L^T xs
+    L = np.linalg.cholesky(A)
+    c, *_ = np.linalg.lstsq(L.T @ X, L.T @ xs, rcond=None)
+    xbar_dense = X @ c
+    xbar = sum((xi @ b) * xi for xi in pr.X)[keep]
+    np.testing.assert_allclose(xbar, xbar_dense, atol=1e-9 * np.abs(xs).max())
+
+
+def test_projection_exact_for_solutions_in_the_span():
+    """A right-hand side whose solution is a combination of earlier ones
+    starts at (near) zero residual and needs no iterations; the solve is
+    otherwise the plain PCG's to tolerance."""
+    P, keep = _proj_problem()
+    pr = oracle.Projection(P, max_vectors=20)
+    b1 = P.rhs_unique(F.random_unique(P.n_u, 1))
+    b2 = P.rhs_unique(F.random_unique(P.n_u, 2))
+    x1, i1 = pr.solve(b1, 1e-12)
+    x2, i2 = pr.solve(b2, 1e-12)
+    assert i1["start_rel_residual"] == 1.0 and i1["iterations"] > 10
+    assert i2["true_rel_residual"] <= 1e-12
+    x3, i3 = pr.solve(2.0 * b1 - 0.5 * b2, 1e-10)
+    assert i3["start_rel_residual"] < 1e-10 and i3["iterations"] == 0
+    np.testing.assert_allclose(x3, 2.0 * x1 - 0.5 * x2, atol=1e-9 * np.abs(x1).max())
+
+
+def test_projection_reset_when_full():
+    P, keep = _proj_problem()
+    pr = oracle.Projection(P, max_vectors=3)
+    sizes = []
+    for k in range(7):
+        pr.solve(P.rhs_unique(F.random_unique(P.n_u, 50 + k)), 1e-11)
+        sizes.append(len(pr.X))
+    assert sizes == [1, 2, 3, 1, 2, 3, 1]
+
+
+def test_projection_lowers_iterations_for_slowly_varying_rhs():
+    """f_k = sin(x - 0.05 k) sin y sin z: after a few steps the projected
+    start residual is far below 1 and PCG needs far fewer iterations."""
+    m = F.box(3, hi=(2 * np.pi,) * 3, deform=0.05)
+    P = oracle.setup(m, 5)
+    X = P.xyz
+    pr = oracle.Projection(P, max_vectors=20)
+    its, rel0 = [], []
+    for k in range(8):
+        fL = np.sin(X[:, 0] - 0.05 * k) * np.sin(X[:, 1]) * np.sin(X[:, 2])
+        x, info = pr.solve(P.rhs_local(fL), 1e-10)
+        assert info["true_rel_residual"] <= 1e-10
+        its.append(info["iterations"])
+        rel0.append(info["start_rel_residual"])
+    assert rel0[0] == 1.0 and max(rel0[3:]) < 1e-3
+    assert max(its[3:]) < 0.5 * its[0]
