@@ -521,3 +521,111 @@ def test_projection_lowers_iterations_for_slowly_varying_rhs():
         rel0.append(info["start_rel_residual"])
     assert rel0[0] == 1.0 and max(rel0[3:]) < 1e-3
     assert max(its[3:]) < 0.5 * its[0]
+
+
+# ---------------------------------------------------------------- hybrid Schwarz + GMRES
+# Sec. II-B: restarted GMRES with an overlapping additive Schwarz
+# preconditioner and a coarse-grid solve of 10 P-CG iterations.
+from oracle import hybrid as HY  # noqa: E402
+
+
+def _box_nodes(hs, e, N):
+    """Unique nodes of the whole extended box of element e (lattice, all
+    (N+3)^3 points), for an axis-aligned box mesh."""
+    box = np.arange(-1, N + 2)
+    return np.array([hs.key[tuple(int(v) for v in (N * hs.org[e] + np.array([i, j, k])))]
+                     for k in box for j in box for i in box])
+
+
+@pytest.mark.parametrize("widths", [None, [[1.0, 1.6, 0.7], [0.8, 1.0, 1.3], [1.2, 0.9, 1.0]]])
+def test_schwarz_local_operator_is_the_assembled_submatrix(widths):
+    """On affine axis-aligned boxes the element operator is exactly
+    separable, so the local operator of the extended box of an element with
+    six neighbours equals the assembled A restricted to the box's nodes
+    (neighbour lengths and GLL spacing included)."""
+    N = 4
+    m = F.box(3, hi=(3.0, 2.5, 2.0), widths=widths, dirichlet=(0,) * 6)
+    P = oracle.setup(m, N)
+    hs = HY.HybridSchwarz(m, P)
+    A = _dense(P)
+    Ainc, keep, gmap = hs.local[13]                         # the centre element
+    assert keep.all()
+    ids = _box_nodes(hs, 13, N)
+    np.testing.assert_allclose(Ainc, A[np.ix_(ids, ids)], atol=1e-12 * np.abs(A).max())
+    # face extensions map to the neighbours' first layer; edges/corners carry nothing
+    assert (gmap >= 0).sum() == (N + 1) ** 3 + 6 * (N + 1) ** 2
+
+
+def test_schwarz_boundary_element_drops_planes():
+    """Corner element of a Dirichlet box: both the extension planes and the
+    element's own face planes on the boundary are dropped; what remains is
+    the assembled (masked) operator on the kept box points."""
+    N = 3
+    m = F.box(3, hi=(3.0, 3.0, 3.0))
+    P = oracle.setup(m, N)
+    hs = HY.HybridSchwarz(m, P)
+    A = _dense(P)
+    Ainc, keep, gmap = hs.local[0]
+    ids = _box_nodes_partial(hs, 0, N, keep)
+    np.testing.assert_allclose(Ainc, A[np.ix_(ids, ids)], atol=1e-12 * np.abs(A).max())
+    assert keep.sum() == (N + 1) ** 3              # per direction: N+3 less the ghost and the face point
+
+
+def _box_nodes_partial(hs, e, N, keep):
+    box = np.arange(-1, N + 2)
+    pts = [(i, j, k) for k in box for j in box for i in box]
+    return np.array([hs.key[tuple(int(v) for v in (N * hs.org[e] + np.array(p)))]
+                     for p, kp in zip(pts, keep) if kp])
+
+
+def test_coarse_interpolation_reproduces_trilinear_fields():
+    """Vertex values of a function in span{1, x, y, z, xy, yz, xz, xyz}
+    interpolate exactly to the GLL nodes of affine axis-aligned elements."""
+    N = 5
+    m = F.box((2, 3, 2), hi=(2.0, 3.0, 1.0), widths=[[1.0, 2.0], [1.0, 0.5, 1.5], [1.0, 1.0]],
+              dirichlet=(0,) * 6)
+    P = oracle.setup(m, N)
+    hs = HY.HybridSchwarz(m, P)
+    f = lambda X: 1 + 2 * X[0] - X[1] + 0.5 * X[2] + X[0] * X[1] - 0.3 * X[1] * X[2] + 0.1 * X[0] * X[1] * X[2]
+    Xc = np.zeros((3, hs.P0.n_u))
+    for d in range(3):
+        Xc[d, hs.P0.gid.ravel()] = hs.P0.xyz[:, d].reshape(-1)
+    Xf = np.zeros((3, P.n_u))
+    for d in range(3):
+        Xf[d, P.gid.ravel()] = P.xyz[:, d].reshape(-1)
+    np.testing.assert_allclose(hs.interp @ f(Xc), f(Xf), atol=1e-12)
+
+
+def test_fgmres_residuals_are_the_krylov_minima():
+    """Without preconditioner the k-th GMRES residual is min ||b - A y|| over
+    the k-dimensional Krylov space, computed independently by QR and least
+    squares on the explicit Krylov basis."""
+    m = F.box(2, hi=(1.0, 1.0, 1.0), deform=0.0)
+    P = oracle.setup(m, 3)
+    b = P.rhs_unique(F.random_unique(P.n_u, 8))
+    _, info = HY.fgmres(P.apply, lambda v: v, b, 1e-30, restart=8, max_iter=8)
+    K = [b / np.linalg.norm(b)]
+    for k in range(1, 9):
+        Q, _ = np.linalg.qr(np.stack(K, 1))
+        AQ = np.stack([P.apply(q) for q in Q.T], 1)
+        y, *_ = np.linalg.lstsq(AQ, b, rcond=None)
+        ref = np.linalg.norm(b - AQ @ y) / np.linalg.norm(b)
+        assert abs(info["history"][k - 1] - ref) <= 1e-9 * max(ref, 1e-3), (k, info["history"][k - 1], ref)
+        K.append(P.apply(K[-1]))
+        K[-1] /= np.linalg.norm(K[-1])
+
+
+def test_hybrid_schwarz_gmres_solves_and_cuts_iterations():
+    """The preconditioned GMRES reaches the requested true residual, agrees
+    with the PCG solution, and needs far fewer iterations than Jacobi-PCG
+    (the coarse grid matters most on the stretched O-grid)."""
+    for m, N, factor in ((F.box(4, hi=(2 * np.pi,) * 3, deform=0.05), 5, 5),
+                         (F.ogrid(8, 3, 4), 3, 3)):
+        P = oracle.setup(m, N)
+        hs = HY.HybridSchwarz(m, P)
+        b = P.rhs_unique(F.random_unique(P.n_u, 3))
+        x, info = HY.fgmres(P.apply, hs.apply, b, 1e-10)
+        xp, pinfo = P.pcg(b, 1e-10)
+        assert info["true_rel_residual"] <= 1e-10
+        assert np.abs(x - xp).max() < 1e-8 * np.abs(xp).max()
+        assert factor * info["iterations"] < pinfo["iterations"], (info["iterations"], pinfo["iterations"])
