@@ -395,6 +395,55 @@ sem_status sem_proj_solve(sem_proj proj, const double *b, double *x,
                           double *start_rel_residual, sem_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * Pressure solver (Sec. II-B): restarted GMRES with a hybrid Schwarz
+ * preconditioner -- overlapping additive Schwarz plus a coarse-grid solve of
+ * 10 P-CG iterations.  Readings where the paper gives no detail:
+ *   local solves   every element extended by one node layer across each face
+ *                  that has a neighbour; the separable operator
+ *                  M x M x K + M x K x M + K x M x M of the box [-1, N+1]^3
+ *                  (1D GLL stiffness K and lumped mass M of the neighbour-
+ *                  element-neighbour line, mean edge lengths; edge and corner
+ *                  points of the extension carry no data; a face without
+ *                  neighbour drops its extension plane, a Dirichlet face also
+ *                  the element's face plane), solved by fast diagonalisation;
+ *                  summed with weights 1 / (subdomains holding the node);
+ *   coarse grid    the N = 1 operator on the element vertices (trilinear map),
+ *                  trilinear interpolation P and restriction P^T, 10 Jacobi-PCG
+ *                  iterations from zero;
+ *   combination    z = z_Schwarz + z_coarse; the coarse PCG makes it nonlinear,
+ *                  so GMRES is the flexible variant (right preconditioning,
+ *                  preconditioned vectors kept), restarted every `restart`
+ *                  steps, two classical Gram-Schmidt passes, FP64.
+ * The context must have geometry and opts.solver = 1, 2 <= N <= 13, and the
+ * Poisson operator (SEM_ERR_UNSUPPORTED for a Helmholtz pair).  The solver
+ * owns an internal N = 1 context (host data); device memory is one
+ * caller-owned workspace (about (2 restart + 5) unique vectors, the
+ * eigenvectors 3 (N+3)^2 and extension maps 6 (N+1)^2 per element, and the
+ * coarse context's workspace).  sem_gmres_bind_workspace uploads the
+ * preconditioner and sets up the coarse geometry (synchronises `stream`).
+ * sem_gmres_solve: b, x device unique vectors (solver order, FP64); opts:
+ * tol (true relative residual, checked in FP64 at each restart), max_iter,
+ * zero_guess; precision must be SEM_FP64.  info->iterations counts GMRES
+ * steps, info->restarts restarts.  sem_gmres_precondition applies the
+ * preconditioner (parts: SEM_PC_SCHWARZ and/or SEM_PC_COARSE) to r -> z.
+ * ------------------------------------------------------------------------- */
+typedef struct sem_gmres_s *sem_gmres;
+#define SEM_PC_SCHWARZ 1u
+#define SEM_PC_COARSE  2u
+
+sem_status sem_gmres_create(sem_ctx ctx, int restart, sem_gmres *out);
+void       sem_gmres_free(sem_gmres solver);
+const char *sem_gmres_last_error(sem_gmres solver);
+sem_status sem_gmres_workspace_size(sem_gmres solver, size_t *bytes);
+sem_status sem_gmres_bind_workspace(sem_gmres solver, void *dev_ptr, size_t bytes,
+                                    sem_stream stream);
+sem_status sem_gmres_precondition(sem_gmres solver, const double *r, double *z,
+                                  unsigned parts, sem_stream stream);
+sem_status sem_gmres_solve(sem_gmres solver, const double *b, double *x,
+                           const sem_solve_options *opts, sem_solve_info *info,
+                           sem_stream stream);
+
+/* ---------------------------------------------------------------------------
  * Batched solve: many independent Poisson problems (meshes of different
  * sizes and orders N <= 9, each set up as its own context with geometry and
  * opts.solver = 1) solved together by Jacobi-PCG in FP64.  Every CG phase

@@ -108,7 +108,9 @@ EXPORTS = ["sem_gll", "sem_setup", "sem_free", "sem_last_error", "sem_query",
            "sem_batch_autotune", "sem_batch_solve", "sem_cg_solve_static",
            "sem_set_helmholtz", "sem_proj_create", "sem_proj_free", "sem_proj_last_error",
            "sem_proj_workspace_size", "sem_proj_bind_workspace", "sem_proj_reset",
-           "sem_proj_size", "sem_proj_solve"]
+           "sem_proj_size", "sem_proj_solve", "sem_gmres_create", "sem_gmres_free",
+           "sem_gmres_last_error", "sem_gmres_workspace_size", "sem_gmres_bind_workspace",
+           "sem_gmres_precondition", "sem_gmres_solve"]
 
 _lib = None
 
@@ -152,6 +154,13 @@ def lib():
         "sem_proj_reset": ([P], i32),
         "sem_proj_size": ([P, P], i32),
         "sem_proj_solve": ([P, P, P, P, P, P, P], i32),
+        "sem_gmres_create": ([P, i32, P], i32),
+        "sem_gmres_free": ([P], None),
+        "sem_gmres_last_error": ([P], ctypes.c_char_p),
+        "sem_gmres_workspace_size": ([P, P], i32),
+        "sem_gmres_bind_workspace": ([P, P, ctypes.c_size_t, P], i32),
+        "sem_gmres_precondition": ([P, P, P, u32, P], i32),
+        "sem_gmres_solve": ([P, P, P, P, P, P], i32),
         "sem_get_tile": ([P, i32, P], i32),
         "sem_set_tile": ([P, i32, P], i32),
         "sem_autotune": ([P, i32, i32, ctypes.c_char_p, P, P, i32, P, P], i32),
@@ -501,6 +510,60 @@ class Projection:
                                   ctypes.byref(info), ctypes.byref(rel0), _stream_handle())
         d = info.as_dict()
         d["start_rel_residual"] = rel0.value
+        if st and raise_on_error:
+            self._check(st)
+        return x, d
+
+
+class PressureSolver:
+    """Restarted flexible GMRES with the hybrid Schwarz preconditioner
+    (overlapping element solves + 10-iteration coarse PCG) on an Operator."""
+
+    SCHWARZ, COARSE = 1, 2
+
+    def __init__(self, op, restart: int = 30):
+        torch = _torch()
+        self.op = op
+        self._g = ctypes.c_void_p()
+        op._check(lib().sem_gmres_create(op._ctx, restart, ctypes.byref(self._g)))
+        nb = ctypes.c_size_t()
+        self._check(lib().sem_gmres_workspace_size(self._g, ctypes.byref(nb)))
+        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=op.device)
+        self._check(lib().sem_gmres_bind_workspace(self._g, _dptr(self.workspace), nb.value,
+                                                   _stream_handle()))
+
+    def _check(self, st):
+        if st:
+            raise SemError(st, lib().sem_gmres_last_error(self._g).decode())
+
+    def __del__(self):
+        try:
+            if self._g:
+                lib().sem_gmres_free(self._g)
+                self._g = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    def precondition(self, r, z=None, parts: int = 3):
+        if z is None:
+            z = self.op.vector()
+        self._check(lib().sem_gmres_precondition(self._g, _dptr(r), _dptr(z), parts,
+                                                 _stream_handle()))
+        return z
+
+    def solve(self, b, x=None, tol: float = 1e-10, max_iter: int = 10000,
+              raise_on_error: bool = True):
+        o = SolveOptions()
+        lib().sem_default_solve_options(ctypes.byref(o))
+        o.tol = tol
+        o.max_iter = max_iter
+        o.zero_guess = 1 if x is None else 0
+        if x is None:
+            x = self.op.vector()
+        info = SolveInfo()
+        st = lib().sem_gmres_solve(self._g, _dptr(b), _dptr(x), ctypes.byref(o),
+                                   ctypes.byref(info), _stream_handle())
+        d = info.as_dict()
         if st and raise_on_error:
             self._check(st)
         return x, d

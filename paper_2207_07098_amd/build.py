@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsem.so")
-SOURCES = ["sem_host.hip", "sem_kernels.hip", "sem_batch.hip", "sem_proj.hip", "sem_numbering.cpp"]
+SOURCES = ["sem_host.hip", "sem_kernels.hip", "sem_batch.hip", "sem_proj.hip", "sem_gmres.hip", "sem_numbering.cpp"]
 ARCH = os.environ.get("SEM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

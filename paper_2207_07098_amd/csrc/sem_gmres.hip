@@ -1,0 +1,1019 @@
+// Pressure solver of Karp et al. (arXiv 2207.07098), Sec. II-B: restarted
+// GMRES preconditioned by an overlapping additive Schwarz method with a
+// coarse-grid solve of 10 P-CG iterations (the hybrid Schwarz scheme of
+// Lottes & Fischer cited there).
+//
+//  * Local solves: every element extended by one node layer across each
+//    face that has a neighbour, on the box [-1, N+1]^3 of local indices
+//    (edge and corner points of the extension carry no data); the operator
+//    on the box is the separable approximation
+//    M_t x M_s x K_r + M_t x K_s x M_r + K_t x M_s x M_r from 1D stiffness K
+//    and lumped mass M of the neighbour-element-neighbour line (mean edge
+//    lengths), solved by fast diagonalisation: per direction K S = M S Lambda
+//    (host, once), then u = S (Lambda_r + Lambda_s + Lambda_t)^-1 S^T r with
+//    three tensor contractions each way (one workgroup per element, k-column
+//    in registers, r/s contractions through LDS).
+//  * Additive combination with counting weights W (1 / number of subdomains
+//    holding the node).
+//  * Coarse grid: the N = 1 operator of the same library on the element
+//    vertices (its own context), trilinear interpolation P and restriction
+//    P^T, 10 Jacobi-PCG iterations from zero.
+//  * Flexible GMRES(m) (the coarse PCG makes the preconditioner nonlinear):
+//    Arnoldi with two classical Gram-Schmidt passes, Givens rotations on the
+//    host, FP64 throughout.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <thread>
+#include <unordered_map>
+
+#include "sem_internal.h"
+
+using namespace sem;
+
+namespace {
+
+constexpr int kGmBlock = 256;
+constexpr int kGmGrid = 2048;
+constexpr int kGmMaxVec = 32;            // basis vectors in one multi-dot
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+unsigned gm_grid(int64_t n) {
+    const int64_t g = (n + kGmBlock - 1) / kGmBlock;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, kGmGrid));
+}
+
+__device__ double gm_block_sum(double v, double *red) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off, 64);
+        v += ((lane ^ off) < (int)blockDim.x - wv * 64) ? o : 0.0;
+    }
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int q = 0; q < nw; ++q) s += red[q];
+    return s;
+}
+
+__device__ __forceinline__ int64_t gm_interior(int64_t n_bnd, int64_t e, int i, int j, int k, int N) {
+    const int nm = N - 1;
+    return n_bnd + e * (int64_t)(nm * nm * nm) + ((k - 1) * nm + (j - 1)) * nm + (i - 1);
+}
+
+__device__ __forceinline__ int gm_ring(int i, int j, int N) {
+    if (j == 0) return i;
+    if (j == N) return N + 1 + 2 * (N - 1) + i;
+    return N + 1 + 2 * (j - 1) + (i == 0 ? 0 : 1);
+}
+
+__device__ __forceinline__ int gm_bpos(int i, int j, int k, int n1) {
+    const int N = n1 - 1, C = n1 * n1;
+    if (k == 0) return i + n1 * j;
+    if (k == N) return C + (N - 1) * 4 * N + i + n1 * j;
+    return C + (k - 1) * 4 * N + gm_ring(i, j, N);
+}
+
+// Solver index of local point (i,j,k) of element e, or -1 on a Dirichlet node.
+__device__ __forceinline__ int64_t gm_node(const int32_t *bmap, int64_t n_bnd, int64_t e, int i,
+                                           int j, int k, int N, int nb) {
+    if (i == 0 || i == N || j == 0 || j == N || k == 0 || k == N) {
+        const int32_t m = bmap[e * nb + gm_bpos(i, j, k, N + 1)];
+        return m < 0 ? -1 : (int64_t)m;
+    }
+    return gm_interior(n_bnd, e, i, j, k, N);
+}
+
+struct FdmParams {
+    const double *r;          // residual (unique, solver order)
+    double *z;                // sum of local solutions (atomic)
+    const double *S;          // [E][3][NE][NE] eigenvectors S[a][m]
+    const double *lam;        // [E][3][NE]
+    const int32_t *ghost;     // [E][6][(N+1)^2] solver index or -1
+    const int32_t *bmap;
+    int64_t E, n_bnd;
+    int N, nb;
+};
+
+// Box index a in 0..NE-1 <-> local index a - 1.  A lane owns the column
+// (a, b) of the box over c (k-direction) in registers.
+template <int NE>
+__global__ void __launch_bounds__(256) k_fdm(FdmParams P) {
+    constexpr int C = NE * NE;
+    const int N = NE - 3, n1 = NE - 2;
+    __shared__ double Sl[3][C];
+    __shared__ double Ll[3][NE];
+    __shared__ double box[NE][NE][NE + 1];        // [c][b][a], padded
+    const int64_t e = blockIdx.x;
+    const int t = threadIdx.x;
+    const bool lane_on = t < C;
+    const int a = t % NE, b = t / NE;
+    for (int q = t; q < 3 * C; q += blockDim.x) Sl[q / C][q % C] = P.S[(size_t)e * 3 * C + q];
+    for (int q = t; q < 3 * NE; q += blockDim.x) Ll[q / NE][q % NE] = P.lam[(size_t)e * 3 * NE + q];
+    // gather the box column (zero where the box holds no data)
+    double v[NE];
+    int64_t idx[NE];
+    const int i = a - 1, j = b - 1;
+#pragma unroll
+    for (int c = 0; c < NE; ++c) {
+        const int k = c - 1;
+        const int oi = (i < 0 || i > N), oj = (j < 0 || j > N), ok = (k < 0 || k > N);
+        int64_t g = -1;
+        if (lane_on) {
+            if (oi + oj + ok == 0) {
+                g = gm_node(P.bmap, P.n_bnd, e, i, j, k, N, P.nb);
+            } else if (oi + oj + ok == 1) {
+                int f, p, q;
+                if (oi) { f = i < 0 ? 0 : 1; p = j; q = k; }
+                else if (oj) { f = j < 0 ? 2 : 3; p = i; q = k; }
+                else { f = k < 0 ? 4 : 5; p = i; q = j; }
+                g = P.ghost[((size_t)e * 6 + f) * n1 * n1 + p + n1 * q];
+            }
+        }
+        idx[c] = g;
+        v[c] = g >= 0 ? P.r[g] : 0.0;
+    }
+    __syncthreads();
+    // forward: w = (S_t^T x S_s^T x S_r^T) v
+    double w[NE];
+#pragma unroll
+    for (int m = 0; m < NE; ++m) {                 // t-direction, register-local
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < NE; ++c) s += Sl[2][c * NE + m] * v[c];
+        w[m] = s;
+    }
+    if (lane_on)
+#pragma unroll
+        for (int c = 0; c < NE; ++c) box[c][b][a] = w[c];
+    __syncthreads();
+    double w2[NE];
+    if (lane_on)                                   // s-direction: lane (a, b) -> mode b
+#pragma unroll
+        for (int c = 0; c < NE; ++c) {
+            double s = 0.0;
+            for (int bb = 0; bb < NE; ++bb) s += Sl[1][bb * NE + b] * box[c][bb][a];
+            w2[c] = s;
+        }
+    __syncthreads();
+    if (lane_on)
+#pragma unroll
+        for (int c = 0; c < NE; ++c) box[c][b][a] = w2[c];
+    __syncthreads();
+    if (lane_on)                                   // r-direction: lane (a, b) -> mode a
+#pragma unroll
+        for (int c = 0; c < NE; ++c) {
+            double s = 0.0;
+            for (int aa = 0; aa < NE; ++aa) s += Sl[0][aa * NE + a] * box[c][b][aa];
+            const double lsum = Ll[0][a] + Ll[1][b] + Ll[2][c];
+            // a zero sum only for an element without any neighbour or
+            // Dirichlet face (its constant mode): pseudo-inverse
+            w2[c] = lsum > 1e-13 * (Ll[0][NE - 1] + Ll[1][NE - 1] + Ll[2][NE - 1]) ? s / lsum : 0.0;
+        }
+    __syncthreads();
+    if (lane_on)
+#pragma unroll
+        for (int c = 0; c < NE; ++c) box[c][b][a] = w2[c];
+    __syncthreads();
+    // backward: u = (S_t x S_s x S_r) w
+    if (lane_on)                                   // r-direction: point a
+#pragma unroll
+        for (int c = 0; c < NE; ++c) {
+            double s = 0.0;
+            for (int aa = 0; aa < NE; ++aa) s += Sl[0][a * NE + aa] * box[c][b][aa];
+            w2[c] = s;
+        }
+    __syncthreads();
+    if (lane_on)
+#pragma unroll
+        for (int c = 0; c < NE; ++c) box[c][b][a] = w2[c];
+    __syncthreads();
+    if (lane_on)                                   // s-direction: point b
+#pragma unroll
+        for (int c = 0; c < NE; ++c) {
+            double s = 0.0;
+            for (int bb = 0; bb < NE; ++bb) s += Sl[1][b * NE + bb] * box[c][bb][a];
+            w2[c] = s;
+        }
+    if (!lane_on) return;
+#pragma unroll
+    for (int c = 0; c < NE; ++c) {                 // t-direction: point c
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < NE; ++m) s += Sl[2][c * NE + m] * w2[m];
+        if (idx[c] >= 0) atomicAdd(P.z + idx[c], s);
+    }
+}
+
+struct CoarseParams {
+    const double *r;          // fine residual (restrict) / fine output z (interp)
+    double *y;                // coarse right-hand side (restrict) / fine z (interp)
+    const double *x0;         // coarse solution (interp)
+    const double *zs;         // Schwarz sum (interp)
+    const double *W;          // counting weights (interp)
+    const int32_t *cmap;      // [E][8] coarse solver index or -1
+    const int32_t *bmap, *csr_off, *csr_idx, *bpos2l;
+    const double *xi;         // GLL nodes [N+1]
+    int64_t E, n_bnd, n_u;
+    int N, nb;
+};
+
+__device__ __forceinline__ double phi(double x, int side) { return side ? 0.5 * (1.0 + x) : 0.5 * (1.0 - x); }
+
+// P^T r: per element, sum over its points of phi_c(x) r[g] / mult[g] for the
+// 8 corners, one wave per element, then 8 atomics into the coarse vector.
+__global__ void __launch_bounds__(64) k_coarse_restrict(CoarseParams P) {
+    const int64_t e = blockIdx.x;
+    const int N = P.N, n1 = N + 1, np = n1 * n1 * n1;
+    double acc[8] = {};
+    for (int l = threadIdx.x; l < np; l += 64) {
+        const int i = l % n1, j = (l / n1) % n1, k = l / (n1 * n1);
+        const int64_t g = gm_node(P.bmap, P.n_bnd, e, i, j, k, N, P.nb);
+        if (g < 0) continue;
+        double m = 1.0;
+        if (g < P.n_bnd) m = (double)(P.csr_off[g + 1] - P.csr_off[g]);
+        const double rv = P.r[g] / m;
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            acc[c] += phi(P.xi[i], c & 1) * phi(P.xi[j], (c >> 1) & 1) * phi(P.xi[k], (c >> 2) & 1) * rv;
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        double s = acc[c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        acc[c] = s;
+    }
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int32_t gc = P.cmap[e * 8 + c];
+            if (gc >= 0) atomicAdd(P.y + gc, acc[c]);
+        }
+}
+
+// z[g] = W[g] zs[g] + (P x0)[g] over fine unique nodes (0 on Dirichlet
+// nodes); P is evaluated in the element of the node's first copy.
+__global__ void k_combine(CoarseParams P) {
+    const int N = P.N, n1 = N + 1, nm = N - 1;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < P.n_u;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        int64_t e;
+        int i, j, k;
+        if (g < P.n_bnd) {
+            const int32_t cq = P.csr_idx[P.csr_off[g]];
+            e = cq / P.nb;
+            const int l = P.bpos2l[cq - e * P.nb];
+            i = l % n1;
+            j = (l / n1) % n1;
+            k = l / (n1 * n1);
+        } else {
+            const int64_t q = g - P.n_bnd, ni = (int64_t)nm * nm * nm;
+            e = q / ni;
+            const int rem = (int)(q - e * ni);
+            i = 1 + rem % nm;
+            j = 1 + (rem / nm) % nm;
+            k = 1 + rem / (nm * nm);
+        }
+        double zc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int32_t gc = P.cmap[e * 8 + c];
+            if (gc >= 0 && P.x0)
+                zc += phi(P.xi[i], c & 1) * phi(P.xi[j], (c >> 1) & 1) * phi(P.xi[k], (c >> 2) & 1) *
+                      P.x0[gc];
+        }
+        const double zs = P.zs ? P.W[g] * P.zs[g] : 0.0;
+        P.y[g] = P.W[g] > 0.0 ? zs + zc : 0.0;            // W = 0 only on Dirichlet nodes
+    }
+}
+
+// part[blk][i] = X_i . v (i < l), part[blk][l] = v . v
+__global__ void __launch_bounds__(kGmBlock) k_gm_dots(int64_t n, int l, int64_t ld,
+                                                      const double *__restrict__ X,
+                                                      const double *__restrict__ v,
+                                                      double *__restrict__ part) {
+    __shared__ double red[kGmBlock / 64];
+    double acc[kGmMaxVec + 1];
+#pragma unroll
+    for (int i = 0; i <= kGmMaxVec; ++i) acc[i] = 0.0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const double vq = v[q];
+#pragma unroll
+        for (int i = 0; i < kGmMaxVec; ++i)
+            if (i < l) acc[i] += X[i * ld + q] * vq;
+        acc[kGmMaxVec] += vq * vq;
+    }
+#pragma unroll
+    for (int i = 0; i <= kGmMaxVec; ++i) {
+        if (i <= l) {                             // l is uniform: no divergent barrier
+            const double s = gm_block_sum(i < l ? acc[i] : acc[kGmMaxVec], red);
+            if (threadIdx.x == 0) part[(size_t)blockIdx.x * (l + 1) + i] = s;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kGmBlock) k_gm_finish(int nblocks, int m,
+                                                        const double *__restrict__ part,
+                                                        double *__restrict__ out) {
+    __shared__ double red[kGmBlock / 64];
+    for (int i = 0; i < m; ++i) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += part[(size_t)b * m + i];
+        s = gm_block_sum(s, red);
+        if (threadIdx.x == 0) out[i] = s;
+    }
+}
+
+// v -= sum_i c_i X_i (i < l); part[blk] = v . v
+__global__ void __launch_bounds__(kGmBlock) k_gm_orth(int64_t n, int l, int64_t ld,
+                                                      const double *__restrict__ X,
+                                                      const double *__restrict__ coef,
+                                                      double *__restrict__ v,
+                                                      double *__restrict__ part) {
+    __shared__ double red[kGmBlock / 64];
+    double s = 0.0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        double x = v[q];
+        for (int i = 0; i < l; ++i) x -= coef[i] * X[i * ld + q];
+        v[q] = x;
+        s += x * x;
+    }
+    s = gm_block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// dst = src * scale[0] (scale from device memory, 1/sqrt of it when inv_sqrt)
+__global__ void k_gm_scale(int64_t n, const double *__restrict__ src, double *__restrict__ dst,
+                           const double *__restrict__ scale, int inv_sqrt) {
+    const double sc = inv_sqrt ? 1.0 / sqrt(scale[0]) : scale[0];
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        dst[q] = src[q] * sc;
+}
+
+// x += sum_i y_i Z_i (i < l)
+__global__ void k_gm_update(int64_t n, int l, int64_t ld, const double *__restrict__ Z,
+                            const double *__restrict__ y, double *__restrict__ x) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        double s = x[q];
+        for (int i = 0; i < l; ++i) s += y[i] * Z[i * ld + q];
+        x[q] = s;
+    }
+}
+
+// Cyclic Jacobi eigenvalue method for a symmetric n x n matrix A (row
+// major, destroyed): eigenvalues in lam, eigenvectors in the columns of V.
+void jacobi_eigen(int n, std::vector<double> &A, std::vector<double> &V, std::vector<double> &lam) {
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double a2 = A[(size_t)i * n + j] * A[(size_t)i * n + j];
+                tot += a2;
+                if (i != j) off += a2;
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[(size_t)p * n + q];
+                if (apq == 0.0) continue;
+                const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+                const double theta = (aqq - app) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < n; ++k) {           // rotate columns p, q
+                    const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+                    A[(size_t)k * n + p] = cs * akp - sn * akq;
+                    A[(size_t)k * n + q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < n; ++k) {           // rotate rows p, q
+                    const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+                    A[(size_t)p * n + k] = cs * apk - sn * aqk;
+                    A[(size_t)q * n + k] = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+                    V[(size_t)k * n + p] = cs * vkp - sn * vkq;
+                    V[(size_t)k * n + q] = sn * vkp + cs * vkq;
+                }
+            }
+    }
+    // ascending eigenvalues, vectors reordered with them
+    std::vector<int> ord(n);
+    for (int i = 0; i < n; ++i) ord[i] = i;
+    std::sort(ord.begin(), ord.end(),
+              [&](int p, int q) { return A[(size_t)p * n + p] < A[(size_t)q * n + q]; });
+    std::vector<double> Vs((size_t)n * n);
+    lam.resize(n);
+    for (int c = 0; c < n; ++c) {
+        lam[c] = A[(size_t)ord[c] * n + ord[c]];
+        for (int r = 0; r < n; ++r) Vs[(size_t)r * n + c] = V[(size_t)r * n + ord[c]];
+    }
+    V.swap(Vs);
+}
+
+}  // namespace
+
+struct sem_gmres_s {
+    sem_ctx ctx = nullptr;           // fine problem (Poisson, FP64)
+    sem_ctx coarse = nullptr;        // N = 1 problem on the element vertices
+    int m = 30;                      // restart length
+    int NE = 0;                      // N + 3
+    int64_t ld = 0;                  // leading dimension of the bases (values)
+    // host-built preconditioner data
+    std::vector<double> S, lam;      // [E][3][NE][NE], [E][3][NE]
+    std::vector<int32_t> ghost;      // [E][6][(N+1)^2]
+    std::vector<int32_t> cmap;       // [E][8]
+    std::vector<double> W;           // [n_u]
+    // device
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    size_t coarse_ws = 0;
+    double *dS = nullptr, *dlam = nullptr, *dW = nullptr, *dxi = nullptr;
+    int32_t *dghost = nullptr, *dcmap = nullptr;
+    double *zs = nullptr, *b0 = nullptr, *x0 = nullptr;
+    double *V = nullptr, *Z = nullptr, *w = nullptr, *r = nullptr;
+    double *part = nullptr, *coef = nullptr;
+    std::string err;
+};
+
+static sem_status gfail(sem_gmres g, sem_status st, const std::string &m) {
+    if (g) g->err = m;
+    return fail(nullptr, st, m);
+}
+
+// Face f = 2d + side of element e in local coordinates: its corner with face
+// coordinates (p, q) in {0, 1}^2 (face coordinates: the two other local
+// directions in increasing order).
+static int face_corner(int f, int p, int q) {
+    const int d = f / 2, side = f % 2;
+    int ijk[3];
+    ijk[d] = side;
+    ijk[d == 0 ? 1 : 0] = p;
+    ijk[d == 2 ? 1 : 2] = q;
+    return ijk[0] + 2 * ijk[1] + 4 * ijk[2];
+}
+
+// Host set-up of the local solves: face neighbours and their orientation
+// from the corner (vertex) ids, the extension maps, element lengths, 1D
+// operators and their generalised eigendecompositions, counting weights.
+static sem_status build_local(sem_gmres G) {
+    sem_ctx c = G->ctx;
+    const int N = c->N, n1 = N + 1, NE = N + 3, F2 = n1 * n1;
+    const int64_t E = c->E;
+    // faces by their sorted vertex ids
+    std::map<std::array<int64_t, 4>, std::vector<std::pair<int64_t, int>>> faces;
+    for (int64_t e = 0; e < E; ++e)
+        for (int f = 0; f < 6; ++f) {
+            std::array<int64_t, 4> k;
+            for (int t = 0; t < 4; ++t) k[t] = c->corners[e * 8 + face_corner(f, t & 1, t >> 1)];
+            std::sort(k.begin(), k.end());
+            faces[k].push_back({e, f});
+        }
+    std::vector<int64_t> nbr(E * 6, -1);
+    std::vector<int> nbr_face(E * 6, -1);
+    for (auto &kv : faces) {
+        if (kv.second.size() == 2) {
+            auto a = kv.second[0], b = kv.second[1];
+            nbr[a.first * 6 + a.second] = b.first;
+            nbr_face[a.first * 6 + a.second] = b.second;
+            nbr[b.first * 6 + b.second] = a.first;
+            nbr_face[b.first * 6 + b.second] = a.second;
+        } else if (kv.second.size() > 2) {
+            return gfail(G, SEM_ERR_MESH, "a face is shared by more than two elements");
+        }
+    }
+    // element lengths: mean of the four edges along each local direction
+    std::vector<double> L(E * 3, 0.0);
+    for (int64_t e = 0; e < E; ++e) {
+        const double *X = c->corner_xyz.data() + e * 24;
+        auto dist = [&](int c0, int c1) {
+            double s = 0;
+            for (int d = 0; d < 3; ++d) s += (X[d * 8 + c1] - X[d * 8 + c0]) * (X[d * 8 + c1] - X[d * 8 + c0]);
+            return std::sqrt(s);
+        };
+        for (int p = 0; p < 2; ++p)
+            for (int q = 0; q < 2; ++q) {
+                L[e * 3 + 0] += 0.25 * dist(0 + 2 * p + 4 * q, 1 + 2 * p + 4 * q);
+                L[e * 3 + 1] += 0.25 * dist(p + 0 + 4 * q, p + 2 + 4 * q);
+                L[e * 3 + 2] += 0.25 * dist(p + 2 * q + 0, p + 2 * q + 4);
+            }
+    }
+    // extension maps
+    G->ghost.assign(E * 6 * F2, -1);
+    auto node_of = [&](int64_t e, int i, int j, int k) -> int64_t {
+        if (i == 0 || i == N || j == 0 || j == N || k == 0 || k == N) {
+            int b;
+            {   // boundary position of (i, j, k): plane 0, ring planes, plane N
+                const int C = n1 * n1;
+                if (k == 0) b = i + n1 * j;
+                else if (k == N) b = C + (N - 1) * 4 * N + i + n1 * j;
+                else {
+                    int rg;
+                    if (j == 0) rg = i;
+                    else if (j == N) rg = N + 1 + 2 * (N - 1) + i;
+                    else rg = N + 1 + 2 * (j - 1) + (i == 0 ? 0 : 1);
+                    b = C + (k - 1) * 4 * N + rg;
+                }
+            }
+            const int32_t m = c->bmap[(size_t)e * c->nb + b];
+            return m < 0 ? -1 : (int64_t)m;
+        }
+        const int nm = N - 1;
+        return c->n_bnd + e * (int64_t)(nm * nm * nm) + ((k - 1) * nm + (j - 1)) * nm + (i - 1);
+    };
+    std::vector<double> lens_nb(E * 6, -1.0);
+    for (int64_t e = 0; e < E; ++e)
+        for (int f = 0; f < 6; ++f) {
+            const int64_t n = nbr[e * 6 + f];
+            if (n < 0) continue;
+            // corners (0,0), (1,0), (0,1) of e's face in n's local frame
+            int loc[3][3];
+            const int pq[3][2] = {{0, 0}, {1, 0}, {0, 1}};
+            for (int t = 0; t < 3; ++t) {
+                const int64_t vid = c->corners[e * 8 + face_corner(f, pq[t][0], pq[t][1])];
+                int cn = -1;
+                for (int q = 0; q < 8; ++q)
+                    if (c->corners[n * 8 + q] == vid) cn = q;
+                if (cn < 0) return gfail(G, SEM_ERR_MESH, "inconsistent face neighbour");
+                loc[t][0] = (cn & 1) * N;
+                loc[t][1] = ((cn >> 1) & 1) * N;
+                loc[t][2] = ((cn >> 2) & 1) * N;
+            }
+            int dP[3], dQ[3], ax = -1;
+            for (int d = 0; d < 3; ++d) {
+                dP[d] = (loc[1][d] - loc[0][d]) / N;
+                dQ[d] = (loc[2][d] - loc[0][d]) / N;
+                if (dP[d] == 0 && dQ[d] == 0) ax = d;
+            }
+            if (ax < 0) return gfail(G, SEM_ERR_MESH, "degenerate face orientation");
+            const int inward = loc[0][ax] == 0 ? 1 : -1;
+            lens_nb[e * 6 + f] = L[n * 3 + ax];
+            for (int q = 0; q < n1; ++q)
+                for (int p = 0; p < n1; ++p) {
+                    int x[3];
+                    for (int d = 0; d < 3; ++d) x[d] = loc[0][d] + p * dP[d] + q * dQ[d];
+                    x[ax] += inward;
+                    const int64_t g = node_of(n, x[0], x[1], x[2]);
+                    G->ghost[(e * 6 + f) * F2 + p + n1 * q] = (int32_t)g;
+                }
+        }
+    // counting weights: element nodes plus mapped extension points
+    std::vector<double> cnt(c->n_unique, 0.0);
+    for (int64_t e = 0; e < E; ++e) {
+        for (int k = 0; k <= N; ++k)
+            for (int j = 0; j <= N; ++j)
+                for (int i = 0; i <= N; ++i) {
+                    const int64_t g = node_of(e, i, j, k);
+                    if (g >= 0) cnt[g] += 1.0;
+                }
+        for (int q = 0; q < 6 * F2; ++q) {
+            const int32_t g = G->ghost[e * 6 * F2 + q];
+            if (g >= 0) cnt[g] += 1.0;
+        }
+    }
+    G->W.assign(c->n_unique, 0.0);
+    for (int64_t g = 0; g < c->n_unique; ++g) G->W[g] = cnt[g] > 0 ? 1.0 / cnt[g] : 0.0;
+    // 1D operators and eigendecompositions
+    std::vector<double> Khat((size_t)n1 * n1, 0.0);
+    for (int i = 0; i < n1; ++i)
+        for (int j = 0; j < n1; ++j) {
+            double s = 0;
+            for (int q = 0; q < n1; ++q) s += c->D[q * n1 + i] * c->rho[q] * c->D[q * n1 + j];
+            Khat[(size_t)i * n1 + j] = s;
+        }
+    G->S.assign((size_t)E * 3 * NE * NE, 0.0);
+    G->lam.assign((size_t)E * 3 * NE, 0.0);
+    auto work = [&](int64_t e0, int64_t e1) {
+        std::vector<double> Kl((size_t)(3 * N + 1) * (3 * N + 1)), Ml(3 * N + 1);
+        std::vector<double> A((size_t)NE * NE), Vv, lm;
+        std::vector<double> Ke((size_t)NE * NE), Me(NE);
+        for (int64_t e = e0; e < e1; ++e)
+            for (int d = 0; d < 3; ++d) {
+                const double h[3] = {lens_nb[e * 6 + 2 * d], L[e * 3 + d], lens_nb[e * 6 + 2 * d + 1]};
+                std::fill(Kl.begin(), Kl.end(), 0.0);
+                std::fill(Ml.begin(), Ml.end(), 0.0);
+                const int nl = 3 * N + 1;
+                for (int el = 0; el < 3; ++el) {
+                    if (!(h[el] > 0)) continue;
+                    for (int i = 0; i < n1; ++i) {
+                        Ml[el * N + i] += 0.5 * h[el] * c->rho[i];
+                        for (int j = 0; j < n1; ++j)
+                            Kl[(size_t)(el * N + i) * nl + el * N + j] += 2.0 / h[el] * Khat[(size_t)i * n1 + j];
+                    }
+                }
+                bool keep[32];
+                for (int a = 0; a < NE; ++a) keep[a] = true;
+                if (!(h[0] > 0)) keep[0] = false;
+                if (!(h[2] > 0)) keep[NE - 1] = false;
+                if (c->face_bc[e * 6 + 2 * d]) keep[0] = keep[1] = false;
+                if (c->face_bc[e * 6 + 2 * d + 1]) keep[NE - 2] = keep[NE - 1] = false;
+                for (int a = 0; a < NE; ++a) {
+                    Me[a] = keep[a] ? Ml[N - 1 + a] : 1.0;
+                    for (int b = 0; b < NE; ++b)
+                        Ke[(size_t)a * NE + b] = (keep[a] && keep[b]) ? Kl[(size_t)(N - 1 + a) * nl + N - 1 + b]
+                                                                      : (a == b ? 1.0 : 0.0);
+                }
+                // K S = M S Lambda via the symmetric M^-1/2 K M^-1/2
+                for (int a = 0; a < NE; ++a)
+                    for (int b = 0; b < NE; ++b)
+                        A[(size_t)a * NE + b] = Ke[(size_t)a * NE + b] / std::sqrt(Me[a] * Me[b]);
+                jacobi_eigen(NE, A, Vv, lm);
+                double *S = G->S.data() + ((size_t)e * 3 + d) * NE * NE;
+                for (int a = 0; a < NE; ++a)
+                    for (int mo = 0; mo < NE; ++mo)
+                        S[(size_t)a * NE + mo] = keep[a] ? Vv[(size_t)a * NE + mo] / std::sqrt(Me[a]) : 0.0;
+                // modes living on dropped points get no weight: zero eigenvector rows there
+                double *lmb = G->lam.data() + ((size_t)e * 3 + d) * NE;
+                for (int mo = 0; mo < NE; ++mo) lmb[mo] = lm[mo];
+            }
+    };
+    const int nth = (int)std::max<unsigned>(1, std::min<unsigned>(16, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t)
+        th.emplace_back(work, E * t / nth, E * (t + 1) / nth);
+    for (auto &t : th) t.join();
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_gmres_create(sem_ctx c, int restart, sem_gmres *out) {
+    if (!c || !out) return fail(c, SEM_ERR_INVALID, "null argument");
+    *out = nullptr;
+    if (!c->geometry_ready || c->corner_xyz.empty())
+        return fail(c, SEM_ERR_STATE, "geometry not set");
+    if (!c->solver || !c->L.r64) return fail(c, SEM_ERR_STATE, "context set up without solver vectors");
+    if (c->N < 2 || c->N > 13) return fail(c, SEM_ERR_UNSUPPORTED, "the Schwarz solves need 2 <= N <= 13");
+    if (restart < 1 || restart > kGmMaxVec - 1)
+        return fail(c, SEM_ERR_INVALID, "restart must be in 1.." + std::to_string(kGmMaxVec - 1));
+    if (c->helm) return fail(c, SEM_ERR_UNSUPPORTED, "the pressure solver is for the Poisson operator");
+    sem_gmres G = new sem_gmres_s();
+    G->ctx = c;
+    G->m = restart;
+    G->NE = c->N + 3;
+    G->ld = (int64_t)(align256(8 * (size_t)c->n_unique) / 8);
+    // the coarse problem: N = 1 on the same connectivity
+    sem_mesh m0;
+    m0.num_elements = c->E;
+    m0.corner_ids = c->corners.data();
+    m0.face_bc = c->face_bc.data();
+    m0.num_vertices = c->num_vertices;
+    m0.vertex_xyz = nullptr;
+    sem_options o0{SEM_PREC_BIT(SEM_FP64), 1};
+    sem_status st = sem_setup(&m0, 1, &o0, &G->coarse);
+    if (st) {
+        const std::string msg = std::string("coarse grid: ") + sem_last_error(nullptr);
+        delete G;
+        return fail(c, st, msg);
+    }
+    st = sem_workspace_size(G->coarse, &G->coarse_ws);
+    if (st) {
+        sem_free(G->coarse);
+        delete G;
+        return fail(c, st, "coarse grid workspace");
+    }
+    st = build_local(G);
+    if (st) {
+        sem_free(G->coarse);
+        delete G;
+        return st;
+    }
+    // coarse index of every element corner (Dirichlet: -1)
+    G->cmap.assign(c->E * 8, -1);
+    for (int64_t e = 0; e < c->E; ++e)
+        for (int q = 0; q < 8; ++q) {
+            // at N = 1 every point is a boundary point; position b = local index
+            const int32_t v = G->coarse->bmap[(size_t)e * G->coarse->nb + q];
+            G->cmap[e * 8 + q] = v < 0 ? -1 : v;
+        }
+    *out = G;
+    return SEM_OK;
+}
+
+extern "C" void sem_gmres_free(sem_gmres G) {
+    if (!G) return;
+    sem_free(G->coarse);
+    delete G;
+}
+
+extern "C" const char *sem_gmres_last_error(sem_gmres G) { return G ? G->err.c_str() : ""; }
+
+static size_t gm_layout(sem_gmres G, size_t *off) {
+    sem_ctx c = G->ctx;
+    const int64_t E = c->E, NE = G->NE, n1 = c->n1;
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        const size_t r = o;
+        o += align256(b);
+        return r;
+    };
+    off[0] = take(G->coarse_ws);
+    off[1] = take(8 * (size_t)E * 3 * NE * NE);       // S
+    off[2] = take(8 * (size_t)E * 3 * NE);            // lambda
+    off[3] = take(4 * (size_t)E * 6 * n1 * n1);       // ghost map
+    off[4] = take(4 * (size_t)E * 8);                 // coarse map
+    off[5] = take(8 * (size_t)c->n_unique);           // W
+    off[6] = take(8 * 16);                            // xi
+    off[7] = take(8 * (size_t)c->n_unique);           // zs
+    off[8] = take(8 * (size_t)G->coarse->n_unique);   // b0
+    off[9] = take(8 * (size_t)G->coarse->n_unique);   // x0
+    off[10] = take(8 * (size_t)G->ld * (G->m + 1));   // V
+    off[11] = take(8 * (size_t)G->ld * G->m);         // Z
+    off[12] = take(8 * (size_t)c->n_unique);          // w
+    off[13] = take(8 * (size_t)c->n_unique);          // r
+    off[14] = take(8 * (size_t)kGmGrid * (kGmMaxVec + 1));
+    off[15] = take(8 * (kGmMaxVec + 4));
+    return o;
+}
+
+extern "C" sem_status sem_gmres_workspace_size(sem_gmres G, size_t *bytes) {
+    if (!G || !bytes) return gfail(G, SEM_ERR_INVALID, "null argument");
+    size_t off[16];
+    *bytes = gm_layout(G, off);
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_gmres_bind_workspace(sem_gmres G, void *dev, size_t bytes,
+                                               sem_stream stream) {
+    if (!G || !dev) return gfail(G, SEM_ERR_INVALID, "null argument");
+    size_t off[16];
+    const size_t need = gm_layout(G, off);
+    if (bytes < need)
+        return gfail(G, SEM_ERR_OOM, "workspace of " + std::to_string(bytes) + " bytes, need " +
+                                         std::to_string(need));
+    if ((uintptr_t)dev & 255) return gfail(G, SEM_ERR_INVALID, "workspace not 256-byte aligned");
+    sem_ctx c = G->ctx;
+    hipStream_t s = (hipStream_t)stream;
+    char *w = static_cast<char *>(dev);
+    G->ws = w;
+    G->ws_bytes = bytes;
+    sem_status st = sem_bind_workspace(G->coarse, w + off[0], G->coarse_ws, stream);
+    if (st) return gfail(G, st, std::string("coarse grid: ") + sem_last_error(G->coarse));
+    // coarse geometry: the element corners ([E][3][8] = [E][3][2][2][2])
+    st = sem_set_geometry(G->coarse, c->corner_xyz.data(), stream);
+    if (st) return gfail(G, st, std::string("coarse grid: ") + sem_last_error(G->coarse));
+    G->dS = reinterpret_cast<double *>(w + off[1]);
+    G->dlam = reinterpret_cast<double *>(w + off[2]);
+    G->dghost = reinterpret_cast<int32_t *>(w + off[3]);
+    G->dcmap = reinterpret_cast<int32_t *>(w + off[4]);
+    G->dW = reinterpret_cast<double *>(w + off[5]);
+    G->dxi = reinterpret_cast<double *>(w + off[6]);
+    G->zs = reinterpret_cast<double *>(w + off[7]);
+    G->b0 = reinterpret_cast<double *>(w + off[8]);
+    G->x0 = reinterpret_cast<double *>(w + off[9]);
+    G->V = reinterpret_cast<double *>(w + off[10]);
+    G->Z = reinterpret_cast<double *>(w + off[11]);
+    G->w = reinterpret_cast<double *>(w + off[12]);
+    G->r = reinterpret_cast<double *>(w + off[13]);
+    G->part = reinterpret_cast<double *>(w + off[14]);
+    G->coef = reinterpret_cast<double *>(w + off[15]);
+    SEM_HIP(c, hipMemcpyAsync(G->dS, G->S.data(), 8 * G->S.size(), hipMemcpyHostToDevice, s));
+    SEM_HIP(c, hipMemcpyAsync(G->dlam, G->lam.data(), 8 * G->lam.size(), hipMemcpyHostToDevice, s));
+    SEM_HIP(c, hipMemcpyAsync(G->dghost, G->ghost.data(), 4 * G->ghost.size(), hipMemcpyHostToDevice, s));
+    SEM_HIP(c, hipMemcpyAsync(G->dcmap, G->cmap.data(), 4 * G->cmap.size(), hipMemcpyHostToDevice, s));
+    SEM_HIP(c, hipMemcpyAsync(G->dW, G->W.data(), 8 * G->W.size(), hipMemcpyHostToDevice, s));
+    SEM_HIP(c, hipMemcpyAsync(G->dxi, c->xi, 8 * c->n1, hipMemcpyHostToDevice, s));
+    SEM_HIP(c, hipStreamSynchronize(s));
+    return SEM_OK;
+}
+
+// z = M^-1 r: parts & 1 local Schwarz solves, parts & 2 coarse grid.
+static sem_status precondition(sem_gmres G, const double *r, double *z, unsigned parts,
+                               hipStream_t s) {
+    sem_ctx c = G->ctx;
+    const int64_t n = c->n_unique;
+    const bool local = parts & SEM_PC_SCHWARZ, coarse = parts & SEM_PC_COARSE;
+    if (local) {
+        SEM_HIP(c, launch_fill(G->zs, n, 0.0, s));
+        FdmParams P{r, G->zs, G->dS, G->dlam, G->dghost, dptr<int32_t>(c, c->L.bmap), c->E,
+                    c->n_bnd, c->N, c->nb};
+#define SEM_FDM(ne)                                                                     \
+    case ne:                                                                            \
+        hipLaunchKernelGGL(k_fdm<ne>, dim3((unsigned)c->E), dim3(((ne) * (ne) + 63) / 64 * 64), 0, s, P); \
+        break;
+        switch (G->NE) {
+            SEM_FDM(5) SEM_FDM(6) SEM_FDM(7) SEM_FDM(8) SEM_FDM(9) SEM_FDM(10) SEM_FDM(11)
+            SEM_FDM(12) SEM_FDM(13) SEM_FDM(14) SEM_FDM(15) SEM_FDM(16)
+            default: return gfail(G, SEM_ERR_UNSUPPORTED, "order");
+        }
+#undef SEM_FDM
+        SEM_HIP(c, hipGetLastError());
+    }
+    CoarseParams C{r, G->b0, G->x0, local ? G->zs : nullptr, G->dW, G->dcmap,
+                   dptr<int32_t>(c, c->L.bmap), dptr<int32_t>(c, c->L.csr_off),
+                   dptr<int32_t>(c, c->L.csr_idx), dptr<int32_t>(c, c->L.bpos2l), G->dxi,
+                   c->E, c->n_bnd, n, c->N, c->nb};
+    if (coarse) {
+        SEM_HIP(c, launch_fill(G->b0, G->coarse->n_unique, 0.0, s));
+        hipLaunchKernelGGL(k_coarse_restrict, dim3((unsigned)c->E), dim3(64), 0, s, C);
+        SEM_HIP(c, hipGetLastError());
+        // 10 Jacobi-PCG iterations from zero on the coarse operator
+        sem_solve_options o;
+        sem_default_solve_options(&o);
+        o.tol = 1e-14;
+        o.max_iter = 10;
+        o.max_restart = 0;
+        o.check_every = 10;
+        sem_solve_info inf;
+        const sem_status st = sem_cg_solve(G->coarse, G->b0, G->x0, &o, &inf, s);
+        if (st != SEM_OK && st != SEM_ERR_NOT_CONVERGED && st != SEM_ERR_BREAKDOWN)
+            return gfail(G, st, std::string("coarse solve: ") + sem_last_error(G->coarse));
+    } else {
+        C.x0 = nullptr;
+    }
+    C.y = z;
+    hipLaunchKernelGGL(k_combine, dim3(gm_grid(n)), dim3(kGmBlock), 0, s, C);
+    SEM_HIP(c, hipGetLastError());
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_gmres_precondition(sem_gmres G, const double *r, double *z,
+                                             unsigned parts, sem_stream stream) {
+    if (!G || !r || !z) return gfail(G, SEM_ERR_INVALID, "null argument");
+    if (!G->ws) return gfail(G, SEM_ERR_STATE, "no workspace bound");
+    if (!(parts & (SEM_PC_SCHWARZ | SEM_PC_COARSE)) || (parts & ~3u))
+        return gfail(G, SEM_ERR_INVALID, "parts must name SEM_PC_SCHWARZ and/or SEM_PC_COARSE");
+    return precondition(G, r, z, parts, (hipStream_t)stream);
+}
+
+// y = A x (fine operator, FP64, atomic summation into a cleared boundary block)
+static sem_status apply_A(sem_gmres G, const double *x, double *y, hipStream_t s) {
+    sem_ctx c = G->ctx;
+    SEM_HIP(c, launch_fill(y, c->n_bnd, 0.0, s));
+    SEM_HIP(c, launch_ax(c, SEM_FP64, x, y, 0, OUT_ATOMIC, nullptr, nullptr, c->tile[0], s));
+    return SEM_OK;
+}
+
+// coef[0..l) = X^T v, coef[l] = v.v
+static hipError_t gm_dots(sem_gmres G, int l, const double *X, const double *v, hipStream_t s) {
+    const int64_t n = G->ctx->n_unique;
+    const unsigned g = gm_grid(n);
+    hipLaunchKernelGGL(k_gm_dots, dim3(g), dim3(kGmBlock), 0, s, n, l, G->ld, X, v, G->part);
+    hipLaunchKernelGGL(k_gm_finish, dim3(1), dim3(kGmBlock), 0, s, (int)g, l + 1,
+                       (const double *)G->part, G->coef);
+    return hipGetLastError();
+}
+
+extern "C" sem_status sem_gmres_solve(sem_gmres G, const double *b, double *x,
+                                      const sem_solve_options *opts, sem_solve_info *info,
+                                      sem_stream stream) {
+    sem_solve_info dummy;
+    if (!info) info = &dummy;
+    std::memset(info, 0, sizeof(*info));
+    if (!G || !b || !x) return info->status = gfail(G, SEM_ERR_INVALID, "null argument");
+    if (!G->ws) return info->status = gfail(G, SEM_ERR_STATE, "no workspace bound");
+    sem_ctx c = G->ctx;
+    if (c->helm) return info->status = gfail(G, SEM_ERR_UNSUPPORTED, "Poisson operator only");
+    sem_solve_options o;
+    if (opts) o = *opts; else sem_default_solve_options(&o);
+    if (!(o.tol > 0) || o.max_iter < 1) return info->status = gfail(G, SEM_ERR_INVALID, "bad tolerance or cap");
+    if (o.precision != SEM_FP64)
+        return info->status = gfail(G, SEM_ERR_UNSUPPORTED, "the GMRES solve is FP64");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = c->n_unique, ld = G->ld;
+    const unsigned grid = gm_grid(n);
+    const int m = G->m;
+    auto t0 = std::chrono::steady_clock::now();
+    // r = b - A x
+    double bb = 0.0, beta = 0.0;
+    SEM_HIP(c, gm_dots(G, 0, G->V, b, s));
+    SEM_HIP(c, hipMemcpyAsync(&bb, G->coef, 8, hipMemcpyDeviceToHost, s));
+    if (o.zero_guess) {
+        SEM_HIP(c, launch_fill(x, n, 0.0, s));
+        SEM_HIP(c, hipMemcpyAsync(G->r, b, 8 * n, hipMemcpyDeviceToDevice, s));
+    } else {
+        sem_status e = apply_A(G, x, G->w, s);
+        if (e) return info->status = e;
+        SEM_HIP(c, hipMemcpyAsync(G->r, b, 8 * n, hipMemcpyDeviceToDevice, s));
+        const double minus1 = -1.0;
+        SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMaxVec + 2, &minus1, 8, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_gm_update, dim3(grid), dim3(kGmBlock), 0, s, n, 1, ld,
+                           (const double *)G->w, (const double *)(G->coef + kGmMaxVec + 2), G->r);
+    }
+    SEM_HIP(c, gm_dots(G, 0, G->V, G->r, s));
+    SEM_HIP(c, hipMemcpyAsync(&beta, G->coef, 8, hipMemcpyDeviceToHost, s));
+    SEM_HIP(c, hipStreamSynchronize(s));
+    const double bn = std::sqrt(bb);
+    beta = std::sqrt(beta);
+    if (!std::isfinite(bn) || !std::isfinite(beta)) return info->status = gfail(G, SEM_ERR_NAN, "non-finite input");
+    if (bn == 0.0 || beta <= o.tol * bn) {
+        info->true_rel_residual = bn > 0 ? beta / bn : 0.0;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return info->status = SEM_OK;
+    }
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    sem_status result = SEM_ERR_NOT_CONVERGED;
+    for (;;) {
+        // V_0 = r / beta
+        const double inv = 1.0 / beta;
+        SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMaxVec + 3, &inv, 8, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_gm_scale, dim3(grid), dim3(kGmBlock), 0, s, n, (const double *)G->r,
+                           G->V, (const double *)(G->coef + kGmMaxVec + 3), 0);
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int jdone = 0;
+        bool hit = false;
+        for (int j = 0; j < m; ++j) {
+            double *Vj = G->V + (size_t)j * ld, *Zj = G->Z + (size_t)j * ld;
+            sem_status e = precondition(G, Vj, Zj, SEM_PC_SCHWARZ | SEM_PC_COARSE, s);
+            if (e) return info->status = e;
+            e = apply_A(G, Zj, G->w, s);
+            if (e) return info->status = e;
+            // two classical Gram-Schmidt passes against V_0..V_j
+            double hcol[kGmMaxVec + 1] = {};
+            double nrm2 = 0.0;
+            for (int pass = 0; pass < 2; ++pass) {
+                SEM_HIP(c, gm_dots(G, j + 1, G->V, G->w, s));
+                double h[kGmMaxVec + 1];
+                SEM_HIP(c, hipMemcpyAsync(h, G->coef, 8 * (j + 2), hipMemcpyDeviceToHost, s));
+                hipLaunchKernelGGL(k_gm_orth, dim3(grid), dim3(kGmBlock), 0, s, n, j + 1, ld,
+                                   (const double *)G->V, (const double *)G->coef, G->w, G->part);
+                hipLaunchKernelGGL(k_gm_finish, dim3(1), dim3(kGmBlock), 0, s, (int)grid, 1,
+                                   (const double *)G->part, G->coef + kGmMaxVec + 1);
+                SEM_HIP(c, hipMemcpyAsync(&nrm2, G->coef + kGmMaxVec + 1, 8, hipMemcpyDeviceToHost, s));
+                SEM_HIP(c, hipStreamSynchronize(s));
+                for (int i = 0; i <= j; ++i) hcol[i] += h[i];
+            }
+            const double hn = std::sqrt(nrm2);
+            if (!std::isfinite(hn)) return info->status = gfail(G, SEM_ERR_NAN, "non-finite Arnoldi vector");
+            // V_{j+1} = w / ||w||
+            if (hn > 0) {
+                const double iv = 1.0 / hn;
+                SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMaxVec + 3, &iv, 8, hipMemcpyHostToDevice, s));
+                hipLaunchKernelGGL(k_gm_scale, dim3(grid), dim3(kGmBlock), 0, s, n,
+                                   (const double *)G->w, G->V + (size_t)(j + 1) * ld,
+                                   (const double *)(G->coef + kGmMaxVec + 3), 0);
+                SEM_HIP(c, hipGetLastError());
+            }
+            // Givens rotations on column j of H
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i];
+            H[(size_t)(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                const double a = H[(size_t)i * m + j], bq = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * bq;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bq;
+            }
+            const double a = H[(size_t)j * m + j], bq = H[(size_t)(j + 1) * m + j];
+            const double den = std::hypot(a, bq);
+            cs[j] = den > 0 ? a / den : 1.0;
+            sn[j] = den > 0 ? bq / den : 0.0;
+            H[(size_t)j * m + j] = den;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            info->iterations += 1;
+            jdone = j + 1;
+            info->rel_residual = std::fabs(g[j + 1]) / bn;
+            if (std::fabs(g[j + 1]) <= o.tol * bn || info->iterations >= o.max_iter || hn == 0) {
+                hit = true;
+                break;
+            }
+        }
+        (void)hit;
+        // y = H^-1 g (upper triangular), x += Z y
+        for (int i = jdone - 1; i >= 0; --i) {
+            double sum = g[i];
+            for (int k = i + 1; k < jdone; ++k) sum -= H[(size_t)i * m + k] * y[k];
+            y[i] = sum / H[(size_t)i * m + i];
+        }
+        SEM_HIP(c, hipMemcpyAsync(G->coef, y.data(), 8 * jdone, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_gm_update, dim3(grid), dim3(kGmBlock), 0, s, n, jdone, ld,
+                           (const double *)G->Z, (const double *)G->coef, x);
+        SEM_HIP(c, hipGetLastError());
+        // true residual r = b - A x
+        sem_status e = apply_A(G, x, G->w, s);
+        if (e) return info->status = e;
+        SEM_HIP(c, hipMemcpyAsync(G->r, b, 8 * n, hipMemcpyDeviceToDevice, s));
+        const double minus1 = -1.0;
+        SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMaxVec + 2, &minus1, 8, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_gm_update, dim3(grid), dim3(kGmBlock), 0, s, n, 1, ld,
+                           (const double *)G->w, (const double *)(G->coef + kGmMaxVec + 2), G->r);
+        SEM_HIP(c, gm_dots(G, 0, G->V, G->r, s));
+        double rr = 0.0;
+        SEM_HIP(c, hipMemcpyAsync(&rr, G->coef, 8, hipMemcpyDeviceToHost, s));
+        SEM_HIP(c, hipStreamSynchronize(s));
+        beta = std::sqrt(rr);
+        info->true_rel_residual = beta / bn;
+        if (!std::isfinite(beta)) { result = gfail(G, SEM_ERR_NAN, "non-finite residual"); break; }
+        if (beta <= o.tol * bn) { result = SEM_OK; break; }
+        if (info->iterations >= o.max_iter) { result = SEM_ERR_NOT_CONVERGED; break; }
+        info->restarts += 1;
+    }
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (result == SEM_ERR_NOT_CONVERGED) G->err = "iteration cap reached";
+    return info->status = result;
+}

@@ -150,10 +150,12 @@ extern "C" sem_status sem_setup(const sem_mesh *mesh, int N, const sem_options *
         c->csr_idx = std::move(num.csr_idx);
         c->bdir = std::move(num.bdir);
     }
-    if (mesh->vertex_xyz) {
+    if (mesh->vertex_xyz)
         c->vertex_xyz.assign(mesh->vertex_xyz, mesh->vertex_xyz + 3 * mesh->num_vertices);
-        c->corners.assign(mesh->corner_ids, mesh->corner_ids + 8 * c->E);
-    }
+    c->corners.assign(mesh->corner_ids, mesh->corner_ids + 8 * c->E);
+    if (mesh->face_bc) c->face_bc.assign(mesh->face_bc, mesh->face_bc + 6 * c->E);
+    else c->face_bc.assign(6 * c->E, 0);
+    c->num_vertices = mesh->num_vertices;
     for (int p = 0; p < kNumPrec; ++p) {
         c->tile[p].epb = std::max(1, 64 / (c->n1 * c->n1));
         if (c->n1 * c->n1 * c->tile[p].epb < 64 && c->n1 <= 6) c->tile[p].epb = 256 / (c->n1 * c->n1);
@@ -363,6 +365,16 @@ extern "C" sem_status sem_set_geometry(sem_ctx c, const double *gll_xyz, sem_str
             SEM_HIP(c, hipStreamSynchronize(s));
             trilinear_chunk(c, e0, ne, tmp.data());
         }
+        // element corners (coarse-grid geometry and element lengths)
+        c->corner_xyz.resize((size_t)c->E * 24);
+        for (int64_t e = 0; e < ne; ++e)
+            for (int d = 0; d < 3; ++d)
+                for (int cc = 0; cc < 8; ++cc) {
+                    const int i = (cc & 1) ? c->N : 0, j = (cc & 2) ? c->N : 0,
+                              k = (cc & 4) ? c->N : 0;
+                    c->corner_xyz[(size_t)(e0 + e) * 24 + d * 8 + cc] =
+                        src[((size_t)e * 3 + d) * c->np + i + c->n1 * (j + c->n1 * k)];
+                }
         SEM_HIP(c, hipMemcpyAsync(stage, src, sizeof(double) * 3 * c->np * ne,
                                   hipMemcpyHostToDevice, s));
         SEM_HIP(c, launch_geometry(c, stage, e0, ne, errflag, s));

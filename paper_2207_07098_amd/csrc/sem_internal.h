@@ -80,7 +80,10 @@ struct sem_ctx_s {
     std::vector<int32_t> csr_idx;     // [E*nb] compact positions e*nb+bpos
     std::vector<uint8_t> bdir;        // [n_bnd]
     std::vector<double> vertex_xyz;   // [num_vertices][3] (optional)
-    std::vector<int64_t> corners;     // [E][8] (kept only with vertex_xyz)
+    std::vector<int64_t> corners;     // [E][8] corner (vertex) ids
+    std::vector<uint8_t> face_bc;     // [E][6] Dirichlet face tags
+    int64_t num_vertices = 0;
+    std::vector<double> corner_xyz;   // [E][3][8] corner coordinates (set with the geometry)
 
     // device
     char *ws = nullptr;
