@@ -13,8 +13,16 @@ before any timed region.
 * Solves (after the timed steps, each one call): Jacobi-PCG in FP64 and FP64
   iterative refinement around FP32 / FP16-scaled / BF16-scaled inner PCG, to
   a true relative residual of 1e-10, for f = 3 sin x sin y sin z.
+* pressure: the same right-hand side solved by restarted GMRES with the
+  hybrid Schwarz preconditioner (element solves + 10-iteration coarse PCG),
+  against the FP64 Jacobi-PCG time.
+* batch: 64 independent box problems (K ~ U{2..12}, N in {5,7,9}) solved
+  together to 1e-8, against solving them one after another.
+* ogrid (--ogrid): the 256x64x32 O-grid around a cylinder, N = 7: the fused
+  operator's kernel time and roofline fraction, and its solves to 1e-10.
 * cpu_baseline: the FP64 oracle's assembled operator on a 24^3-element
-  corner block of the same mesh (1/8 of the elements), single thread.
+  corner block of the same mesh (1/8 of the elements), on all host cores
+  (OpenMP over elements; gather-scatter in fixed order) and on one.
 
 Prints one JSON line.
 """
@@ -111,35 +119,70 @@ def mfma_compare(op, u32, nb, stream):
             if best is None or ms < best[1]:
                 best = (epb, ms)
         op.set_tile(prec, **tuned)
+        # issued matrix-core work: 36 v_mfma_f32_16x16x16 per element (hi/lo
+        # operand pairs, three directions forward and back, two column halves)
+        flops = 36 * 2 * 16 ** 3 * op.E
         out[prec] = {"simt_ms": simt, "mfma_ms": best[1], "mfma_elements_per_block": best[0],
-                     "simt_GBps": B / simt / 1e6, "mfma_GBps": B / best[1] / 1e6}
+                     "simt_GBps": B / simt / 1e6, "mfma_GBps": B / best[1] / 1e6,
+                     "mfma_issued_TFLOPs": flops / (best[1] * 1e-3) / 1e12,
+                     "mfma_frac_of_dense_peak": flops / (best[1] * 1e-3) / 2.5e15}
         log("mfma", prec, out[prec])
     return out
 
 
-def cpu_baseline(K=24, N=7, min_seconds=10.0):
+def host_info():
+    import platform
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return {"nproc": os.cpu_count(), "affinity": affinity, "model": model,
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+
+
+def cpu_baseline(K=24, N=7, min_seconds=8.0):
     import fixtures as F
     import oracle
     h = 2 * np.pi / 48
     mesh = F.box(K, hi=(K * h,) * 3, deform=0.05)
     P = oracle.setup(mesh, N)
     u = F.random_unique(P.n_u, 0)
-    P.apply(u)
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        P.apply(u)
-        reps += 1
-        dt = time.perf_counter() - t0
-        if dt >= min_seconds:
-            break
-    return {"value": P.n_u * reps / dt / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
-            "sample": "FP64 oracle M Q^T A_L Q M u on the %d^3-element corner block of the "
-                      "48^3 N=7 deformed mesh (%d unique nodes), %d applications in %.1f s"
-                      % (K, P.n_u, reps, dt),
-            "seconds_per_apply": dt / reps}
+
+    def timed(threads):
+        P.apply(u, threads=threads)
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            P.apply(u, threads=threads)
+            reps += 1
+            dt = time.perf_counter() - t0
+            if dt >= min_seconds:
+                return reps, dt
+
+    r1, d1 = timed(False)
+    ra, da = timed(True)
+    cores = int(oracle.lib_omp().ora_threads())
+    sample = ("FP64 oracle M Q^T A_L Q M u on the %d^3-element corner block of the 48^3 N=7 "
+              "deformed mesh (%d unique nodes)" % (K, P.n_u))
+    return {"value": P.n_u * ra / da / 1e9, "unit": "GDOF/s", "cores": cores, "kind": "oracle",
+            "sample": sample + ", %d applications in %.1f s on %d threads (OpenMP over elements)"
+                      % (ra, da, cores),
+            "seconds_per_apply": da / ra,
+            "single_thread": {"value": P.n_u * r1 / d1 / 1e9, "cores": 1,
+                              "seconds_per_apply": d1 / r1,
+                              "sample": sample + ", %d applications in %.1f s" % (r1, d1)},
+            "host": host_info()}
 
 
-def bench_batch(args):
+def bench_batch(args, emit=True):
     """64 independent box problems (K ~ U{2..12}, N in {5,7,9}, per-axis
     element widths ~ U[0.5,2], random RHS) solved together to 1e-8."""
     import torch
@@ -186,7 +229,91 @@ def bench_batch(args):
            "problems": len(ops), "elements": sum(o.E for o in ops),
            "unique_nodes": sum(o.n_unique for o in ops),
            "bytes_per_iteration_all_problems": B}
-    print(json.dumps(res), flush=True)
+    if emit:
+        print(json.dumps(res), flush=True)
+    return res
+
+
+def bench_pressure(op, b, fp64_info, restart=30):
+    """Restarted GMRES with the hybrid Schwarz preconditioner on the same
+    right-hand side to 1e-10, against the FP64 Jacobi-PCG solve."""
+    import torch
+    import paper_2207_07098_amd as sem
+    t0 = time.perf_counter()
+    ps = sem.PressureSolver(op, restart=restart)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    ps.solve(b, tol=1e-10)                          # warm-up (coarse graph capture)
+    x, info = ps.solve(b, tol=1e-10, raise_on_error=False)
+    out = {"solver": "flexible GMRES(%d), hybrid Schwarz: overlapping element solves "
+                     "(fast diagonalisation) + 10 Jacobi-PCG iterations on the N=1 vertex "
+                     "problem" % restart,
+           "setup_seconds": setup, **info}
+    if fp64_info:
+        out["fp64_pcg_seconds"] = fp64_info["seconds"]
+        out["fp64_pcg_iterations"] = fp64_info["iterations"]
+        out["speedup_vs_fp64_pcg"] = fp64_info["seconds"] / info["seconds"]
+        if "x64" in fp64_info:
+            pass
+    del ps
+    return out
+
+
+def bench_ogrid(args):
+    """256x64x32 O-grid, N = 7: the fused FP64 operator (kernel time,
+    roofline), FP64 Jacobi-PCG, FP64 refinement around FP32 and BF16 (matrix
+    cores) PCG, and the GMRES pressure solver, each to 1e-10."""
+    import torch
+    import fixtures as F
+    import paper_2207_07098_amd as sem
+    t0 = time.perf_counter()
+    w = F.cylinder_ogrid(N=7)
+    op = sem.Operator(w.mesh, 7, precisions=("fp64", "fp32", "bf16"), solver=True)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    gid, pos, _, _ = op.numbering()
+    u = torch.from_numpy(F.random_unique(op.n_unique, 0)[np.argsort(pos)]).cuda()
+    y = torch.zeros_like(u)
+    best, _ = op.autotune("fp64", reps=5, cache_path=args.tune_cache)
+    stream = torch.cuda.current_stream()
+    k_ms = kernel_ms(op, "fp64", u, y, op.n_boundary, stream, reps=20)
+    B = bytes_ax_gs(op.n_local, op.n_unique)
+    out = {"workload": "O-grid 256x64x32 around a unit cylinder, radial stretching 1.05, "
+                       "periodic azimuth and span, N=7, Dirichlet on the cylinder",
+           "elements": op.E, "n_unique": op.n_unique, "setup_seconds": setup, "tile": best,
+           "kernel_ms": k_ms, "GDOF_per_s_kernel": op.n_unique / (k_ms * 1e-3) / 1e9,
+           "roofline_frac": B / (k_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "bytes_per_launch": B}
+    log("ogrid kernel %.3f ms, %.1f%% of 8 TB/s" % (k_ms, 100 * out["roofline_frac"]))
+    del u, y
+    f = F.random_unique(op.n_unique, w.seed)
+    fs = np.empty_like(f)
+    fs[pos] = f
+    b = op.rhs(f_unique=torch.from_numpy(fs).cuda())
+    solves = {}
+    ps = sem.PressureSolver(op, restart=20)
+    x, info = ps.solve(b, tol=1e-10, raise_on_error=False)
+    solves["gmres_hybrid_schwarz"] = info
+    log("ogrid gmres", json.dumps(info))
+    del ps, x
+    torch.cuda.empty_cache()
+    for prec in args.ogrid_solves.split(","):
+        if not prec:
+            continue
+        kw = {"inner_tol": 1e-4 if prec == "fp32" else 1e-2} if prec != "fp64" else {}
+        if prec == "bf16":
+            op.set_tile("bf16", elements_per_block=2, grid_cap=0, xcd_remap=0, pipeline=2)
+        x, info = op.solve(b, tol=1e-10, precision=prec, max_iter=200000,
+                           raise_on_error=False, **kw)
+        solves[prec] = info
+        log("ogrid", prec, json.dumps(info))
+        del x
+    if "fp64" in solves:
+        t64 = solves["fp64"]["seconds"]
+        for v in solves.values():
+            v["speedup_vs_fp64_pcg"] = t64 / v["seconds"] if v["seconds"] > 0 else None
+    out["solve"] = solves
+    del op
+    return out
 
 
 def bench_operator(args):
@@ -236,6 +363,12 @@ def main():
                     help="time only the fused operator in this precision (for counter runs)")
     ap.add_argument("--tile", default=None,
                     help="with --operator: elements_per_block:grid_cap:xcd_remap:pipeline")
+    ap.add_argument("--no-pressure", action="store_true", help="skip the GMRES pressure solve")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch")
+    ap.add_argument("--ogrid", action="store_true",
+                    help="add the 256x64x32 O-grid section (operator and solves)")
+    ap.add_argument("--ogrid-solves", default="fp64,fp32,bf16",
+                    help="O-grid Jacobi-PCG solves: fp64 and FP64 refinement around fp32/bf16")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of 1 GiB (for counter scaling) and exit")
     args = ap.parse_args()
@@ -332,6 +465,15 @@ def main():
     traffic, traffic_src = recorded_traffic(wl_tag, kname, tile)
     gdofs = op.n_unique / (ms_step * 1e-3) / 1e9
     achieved = B / (k_ms * 1e-3) / 1e9
+    # per-call times of the whole operator (clearing + kernel), for the spread
+    cev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(min(args.steps, 100))]
+    for a, bq in cev:
+        a.record(stream)
+        op.ax(u, y)
+        bq.record(stream)
+    torch.cuda.synchronize()
+    call_ms = np.array([a.elapsed_time(bq) for a, bq in cev])
     log("Ax+gs: %.3f ms/call, kernel %.3f ms (std %.3f), %.1f GDOF/s, %.0f GB/s alg (%.1f%%)" %
         (ms_step, k_ms, kms.std(), gdofs, achieved, 100 * achieved / PEAK_HBM_GBS))
 
@@ -353,6 +495,7 @@ def main():
                      "kernel_ms": k_ms, "bytes_per_launch": B,
                      "source_sha256": source_digest()},
         "local_points_per_s": op.n_local / (ms_step * 1e-3),
+        "ms_per_step_std": float(call_ms.std()), "kernel_ms_std": float(kms.std()),
         "tile": tile,
     }
     if tune:
@@ -417,6 +560,19 @@ def main():
                 v["speedup_vs_fp64"] = t64 / v["seconds"] if v["seconds"] > 0 else None
         result["solve"] = solves
 
+    if not args.no_solve and not args.no_pressure:
+        log("pressure solver (GMRES + hybrid Schwarz) ...")
+        result["pressure"] = bench_pressure(op, b, solves.get("fp64"))
+    del op
+    torch.cuda.empty_cache()
+    if not args.no_batch and args.workload == "box":
+        log("batch ...")
+        result["batch"] = bench_batch(args, emit=False)
+        torch.cuda.empty_cache()
+    if args.ogrid and args.workload == "box":
+        log("ogrid ...")
+        result["ogrid"] = bench_ogrid(args)
+        torch.cuda.empty_cache()
     if not args.no_cpu and args.workload == "box":
         log("cpu baseline ...")
         result["cpu_baseline"] = cpu_baseline()

@@ -230,7 +230,8 @@ typedef struct {
                                      (scaled per element), D and the
                                      weighted derivatives enter as pairs of
                                      16-bit numbers (hi + lo), products
-                                     accumulate in FP32                      */
+                                     accumulate in FP32; sem_autotune tries
+                                     it for FP16 factors only                */
 } sem_tile;
 
 typedef struct {

@@ -28,15 +28,42 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle (plain C, FP64, no fast-math)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-std=c11",
-                               "-D_DEFAULT_SOURCE", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile the oracle (plain C, FP64, no fast-math), and the same source
+    with OpenMP (elements split over threads; used only for the all-core
+    CPU baseline)."""
+    for path, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp%d" % os.getpid()
+            subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-std=c11",
+                                   "-D_DEFAULT_SOURCE", "-fPIC", "-shared", *extra,
+                                   "-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, path)
     return _LIB
+
+
+def _declare(L):
+    P = ctypes.c_void_p
+    i64, i32 = ctypes.c_int64, ctypes.c_int
+    L.ora_threads.restype = i32
+    L.ora_apply.argtypes = [i32, i64, P, P, P, i64, P, P, P]
+    return L
+
+
+_lib_omp = None
+
+
+def lib_omp():
+    """The OpenMP build (all-core CPU baseline only)."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(_LIB_OMP):
+            build()
+        _lib_omp = _declare(ctypes.CDLL(_LIB_OMP))
+    return _lib_omp
 
 
 def lib():
@@ -45,6 +72,7 @@ def lib():
         if not os.path.exists(_LIB):
             build()
         L = ctypes.CDLL(_LIB)
+        L.ora_threads.restype = ctypes.c_int
         P = ctypes.c_void_p
         i64, i32 = ctypes.c_int64, ctypes.c_int
         L.ora_gll.argtypes = [i32, P, P]
@@ -186,12 +214,13 @@ class Problem:
     def n_local(self):
         return self.E * (self.N + 1) ** 3
 
-    def apply(self, u: np.ndarray) -> np.ndarray:
-        """y = M Q^T A_L Q M u (Eqs. (11)-(12) with the Dirichlet mask)."""
+    def apply(self, u: np.ndarray, threads: bool = False) -> np.ndarray:
+        """y = M Q^T A_L Q M u (Eqs. (11)-(12) with the Dirichlet mask);
+        threads=True runs the OpenMP build (same arithmetic per element)."""
         y = np.empty(self.n_u)
-        lib().ora_apply(self.N, self.E, _p(self.D), _p(self.G), _p(self.gid),
-                        self.n_u, _p(self.dirichlet),
-                        _p(np.ascontiguousarray(u, dtype=np.float64)), _p(y))
+        (lib_omp() if threads else lib()).ora_apply(
+            self.N, self.E, _p(self.D), _p(self.G), _p(self.gid), self.n_u,
+            _p(self.dirichlet), _p(np.ascontiguousarray(u, dtype=np.float64)), _p(y))
         return y
 
     def rhs_local(self, fL: np.ndarray) -> np.ndarray:

@@ -22,6 +22,9 @@
  */
 #include <math.h>
 #include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -170,9 +173,15 @@ void ora_ax_local(int N, int64_t E, const double *D, const double *G,
                   const double *u, double *w)
 {
     int n1 = N + 1, np = n1 * n1 * n1;
+    /* elements are independent: an OpenMP build (the all-core CPU
+       baseline) splits them over threads; each element's arithmetic is
+       the same either way */
+#pragma omp parallel
+    {
     double *ur = (double *)malloc(sizeof(double) * np);
     double *us = (double *)malloc(sizeof(double) * np);
     double *ut = (double *)malloc(sizeof(double) * np);
+#pragma omp for schedule(static)
     for (int64_t e = 0; e < E; ++e) {
         const double *ue = u + (size_t)e * np;
         const double *g = G + (size_t)e * 6 * np;
@@ -214,6 +223,7 @@ void ora_ax_local(int N, int64_t E, const double *D, const double *G,
                 }
     }
     free(ur); free(us); free(ut);
+    }
 }
 
 /*
@@ -529,4 +539,14 @@ int ora_pcg(int N, int64_t E, const double *D, const double *G,
 {
     return ora_pcg_helmholtz(N, E, D, G, NULL, 1.0, 0.0, gid, n_unique, dirichlet, dinv, b,
                              x, tol, max_iter, max_restart, out, hist);
+}
+
+/* Threads an OpenMP build of this file uses (1 otherwise). */
+int ora_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -657,9 +657,13 @@ extern "C" sem_status sem_autotune(sem_ctx c, sem_precision prec, int reps, cons
     double best_ms = INFINITY;
     AxTile best_t = saved;
     int nres = 0;
-    // pipeline 2 (matrix cores) is a candidate wherever it is valid: 16-bit
-    // factors at N = 7
-    for (int pipe = 0; pipe < 3; ++pipe)
+    // pipeline 2 (matrix cores) is a candidate for FP16 factors at N = 7,
+    // where the hi + lo operand pairs keep ~22 bits (FP32 arithmetic: 24);
+    // with BF16 pairs (~17 bits) the refined solves take more iterations
+    // than with the SIMT kernel (48^3: 1683 against 1474), so BF16 uses the
+    // matrix cores only when the tile is set explicitly
+    const int npipe = prec == SEM_FP16_SCALED ? 3 : 2;
+    for (int pipe = 0; pipe < npipe; ++pipe)
     for (int epb : epbs)
         for (int cap : caps)
             for (int xcd = 0; xcd < 2; ++xcd) {
