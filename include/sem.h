@@ -424,8 +424,14 @@ sem_status sem_proj_solve(sem_proj proj, const double *b, double *x,
  * preconditioner and sets up the coarse geometry (synchronises `stream`).
  * sem_gmres_solve: b, x device unique vectors (solver order, FP64); opts:
  * tol (true relative residual, checked in FP64 at each restart), max_iter,
- * zero_guess; precision must be SEM_FP64.  info->iterations counts GMRES
- * steps, info->restarts restarts.  sem_gmres_precondition applies the
+ * zero_guess, precision.  SEM_FP64: GMRES in FP64.  A reduced precision
+ * (configured at set-up): FP64 iterative refinement r = b - A x, inner GMRES
+ * with FP32 vectors and that precision's operator on A d = r / ||r|| to
+ * opts.inner_tol, x += ||r|| d (the preconditioner computes in FP64 on FP32
+ * vectors); two corrections in a row that do not halve the FP64 residual,
+ * or max_outer corrections, hand over to FP64 GMRES from the current x
+ * (info->fallback).  info->iterations counts GMRES steps of all levels,
+ * info->restarts restarts, info->outer_iterations corrections.  sem_gmres_precondition applies the
  * preconditioner (parts: SEM_PC_SCHWARZ and/or SEM_PC_COARSE) to r -> z.
  * ------------------------------------------------------------------------- */
 typedef struct sem_gmres_s *sem_gmres;

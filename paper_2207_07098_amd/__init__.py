@@ -552,11 +552,17 @@ class PressureSolver:
         return z
 
     def solve(self, b, x=None, tol: float = 1e-10, max_iter: int = 10000,
+              precision: str = "fp64", inner_tol: float = 1e-3, max_outer: int = 50,
               raise_on_error: bool = True):
+        """FP64 GMRES, or (precision fp32/fp16/bf16) FP64 refinement around
+        FP32-vector GMRES with that operator.  Returns (x, info dict)."""
         o = SolveOptions()
         lib().sem_default_solve_options(ctypes.byref(o))
         o.tol = tol
         o.max_iter = max_iter
+        o.precision = PRECISIONS[precision]
+        o.inner_tol = inner_tol
+        o.max_outer = max_outer
         o.zero_guess = 1 if x is None else 0
         if x is None:
             x = self.op.vector()

@@ -30,6 +30,7 @@
 #include <cstring>
 #include <map>
 #include <thread>
+#include <type_traits>
 #include <unordered_map>
 
 #include "sem_internal.h"
@@ -92,8 +93,9 @@ __device__ __forceinline__ int64_t gm_node(const int32_t *bmap, int64_t n_bnd, i
     return gm_interior(n_bnd, e, i, j, k, N);
 }
 
+template <typename VT>
 struct FdmParams {
-    const double *r;          // residual (unique, solver order)
+    const VT *r;              // residual (unique, solver order; FP64 or FP32)
     double *z;                // sum of local solutions (atomic)
     const double *S;          // [E][3][NE][NE] eigenvectors S[a][m]
     const double *lam;        // [E][3][NE]
@@ -105,8 +107,8 @@ struct FdmParams {
 
 // Box index a in 0..NE-1 <-> local index a - 1.  A lane owns the column
 // (a, b) of the box over c (k-direction) in registers.
-template <int NE>
-__global__ void __launch_bounds__(256) k_fdm(FdmParams P) {
+template <int NE, typename VT>
+__global__ void __launch_bounds__(256) k_fdm(FdmParams<VT> P) {
     constexpr int C = NE * NE;
     const int N = NE - 3, n1 = NE - 2;
     __shared__ double Sl[3][C];
@@ -139,7 +141,7 @@ __global__ void __launch_bounds__(256) k_fdm(FdmParams P) {
             }
         }
         idx[c] = g;
-        v[c] = g >= 0 ? P.r[g] : 0.0;
+        v[c] = g >= 0 ? (double)P.r[g] : 0.0;
     }
     __syncthreads();
     // forward: w = (S_t^T x S_s^T x S_r^T) v
@@ -213,9 +215,11 @@ __global__ void __launch_bounds__(256) k_fdm(FdmParams P) {
     }
 }
 
+template <typename VT>
 struct CoarseParams {
-    const double *r;          // fine residual (restrict) / fine output z (interp)
-    double *y;                // coarse right-hand side (restrict) / fine z (interp)
+    const VT *r;              // fine residual (restrict)
+    double *b0;               // coarse right-hand side (restrict)
+    VT *y;                    // fine output z (combine)
     const double *x0;         // coarse solution (interp)
     const double *zs;         // Schwarz sum (interp)
     const double *W;          // counting weights (interp)
@@ -230,7 +234,8 @@ __device__ __forceinline__ double phi(double x, int side) { return side ? 0.5 * 
 
 // P^T r: per element, sum over its points of phi_c(x) r[g] / mult[g] for the
 // 8 corners, one wave per element, then 8 atomics into the coarse vector.
-__global__ void __launch_bounds__(64) k_coarse_restrict(CoarseParams P) {
+template <typename VT>
+__global__ void __launch_bounds__(64) k_coarse_restrict(CoarseParams<VT> P) {
     const int64_t e = blockIdx.x;
     const int N = P.N, n1 = N + 1, np = n1 * n1 * n1;
     double acc[8] = {};
@@ -240,7 +245,7 @@ __global__ void __launch_bounds__(64) k_coarse_restrict(CoarseParams P) {
         if (g < 0) continue;
         double m = 1.0;
         if (g < P.n_bnd) m = (double)(P.csr_off[g + 1] - P.csr_off[g]);
-        const double rv = P.r[g] / m;
+        const double rv = (double)P.r[g] / m;
 #pragma unroll
         for (int c = 0; c < 8; ++c)
             acc[c] += phi(P.xi[i], c & 1) * phi(P.xi[j], (c >> 1) & 1) * phi(P.xi[k], (c >> 2) & 1) * rv;
@@ -256,13 +261,14 @@ __global__ void __launch_bounds__(64) k_coarse_restrict(CoarseParams P) {
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const int32_t gc = P.cmap[e * 8 + c];
-            if (gc >= 0) atomicAdd(P.y + gc, acc[c]);
+            if (gc >= 0) atomicAdd(P.b0 + gc, acc[c]);
         }
 }
 
 // z[g] = W[g] zs[g] + (P x0)[g] over fine unique nodes (0 on Dirichlet
 // nodes); P is evaluated in the element of the node's first copy.
-__global__ void k_combine(CoarseParams P) {
+template <typename VT>
+__global__ void k_combine(CoarseParams<VT> P) {
     const int N = P.N, n1 = N + 1, nm = N - 1;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < P.n_u;
          g += (int64_t)gridDim.x * blockDim.x) {
@@ -292,14 +298,15 @@ __global__ void k_combine(CoarseParams P) {
                       P.x0[gc];
         }
         const double zs = P.zs ? P.W[g] * P.zs[g] : 0.0;
-        P.y[g] = P.W[g] > 0.0 ? zs + zc : 0.0;            // W = 0 only on Dirichlet nodes
+        P.y[g] = (VT)(P.W[g] > 0.0 ? zs + zc : 0.0);      // W = 0 only on Dirichlet nodes
     }
 }
 
 // part[blk][i] = X_i . v (i < l), part[blk][l] = v . v
+template <typename T>
 __global__ void __launch_bounds__(kGmBlock) k_gm_dots(int64_t n, int l, int64_t ld,
-                                                      const double *__restrict__ X,
-                                                      const double *__restrict__ v,
+                                                      const T *__restrict__ X,
+                                                      const T *__restrict__ v,
                                                       double *__restrict__ part) {
     __shared__ double red[kGmBlock / 64];
     double acc[kGmMaxVec + 1];
@@ -307,10 +314,10 @@ __global__ void __launch_bounds__(kGmBlock) k_gm_dots(int64_t n, int l, int64_t 
     for (int i = 0; i <= kGmMaxVec; ++i) acc[i] = 0.0;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * blockDim.x) {
-        const double vq = v[q];
+        const double vq = (double)v[q];
 #pragma unroll
         for (int i = 0; i < kGmMaxVec; ++i)
-            if (i < l) acc[i] += X[i * ld + q] * vq;
+            if (i < l) acc[i] += (double)X[i * ld + q] * vq;
         acc[kGmMaxVec] += vq * vq;
     }
 #pragma unroll
@@ -335,41 +342,45 @@ __global__ void __launch_bounds__(kGmBlock) k_gm_finish(int nblocks, int m,
 }
 
 // v -= sum_i c_i X_i (i < l); part[blk] = v . v
+template <typename T>
 __global__ void __launch_bounds__(kGmBlock) k_gm_orth(int64_t n, int l, int64_t ld,
-                                                      const double *__restrict__ X,
+                                                      const T *__restrict__ X,
                                                       const double *__restrict__ coef,
-                                                      double *__restrict__ v,
+                                                      T *__restrict__ v,
                                                       double *__restrict__ part) {
     __shared__ double red[kGmBlock / 64];
     double s = 0.0;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * blockDim.x) {
-        double x = v[q];
-        for (int i = 0; i < l; ++i) x -= coef[i] * X[i * ld + q];
-        v[q] = x;
-        s += x * x;
+        double x = (double)v[q];
+        for (int i = 0; i < l; ++i) x -= coef[i] * (double)X[i * ld + q];
+        const T xt = (T)x;
+        v[q] = xt;
+        s += (double)xt * (double)xt;
     }
     s = gm_block_sum(s, red);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 // dst = src * scale[0] (scale from device memory, 1/sqrt of it when inv_sqrt)
-__global__ void k_gm_scale(int64_t n, const double *__restrict__ src, double *__restrict__ dst,
+template <typename TS, typename TD>
+__global__ void k_gm_scale(int64_t n, const TS *__restrict__ src, TD *__restrict__ dst,
                            const double *__restrict__ scale, int inv_sqrt) {
     const double sc = inv_sqrt ? 1.0 / sqrt(scale[0]) : scale[0];
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * blockDim.x)
-        dst[q] = src[q] * sc;
+        dst[q] = (TD)((double)src[q] * sc);
 }
 
 // x += sum_i y_i Z_i (i < l)
-__global__ void k_gm_update(int64_t n, int l, int64_t ld, const double *__restrict__ Z,
-                            const double *__restrict__ y, double *__restrict__ x) {
+template <typename TZ, typename TX>
+__global__ void k_gm_update(int64_t n, int l, int64_t ld, const TZ *__restrict__ Z,
+                            const double *__restrict__ y, TX *__restrict__ x) {
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * blockDim.x) {
-        double s = x[q];
-        for (int i = 0; i < l; ++i) s += y[i] * Z[i * ld + q];
-        x[q] = s;
+        double s = (double)x[q];
+        for (int i = 0; i < l; ++i) s += y[i] * (double)Z[i * ld + q];
+        x[q] = (TX)s;
     }
 }
 
@@ -448,6 +459,7 @@ struct sem_gmres_s {
     double *zs = nullptr, *b0 = nullptr, *x0 = nullptr;
     double *V = nullptr, *Z = nullptr, *w = nullptr, *r = nullptr;
     double *part = nullptr, *coef = nullptr;
+    float *rhs32 = nullptr, *d32 = nullptr;
     std::string err;
 };
 
@@ -736,12 +748,14 @@ static size_t gm_layout(sem_gmres G, size_t *off) {
     off[13] = take(8 * (size_t)c->n_unique);          // r
     off[14] = take(8 * (size_t)kGmGrid * (kGmMaxVec + 1));
     off[15] = take(8 * (kGmMaxVec + 4));
+    off[16] = take(4 * (size_t)c->n_unique);          // FP32 inner right-hand side
+    off[17] = take(4 * (size_t)c->n_unique);          // FP32 inner correction
     return o;
 }
 
 extern "C" sem_status sem_gmres_workspace_size(sem_gmres G, size_t *bytes) {
     if (!G || !bytes) return gfail(G, SEM_ERR_INVALID, "null argument");
-    size_t off[16];
+    size_t off[18];
     *bytes = gm_layout(G, off);
     return SEM_OK;
 }
@@ -749,7 +763,7 @@ extern "C" sem_status sem_gmres_workspace_size(sem_gmres G, size_t *bytes) {
 extern "C" sem_status sem_gmres_bind_workspace(sem_gmres G, void *dev, size_t bytes,
                                                sem_stream stream) {
     if (!G || !dev) return gfail(G, SEM_ERR_INVALID, "null argument");
-    size_t off[16];
+    size_t off[18];
     const size_t need = gm_layout(G, off);
     if (bytes < need)
         return gfail(G, SEM_ERR_OOM, "workspace of " + std::to_string(bytes) + " bytes, need " +
@@ -780,6 +794,8 @@ extern "C" sem_status sem_gmres_bind_workspace(sem_gmres G, void *dev, size_t by
     G->r = reinterpret_cast<double *>(w + off[13]);
     G->part = reinterpret_cast<double *>(w + off[14]);
     G->coef = reinterpret_cast<double *>(w + off[15]);
+    G->rhs32 = reinterpret_cast<float *>(w + off[16]);
+    G->d32 = reinterpret_cast<float *>(w + off[17]);
     SEM_HIP(c, hipMemcpyAsync(G->dS, G->S.data(), 8 * G->S.size(), hipMemcpyHostToDevice, s));
     SEM_HIP(c, hipMemcpyAsync(G->dlam, G->lam.data(), 8 * G->lam.size(), hipMemcpyHostToDevice, s));
     SEM_HIP(c, hipMemcpyAsync(G->dghost, G->ghost.data(), 4 * G->ghost.size(), hipMemcpyHostToDevice, s));
@@ -790,19 +806,22 @@ extern "C" sem_status sem_gmres_bind_workspace(sem_gmres G, void *dev, size_t by
     return SEM_OK;
 }
 
-// z = M^-1 r: parts & 1 local Schwarz solves, parts & 2 coarse grid.
-static sem_status precondition(sem_gmres G, const double *r, double *z, unsigned parts,
-                               hipStream_t s) {
+// z = M^-1 r: parts & 1 local Schwarz solves, parts & 2 coarse grid.  r and
+// z are FP64 or FP32 vectors; the local solves and the coarse grid compute
+// in FP64 either way.
+template <typename VT>
+static sem_status precondition(sem_gmres G, const VT *r, VT *z, unsigned parts, hipStream_t s) {
     sem_ctx c = G->ctx;
     const int64_t n = c->n_unique;
     const bool local = parts & SEM_PC_SCHWARZ, coarse = parts & SEM_PC_COARSE;
     if (local) {
         SEM_HIP(c, launch_fill(G->zs, n, 0.0, s));
-        FdmParams P{r, G->zs, G->dS, G->dlam, G->dghost, dptr<int32_t>(c, c->L.bmap), c->E,
-                    c->n_bnd, c->N, c->nb};
-#define SEM_FDM(ne)                                                                     \
-    case ne:                                                                            \
-        hipLaunchKernelGGL(k_fdm<ne>, dim3((unsigned)c->E), dim3(((ne) * (ne) + 63) / 64 * 64), 0, s, P); \
+        FdmParams<VT> P{r, G->zs, G->dS, G->dlam, G->dghost, dptr<int32_t>(c, c->L.bmap), c->E,
+                        c->n_bnd, c->N, c->nb};
+#define SEM_FDM(ne)                                                                          \
+    case ne:                                                                                 \
+        hipLaunchKernelGGL((k_fdm<ne, VT>), dim3((unsigned)c->E), dim3(((ne) * (ne) + 63) / 64 * 64), \
+                           0, s, P);                                                         \
         break;
         switch (G->NE) {
             SEM_FDM(5) SEM_FDM(6) SEM_FDM(7) SEM_FDM(8) SEM_FDM(9) SEM_FDM(10) SEM_FDM(11)
@@ -812,13 +831,13 @@ static sem_status precondition(sem_gmres G, const double *r, double *z, unsigned
 #undef SEM_FDM
         SEM_HIP(c, hipGetLastError());
     }
-    CoarseParams C{r, G->b0, G->x0, local ? G->zs : nullptr, G->dW, G->dcmap,
-                   dptr<int32_t>(c, c->L.bmap), dptr<int32_t>(c, c->L.csr_off),
-                   dptr<int32_t>(c, c->L.csr_idx), dptr<int32_t>(c, c->L.bpos2l), G->dxi,
-                   c->E, c->n_bnd, n, c->N, c->nb};
+    CoarseParams<VT> C{r, G->b0, z, G->x0, local ? G->zs : nullptr, G->dW, G->dcmap,
+                       dptr<int32_t>(c, c->L.bmap), dptr<int32_t>(c, c->L.csr_off),
+                       dptr<int32_t>(c, c->L.csr_idx), dptr<int32_t>(c, c->L.bpos2l), G->dxi,
+                       c->E, c->n_bnd, n, c->N, c->nb};
     if (coarse) {
         SEM_HIP(c, launch_fill(G->b0, G->coarse->n_unique, 0.0, s));
-        hipLaunchKernelGGL(k_coarse_restrict, dim3((unsigned)c->E), dim3(64), 0, s, C);
+        hipLaunchKernelGGL(k_coarse_restrict<VT>, dim3((unsigned)c->E), dim3(64), 0, s, C);
         SEM_HIP(c, hipGetLastError());
         // 10 Jacobi-PCG iterations from zero on the coarse operator
         sem_solve_options o;
@@ -834,8 +853,7 @@ static sem_status precondition(sem_gmres G, const double *r, double *z, unsigned
     } else {
         C.x0 = nullptr;
     }
-    C.y = z;
-    hipLaunchKernelGGL(k_combine, dim3(gm_grid(n)), dim3(kGmBlock), 0, s, C);
+    hipLaunchKernelGGL(k_combine<VT>, dim3(gm_grid(n)), dim3(kGmBlock), 0, s, C);
     SEM_HIP(c, hipGetLastError());
     return SEM_OK;
 }
@@ -846,102 +864,112 @@ extern "C" sem_status sem_gmres_precondition(sem_gmres G, const double *r, doubl
     if (!G->ws) return gfail(G, SEM_ERR_STATE, "no workspace bound");
     if (!(parts & (SEM_PC_SCHWARZ | SEM_PC_COARSE)) || (parts & ~3u))
         return gfail(G, SEM_ERR_INVALID, "parts must name SEM_PC_SCHWARZ and/or SEM_PC_COARSE");
-    return precondition(G, r, z, parts, (hipStream_t)stream);
+    return precondition<double>(G, r, z, parts, (hipStream_t)stream);
 }
 
-// y = A x (fine operator, FP64, atomic summation into a cleared boundary block)
-static sem_status apply_A(sem_gmres G, const double *x, double *y, hipStream_t s) {
+// y = A x with the operator of precision prec (FP64 vectors for SEM_FP64,
+// FP32 otherwise; atomic summation into a cleared boundary block)
+template <typename T>
+static sem_status apply_A(sem_gmres G, int prec, const T *x, T *y, hipStream_t s) {
     sem_ctx c = G->ctx;
-    SEM_HIP(c, launch_fill(y, c->n_bnd, 0.0, s));
-    SEM_HIP(c, launch_ax(c, SEM_FP64, x, y, 0, OUT_ATOMIC, nullptr, nullptr, c->tile[0], s));
+    if (std::is_same<T, double>::value) SEM_HIP(c, launch_fill((double *)y, c->n_bnd, 0.0, s));
+    else SEM_HIP(c, launch_fill32((float *)y, c->n_bnd, 0.0f, s));
+    SEM_HIP(c, launch_ax(c, prec, x, y, 0, OUT_ATOMIC, nullptr, nullptr, c->tile[prec], s));
     return SEM_OK;
 }
 
-// coef[0..l) = X^T v, coef[l] = v.v
-static hipError_t gm_dots(sem_gmres G, int l, const double *X, const double *v, hipStream_t s) {
+// coef[0..l) = X^T v, coef[l] = v.v (FP64 sums)
+template <typename T>
+static hipError_t gm_dots(sem_gmres G, int l, const T *X, const T *v, hipStream_t s) {
     const int64_t n = G->ctx->n_unique;
     const unsigned g = gm_grid(n);
-    hipLaunchKernelGGL(k_gm_dots, dim3(g), dim3(kGmBlock), 0, s, n, l, G->ld, X, v, G->part);
+    hipLaunchKernelGGL(k_gm_dots<T>, dim3(g), dim3(kGmBlock), 0, s, n, l, G->ld, X, v, G->part);
     hipLaunchKernelGGL(k_gm_finish, dim3(1), dim3(kGmBlock), 0, s, (int)g, l + 1,
                        (const double *)G->part, G->coef);
     return hipGetLastError();
 }
 
-extern "C" sem_status sem_gmres_solve(sem_gmres G, const double *b, double *x,
-                                      const sem_solve_options *opts, sem_solve_info *info,
-                                      sem_stream stream) {
-    sem_solve_info dummy;
-    if (!info) info = &dummy;
-    std::memset(info, 0, sizeof(*info));
-    if (!G || !b || !x) return info->status = gfail(G, SEM_ERR_INVALID, "null argument");
-    if (!G->ws) return info->status = gfail(G, SEM_ERR_STATE, "no workspace bound");
+// Host copy of coef[0] after the stream has reached it.
+static sem_status read_coef(sem_gmres G, int at, double *out, hipStream_t s) {
+    SEM_HIP(G->ctx, hipMemcpyAsync(out, G->coef + at, 8, hipMemcpyDeviceToHost, s));
+    SEM_HIP(G->ctx, hipStreamSynchronize(s));
+    return SEM_OK;
+}
+
+// r = b - A x in T vectors; returns ||r|| in *rn.
+template <typename T>
+static sem_status residual(sem_gmres G, int prec, const T *b, const T *x, T *r, T *w, bool x_zero,
+                           double *rn, hipStream_t s) {
     sem_ctx c = G->ctx;
-    if (c->helm) return info->status = gfail(G, SEM_ERR_UNSUPPORTED, "Poisson operator only");
-    sem_solve_options o;
-    if (opts) o = *opts; else sem_default_solve_options(&o);
-    if (!(o.tol > 0) || o.max_iter < 1) return info->status = gfail(G, SEM_ERR_INVALID, "bad tolerance or cap");
-    if (o.precision != SEM_FP64)
-        return info->status = gfail(G, SEM_ERR_UNSUPPORTED, "the GMRES solve is FP64");
-    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = c->n_unique;
+    SEM_HIP(c, hipMemcpyAsync(r, b, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+    if (!x_zero) {
+        sem_status e = apply_A<T>(G, prec, x, w, s);
+        if (e) return e;
+        const double minus1 = -1.0;
+        SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMaxVec + 2, &minus1, 8, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL((k_gm_update<T, T>), dim3(gm_grid(n)), dim3(kGmBlock), 0, s, n, 1, G->ld,
+                           (const T *)w, (const double *)(G->coef + kGmMaxVec + 2), r);
+        SEM_HIP(c, hipGetLastError());
+    }
+    SEM_HIP(c, gm_dots<T>(G, 0, (const T *)nullptr, r, s));
+    double rr = 0.0;
+    sem_status e = read_coef(G, 0, &rr, s);
+    if (e) return e;
+    *rn = std::sqrt(rr);
+    return SEM_OK;
+}
+
+// Flexible GMRES(m) cycles on A x = b in T vectors (operator precision
+// prec) until ||b - A x|| <= atol (recurrence estimate within a cycle, true
+// residual at its end) or max_iter steps in all.  V, Z, w, r live in the
+// solver's basis arrays (FP32 vectors use the first half of each slot).
+// Returns SEM_OK when converged, SEM_ERR_NOT_CONVERGED at the cap; *res_out
+// is the last true residual norm.
+template <typename T>
+static sem_status fgmres(sem_gmres G, int prec, const T *b, T *x, bool x_zero, double atol,
+                         int64_t max_iter, sem_solve_info *info, double *res_out, hipStream_t s) {
+    sem_ctx c = G->ctx;
     const int64_t n = c->n_unique, ld = G->ld;
     const unsigned grid = gm_grid(n);
     const int m = G->m;
-    auto t0 = std::chrono::steady_clock::now();
-    // r = b - A x
-    double bb = 0.0, beta = 0.0;
-    SEM_HIP(c, gm_dots(G, 0, G->V, b, s));
-    SEM_HIP(c, hipMemcpyAsync(&bb, G->coef, 8, hipMemcpyDeviceToHost, s));
-    if (o.zero_guess) {
-        SEM_HIP(c, launch_fill(x, n, 0.0, s));
-        SEM_HIP(c, hipMemcpyAsync(G->r, b, 8 * n, hipMemcpyDeviceToDevice, s));
-    } else {
-        sem_status e = apply_A(G, x, G->w, s);
-        if (e) return info->status = e;
-        SEM_HIP(c, hipMemcpyAsync(G->r, b, 8 * n, hipMemcpyDeviceToDevice, s));
-        const double minus1 = -1.0;
-        SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMaxVec + 2, &minus1, 8, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_gm_update, dim3(grid), dim3(kGmBlock), 0, s, n, 1, ld,
-                           (const double *)G->w, (const double *)(G->coef + kGmMaxVec + 2), G->r);
+    T *V = reinterpret_cast<T *>(G->V), *Z = reinterpret_cast<T *>(G->Z);
+    T *w = reinterpret_cast<T *>(G->w), *r = reinterpret_cast<T *>(G->r);
+    if (x_zero) {
+        if (std::is_same<T, double>::value) SEM_HIP(c, launch_fill((double *)x, n, 0.0, s));
+        else SEM_HIP(c, launch_fill32((float *)x, n, 0.0f, s));
     }
-    SEM_HIP(c, gm_dots(G, 0, G->V, G->r, s));
-    SEM_HIP(c, hipMemcpyAsync(&beta, G->coef, 8, hipMemcpyDeviceToHost, s));
-    SEM_HIP(c, hipStreamSynchronize(s));
-    const double bn = std::sqrt(bb);
-    beta = std::sqrt(beta);
-    if (!std::isfinite(bn) || !std::isfinite(beta)) return info->status = gfail(G, SEM_ERR_NAN, "non-finite input");
-    if (bn == 0.0 || beta <= o.tol * bn) {
-        info->true_rel_residual = bn > 0 ? beta / bn : 0.0;
-        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        return info->status = SEM_OK;
-    }
+    double beta = 0.0;
+    sem_status e = residual<T>(G, prec, b, x, r, w, x_zero, &beta, s);
+    if (e) return e;
+    *res_out = beta;
+    if (!std::isfinite(beta)) return gfail(G, SEM_ERR_NAN, "non-finite residual");
+    if (beta <= atol) return SEM_OK;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-    sem_status result = SEM_ERR_NOT_CONVERGED;
     for (;;) {
-        // V_0 = r / beta
-        const double inv = 1.0 / beta;
+        const double inv = 1.0 / beta;                 // V_0 = r / beta
         SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMaxVec + 3, &inv, 8, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_gm_scale, dim3(grid), dim3(kGmBlock), 0, s, n, (const double *)G->r,
-                           G->V, (const double *)(G->coef + kGmMaxVec + 3), 0);
+        hipLaunchKernelGGL((k_gm_scale<T, T>), dim3(grid), dim3(kGmBlock), 0, s, n, (const T *)r, V,
+                           (const double *)(G->coef + kGmMaxVec + 3), 0);
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         int jdone = 0;
-        bool hit = false;
         for (int j = 0; j < m; ++j) {
-            double *Vj = G->V + (size_t)j * ld, *Zj = G->Z + (size_t)j * ld;
-            sem_status e = precondition(G, Vj, Zj, SEM_PC_SCHWARZ | SEM_PC_COARSE, s);
-            if (e) return info->status = e;
-            e = apply_A(G, Zj, G->w, s);
-            if (e) return info->status = e;
+            T *Vj = V + (size_t)j * ld, *Zj = Z + (size_t)j * ld;
+            e = precondition<T>(G, Vj, Zj, SEM_PC_SCHWARZ | SEM_PC_COARSE, s);
+            if (e) return e;
+            e = apply_A<T>(G, prec, Zj, w, s);
+            if (e) return e;
             // two classical Gram-Schmidt passes against V_0..V_j
             double hcol[kGmMaxVec + 1] = {};
             double nrm2 = 0.0;
             for (int pass = 0; pass < 2; ++pass) {
-                SEM_HIP(c, gm_dots(G, j + 1, G->V, G->w, s));
+                SEM_HIP(c, gm_dots<T>(G, j + 1, V, w, s));
                 double h[kGmMaxVec + 1];
                 SEM_HIP(c, hipMemcpyAsync(h, G->coef, 8 * (j + 2), hipMemcpyDeviceToHost, s));
-                hipLaunchKernelGGL(k_gm_orth, dim3(grid), dim3(kGmBlock), 0, s, n, j + 1, ld,
-                                   (const double *)G->V, (const double *)G->coef, G->w, G->part);
+                hipLaunchKernelGGL(k_gm_orth<T>, dim3(grid), dim3(kGmBlock), 0, s, n, j + 1, ld,
+                                   (const T *)V, (const double *)G->coef, w, G->part);
                 hipLaunchKernelGGL(k_gm_finish, dim3(1), dim3(kGmBlock), 0, s, (int)grid, 1,
                                    (const double *)G->part, G->coef + kGmMaxVec + 1);
                 SEM_HIP(c, hipMemcpyAsync(&nrm2, G->coef + kGmMaxVec + 1, 8, hipMemcpyDeviceToHost, s));
@@ -949,14 +977,12 @@ extern "C" sem_status sem_gmres_solve(sem_gmres G, const double *b, double *x,
                 for (int i = 0; i <= j; ++i) hcol[i] += h[i];
             }
             const double hn = std::sqrt(nrm2);
-            if (!std::isfinite(hn)) return info->status = gfail(G, SEM_ERR_NAN, "non-finite Arnoldi vector");
-            // V_{j+1} = w / ||w||
-            if (hn > 0) {
+            if (!std::isfinite(hn)) return gfail(G, SEM_ERR_NAN, "non-finite Arnoldi vector");
+            if (hn > 0) {                               // V_{j+1} = w / ||w||
                 const double iv = 1.0 / hn;
                 SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMaxVec + 3, &iv, 8, hipMemcpyHostToDevice, s));
-                hipLaunchKernelGGL(k_gm_scale, dim3(grid), dim3(kGmBlock), 0, s, n,
-                                   (const double *)G->w, G->V + (size_t)(j + 1) * ld,
-                                   (const double *)(G->coef + kGmMaxVec + 3), 0);
+                hipLaunchKernelGGL((k_gm_scale<T, T>), dim3(grid), dim3(kGmBlock), 0, s, n, (const T *)w,
+                                   V + (size_t)(j + 1) * ld, (const double *)(G->coef + kGmMaxVec + 3), 0);
                 SEM_HIP(c, hipGetLastError());
             }
             // Givens rotations on column j of H
@@ -977,13 +1003,9 @@ extern "C" sem_status sem_gmres_solve(sem_gmres G, const double *b, double *x,
             g[j] = cs[j] * g[j];
             info->iterations += 1;
             jdone = j + 1;
-            info->rel_residual = std::fabs(g[j + 1]) / bn;
-            if (std::fabs(g[j + 1]) <= o.tol * bn || info->iterations >= o.max_iter || hn == 0) {
-                hit = true;
-                break;
-            }
+            info->rel_residual = std::fabs(g[j + 1]);
+            if (std::fabs(g[j + 1]) <= atol || info->iterations >= max_iter || hn == 0) break;
         }
-        (void)hit;
         // y = H^-1 g (upper triangular), x += Z y
         for (int i = jdone - 1; i >= 0; --i) {
             double sum = g[i];
@@ -991,29 +1013,103 @@ extern "C" sem_status sem_gmres_solve(sem_gmres G, const double *b, double *x,
             y[i] = sum / H[(size_t)i * m + i];
         }
         SEM_HIP(c, hipMemcpyAsync(G->coef, y.data(), 8 * jdone, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_gm_update, dim3(grid), dim3(kGmBlock), 0, s, n, jdone, ld,
-                           (const double *)G->Z, (const double *)G->coef, x);
+        hipLaunchKernelGGL((k_gm_update<T, T>), dim3(grid), dim3(kGmBlock), 0, s, n, jdone, ld,
+                           (const T *)Z, (const double *)G->coef, x);
         SEM_HIP(c, hipGetLastError());
-        // true residual r = b - A x
-        sem_status e = apply_A(G, x, G->w, s);
-        if (e) return info->status = e;
-        SEM_HIP(c, hipMemcpyAsync(G->r, b, 8 * n, hipMemcpyDeviceToDevice, s));
-        const double minus1 = -1.0;
-        SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMaxVec + 2, &minus1, 8, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_gm_update, dim3(grid), dim3(kGmBlock), 0, s, n, 1, ld,
-                           (const double *)G->w, (const double *)(G->coef + kGmMaxVec + 2), G->r);
-        SEM_HIP(c, gm_dots(G, 0, G->V, G->r, s));
-        double rr = 0.0;
-        SEM_HIP(c, hipMemcpyAsync(&rr, G->coef, 8, hipMemcpyDeviceToHost, s));
-        SEM_HIP(c, hipStreamSynchronize(s));
-        beta = std::sqrt(rr);
-        info->true_rel_residual = beta / bn;
-        if (!std::isfinite(beta)) { result = gfail(G, SEM_ERR_NAN, "non-finite residual"); break; }
-        if (beta <= o.tol * bn) { result = SEM_OK; break; }
-        if (info->iterations >= o.max_iter) { result = SEM_ERR_NOT_CONVERGED; break; }
+        e = residual<T>(G, prec, b, x, r, w, false, &beta, s);
+        if (e) return e;
+        *res_out = beta;
+        if (!std::isfinite(beta)) return gfail(G, SEM_ERR_NAN, "non-finite residual");
+        if (beta <= atol) return SEM_OK;
+        if (info->iterations >= max_iter) return SEM_ERR_NOT_CONVERGED;
         info->restarts += 1;
     }
-    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (result == SEM_ERR_NOT_CONVERGED) G->err = "iteration cap reached";
-    return info->status = result;
+}
+
+extern "C" sem_status sem_gmres_solve(sem_gmres G, const double *b, double *x,
+                                      const sem_solve_options *opts, sem_solve_info *info,
+                                      sem_stream stream) {
+    sem_solve_info dummy;
+    if (!info) info = &dummy;
+    std::memset(info, 0, sizeof(*info));
+    if (!G || !b || !x) return info->status = gfail(G, SEM_ERR_INVALID, "null argument");
+    if (!G->ws) return info->status = gfail(G, SEM_ERR_STATE, "no workspace bound");
+    sem_ctx c = G->ctx;
+    if (c->helm) return info->status = gfail(G, SEM_ERR_UNSUPPORTED, "Poisson operator only");
+    sem_solve_options o;
+    if (opts) o = *opts; else sem_default_solve_options(&o);
+    if (!(o.tol > 0) || o.max_iter < 1) return info->status = gfail(G, SEM_ERR_INVALID, "bad tolerance or cap");
+    const int prec = (int)o.precision;
+    if (prec < 0 || prec >= kNumPrec || !((c->precisions >> prec) & 1u))
+        return info->status = gfail(G, SEM_ERR_UNSUPPORTED, "precision not configured at setup");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = c->n_unique;
+    auto t0 = std::chrono::steady_clock::now();
+    auto done = [&](sem_status st) {
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        info->rel_residual = info->true_rel_residual;
+        if (st == SEM_ERR_NOT_CONVERGED && G->err.empty()) G->err = "iteration cap reached";
+        return info->status = st;
+    };
+    double bn = 0.0;
+    SEM_HIP(c, gm_dots<double>(G, 0, nullptr, b, s));
+    {
+        double bb = 0.0;
+        sem_status e = read_coef(G, 0, &bb, s);
+        if (e) return done(e);
+        bn = std::sqrt(bb);
+    }
+    if (!std::isfinite(bn)) return done(gfail(G, SEM_ERR_NAN, "non-finite right-hand side"));
+    if (bn == 0.0) {
+        SEM_HIP(c, launch_fill(x, n, 0.0, s));
+        info->true_rel_residual = 0.0;
+        return done(SEM_OK);
+    }
+    double res = 0.0;
+    if (prec == SEM_FP64) {
+        const sem_status st = fgmres<double>(G, SEM_FP64, b, x, o.zero_guess != 0, o.tol * bn,
+                                             o.max_iter, info, &res, s);
+        info->true_rel_residual = res / bn;
+        return done(st);
+    }
+    // FP64 iterative refinement around FP32-vector GMRES with the operator
+    // of precision prec: r = b - A x (FP64), inner A d = r / ||r|| to
+    // inner_tol, x += ||r|| d; two corrections in a row that do not halve
+    // the FP64 residual hand over to FP64 GMRES from the current x.
+    if (o.zero_guess) SEM_HIP(c, launch_fill(x, n, 0.0, s));
+    double prev = INFINITY, prev2 = INFINITY;
+    for (int outer = 0;; ++outer) {
+        double rn = 0.0;
+        // FP64 residual into G->r
+        sem_status e = residual<double>(G, SEM_FP64, b, x, G->r, G->w, false, &rn, s);
+        if (e) return done(e);
+        info->true_rel_residual = rn / bn;
+        info->outer_iterations = outer;
+        if (!std::isfinite(rn)) return done(gfail(G, SEM_ERR_NAN, "non-finite residual"));
+        if (rn <= o.tol * bn) return done(SEM_OK);
+        const bool stalled = outer >= 2 && rn > 0.5 * prev2;
+        if (stalled || outer >= o.max_outer || info->iterations >= o.max_iter) {
+            info->fallback = stalled ? SEM_FALLBACK_STAGNATION : SEM_FALLBACK_OUTER_CAP;
+            const int64_t before = info->iterations;
+            const sem_status st = fgmres<double>(G, SEM_FP64, b, x, false, o.tol * bn,
+                                                 o.max_iter, info, &res, s);
+            info->fallback_iterations = info->iterations - before;
+            info->true_rel_residual = res / bn;
+            return done(st);
+        }
+        prev2 = prev;
+        prev = rn;
+        // inner right-hand side r / ||r|| in FP32
+        const double inv = 1.0 / rn;
+        SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMaxVec + 3, &inv, 8, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL((k_gm_scale<double, float>), dim3(gm_grid(n)), dim3(kGmBlock), 0, s, n,
+                           (const double *)G->r, G->rhs32, (const double *)(G->coef + kGmMaxVec + 3), 0);
+        SEM_HIP(c, hipGetLastError());
+        double rin = 0.0;
+        e = fgmres<float>(G, prec, G->rhs32, G->d32, true, o.inner_tol,
+                          std::max<int64_t>(1, o.max_iter - info->iterations), info, &rin, s);
+        if (e != SEM_OK && e != SEM_ERR_NOT_CONVERGED) return done(e);
+        // x += ||r|| d
+        SEM_HIP(c, launch_ir_update(c, x, G->d32, nullptr, 0, s, rn));
+    }
 }

@@ -84,6 +84,32 @@ def test_gmres_solve_matches_oracle(name):
     assert relerr(xc, xp) < 1e-8
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("name", ["deformed4_N5", "ogrid_N3", "deformed3_N7"])
+def test_refined_gmres(name, prec):
+    """FP64 refinement around FP32-vector GMRES with the FP32, FP16 or BF16
+    operator (hybrid Schwarz preconditioner in FP64 on FP32 vectors): oracle
+    true residual 1e-10 without a hand-over to FP64, solution as the
+    oracle's PCG."""
+    _, hs, _ = case(name)
+    key = name + "_lowprec"
+    if key not in _cache:
+        m, N = _meshes()[name]
+        q = Pair(m, N, precisions=("fp64", "fp32", "fp16", "bf16"))
+        _cache[key] = (q, hs, sem.PressureSolver(q.op, restart=30))
+    p, _, ps = _cache[key]
+    b = p.ora.rhs_unique(F.random_unique(p.op.n_unique, 29))
+    x, info = ps.solve(p.to_dev(b), tol=1e-10, precision=prec)
+    xc = p.from_dev(x)
+    res = p.ora.true_residual(xc, b)
+    xp, _ = p.ora.pcg(b, 1e-12)
+    print(name, prec, "its %d outer %d res %.2e fallback %s" % (
+        info["iterations"], info["outer_iterations"], res, info["fallback"]), flush=True)
+    assert info["status"] == "SEM_OK" and info["fallback"] == "none", info
+    assert res <= 1.01e-10
+    assert relerr(xc, xp) < 1e-8
+
+
 def test_gmres_box16_against_pcg():
     """16^3 deformed box, N = 7 (1.44M unique nodes): the GMRES solution
     reaches 1e-10 (oracle true residual) in far fewer iterations than
