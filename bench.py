@@ -18,8 +18,10 @@ before any timed region.
   against the FP64 Jacobi-PCG time.
 * batch: 64 independent box problems (K ~ U{2..12}, N in {5,7,9}) solved
   together to 1e-8, against solving them one after another.
-* ogrid (--ogrid): the 256x64x32 O-grid around a cylinder, N = 7: the fused
-  operator's kernel time and roofline fraction, and its solves to 1e-10.
+* ogrid: the 256x64x32 O-grid around a cylinder, N = 7: the fused
+  operator's kernel time and roofline fraction, and its solves to 1e-10
+  (GMRES with hybrid Schwarz in FP64 and FP64-refined around FP32 / BF16
+  matrix-core GMRES, and FP64 Jacobi-PCG).
 * cpu_baseline: the FP64 oracle's assembled operator on a 24^3-element
   corner block of the same mesh (1/8 of the elements), on all host cores
   (OpenMP over elements; gather-scatter in fixed order) and on one.
@@ -249,6 +251,14 @@ def bench_pressure(op, b, fp64_info, restart=30):
                      "(fast diagonalisation) + 10 Jacobi-PCG iterations on the N=1 vertex "
                      "problem" % restart,
            "setup_seconds": setup, **info}
+    ref = {}
+    for prec in ("fp32", "fp16"):
+        _, inf = ps.solve(b, tol=1e-10, precision=prec, raise_on_error=False)
+        inf["speedup_vs_fp64_gmres"] = info["seconds"] / inf["seconds"]
+        if fp64_info:
+            inf["speedup_vs_fp64_pcg"] = fp64_info["seconds"] / inf["seconds"]
+        ref[prec + "_refined"] = inf
+    out["refined"] = ref
     if fp64_info:
         out["fp64_pcg_seconds"] = fp64_info["seconds"]
         out["fp64_pcg_iterations"] = fp64_info["iterations"]
@@ -290,18 +300,21 @@ def bench_ogrid(args):
     fs[pos] = f
     b = op.rhs(f_unique=torch.from_numpy(fs).cuda())
     solves = {}
-    ps = sem.PressureSolver(op, restart=20)
-    x, info = ps.solve(b, tol=1e-10, raise_on_error=False)
-    solves["gmres_hybrid_schwarz"] = info
-    log("ogrid gmres", json.dumps(info))
-    del ps, x
+    ps = sem.PressureSolver(op, restart=args.ogrid_restart)
+    for prec in ("fp64", "fp32", "bf16"):
+        if prec == "bf16":
+            op.set_tile("bf16", elements_per_block=2, grid_cap=0, xcd_remap=0, pipeline=2)
+        x, info = ps.solve(b, tol=1e-10, precision=prec, raise_on_error=False)
+        key = "gmres_hybrid_schwarz" + ("" if prec == "fp64" else "_%s_refined" % prec)
+        solves[key] = info
+        log("ogrid", key, json.dumps(info))
+        del x
+    del ps
     torch.cuda.empty_cache()
     for prec in args.ogrid_solves.split(","):
         if not prec:
             continue
         kw = {"inner_tol": 1e-4 if prec == "fp32" else 1e-2} if prec != "fp64" else {}
-        if prec == "bf16":
-            op.set_tile("bf16", elements_per_block=2, grid_cap=0, xcd_remap=0, pipeline=2)
         x, info = op.solve(b, tol=1e-10, precision=prec, max_iter=200000,
                            raise_on_error=False, **kw)
         solves[prec] = info
@@ -365,10 +378,12 @@ def main():
                     help="with --operator: elements_per_block:grid_cap:xcd_remap:pipeline")
     ap.add_argument("--no-pressure", action="store_true", help="skip the GMRES pressure solve")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch")
-    ap.add_argument("--ogrid", action="store_true",
-                    help="add the 256x64x32 O-grid section (operator and solves)")
-    ap.add_argument("--ogrid-solves", default="fp64,fp32,bf16",
-                    help="O-grid Jacobi-PCG solves: fp64 and FP64 refinement around fp32/bf16")
+    ap.add_argument("--no-ogrid", action="store_true",
+                    help="skip the 256x64x32 O-grid section (operator and solves)")
+    ap.add_argument("--ogrid-restart", type=int, default=30, help="GMRES restart on the O-grid")
+    ap.add_argument("--ogrid-solves", default="fp64",
+                    help="O-grid Jacobi-PCG solves: fp64, and FP64 refinement around fp32/bf16 "
+                         "Jacobi-PCG (about a minute each)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of 1 GiB (for counter scaling) and exit")
     args = ap.parse_args()
@@ -569,7 +584,7 @@ def main():
         log("batch ...")
         result["batch"] = bench_batch(args, emit=False)
         torch.cuda.empty_cache()
-    if args.ogrid and args.workload == "box":
+    if not args.no_ogrid and args.workload == "box":
         log("ogrid ...")
         result["ogrid"] = bench_ogrid(args)
         torch.cuda.empty_cache()

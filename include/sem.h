@@ -425,9 +425,10 @@ sem_status sem_proj_solve(sem_proj proj, const double *b, double *x,
  * sem_gmres_solve: b, x device unique vectors (solver order, FP64); opts:
  * tol (true relative residual, checked in FP64 at each restart), max_iter,
  * zero_guess, precision.  SEM_FP64: GMRES in FP64.  A reduced precision
- * (configured at set-up): FP64 iterative refinement r = b - A x, inner GMRES
- * with FP32 vectors and that precision's operator on A d = r / ||r|| to
- * opts.inner_tol, x += ||r|| d (the preconditioner computes in FP64 on FP32
+ * (configured at set-up): FP64 iterative refinement r = b - A x, then one
+ * GMRES cycle (at most `restart` steps, stopped when its recurrence estimate
+ * reaches opts.inner_tol) with FP32 vectors and that precision's operator on
+ * A d = r / ||r||, x += ||r|| d (the preconditioner computes in FP64 on FP32
  * vectors); two corrections in a row that do not halve the FP64 residual,
  * or max_outer corrections, hand over to FP64 GMRES from the current x
  * (info->fallback).  info->iterations counts GMRES steps of all levels,

@@ -925,10 +925,15 @@ static sem_status residual(sem_gmres G, int prec, const T *b, const T *x, T *r, 
 // residual at its end) or max_iter steps in all.  V, Z, w, r live in the
 // solver's basis arrays (FP32 vectors use the first half of each slot).
 // Returns SEM_OK when converged, SEM_ERR_NOT_CONVERGED at the cap; *res_out
-// is the last true residual norm.
+// is the last true residual norm.  one_cycle (inner solves of the
+// refinement): a single cycle from x = 0 that stops on the recurrence
+// estimate alone -- a residual recomputed in FP32 carries a rounding floor
+// of about eps_32 ||A|| ||x||, which on ill-conditioned meshes exceeds the
+// inner tolerance, so the FP64 outer residual judges the correction.
 template <typename T>
 static sem_status fgmres(sem_gmres G, int prec, const T *b, T *x, bool x_zero, double atol,
-                         int64_t max_iter, sem_solve_info *info, double *res_out, hipStream_t s) {
+                         int64_t max_iter, sem_solve_info *info, double *res_out, hipStream_t s,
+                         bool one_cycle = false) {
     sem_ctx c = G->ctx;
     const int64_t n = c->n_unique, ld = G->ld;
     const unsigned grid = gm_grid(n);
@@ -1016,6 +1021,10 @@ static sem_status fgmres(sem_gmres G, int prec, const T *b, T *x, bool x_zero, d
         hipLaunchKernelGGL((k_gm_update<T, T>), dim3(grid), dim3(kGmBlock), 0, s, n, jdone, ld,
                            (const T *)Z, (const double *)G->coef, x);
         SEM_HIP(c, hipGetLastError());
+        if (one_cycle) {
+            *res_out = std::fabs(g[jdone]);
+            return SEM_OK;
+        }
         e = residual<T>(G, prec, b, x, r, w, false, &beta, s);
         if (e) return e;
         *res_out = beta;
@@ -1107,7 +1116,8 @@ extern "C" sem_status sem_gmres_solve(sem_gmres G, const double *b, double *x,
         SEM_HIP(c, hipGetLastError());
         double rin = 0.0;
         e = fgmres<float>(G, prec, G->rhs32, G->d32, true, o.inner_tol,
-                          std::max<int64_t>(1, o.max_iter - info->iterations), info, &rin, s);
+                          std::max<int64_t>(1, o.max_iter - info->iterations), info, &rin, s,
+                          true);
         if (e != SEM_OK && e != SEM_ERR_NOT_CONVERGED) return done(e);
         // x += ||r|| d
         SEM_HIP(c, launch_ir_update(c, x, G->d32, nullptr, 0, s, rn));
