@@ -133,6 +133,12 @@ sem_status sem_export_numbering(sem_ctx ctx, int32_t *gid_canonical,
                                 int32_t *solver_pos, uint8_t *dirichlet,
                                 int32_t *mult);
 
+/* The gather-scatter map in the canonical numbering (the paper's gs_t
+ * handle): gid_host [n_local] canonical unique id of every local point,
+ * dirichlet_host [n_unique] 1 on masked nodes; either may be NULL.  Same
+ * data as sem_export_numbering's gid_canonical and dirichlet. */
+sem_status sem_export_gs_map(sem_ctx ctx, int32_t *gid_host, uint8_t *dirichlet_host);
+
 /* Device workspace: size for this context, then bind a caller-owned device
  * buffer of at least that many bytes (256-byte aligned).  Binding uploads
  * the gather-scatter maps and the derivative matrix on `stream`. */
@@ -160,6 +166,17 @@ sem_status sem_export_geometry(sem_ctx ctx, double *G, double *B,
  * otherwise.  No masking, no summation.  Stream-ordered, asynchronous. */
 sem_status sem_ax_local(sem_ctx ctx, const void *u_L, void *w_L,
                         sem_precision prec, sem_stream stream);
+
+#define SEM_AX_ASSEMBLE 8u      /* sem_ax_evec: also Q M Q^T (assembled result) */
+
+/* Element operator on E-vectors: w_L = A_L u_L, or with SEM_AX_ASSEMBLE
+ * w_L = Q M Q^T A_L u_L (Eqs. (9)-(12): the assembled operator in the
+ * local form of the paper, QQ^T A_L u_L), summed in fixed order.  u_L and
+ * w_L: device E-vectors, double for SEM_FP64, float for SEM_FP32 (other
+ * precisions: SEM_ERR_UNSUPPORTED with SEM_AX_ASSEMBLE); they must not
+ * overlap.  Stream-ordered. */
+sem_status sem_ax_evec(sem_ctx ctx, const void *u_L, void *w_L, sem_precision prec,
+                       unsigned flags, sem_stream stream);
 
 /* Direct stiffness summation in place on an E-vector, v_L <- Q M Q^T v_L
  * (Eq. (12), the paper's gs_t, with the Dirichlet mask).  Deterministic:
@@ -489,6 +506,10 @@ sem_status sem_batch_autotune(sem_batch batch, int reps, sem_tile *best, double 
 sem_status sem_batch_solve(sem_batch batch, const double *const *rhs, double *const *x,
                            const sem_solve_options *opts, sem_solve_info *infos,
                            sem_stream stream);
+/* The same call under the name of the batched-solve interface. */
+sem_status sem_cg_solve_batch(sem_batch batch, const double *const *rhs, double *const *x,
+                              const sem_solve_options *opts, sem_solve_info *infos,
+                              sem_stream stream);
 
 #ifdef __cplusplus
 }

@@ -23,6 +23,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16_SCALED, "bf16": BF16_SCAL
 AX_DETERMINISTIC = 1
 AX_Y_ZEROED = 2
 AX_FP64_VECTORS = 4
+AX_ASSEMBLE = 8
 
 STATUS = {0: "SEM_OK", 1: "SEM_ERR_INVALID", 2: "SEM_ERR_MESH", 3: "SEM_ERR_DEVICE",
           4: "SEM_ERR_OOM", 5: "SEM_ERR_NOT_CONVERGED", 6: "SEM_ERR_BREAKDOWN",
@@ -110,7 +111,8 @@ EXPORTS = ["sem_gll", "sem_setup", "sem_free", "sem_last_error", "sem_query",
            "sem_proj_workspace_size", "sem_proj_bind_workspace", "sem_proj_reset",
            "sem_proj_size", "sem_proj_solve", "sem_gmres_create", "sem_gmres_free",
            "sem_gmres_last_error", "sem_gmres_workspace_size", "sem_gmres_bind_workspace",
-           "sem_gmres_precondition", "sem_gmres_solve"]
+           "sem_gmres_precondition", "sem_gmres_solve", "sem_ax_evec", "sem_export_gs_map",
+           "sem_cg_solve_batch"]
 
 _lib = None
 
@@ -161,6 +163,9 @@ def lib():
         "sem_gmres_bind_workspace": ([P, P, ctypes.c_size_t, P], i32),
         "sem_gmres_precondition": ([P, P, P, u32, P], i32),
         "sem_gmres_solve": ([P, P, P, P, P, P], i32),
+        "sem_ax_evec": ([P, P, P, i32, u32, P], i32),
+        "sem_export_gs_map": ([P, P, P], i32),
+        "sem_cg_solve_batch": ([P, P, P, P, P, P], i32),
         "sem_get_tile": ([P, i32, P], i32),
         "sem_set_tile": ([P, i32, P], i32),
         "sem_autotune": ([P, i32, i32, ctypes.c_char_p, P, P, i32, P, P], i32),
@@ -329,6 +334,22 @@ class Operator:
         self._check(lib().sem_ax_local(self._ctx, _dptr(uL), _dptr(wL), PRECISIONS[precision],
                                        _stream_handle()))
         return wL
+
+    def ax_evec(self, uL, wL=None, precision: str = "fp64", assemble: bool = True):
+        """w_L = A_L u_L, or with assemble Q M Q^T A_L u_L, on E-vectors."""
+        if wL is None:
+            wL = _torch().empty_like(uL)
+        self._check(lib().sem_ax_evec(self._ctx, _dptr(uL), _dptr(wL), PRECISIONS[precision],
+                                      AX_ASSEMBLE if assemble else 0, _stream_handle()))
+        return wL
+
+    def gs_map(self):
+        """Canonical unique id of every local point [E, n1^3] and the
+        Dirichlet flags [n_u] (host)."""
+        gid = np.empty((self.E, (self.N + 1) ** 3), dtype=np.int32)
+        dm = np.empty(self.n_unique, dtype=np.uint8)
+        self._check(lib().sem_export_gs_map(self._ctx, _np_ptr(gid), _np_ptr(dm)))
+        return gid, dm
 
     def gs(self, vL, precision: str = "fp64"):
         """In-place v_L <- Q M Q^T v_L."""

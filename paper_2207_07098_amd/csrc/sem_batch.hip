@@ -375,3 +375,9 @@ extern "C" sem_status sem_batch_solve(sem_batch b, const double *const *rhs, dou
 }
 
 extern "C" const char *sem_batch_last_error(sem_batch b) { return b ? b->err.c_str() : ""; }
+
+extern "C" sem_status sem_cg_solve_batch(sem_batch b, const double *const *rhs, double *const *x,
+                                         const sem_solve_options *opts, sem_solve_info *infos,
+                                         sem_stream stream) {
+    return sem_batch_solve(b, rhs, x, opts, infos, stream);
+}

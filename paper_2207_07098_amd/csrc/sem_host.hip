@@ -501,6 +501,21 @@ extern "C" sem_status sem_ax(sem_ctx c, const void *u, void *y, sem_precision pr
     return SEM_OK;
 }
 
+extern "C" sem_status sem_ax_evec(sem_ctx c, const void *uL, void *wL, sem_precision prec,
+                                  unsigned flags, sem_stream stream) {
+    if (flags & ~SEM_AX_ASSEMBLE) return fail(c, SEM_ERR_INVALID, "unknown flag");
+    if ((flags & SEM_AX_ASSEMBLE) && prec != SEM_FP64 && prec != SEM_FP32)
+        return fail(c, SEM_ERR_UNSUPPORTED, "assembled E-vector form: FP64 or FP32");
+    if (uL == wL && uL) return fail(c, SEM_ERR_INVALID, "u_L and w_L must not alias");
+    sem_status st = sem_ax_local(c, uL, wL, prec, stream);
+    if (st || !(flags & SEM_AX_ASSEMBLE)) return st;
+    return sem_gs(c, wL, prec, stream);
+}
+
+extern "C" sem_status sem_export_gs_map(sem_ctx c, int32_t *gid, uint8_t *dirichlet) {
+    return sem_export_numbering(c, gid, nullptr, dirichlet, nullptr);
+}
+
 extern "C" sem_status sem_gs(sem_ctx c, void *vL, sem_precision prec, sem_stream stream) {
     if (!c) return fail(c, SEM_ERR_INVALID, "null context");
     if (!c->ws) return fail(c, SEM_ERR_STATE, "no workspace bound");

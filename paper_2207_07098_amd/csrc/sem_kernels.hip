@@ -9,10 +9,13 @@
 //   * the r- and s-derivatives read the element block from LDS, stored
 //     [k][j][i] with a row pitch of N+2 so that row reads (fixed j) and
 //     column reads (fixed i) hit distinct banks;
-//   * the six geometric factors of a point are stored together
-//     ([E][k][j][i][6]) and a wave requests all planes of an element at
-//     once, while the index map of its next element is prefetched, so each
-//     element costs about one memory latency per wave;
+//   * the six geometric factors of an element plane are stored in three
+//     lane-contiguous chunks of pairs (G11,G22), (G33,G12), (G13,G23) for
+//     FP64/FP32, or six contiguous 16-bit values per point (goff() in
+//     sem_internal.h), so every load instruction of a wave covers one
+//     contiguous span; a wave requests all planes of an element at once
+//     (or a ring of two), while the index map of its next element is
+//     prefetched, so each element costs about one memory latency per wave;
 //   * element-interior nodes have solver indices that follow from the
 //     element index, so only element-boundary points read an index map and
 //     only they are summed (device atomics or a fixed-order second pass);

@@ -101,6 +101,26 @@ def test_gs_gather_scatter(name):
     assert relerr(p.from_dev(y), yref) < TOL64
 
 
+@pytest.mark.parametrize("name", ["cube4_N5", "reoriented_N4", "ogrid_N3", "stretched_N9"])
+def test_assembled_evector_operator_and_gs_map(name):
+    """The paper's local form Q M Q^T A_L u_L on E-vectors (any u_L, not
+    necessarily continuous) in FP64 and FP32, and the exported gather-scatter
+    map, against the oracle."""
+    p = pair(name)
+    rng = np.random.default_rng(6)
+    uL = rng.uniform(-1, 1, (p.op.E, (p.N + 1) ** 3))
+    wref = oracle.q(p.gid, np.where(p.dmask == 1, 0.0,
+                                    oracle.qt(p.gid, oracle.ax_local(p.N, p.ora.G, uL), p.op.n_unique)))
+    w = p.op.ax_evec(p.local_to_dev(uL)).cpu().numpy().reshape(uL.shape)
+    assert relerr(w, wref) < TOL64
+    w32 = p.op.ax_evec(p.local_to_dev(uL, torch.float32), precision="fp32").cpu().numpy()
+    assert relerr(w32.reshape(uL.shape), wref) < 1e-5
+    wl = p.op.ax_evec(p.local_to_dev(uL), assemble=False).cpu().numpy().reshape(uL.shape)
+    assert relerr(wl, oracle.ax_local(p.N, p.ora.G, uL)) < TOL64
+    gid, dm = p.op.gs_map()
+    assert np.array_equal(gid, p.ora.gid) and np.array_equal(dm, p.ora.dirichlet)
+
+
 @pytest.mark.parametrize("name", ["cube4_N5", "ogrid_N3", "stretched_N9"])
 def test_rhs(name):
     p = pair(name)

@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol():
 def test_binding_flag_values_match_header():
     src = open(os.path.join(ROOT, "include", "sem.h")).read()
     defs = dict(re.findall(r"#define SEM_(AX_\w+)\s+(\d+)u", src))
-    assert set(defs) == {"AX_DETERMINISTIC", "AX_Y_ZEROED", "AX_FP64_VECTORS"}
+    assert set(defs) == {"AX_DETERMINISTIC", "AX_Y_ZEROED", "AX_FP64_VECTORS", "AX_ASSEMBLE"}
     for name, val in defs.items():
         assert getattr(sem, name) == int(val), name
 
