@@ -224,6 +224,7 @@ struct CoarseParams {
     const double *zs;         // Schwarz sum (interp)
     const double *W;          // counting weights (interp)
     const int32_t *cmap;      // [E][8] coarse solver index or -1
+    const uint8_t *owner;     // [E][n_b] 1 on the first copy of each boundary node
     const int32_t *bmap, *csr_off, *csr_idx, *bpos2l;
     const double *xi;         // GLL nodes [N+1]
     int64_t E, n_bnd, n_u;
@@ -232,30 +233,51 @@ struct CoarseParams {
 
 __device__ __forceinline__ double phi(double x, int side) { return side ? 0.5 * (1.0 + x) : 0.5 * (1.0 - x); }
 
-// P^T r: per element, sum over its points of phi_c(x) r[g] / mult[g] for the
-// 8 corners, one wave per element, then 8 atomics into the coarse vector.
-template <typename VT>
-__global__ void __launch_bounds__(64) k_coarse_restrict(CoarseParams<VT> P) {
+// Element-based forms (one 64-lane workgroup per element, N1 known at
+// compile time so that each lane's points are unrolled and their loads are
+// in flight together).  Every unique node is handled by exactly one local
+// copy: element-interior points and, on element boundaries, the copy that
+// comes first in the node's copy list (owner flag, built on the host).
+//
+// Restriction: b0[corner c of e] += sum over owned points of phi_c(x) r[g].
+template <int N1, typename VT>
+__global__ void __launch_bounds__(64) k_restrict_e(CoarseParams<VT> P) {
+    constexpr int N = N1 - 1, NP = N1 * N1 * N1, Q = (NP + 63) / 64;
     const int64_t e = blockIdx.x;
-    const int N = P.N, n1 = N + 1, np = n1 * n1 * n1;
     double acc[8] = {};
-    for (int l = threadIdx.x; l < np; l += 64) {
-        const int i = l % n1, j = (l / n1) % n1, k = l / (n1 * n1);
-        const int64_t g = gm_node(P.bmap, P.n_bnd, e, i, j, k, N, P.nb);
-        if (g < 0) continue;
-        double m = 1.0;
-        if (g < P.n_bnd) m = (double)(P.csr_off[g + 1] - P.csr_off[g]);
-        const double rv = (double)P.r[g] / m;
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-            acc[c] += phi(P.xi[i], c & 1) * phi(P.xi[j], (c >> 1) & 1) * phi(P.xi[k], (c >> 2) & 1) * rv;
+    for (int q = 0; q < Q; ++q) {
+        const int l = threadIdx.x + 64 * q;
+        if (l < NP) {
+            const int i = l % N1, j = (l / N1) % N1, k = l / (N1 * N1);
+            const bool bnd = i == 0 || i == N || j == 0 || j == N || k == 0 || k == N;
+            int64_t g;
+            bool take;
+            if (bnd) {
+                const int b = gm_bpos(i, j, k, N1);
+                const int32_t m = P.bmap[e * P.nb + b];
+                take = m >= 0 && P.owner[e * P.nb + b];
+                g = m & 0x7fffffff;
+            } else {
+                g = gm_interior(P.n_bnd, e, i, j, k, N);
+                take = true;
+            }
+            if (take) {
+                const double rv = (double)P.r[g];
+                const double wi[2] = {0.5 * (1.0 - P.xi[i]), 0.5 * (1.0 + P.xi[i])};
+                const double wj[2] = {0.5 * (1.0 - P.xi[j]), 0.5 * (1.0 + P.xi[j])};
+                const double wk[2] = {0.5 * (1.0 - P.xi[k]), 0.5 * (1.0 + P.xi[k])};
+#pragma unroll
+                for (int c = 0; c < 8; ++c) acc[c] += wi[c & 1] * wj[(c >> 1) & 1] * wk[(c >> 2) & 1] * rv;
+            }
+        }
     }
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        double s = acc[c];
+        double sum = acc[c];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        acc[c] = s;
+        for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+        acc[c] = sum;
     }
     if (threadIdx.x == 0)
 #pragma unroll
@@ -265,40 +287,47 @@ __global__ void __launch_bounds__(64) k_coarse_restrict(CoarseParams<VT> P) {
         }
 }
 
-// z[g] = W[g] zs[g] + (P x0)[g] over fine unique nodes (0 on Dirichlet
-// nodes); P is evaluated in the element of the node's first copy.
-template <typename VT>
-__global__ void k_combine(CoarseParams<VT> P) {
-    const int N = P.N, n1 = N + 1, nm = N - 1;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < P.n_u;
-         g += (int64_t)gridDim.x * blockDim.x) {
-        int64_t e;
-        int i, j, k;
-        if (g < P.n_bnd) {
-            const int32_t cq = P.csr_idx[P.csr_off[g]];
-            e = cq / P.nb;
-            const int l = P.bpos2l[cq - e * P.nb];
-            i = l % n1;
-            j = (l / n1) % n1;
-            k = l / (n1 * n1);
-        } else {
-            const int64_t q = g - P.n_bnd, ni = (int64_t)nm * nm * nm;
-            e = q / ni;
-            const int rem = (int)(q - e * ni);
-            i = 1 + rem % nm;
-            j = 1 + (rem / nm) % nm;
-            k = 1 + rem / (nm * nm);
-        }
-        double zc = 0.0;
+// z[g] = W[g] zs[g] + (P x0)[g] at the owned points of each element (0 on
+// Dirichlet nodes); the element's coarse corner values are loaded once.
+template <int N1, typename VT>
+__global__ void __launch_bounds__(64) k_combine_e(CoarseParams<VT> P) {
+    constexpr int N = N1 - 1, NP = N1 * N1 * N1, Q = (NP + 63) / 64;
+    const int64_t e = blockIdx.x;
+    double xc[8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int32_t gc = P.cmap[e * 8 + c];
-            if (gc >= 0 && P.x0)
-                zc += phi(P.xi[i], c & 1) * phi(P.xi[j], (c >> 1) & 1) * phi(P.xi[k], (c >> 2) & 1) *
-                      P.x0[gc];
+    for (int c = 0; c < 8; ++c) {
+        const int32_t gc = P.cmap[e * 8 + c];
+        xc[c] = (P.x0 && gc >= 0) ? P.x0[gc] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int l = threadIdx.x + 64 * q;
+        if (l < NP) {
+            const int i = l % N1, j = (l / N1) % N1, k = l / (N1 * N1);
+            const bool bnd = i == 0 || i == N || j == 0 || j == N || k == 0 || k == N;
+            int64_t g;
+            bool own, dir = false;
+            if (bnd) {
+                const int b = gm_bpos(i, j, k, N1);
+                const int32_t m = P.bmap[e * P.nb + b];
+                own = P.owner[e * P.nb + b];
+                dir = m < 0;
+                g = m & 0x7fffffff;
+            } else {
+                g = gm_interior(P.n_bnd, e, i, j, k, N);
+                own = true;
+            }
+            if (own) {
+                const double wi[2] = {0.5 * (1.0 - P.xi[i]), 0.5 * (1.0 + P.xi[i])};
+                const double wj[2] = {0.5 * (1.0 - P.xi[j]), 0.5 * (1.0 + P.xi[j])};
+                const double wk[2] = {0.5 * (1.0 - P.xi[k]), 0.5 * (1.0 + P.xi[k])};
+                double zc = 0.0;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) zc += wi[c & 1] * wj[(c >> 1) & 1] * wk[(c >> 2) & 1] * xc[c];
+                const double zsv = P.zs ? P.W[g] * P.zs[g] : 0.0;
+                P.y[g] = (VT)(dir ? 0.0 : zsv + zc);
+            }
         }
-        const double zs = P.zs ? P.W[g] * P.zs[g] : 0.0;
-        P.y[g] = (VT)(P.W[g] > 0.0 ? zs + zc : 0.0);      // W = 0 only on Dirichlet nodes
     }
 }
 
@@ -450,12 +479,14 @@ struct sem_gmres_s {
     std::vector<int32_t> ghost;      // [E][6][(N+1)^2]
     std::vector<int32_t> cmap;       // [E][8]
     std::vector<double> W;           // [n_u]
+    std::vector<uint8_t> owner;      // [E][n_b] first copy of each boundary node
     // device
     char *ws = nullptr;
     size_t ws_bytes = 0;
     size_t coarse_ws = 0;
     double *dS = nullptr, *dlam = nullptr, *dW = nullptr, *dxi = nullptr;
     int32_t *dghost = nullptr, *dcmap = nullptr;
+    uint8_t *downer = nullptr;
     double *zs = nullptr, *b0 = nullptr, *x0 = nullptr;
     double *V = nullptr, *Z = nullptr, *w = nullptr, *r = nullptr;
     double *part = nullptr, *coef = nullptr;
@@ -703,6 +734,9 @@ extern "C" sem_status sem_gmres_create(sem_ctx c, int restart, sem_gmres *out) {
         delete G;
         return st;
     }
+    // the first copy of every element-boundary node owns it
+    G->owner.assign((size_t)c->E * c->nb, 0);
+    for (int64_t g = 0; g < c->n_bnd; ++g) G->owner[c->csr_idx[c->csr_off[g]]] = 1;
     // coarse index of every element corner (Dirichlet: -1)
     G->cmap.assign(c->E * 8, -1);
     for (int64_t e = 0; e < c->E; ++e)
@@ -750,12 +784,13 @@ static size_t gm_layout(sem_gmres G, size_t *off) {
     off[15] = take(8 * (kGmMaxVec + 4));
     off[16] = take(4 * (size_t)c->n_unique);          // FP32 inner right-hand side
     off[17] = take(4 * (size_t)c->n_unique);          // FP32 inner correction
+    off[18] = take((size_t)E * c->nb);                // owner flags
     return o;
 }
 
 extern "C" sem_status sem_gmres_workspace_size(sem_gmres G, size_t *bytes) {
     if (!G || !bytes) return gfail(G, SEM_ERR_INVALID, "null argument");
-    size_t off[18];
+    size_t off[19];
     *bytes = gm_layout(G, off);
     return SEM_OK;
 }
@@ -763,7 +798,7 @@ extern "C" sem_status sem_gmres_workspace_size(sem_gmres G, size_t *bytes) {
 extern "C" sem_status sem_gmres_bind_workspace(sem_gmres G, void *dev, size_t bytes,
                                                sem_stream stream) {
     if (!G || !dev) return gfail(G, SEM_ERR_INVALID, "null argument");
-    size_t off[18];
+    size_t off[19];
     const size_t need = gm_layout(G, off);
     if (bytes < need)
         return gfail(G, SEM_ERR_OOM, "workspace of " + std::to_string(bytes) + " bytes, need " +
@@ -796,11 +831,13 @@ extern "C" sem_status sem_gmres_bind_workspace(sem_gmres G, void *dev, size_t by
     G->coef = reinterpret_cast<double *>(w + off[15]);
     G->rhs32 = reinterpret_cast<float *>(w + off[16]);
     G->d32 = reinterpret_cast<float *>(w + off[17]);
+    G->downer = reinterpret_cast<uint8_t *>(w + off[18]);
     SEM_HIP(c, hipMemcpyAsync(G->dS, G->S.data(), 8 * G->S.size(), hipMemcpyHostToDevice, s));
     SEM_HIP(c, hipMemcpyAsync(G->dlam, G->lam.data(), 8 * G->lam.size(), hipMemcpyHostToDevice, s));
     SEM_HIP(c, hipMemcpyAsync(G->dghost, G->ghost.data(), 4 * G->ghost.size(), hipMemcpyHostToDevice, s));
     SEM_HIP(c, hipMemcpyAsync(G->dcmap, G->cmap.data(), 4 * G->cmap.size(), hipMemcpyHostToDevice, s));
     SEM_HIP(c, hipMemcpyAsync(G->dW, G->W.data(), 8 * G->W.size(), hipMemcpyHostToDevice, s));
+    SEM_HIP(c, hipMemcpyAsync(G->downer, G->owner.data(), G->owner.size(), hipMemcpyHostToDevice, s));
     SEM_HIP(c, hipMemcpyAsync(G->dxi, c->xi, 8 * c->n1, hipMemcpyHostToDevice, s));
     SEM_HIP(c, hipStreamSynchronize(s));
     return SEM_OK;
@@ -831,13 +868,23 @@ static sem_status precondition(sem_gmres G, const VT *r, VT *z, unsigned parts, 
 #undef SEM_FDM
         SEM_HIP(c, hipGetLastError());
     }
-    CoarseParams<VT> C{r, G->b0, z, G->x0, local ? G->zs : nullptr, G->dW, G->dcmap,
+    CoarseParams<VT> C{r, G->b0, z, G->x0, local ? G->zs : nullptr, G->dW, G->dcmap, G->downer,
                        dptr<int32_t>(c, c->L.bmap), dptr<int32_t>(c, c->L.csr_off),
                        dptr<int32_t>(c, c->L.csr_idx), dptr<int32_t>(c, c->L.bpos2l), G->dxi,
                        c->E, c->n_bnd, n, c->N, c->nb};
     if (coarse) {
         SEM_HIP(c, launch_fill(G->b0, G->coarse->n_unique, 0.0, s));
-        hipLaunchKernelGGL(k_coarse_restrict<VT>, dim3((unsigned)c->E), dim3(64), 0, s, C);
+#define SEM_RESTRICT(n1)                                                                    \
+    case n1:                                                                                \
+        hipLaunchKernelGGL((k_restrict_e<n1, VT>), dim3((unsigned)c->E), dim3(64), 0, s, C); \
+        break;
+        switch (c->n1) {
+            SEM_RESTRICT(3) SEM_RESTRICT(4) SEM_RESTRICT(5) SEM_RESTRICT(6) SEM_RESTRICT(7)
+            SEM_RESTRICT(8) SEM_RESTRICT(9) SEM_RESTRICT(10) SEM_RESTRICT(11) SEM_RESTRICT(12)
+            SEM_RESTRICT(13) SEM_RESTRICT(14)
+            default: return gfail(G, SEM_ERR_UNSUPPORTED, "order");
+        }
+#undef SEM_RESTRICT
         SEM_HIP(c, hipGetLastError());
         // 10 Jacobi-PCG iterations from zero on the coarse operator
         sem_solve_options o;
@@ -853,7 +900,16 @@ static sem_status precondition(sem_gmres G, const VT *r, VT *z, unsigned parts, 
     } else {
         C.x0 = nullptr;
     }
-    hipLaunchKernelGGL(k_combine<VT>, dim3(gm_grid(n)), dim3(kGmBlock), 0, s, C);
+#define SEM_COMBINE(n1)                                                                     \
+    case n1:                                                                                \
+        hipLaunchKernelGGL((k_combine_e<n1, VT>), dim3((unsigned)c->E), dim3(64), 0, s, C); \
+        break;
+    switch (c->n1) {
+        SEM_COMBINE(3) SEM_COMBINE(4) SEM_COMBINE(5) SEM_COMBINE(6) SEM_COMBINE(7) SEM_COMBINE(8)
+        SEM_COMBINE(9) SEM_COMBINE(10) SEM_COMBINE(11) SEM_COMBINE(12) SEM_COMBINE(13) SEM_COMBINE(14)
+        default: return gfail(G, SEM_ERR_UNSUPPORTED, "order");
+    }
+#undef SEM_COMBINE
     SEM_HIP(c, hipGetLastError());
     return SEM_OK;
 }
