@@ -42,6 +42,11 @@ namespace {
 constexpr int kGmBlock = 256;
 constexpr int kGmGrid = 2048;
 constexpr int kGmMaxVec = 32;            // basis vectors in one multi-dot
+// coef[] slots: first-pass sums at 0.., second-pass sums at kGmC2..,
+// normalisation factor and squared norm of the new basis vector after them,
+// scalars for the update kernels at kGmMisc..
+constexpr int kGmC2 = kGmMaxVec + 2, kGmInv = 2 * kGmMaxVec + 4, kGmRho = kGmInv + 1;
+constexpr int kGmMisc = kGmRho + 1, kGmCoef = kGmMisc + 4;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -331,33 +336,7 @@ __global__ void __launch_bounds__(64) k_combine_e(CoarseParams<VT> P) {
     }
 }
 
-// part[blk][i] = X_i . v (i < l), part[blk][l] = v . v
-template <typename T>
-__global__ void __launch_bounds__(kGmBlock) k_gm_dots(int64_t n, int l, int64_t ld,
-                                                      const T *__restrict__ X,
-                                                      const T *__restrict__ v,
-                                                      double *__restrict__ part) {
-    __shared__ double red[kGmBlock / 64];
-    double acc[kGmMaxVec + 1];
-#pragma unroll
-    for (int i = 0; i <= kGmMaxVec; ++i) acc[i] = 0.0;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const double vq = (double)v[q];
-#pragma unroll
-        for (int i = 0; i < kGmMaxVec; ++i)
-            if (i < l) acc[i] += (double)X[i * ld + q] * vq;
-        acc[kGmMaxVec] += vq * vq;
-    }
-#pragma unroll
-    for (int i = 0; i <= kGmMaxVec; ++i) {
-        if (i <= l) {                             // l is uniform: no divergent barrier
-            const double s = gm_block_sum(i < l ? acc[i] : acc[kGmMaxVec], red);
-            if (threadIdx.x == 0) part[(size_t)blockIdx.x * (l + 1) + i] = s;
-        }
-    }
-}
-
+// out[i] = sum over blocks of part[b][i], i < m
 __global__ void __launch_bounds__(kGmBlock) k_gm_finish(int nblocks, int m,
                                                         const double *__restrict__ part,
                                                         double *__restrict__ out) {
@@ -370,25 +349,182 @@ __global__ void __launch_bounds__(kGmBlock) k_gm_finish(int nblocks, int m,
     }
 }
 
-// v -= sum_i c_i X_i (i < l); part[blk] = v . v
+// part[blk] = v . v over the block's share (any alignment of v)
 template <typename T>
-__global__ void __launch_bounds__(kGmBlock) k_gm_orth(int64_t n, int l, int64_t ld,
-                                                      const T *__restrict__ X,
-                                                      const double *__restrict__ coef,
-                                                      T *__restrict__ v,
-                                                      double *__restrict__ part) {
+__global__ void __launch_bounds__(kGmBlock) k_gm_norm2(int64_t n, const T *__restrict__ v,
+                                                       double *__restrict__ part) {
     __shared__ double red[kGmBlock / 64];
-    double s = 0.0;
+    double acc = 0.0;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * blockDim.x) {
-        double x = (double)v[q];
-        for (int i = 0; i < l; ++i) x -= coef[i] * (double)X[i * ld + q];
-        const T xt = (T)x;
-        v[q] = xt;
-        s += (double)xt * (double)xt;
+        const double x = (double)v[q];
+        acc += x * x;
     }
-    s = gm_block_sum(s, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    acc = gm_block_sum(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// The Gram-Schmidt kernels below are instantiated for the exact number L of
+// basis vectors, so that the loads of all L vectors at a point are issued
+// together; each lane takes two consecutive points per step (one 16-byte
+// load per FP64 vector).  The bases and w are workspace arrays, aligned to
+// 256 bytes with a leading dimension ld that is a multiple of 32 values.
+template <typename T> struct PairOf;
+template <> struct PairOf<double> { using type = double2; };
+template <> struct PairOf<float> { using type = float2; };
+
+// Block sums of acc[0..L] into part[blk][0..L].
+template <int L>
+__device__ __forceinline__ void gm_store_sums(const double *acc, double *part, double *red) {
+#pragma unroll
+    for (int i = 0; i <= L; ++i) {
+        const double sum = gm_block_sum(acc[i], red);
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * (L + 1) + i] = sum;
+    }
+}
+
+// part[blk][i] = X_i . v (i < L), part[blk][L] = v . v
+template <int L, typename T>
+__global__ void __launch_bounds__(kGmBlock) k_gm_dots(int64_t n, int64_t ld,
+                                                      const T *__restrict__ X,
+                                                      const T *__restrict__ v,
+                                                      double *__restrict__ part) {
+    using P = typename PairOf<T>::type;
+    __shared__ double red[kGmBlock / 64];
+    double acc[L + 1];
+#pragma unroll
+    for (int i = 0; i <= L; ++i) acc[i] = 0.0;
+    const int64_t np = n >> 1, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += stride) {
+        const P vp = reinterpret_cast<const P *>(v)[p];
+        const double v0 = (double)vp.x, v1 = (double)vp.y;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const P xp = reinterpret_cast<const P *>(X + i * ld)[p];
+            acc[i] += (double)xp.x * v0 + (double)xp.y * v1;
+        }
+        acc[L] += v0 * v0 + v1 * v1;
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {   // odd length: last point
+        const double vq = (double)v[n - 1];
+#pragma unroll
+        for (int i = 0; i < L; ++i) acc[i] += (double)X[i * ld + n - 1] * vq;
+        acc[L] += vq * vq;
+    }
+    gm_store_sums<L>(acc, part, red);
+}
+
+// Second Gram-Schmidt pass fused with the first one's update: v -= X c
+// (c = coef[0..L), subtracted in index order), then part[blk][i] = X_i . v
+// and part[blk][L] = v . v for the updated (stored) v.
+template <int L, typename T>
+__device__ __forceinline__ void gm_orth_dots_point(const T *X, int64_t ld, int64_t q,
+                                                   const double *cf, T *v, double *acc) {
+    double xv[L];
+    double x = (double)v[q];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        xv[i] = (double)X[i * ld + q];
+        x -= cf[i] * xv[i];
+    }
+    const T xt = (T)x;
+    v[q] = xt;
+    const double xd = (double)xt;
+#pragma unroll
+    for (int i = 0; i < L; ++i) acc[i] += xv[i] * xd;
+    acc[L] += xd * xd;
+}
+
+template <int L, typename T>
+__global__ void __launch_bounds__(kGmBlock) k_gm_orth_dots(int64_t n, int64_t ld,
+                                                           const T *__restrict__ X,
+                                                           const double *__restrict__ coef,
+                                                           T *__restrict__ v,
+                                                           double *__restrict__ part) {
+    using P = typename PairOf<T>::type;
+    __shared__ double red[kGmBlock / 64];
+    double cf[L], acc[L + 1];
+#pragma unroll
+    for (int i = 0; i < L; ++i) cf[i] = coef[i];
+#pragma unroll
+    for (int i = 0; i <= L; ++i) acc[i] = 0.0;
+    const int64_t np = n >> 1, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += stride) {
+        P xp[L];
+        const P vp = reinterpret_cast<const P *>(v)[p];
+        double x0 = (double)vp.x, x1 = (double)vp.y;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            xp[i] = reinterpret_cast<const P *>(X + i * ld)[p];
+            x0 -= cf[i] * (double)xp[i].x;
+            x1 -= cf[i] * (double)xp[i].y;
+        }
+        P out;
+        out.x = (T)x0;
+        out.y = (T)x1;
+        reinterpret_cast<P *>(v)[p] = out;
+        const double d0 = (double)out.x, d1 = (double)out.y;
+#pragma unroll
+        for (int i = 0; i < L; ++i) acc[i] += (double)xp[i].x * d0 + (double)xp[i].y * d1;
+        acc[L] += d0 * d0 + d1 * d1;
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0)
+        gm_orth_dots_point<L, T>(X, ld, n - 1, cf, v, acc);
+    gm_store_sums<L>(acc, part, red);
+}
+
+// Closing update of an Arnoldi step, normalisation included:
+// out = (v - X c) * inv, c = coef[0..L), with inv = 1/sqrt(v.v - |c|^2)
+// (the squared norm of v - X c when X is orthonormal and c = X^T v; v.v is
+// coef[L]).  Where that difference is not safely positive, inv = 1/|v|
+// instead (0 for v = 0).  Block 0 stores inv in *inv_out; part[blk] =
+// out . out, so the caller can check the normalisation.
+template <int L, typename T>
+__global__ void __launch_bounds__(kGmBlock) k_gm_orth_scale(int64_t n, int64_t ld,
+                                                            const T *__restrict__ X,
+                                                            const double *__restrict__ coef,
+                                                            const T *__restrict__ v,
+                                                            T *__restrict__ out,
+                                                            double *__restrict__ part,
+                                                            double *__restrict__ inv_out) {
+    using P = typename PairOf<T>::type;
+    __shared__ double red[kGmBlock / 64];
+    double cf[L], cc = 0.0;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        cf[i] = coef[i];
+        cc += cf[i] * cf[i];
+    }
+    const double vv = coef[L], est = vv - cc;
+    const double inv = est > 1e-4 * vv ? 1.0 / sqrt(est) : (vv > 0.0 ? 1.0 / sqrt(vv) : 0.0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *inv_out = inv;
+    double sum = 0.0;
+    const int64_t np = n >> 1, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += stride) {
+        const P vp = reinterpret_cast<const P *>(v)[p];
+        double x0 = (double)vp.x, x1 = (double)vp.y;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const P xp = reinterpret_cast<const P *>(X + i * ld)[p];
+            x0 -= cf[i] * (double)xp.x;
+            x1 -= cf[i] * (double)xp.y;
+        }
+        P o;
+        o.x = (T)(x0 * inv);
+        o.y = (T)(x1 * inv);
+        reinterpret_cast<P *>(out)[p] = o;
+        sum += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        double x = (double)v[n - 1];
+#pragma unroll
+        for (int i = 0; i < L; ++i) x -= cf[i] * (double)X[i * ld + n - 1];
+        const T xt = (T)(x * inv);
+        out[n - 1] = xt;
+        sum += (double)xt * (double)xt;
+    }
+    sum = gm_block_sum(sum, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = sum;
 }
 
 // dst = src * scale[0] (scale from device memory, 1/sqrt of it when inv_sqrt)
@@ -781,7 +917,7 @@ static size_t gm_layout(sem_gmres G, size_t *off) {
     off[12] = take(8 * (size_t)c->n_unique);          // w
     off[13] = take(8 * (size_t)c->n_unique);          // r
     off[14] = take(8 * (size_t)kGmGrid * (kGmMaxVec + 1));
-    off[15] = take(8 * (kGmMaxVec + 4));
+    off[15] = take(8 * kGmCoef);
     off[16] = take(4 * (size_t)c->n_unique);          // FP32 inner right-hand side
     off[17] = take(4 * (size_t)c->n_unique);          // FP32 inner correction
     off[18] = take((size_t)E * c->nb);                // owner flags
@@ -934,15 +1070,128 @@ static sem_status apply_A(sem_gmres G, int prec, const T *x, T *y, hipStream_t s
     return SEM_OK;
 }
 
-// coef[0..l) = X^T v, coef[l] = v.v (FP64 sums)
+// Grid of a reduction kernel: the workgroups that are resident at once on
+// the device (no partial second wave), at most one per kGmBlock entries and
+// at most kGmGrid (the size of the partial-sum buffer).
+template <typename K>
+static unsigned resident_grid(K kern, int &per_cu, int ncu, int64_t n) {
+    if (per_cu == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, kGmBlock, 0) != hipSuccess || nb < 1)
+            nb = 1;
+        per_cu = nb;
+    }
+    const int64_t need = (n + kGmBlock - 1) / kGmBlock;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>({need, (int64_t)per_cu * ncu, (int64_t)kGmGrid}));
+}
+
+#define SEM_GM_CASES(M)                                                                      \
+    M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15) M(16)    \
+    M(17) M(18) M(19) M(20) M(21) M(22) M(23) M(24) M(25) M(26) M(27) M(28) M(29) M(30) M(31)
+
+// coef[i] = X_i . v (i < L), coef[L] = v.v
+template <int L, typename T>
+struct GmDots {
+    static hipError_t run(sem_gmres G, const T *X, const T *v, hipStream_t s) {
+        static int per_cu = 0;
+        const int64_t n = G->ctx->n_unique;
+        const unsigned g = resident_grid(k_gm_dots<L, T>, per_cu, G->ctx->num_cus, n / 2);
+        hipLaunchKernelGGL((k_gm_dots<L, T>), dim3(g), dim3(kGmBlock), 0, s, n, G->ld, X, v, G->part);
+        hipLaunchKernelGGL(k_gm_finish, dim3(1), dim3(kGmBlock), 0, s, (int)g, L + 1,
+                           (const double *)G->part, G->coef);
+        return hipGetLastError();
+    }
+};
+
+// v -= X coef[0..L); coef[kGmC2 + i] = X_i . v, coef[kGmC2 + L] = v.v
+template <int L, typename T>
+struct GmOrthDots {
+    static hipError_t run(sem_gmres G, const T *X, T *v, hipStream_t s) {
+        static int per_cu = 0;
+        const int64_t n = G->ctx->n_unique;
+        const unsigned g = resident_grid(k_gm_orth_dots<L, T>, per_cu, G->ctx->num_cus, n / 2);
+        hipLaunchKernelGGL((k_gm_orth_dots<L, T>), dim3(g), dim3(kGmBlock), 0, s, n, G->ld, X,
+                           (const double *)G->coef, v, G->part);
+        hipLaunchKernelGGL(k_gm_finish, dim3(1), dim3(kGmBlock), 0, s, (int)g, L + 1,
+                           (const double *)G->part, G->coef + kGmC2);
+        return hipGetLastError();
+    }
+};
+
+// out = (v - X coef[kGmC2..]) * inv; coef[kGmInv] = inv, coef[kGmRho] = out.out
+template <int L, typename T>
+struct GmOrthScale {
+    static hipError_t run(sem_gmres G, const T *X, const T *v, T *out, hipStream_t s) {
+        static int per_cu = 0;
+        const int64_t n = G->ctx->n_unique;
+        const unsigned g = resident_grid(k_gm_orth_scale<L, T>, per_cu, G->ctx->num_cus, n / 2);
+        hipLaunchKernelGGL((k_gm_orth_scale<L, T>), dim3(g), dim3(kGmBlock), 0, s, n, G->ld, X,
+                           (const double *)(G->coef + kGmC2), v, out, G->part, G->coef + kGmInv);
+        hipLaunchKernelGGL(k_gm_finish, dim3(1), dim3(kGmBlock), 0, s, (int)g, 1,
+                           (const double *)G->part, G->coef + kGmRho);
+        return hipGetLastError();
+    }
+};
+
+// Op<l, T>::run(args...) for the basis size l in 1..kGmMaxVec-1
+template <template <int, typename> class Op, typename T, typename... A>
+static hipError_t gm_dispatch(int l, A... a) {
+    switch (l) {
+#define SEM_GM_CASE(L) \
+    case L: return Op<L, T>::run(a...);
+        SEM_GM_CASES(SEM_GM_CASE)
+#undef SEM_GM_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// coef[0] = v.v (FP64 sum; v of any alignment)
 template <typename T>
-static hipError_t gm_dots(sem_gmres G, int l, const T *X, const T *v, hipStream_t s) {
+static hipError_t gm_norm2(sem_gmres G, const T *v, hipStream_t s) {
+    static int per_cu = 0;
     const int64_t n = G->ctx->n_unique;
-    const unsigned g = gm_grid(n);
-    hipLaunchKernelGGL(k_gm_dots<T>, dim3(g), dim3(kGmBlock), 0, s, n, l, G->ld, X, v, G->part);
-    hipLaunchKernelGGL(k_gm_finish, dim3(1), dim3(kGmBlock), 0, s, (int)g, l + 1,
-                       (const double *)G->part, G->coef);
+    const unsigned g = resident_grid(k_gm_norm2<T>, per_cu, G->ctx->num_cus, n);
+    hipLaunchKernelGGL(k_gm_norm2<T>, dim3(g), dim3(kGmBlock), 0, s, n, v, G->part);
+    hipLaunchKernelGGL(k_gm_finish, dim3(1), dim3(kGmBlock), 0, s, (int)g, 1, (const double *)G->part,
+                       G->coef);
     return hipGetLastError();
+}
+
+// One Arnoldi orthogonalisation against V_0..V_{l-1}: classical
+// Gram-Schmidt twice, in three sweeps over the basis (dots; update fused
+// with the second dots; second update fused with the normalisation), then
+// one host read.  hcol[0..l) gets the summed coefficients, *hn the norm of
+// the orthogonalised w, and V_l = w / *hn (checked: a normalisation off by
+// more than rounding is redone exactly).
+template <typename T>
+static sem_status gm_arnoldi(sem_gmres G, int l, const T *V, T *w, T *Vl, double *hcol, double *hn,
+                             hipStream_t s) {
+    sem_ctx c = G->ctx;
+    SEM_HIP(c, (gm_dispatch<GmDots, T>(l, G, V, (const T *)w, s)));
+    SEM_HIP(c, (gm_dispatch<GmOrthDots, T>(l, G, V, w, s)));
+    SEM_HIP(c, (gm_dispatch<GmOrthScale, T>(l, G, V, (const T *)w, Vl, s)));
+    double h[kGmMisc];
+    SEM_HIP(c, hipMemcpyAsync(h, G->coef, 8 * kGmMisc, hipMemcpyDeviceToHost, s));
+    SEM_HIP(c, hipStreamSynchronize(s));
+    for (int i = 0; i < l; ++i) hcol[i] = h[i] + h[kGmC2 + i];
+    const double inv = h[kGmInv], rho = std::sqrt(h[kGmRho]);
+    if (!std::isfinite(inv) || !std::isfinite(rho)) return gfail(G, SEM_ERR_NAN, "non-finite Arnoldi vector");
+    if (inv == 0.0 || rho == 0.0) {                 // w lies in span(V): breakdown
+        *hn = 0.0;
+        return SEM_OK;
+    }
+    const double tol = std::is_same<T, double>::value ? 1e-11 : 1e-5;
+    if (std::fabs(rho - 1.0) > tol) {
+        const double r = 1.0 / rho;
+        SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMisc + 1, &r, 8, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL((k_gm_scale<T, T>), dim3(gm_grid(c->n_unique)), dim3(kGmBlock), 0, s,
+                           c->n_unique, (const T *)Vl, Vl, (const double *)(G->coef + kGmMisc + 1), 0);
+        SEM_HIP(c, hipGetLastError());
+        *hn = rho / inv;
+    } else {
+        *hn = 1.0 / inv;
+    }
+    return SEM_OK;
 }
 
 // Host copy of coef[0] after the stream has reached it.
@@ -963,12 +1212,12 @@ static sem_status residual(sem_gmres G, int prec, const T *b, const T *x, T *r, 
         sem_status e = apply_A<T>(G, prec, x, w, s);
         if (e) return e;
         const double minus1 = -1.0;
-        SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMaxVec + 2, &minus1, 8, hipMemcpyHostToDevice, s));
+        SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMisc, &minus1, 8, hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL((k_gm_update<T, T>), dim3(gm_grid(n)), dim3(kGmBlock), 0, s, n, 1, G->ld,
-                           (const T *)w, (const double *)(G->coef + kGmMaxVec + 2), r);
+                           (const T *)w, (const double *)(G->coef + kGmMisc), r);
         SEM_HIP(c, hipGetLastError());
     }
-    SEM_HIP(c, gm_dots<T>(G, 0, (const T *)nullptr, r, s));
+    SEM_HIP(c, gm_norm2<T>(G, r, s));
     double rr = 0.0;
     sem_status e = read_coef(G, 0, &rr, s);
     if (e) return e;
@@ -1009,9 +1258,9 @@ static sem_status fgmres(sem_gmres G, int prec, const T *b, T *x, bool x_zero, d
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
     for (;;) {
         const double inv = 1.0 / beta;                 // V_0 = r / beta
-        SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMaxVec + 3, &inv, 8, hipMemcpyHostToDevice, s));
+        SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMisc + 1, &inv, 8, hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL((k_gm_scale<T, T>), dim3(grid), dim3(kGmBlock), 0, s, n, (const T *)r, V,
-                           (const double *)(G->coef + kGmMaxVec + 3), 0);
+                           (const double *)(G->coef + kGmMisc + 1), 0);
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
@@ -1022,30 +1271,10 @@ static sem_status fgmres(sem_gmres G, int prec, const T *b, T *x, bool x_zero, d
             if (e) return e;
             e = apply_A<T>(G, prec, Zj, w, s);
             if (e) return e;
-            // two classical Gram-Schmidt passes against V_0..V_j
             double hcol[kGmMaxVec + 1] = {};
-            double nrm2 = 0.0;
-            for (int pass = 0; pass < 2; ++pass) {
-                SEM_HIP(c, gm_dots<T>(G, j + 1, V, w, s));
-                double h[kGmMaxVec + 1];
-                SEM_HIP(c, hipMemcpyAsync(h, G->coef, 8 * (j + 2), hipMemcpyDeviceToHost, s));
-                hipLaunchKernelGGL(k_gm_orth<T>, dim3(grid), dim3(kGmBlock), 0, s, n, j + 1, ld,
-                                   (const T *)V, (const double *)G->coef, w, G->part);
-                hipLaunchKernelGGL(k_gm_finish, dim3(1), dim3(kGmBlock), 0, s, (int)grid, 1,
-                                   (const double *)G->part, G->coef + kGmMaxVec + 1);
-                SEM_HIP(c, hipMemcpyAsync(&nrm2, G->coef + kGmMaxVec + 1, 8, hipMemcpyDeviceToHost, s));
-                SEM_HIP(c, hipStreamSynchronize(s));
-                for (int i = 0; i <= j; ++i) hcol[i] += h[i];
-            }
-            const double hn = std::sqrt(nrm2);
-            if (!std::isfinite(hn)) return gfail(G, SEM_ERR_NAN, "non-finite Arnoldi vector");
-            if (hn > 0) {                               // V_{j+1} = w / ||w||
-                const double iv = 1.0 / hn;
-                SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMaxVec + 3, &iv, 8, hipMemcpyHostToDevice, s));
-                hipLaunchKernelGGL((k_gm_scale<T, T>), dim3(grid), dim3(kGmBlock), 0, s, n, (const T *)w,
-                                   V + (size_t)(j + 1) * ld, (const double *)(G->coef + kGmMaxVec + 3), 0);
-                SEM_HIP(c, hipGetLastError());
-            }
+            double hn = 0.0;
+            e = gm_arnoldi<T>(G, j + 1, V, w, V + (size_t)(j + 1) * ld, hcol, &hn, s);
+            if (e) return e;
             // Givens rotations on column j of H
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i];
             H[(size_t)(j + 1) * m + j] = hn;
@@ -1117,7 +1346,7 @@ extern "C" sem_status sem_gmres_solve(sem_gmres G, const double *b, double *x,
         return info->status = st;
     };
     double bn = 0.0;
-    SEM_HIP(c, gm_dots<double>(G, 0, nullptr, b, s));
+    SEM_HIP(c, gm_norm2<double>(G, b, s));
     {
         double bb = 0.0;
         sem_status e = read_coef(G, 0, &bb, s);
@@ -1166,9 +1395,9 @@ extern "C" sem_status sem_gmres_solve(sem_gmres G, const double *b, double *x,
         prev = rn;
         // inner right-hand side r / ||r|| in FP32
         const double inv = 1.0 / rn;
-        SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMaxVec + 3, &inv, 8, hipMemcpyHostToDevice, s));
+        SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMisc + 1, &inv, 8, hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL((k_gm_scale<double, float>), dim3(gm_grid(n)), dim3(kGmBlock), 0, s, n,
-                           (const double *)G->r, G->rhs32, (const double *)(G->coef + kGmMaxVec + 3), 0);
+                           (const double *)G->r, G->rhs32, (const double *)(G->coef + kGmMisc + 1), 0);
         SEM_HIP(c, hipGetLastError());
         double rin = 0.0;
         e = fgmres<float>(G, prec, G->rhs32, G->d32, true, o.inner_tol,
