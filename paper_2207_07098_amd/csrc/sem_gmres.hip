@@ -104,119 +104,167 @@ struct FdmParams {
     double *z;                // sum of local solutions (atomic)
     const double *S;          // [E][3][NE][NE] eigenvectors S[a][m]
     const double *lam;        // [E][3][NE]
-    const int32_t *ghost;     // [E][6][(N+1)^2] solver index or -1
-    const int32_t *bmap;
-    int64_t E, n_bnd;
-    int N, nb;
+    const int32_t *fmap;      // [E][NE][NE^2] box gather map: solver index or -1
+    int64_t E;
 };
 
-// Box index a in 0..NE-1 <-> local index a - 1.  A lane owns the column
-// (a, b) of the box over c (k-direction) in registers.
-template <int NE, typename VT>
-__global__ void __launch_bounds__(256) k_fdm(FdmParams<VT> P) {
-    constexpr int C = NE * NE;
-    const int N = NE - 3, n1 = NE - 2;
-    __shared__ double Sl[3][C];
-    __shared__ double Ll[3][NE];
-    __shared__ double box[NE][NE][NE + 1];        // [c][b][a], padded
+// Box gather map of every element, built once when the workspace is bound:
+// fmap[e][c][a + NE b] = solver index of box point (a, b, c) (own points
+// through the element's map, one-layer extension through the face map),
+// -1 where the box holds no data (edges and corners of the extension).
+template <int NE>
+__global__ void __launch_bounds__((NE * NE + 63) / 64 * 64)
+k_fdm_map(const int32_t *__restrict__ ghost, const int32_t *__restrict__ bmap, int64_t E,
+          int64_t n_bnd, int nb, int32_t *__restrict__ fmap) {
+    constexpr int C = NE * NE, N = NE - 3, n1 = NE - 2;
     const int64_t e = blockIdx.x;
     const int t = threadIdx.x;
-    const bool lane_on = t < C;
-    const int a = t % NE, b = t / NE;
-    for (int q = t; q < 3 * C; q += blockDim.x) Sl[q / C][q % C] = P.S[(size_t)e * 3 * C + q];
-    for (int q = t; q < 3 * NE; q += blockDim.x) Ll[q / NE][q % NE] = P.lam[(size_t)e * 3 * NE + q];
-    // gather the box column (zero where the box holds no data)
-    double v[NE];
-    int64_t idx[NE];
-    const int i = a - 1, j = b - 1;
-#pragma unroll
+    if (t >= C || e >= E) return;
+    const int i = t % NE - 1, j = t / NE - 1;
     for (int c = 0; c < NE; ++c) {
         const int k = c - 1;
         const int oi = (i < 0 || i > N), oj = (j < 0 || j > N), ok = (k < 0 || k > N);
         int64_t g = -1;
-        if (lane_on) {
-            if (oi + oj + ok == 0) {
-                g = gm_node(P.bmap, P.n_bnd, e, i, j, k, N, P.nb);
-            } else if (oi + oj + ok == 1) {
-                int f, p, q;
-                if (oi) { f = i < 0 ? 0 : 1; p = j; q = k; }
-                else if (oj) { f = j < 0 ? 2 : 3; p = i; q = k; }
-                else { f = k < 0 ? 4 : 5; p = i; q = j; }
-                g = P.ghost[((size_t)e * 6 + f) * n1 * n1 + p + n1 * q];
+        if (oi + oj + ok == 0) {
+            g = gm_node(bmap, n_bnd, e, i, j, k, N, nb);
+        } else if (oi + oj + ok == 1) {
+            int f, p, q;
+            if (oi) { f = i < 0 ? 0 : 1; p = j; q = k; }
+            else if (oj) { f = j < 0 ? 2 : 3; p = i; q = k; }
+            else { f = k < 0 ? 4 : 5; p = i; q = j; }
+            g = ghost[((size_t)e * 6 + f) * n1 * n1 + p + n1 * q];
+        }
+        fmap[((size_t)e * NE + c) * C + t] = (int32_t)g;
+    }
+}
+
+// Box index a in 0..NE-1 <-> local index a - 1.  A lane owns the column
+// (a, b) of the box over c (k-direction) in registers.  Persistent over
+// elements: while element e is transformed, the gather indices and the
+// eigenvector tables of the next element are already being fetched, so an
+// element waits for one memory round trip (its residual values) instead of
+// three (map, then values; tables).
+template <int NE, typename VT>
+__global__ void __launch_bounds__((NE * NE + 63) / 64 * 64) k_fdm(FdmParams<VT> P) {
+    constexpr int C = NE * NE, NT = (C + 63) / 64 * 64;
+    constexpr int QS = (3 * C + NT - 1) / NT, QL = (3 * NE + NT - 1) / NT;
+    __shared__ double Sl[3][C];
+    __shared__ double Ll[3][NE];
+    __shared__ double box[NE][NE][NE + 1];        // [c][b][a], padded
+    const int t = threadIdx.x;
+    const bool lane_on = t < C;
+    const int a = t % NE, b = t / NE;
+    int32_t idx[NE], nidx[NE];
+    double sreg[QS], lreg[QL];
+    auto fetch = [&](int64_t e, int32_t (&ix)[NE], double (&sr)[QS], double (&lr)[QL]) {
+        const bool ok = e < P.E;
+#pragma unroll
+        for (int c = 0; c < NE; ++c)
+            ix[c] = (lane_on && ok) ? __builtin_nontemporal_load(P.fmap + ((size_t)e * NE + c) * C + t) : -1;
+#pragma unroll
+        for (int q = 0; q < QS; ++q) {
+            const int x = t + q * NT;
+            sr[q] = (ok && x < 3 * C) ? __builtin_nontemporal_load(P.S + (size_t)e * 3 * C + x) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < QL; ++q) {
+            const int x = t + q * NT;
+            lr[q] = (ok && x < 3 * NE) ? P.lam[(size_t)e * 3 * NE + x] : 0.0;
+        }
+    };
+    fetch(blockIdx.x, idx, sreg, lreg);
+    for (int64_t e = blockIdx.x; e < P.E; e += gridDim.x) {
+        // gather the box column (zero where the box holds no data): one
+        // unconditional load per point from a valid address, masked after
+        double v[NE];
+#pragma unroll
+        for (int c = 0; c < NE; ++c) v[c] = (double)P.r[idx[c] >= 0 ? idx[c] : 0];
+        __syncthreads();                           // previous element done with LDS
+#pragma unroll
+        for (int q = 0; q < QS; ++q) {
+            const int x = t + q * NT;
+            if (x < 3 * C) Sl[x / C][x % C] = sreg[q];
+        }
+#pragma unroll
+        for (int q = 0; q < QL; ++q) {
+            const int x = t + q * NT;
+            if (x < 3 * NE) Ll[x / NE][x % NE] = lreg[q];
+        }
+        fetch(e + gridDim.x, nidx, sreg, lreg);   // next element, in flight meanwhile
+#pragma unroll
+        for (int c = 0; c < NE; ++c) v[c] = idx[c] >= 0 ? v[c] : 0.0;
+        __syncthreads();
+        // forward: w = (S_t^T x S_s^T x S_r^T) v
+        double w[NE];
+#pragma unroll
+        for (int m = 0; m < NE; ++m) {             // t-direction, register-local
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < NE; ++c) acc += Sl[2][c * NE + m] * v[c];
+            w[m] = acc;
+        }
+        if (lane_on)
+#pragma unroll
+            for (int c = 0; c < NE; ++c) box[c][b][a] = w[c];
+        __syncthreads();
+        double w2[NE];
+        if (lane_on)                               // s-direction: lane (a, b) -> mode b
+#pragma unroll
+            for (int c = 0; c < NE; ++c) {
+                double acc = 0.0;
+                for (int bb = 0; bb < NE; ++bb) acc += Sl[1][bb * NE + b] * box[c][bb][a];
+                w2[c] = acc;
+            }
+        __syncthreads();
+        if (lane_on)
+#pragma unroll
+            for (int c = 0; c < NE; ++c) box[c][b][a] = w2[c];
+        __syncthreads();
+        if (lane_on)                               // r-direction: lane (a, b) -> mode a
+#pragma unroll
+            for (int c = 0; c < NE; ++c) {
+                double acc = 0.0;
+                for (int aa = 0; aa < NE; ++aa) acc += Sl[0][aa * NE + a] * box[c][b][aa];
+                const double lsum = Ll[0][a] + Ll[1][b] + Ll[2][c];
+                // a zero sum only for an element without any neighbour or
+                // Dirichlet face (its constant mode): pseudo-inverse
+                w2[c] = lsum > 1e-13 * (Ll[0][NE - 1] + Ll[1][NE - 1] + Ll[2][NE - 1]) ? acc / lsum : 0.0;
+            }
+        __syncthreads();
+        if (lane_on)
+#pragma unroll
+            for (int c = 0; c < NE; ++c) box[c][b][a] = w2[c];
+        __syncthreads();
+        // backward: u = (S_t x S_s x S_r) w
+        if (lane_on)                               // r-direction: point a
+#pragma unroll
+            for (int c = 0; c < NE; ++c) {
+                double acc = 0.0;
+                for (int aa = 0; aa < NE; ++aa) acc += Sl[0][a * NE + aa] * box[c][b][aa];
+                w2[c] = acc;
+            }
+        __syncthreads();
+        if (lane_on)
+#pragma unroll
+            for (int c = 0; c < NE; ++c) box[c][b][a] = w2[c];
+        __syncthreads();
+        if (lane_on) {                             // s-direction: point b
+#pragma unroll
+            for (int c = 0; c < NE; ++c) {
+                double acc = 0.0;
+                for (int bb = 0; bb < NE; ++bb) acc += Sl[1][b * NE + bb] * box[c][bb][a];
+                w2[c] = acc;
+            }
+#pragma unroll
+            for (int c = 0; c < NE; ++c) {         // t-direction: point c, then scatter
+                double acc = 0.0;
+#pragma unroll
+                for (int m = 0; m < NE; ++m) acc += Sl[2][c * NE + m] * w2[m];
+                if (idx[c] >= 0) atomicAdd(P.z + idx[c], acc);
             }
         }
-        idx[c] = g;
-        v[c] = g >= 0 ? (double)P.r[g] : 0.0;
-    }
-    __syncthreads();
-    // forward: w = (S_t^T x S_s^T x S_r^T) v
-    double w[NE];
 #pragma unroll
-    for (int m = 0; m < NE; ++m) {                 // t-direction, register-local
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < NE; ++c) s += Sl[2][c * NE + m] * v[c];
-        w[m] = s;
-    }
-    if (lane_on)
-#pragma unroll
-        for (int c = 0; c < NE; ++c) box[c][b][a] = w[c];
-    __syncthreads();
-    double w2[NE];
-    if (lane_on)                                   // s-direction: lane (a, b) -> mode b
-#pragma unroll
-        for (int c = 0; c < NE; ++c) {
-            double s = 0.0;
-            for (int bb = 0; bb < NE; ++bb) s += Sl[1][bb * NE + b] * box[c][bb][a];
-            w2[c] = s;
-        }
-    __syncthreads();
-    if (lane_on)
-#pragma unroll
-        for (int c = 0; c < NE; ++c) box[c][b][a] = w2[c];
-    __syncthreads();
-    if (lane_on)                                   // r-direction: lane (a, b) -> mode a
-#pragma unroll
-        for (int c = 0; c < NE; ++c) {
-            double s = 0.0;
-            for (int aa = 0; aa < NE; ++aa) s += Sl[0][aa * NE + a] * box[c][b][aa];
-            const double lsum = Ll[0][a] + Ll[1][b] + Ll[2][c];
-            // a zero sum only for an element without any neighbour or
-            // Dirichlet face (its constant mode): pseudo-inverse
-            w2[c] = lsum > 1e-13 * (Ll[0][NE - 1] + Ll[1][NE - 1] + Ll[2][NE - 1]) ? s / lsum : 0.0;
-        }
-    __syncthreads();
-    if (lane_on)
-#pragma unroll
-        for (int c = 0; c < NE; ++c) box[c][b][a] = w2[c];
-    __syncthreads();
-    // backward: u = (S_t x S_s x S_r) w
-    if (lane_on)                                   // r-direction: point a
-#pragma unroll
-        for (int c = 0; c < NE; ++c) {
-            double s = 0.0;
-            for (int aa = 0; aa < NE; ++aa) s += Sl[0][a * NE + aa] * box[c][b][aa];
-            w2[c] = s;
-        }
-    __syncthreads();
-    if (lane_on)
-#pragma unroll
-        for (int c = 0; c < NE; ++c) box[c][b][a] = w2[c];
-    __syncthreads();
-    if (lane_on)                                   // s-direction: point b
-#pragma unroll
-        for (int c = 0; c < NE; ++c) {
-            double s = 0.0;
-            for (int bb = 0; bb < NE; ++bb) s += Sl[1][b * NE + bb] * box[c][bb][a];
-            w2[c] = s;
-        }
-    if (!lane_on) return;
-#pragma unroll
-    for (int c = 0; c < NE; ++c) {                 // t-direction: point c
-        double s = 0.0;
-#pragma unroll
-        for (int m = 0; m < NE; ++m) s += Sl[2][c * NE + m] * w2[m];
-        if (idx[c] >= 0) atomicAdd(P.z + idx[c], s);
+        for (int c = 0; c < NE; ++c) idx[c] = nidx[c];
     }
 }
 
@@ -623,6 +671,8 @@ struct sem_gmres_s {
     double *dS = nullptr, *dlam = nullptr, *dW = nullptr, *dxi = nullptr;
     int32_t *dghost = nullptr, *dcmap = nullptr;
     uint8_t *downer = nullptr;
+    int32_t *dfmap = nullptr;
+    int fdm_per_cu = 0;              // resident FDM workgroups per CU
     double *zs = nullptr, *b0 = nullptr, *x0 = nullptr;
     double *V = nullptr, *Z = nullptr, *w = nullptr, *r = nullptr;
     double *part = nullptr, *coef = nullptr;
@@ -921,12 +971,13 @@ static size_t gm_layout(sem_gmres G, size_t *off) {
     off[16] = take(4 * (size_t)c->n_unique);          // FP32 inner right-hand side
     off[17] = take(4 * (size_t)c->n_unique);          // FP32 inner correction
     off[18] = take((size_t)E * c->nb);                // owner flags
+    off[19] = take(4 * (size_t)E * NE * NE * NE);    // box gather map
     return o;
 }
 
 extern "C" sem_status sem_gmres_workspace_size(sem_gmres G, size_t *bytes) {
     if (!G || !bytes) return gfail(G, SEM_ERR_INVALID, "null argument");
-    size_t off[19];
+    size_t off[20];
     *bytes = gm_layout(G, off);
     return SEM_OK;
 }
@@ -934,7 +985,7 @@ extern "C" sem_status sem_gmres_workspace_size(sem_gmres G, size_t *bytes) {
 extern "C" sem_status sem_gmres_bind_workspace(sem_gmres G, void *dev, size_t bytes,
                                                sem_stream stream) {
     if (!G || !dev) return gfail(G, SEM_ERR_INVALID, "null argument");
-    size_t off[19];
+    size_t off[20];
     const size_t need = gm_layout(G, off);
     if (bytes < need)
         return gfail(G, SEM_ERR_OOM, "workspace of " + std::to_string(bytes) + " bytes, need " +
@@ -968,6 +1019,7 @@ extern "C" sem_status sem_gmres_bind_workspace(sem_gmres G, void *dev, size_t by
     G->rhs32 = reinterpret_cast<float *>(w + off[16]);
     G->d32 = reinterpret_cast<float *>(w + off[17]);
     G->downer = reinterpret_cast<uint8_t *>(w + off[18]);
+    G->dfmap = reinterpret_cast<int32_t *>(w + off[19]);
     SEM_HIP(c, hipMemcpyAsync(G->dS, G->S.data(), 8 * G->S.size(), hipMemcpyHostToDevice, s));
     SEM_HIP(c, hipMemcpyAsync(G->dlam, G->lam.data(), 8 * G->lam.size(), hipMemcpyHostToDevice, s));
     SEM_HIP(c, hipMemcpyAsync(G->dghost, G->ghost.data(), 4 * G->ghost.size(), hipMemcpyHostToDevice, s));
@@ -975,6 +1027,20 @@ extern "C" sem_status sem_gmres_bind_workspace(sem_gmres G, void *dev, size_t by
     SEM_HIP(c, hipMemcpyAsync(G->dW, G->W.data(), 8 * G->W.size(), hipMemcpyHostToDevice, s));
     SEM_HIP(c, hipMemcpyAsync(G->downer, G->owner.data(), G->owner.size(), hipMemcpyHostToDevice, s));
     SEM_HIP(c, hipMemcpyAsync(G->dxi, c->xi, 8 * c->n1, hipMemcpyHostToDevice, s));
+    // box gather maps from the element and face maps
+#define SEM_FMAP(ne)                                                                            \
+    case ne:                                                                                    \
+        hipLaunchKernelGGL(k_fdm_map<ne>, dim3((unsigned)c->E), dim3(((ne) * (ne) + 63) / 64 * 64), 0, \
+                           s, (const int32_t *)G->dghost, dptr<int32_t>(c, c->L.bmap), c->E,   \
+                           c->n_bnd, c->nb, G->dfmap);                                          \
+        break;
+    switch (G->NE) {
+        SEM_FMAP(5) SEM_FMAP(6) SEM_FMAP(7) SEM_FMAP(8) SEM_FMAP(9) SEM_FMAP(10) SEM_FMAP(11)
+        SEM_FMAP(12) SEM_FMAP(13) SEM_FMAP(14) SEM_FMAP(15) SEM_FMAP(16)
+        default: return gfail(G, SEM_ERR_UNSUPPORTED, "order");
+    }
+#undef SEM_FMAP
+    SEM_HIP(c, hipGetLastError());
     SEM_HIP(c, hipStreamSynchronize(s));
     return SEM_OK;
 }
@@ -989,13 +1055,23 @@ static sem_status precondition(sem_gmres G, const VT *r, VT *z, unsigned parts, 
     const bool local = parts & SEM_PC_SCHWARZ, coarse = parts & SEM_PC_COARSE;
     if (local) {
         SEM_HIP(c, launch_fill(G->zs, n, 0.0, s));
-        FdmParams<VT> P{r, G->zs, G->dS, G->dlam, G->dghost, dptr<int32_t>(c, c->L.bmap), c->E,
-                        c->n_bnd, c->N, c->nb};
+        FdmParams<VT> P{r, G->zs, G->dS, G->dlam, G->dfmap, c->E};
+        // persistent: the workgroups resident at once, each taking every
+        // grid-th element
 #define SEM_FDM(ne)                                                                          \
-    case ne:                                                                                 \
-        hipLaunchKernelGGL((k_fdm<ne, VT>), dim3((unsigned)c->E), dim3(((ne) * (ne) + 63) / 64 * 64), \
-                           0, s, P);                                                         \
-        break;
+    case ne: {                                                                               \
+        const int nt = ((ne) * (ne) + 63) / 64 * 64;                                         \
+        if (G->fdm_per_cu == 0) {                                                            \
+            int nb = 0;                                                                      \
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fdm<ne, VT>, nt, 0) !=   \
+                    hipSuccess || nb < 1)                                                    \
+                nb = 1;                                                                      \
+            G->fdm_per_cu = nb;                                                              \
+        }                                                                                    \
+        const int64_t grid = std::min<int64_t>(c->E, (int64_t)G->fdm_per_cu * c->num_cus);   \
+        hipLaunchKernelGGL((k_fdm<ne, VT>), dim3((unsigned)grid), dim3(nt), 0, s, P);        \
+        break;                                                                               \
+    }
         switch (G->NE) {
             SEM_FDM(5) SEM_FDM(6) SEM_FDM(7) SEM_FDM(8) SEM_FDM(9) SEM_FDM(10) SEM_FDM(11)
             SEM_FDM(12) SEM_FDM(13) SEM_FDM(14) SEM_FDM(15) SEM_FDM(16)
