@@ -143,9 +143,12 @@ k_fdm_map(const int32_t *__restrict__ ghost, const int32_t *__restrict__ bmap, i
 // elements: while element e is transformed, the gather indices and the
 // eigenvector tables of the next element are already being fetched, so an
 // element waits for one memory round trip (its residual values) instead of
-// three (map, then values; tables).
+// three (map, then values; tables).  Register budget: three waves per SIMD
+// up to NE = 11 (FP32 residuals would otherwise take two), two above.
 template <int NE, typename VT>
-__global__ void __launch_bounds__((NE * NE + 63) / 64 * 64) k_fdm(FdmParams<VT> P) {
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, (NE * NE + 63) / 64 * 64),
+                               amdgpu_waves_per_eu(NE <= 11 ? 3 : 2)))
+k_fdm(FdmParams<VT> P) {
     constexpr int C = NE * NE, NT = (C + 63) / 64 * 64;
     constexpr int QS = (3 * C + NT - 1) / NT, QL = (3 * NE + NT - 1) / NT;
     __shared__ double Sl[3][C];
