@@ -431,7 +431,9 @@ sem_status sem_proj_solve(sem_proj proj, const double *b, double *x,
  *   combination    z = z_Schwarz + z_coarse; the coarse PCG makes it nonlinear,
  *                  so GMRES is the flexible variant (right preconditioning,
  *                  preconditioned vectors kept), restarted every `restart`
- *                  steps, two classical Gram-Schmidt passes, FP64.
+ *                  steps, classical Gram-Schmidt twice with the second
+ *                  projection of each new basis vector made during the next
+ *                  step (two sweeps over the basis per step), FP64 sums.
  * The context must have geometry and opts.solver = 1, 2 <= N <= 13, and the
  * Poisson operator (SEM_ERR_UNSUPPORTED for a Helmholtz pair).  The solver
  * owns an internal N = 1 context (host data); device memory is one

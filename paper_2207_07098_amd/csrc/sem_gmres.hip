@@ -42,11 +42,12 @@ namespace {
 constexpr int kGmBlock = 256;
 constexpr int kGmGrid = 2048;
 constexpr int kGmMaxVec = 32;            // basis vectors in one multi-dot
-// coef[] slots: first-pass sums at 0.., second-pass sums at kGmC2..,
+// coef[] slots: single-vector sums at 0.., the sums of a delayed step at
+// kGmD.. (2 * kGmMaxVec + 3 values), that step's scalars at kGmScal..,
 // normalisation factor and squared norm of the new basis vector after them,
 // scalars for the update kernels at kGmMisc..
-constexpr int kGmC2 = kGmMaxVec + 2, kGmInv = 2 * kGmMaxVec + 4, kGmRho = kGmInv + 1;
-constexpr int kGmMisc = kGmRho + 1, kGmCoef = kGmMisc + 4;
+constexpr int kGmD = kGmMaxVec + 2, kGmScal = kGmD + 2 * kGmMaxVec + 4;
+constexpr int kGmMisc = kGmScal + 4, kGmCoef = kGmMisc + 4;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -465,63 +466,141 @@ __global__ void __launch_bounds__(kGmBlock) k_gm_dots(int64_t n, int64_t ld,
     gm_store_sums<L>(acc, part, red);
 }
 
-// Second Gram-Schmidt pass fused with the first one's update: v -= X c
-// (c = coef[0..L), subtracted in index order), then part[blk][i] = X_i . v
-// and part[blk][L] = v . v for the updated (stored) v.
+// Arnoldi with delayed reorthogonalisation (classical Gram-Schmidt twice,
+// the second projection of each new vector done during the next step).
+// At step j the basis V_0..V_{L-1} (L = j) is final and slot j holds the
+// once-projected, roughly normalised vector vt; w = A z with z the search
+// direction computed from vt.  One sweep forms all inner products
+//   part[blk] = [ X_i . vt (i < L), X_i . w (i < L), vt.vt, vt.w, w.w ].
 template <int L, typename T>
-__device__ __forceinline__ void gm_orth_dots_point(const T *X, int64_t ld, int64_t q,
-                                                   const double *cf, T *v, double *acc) {
-    double xv[L];
-    double x = (double)v[q];
-#pragma unroll
-    for (int i = 0; i < L; ++i) {
-        xv[i] = (double)X[i * ld + q];
-        x -= cf[i] * xv[i];
-    }
-    const T xt = (T)x;
-    v[q] = xt;
-    const double xd = (double)xt;
-#pragma unroll
-    for (int i = 0; i < L; ++i) acc[i] += xv[i] * xd;
-    acc[L] += xd * xd;
-}
-
-template <int L, typename T>
-__global__ void __launch_bounds__(kGmBlock) k_gm_orth_dots(int64_t n, int64_t ld,
-                                                           const T *__restrict__ X,
-                                                           const double *__restrict__ coef,
-                                                           T *__restrict__ v,
-                                                           double *__restrict__ part) {
+__global__ void __launch_bounds__(kGmBlock) k_gm_dots2(int64_t n, int64_t ld,
+                                                       const T *__restrict__ X,
+                                                       const T *__restrict__ vt,
+                                                       const T *__restrict__ w,
+                                                       double *__restrict__ part) {
     using P = typename PairOf<T>::type;
+    constexpr int M = 2 * L + 3;
     __shared__ double red[kGmBlock / 64];
-    double cf[L], acc[L + 1];
+    double acc[M];
 #pragma unroll
-    for (int i = 0; i < L; ++i) cf[i] = coef[i];
-#pragma unroll
-    for (int i = 0; i <= L; ++i) acc[i] = 0.0;
+    for (int i = 0; i < M; ++i) acc[i] = 0.0;
     const int64_t np = n >> 1, stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += stride) {
-        P xp[L];
-        const P vp = reinterpret_cast<const P *>(v)[p];
-        double x0 = (double)vp.x, x1 = (double)vp.y;
+        const P vp = reinterpret_cast<const P *>(vt)[p];
+        const P wp = reinterpret_cast<const P *>(w)[p];
+        const double v0 = (double)vp.x, v1 = (double)vp.y, w0 = (double)wp.x, w1 = (double)wp.y;
 #pragma unroll
         for (int i = 0; i < L; ++i) {
-            xp[i] = reinterpret_cast<const P *>(X + i * ld)[p];
-            x0 -= cf[i] * (double)xp[i].x;
-            x1 -= cf[i] * (double)xp[i].y;
+            const P xp = reinterpret_cast<const P *>(X + i * ld)[p];
+            const double x0 = (double)xp.x, x1 = (double)xp.y;
+            acc[i] += x0 * v0 + x1 * v1;
+            acc[L + i] += x0 * w0 + x1 * w1;
         }
-        P out;
-        out.x = (T)x0;
-        out.y = (T)x1;
-        reinterpret_cast<P *>(v)[p] = out;
-        const double d0 = (double)out.x, d1 = (double)out.y;
-#pragma unroll
-        for (int i = 0; i < L; ++i) acc[i] += (double)xp[i].x * d0 + (double)xp[i].y * d1;
-        acc[L] += d0 * d0 + d1 * d1;
+        acc[2 * L] += v0 * v0 + v1 * v1;
+        acc[2 * L + 1] += v0 * w0 + v1 * w1;
+        acc[2 * L + 2] += w0 * w0 + w1 * w1;
     }
-    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0)
-        gm_orth_dots_point<L, T>(X, ld, n - 1, cf, v, acc);
-    gm_store_sums<L>(acc, part, red);
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {   // odd length: last point
+        const double v0 = (double)vt[n - 1], w0 = (double)w[n - 1];
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const double x0 = (double)X[i * ld + n - 1];
+            acc[i] += x0 * v0;
+            acc[L + i] += x0 * w0;
+        }
+        acc[2 * L] += v0 * v0;
+        acc[2 * L + 1] += v0 * w0;
+        acc[2 * L + 2] += w0 * w0;
+    }
+    gm_store_sums<M - 1>(acc, part, red);
+}
+
+// Scalars of the delayed step from the sums d = [q (L), p (L), r, s, t]
+// (q = X^T vt, p = X^T w, r = vt.vt, s = vt.w, t = w.w):
+//   beta = |vt - X q| = sqrt(r - |q|^2)   (X orthonormal)
+//   h    = (s - q.p) / beta               (w against the final vector)
+//   c    = 1 / |w - X p - h v|, |.|^2 = t - |p|^2 - h^2, or 1/|w| where that
+//          difference is not safely positive (any positive scale is exact
+//          here: the next step measures the stored vector).
+__device__ __forceinline__ void gm_delayed_scalars(const double *q, const double *pv, int L,
+                                                   double r, double s, double t, double &beta,
+                                                   double &h, double &c) {
+    double qq = 0.0, qp = 0.0, pp = 0.0;
+    for (int i = 0; i < L; ++i) {
+        qq += q[i] * q[i];
+        qp += q[i] * pv[i];
+        pp += pv[i] * pv[i];
+    }
+    const double b2 = r - qq;
+    beta = b2 > 0.0 ? sqrt(b2) : 0.0;
+    h = beta > 0.0 ? (s - qp) / beta : 0.0;
+    const double est = t - pp - h * h;
+    c = est > 1e-4 * t ? 1.0 / sqrt(est) : (t > 0.0 ? 1.0 / sqrt(t) : 0.0);
+}
+
+// The sweep that closes step j: the final basis vector and the next
+// once-projected one,
+//   v   = (vt - X q) / beta           (stored over vt),
+//   out = (w - X p - h v) * c          (the next slot),
+// with q, p, r, s, t from d and beta, h, c as above (block 0 stores them in
+// scal[0..2]).
+template <int L, typename T>
+__global__ void __launch_bounds__(kGmBlock) k_gm_update2(int64_t n, int64_t ld,
+                                                         const T *__restrict__ X,
+                                                         const double *__restrict__ d,
+                                                         T *__restrict__ vt,
+                                                         const T *__restrict__ w,
+                                                         T *__restrict__ out,
+                                                         double *__restrict__ scal) {
+    using P = typename PairOf<T>::type;
+    double q[L], pv[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        q[i] = d[i];
+        pv[i] = d[L + i];
+    }
+    double beta, h, c;
+    gm_delayed_scalars(q, pv, L, d[2 * L], d[2 * L + 1], d[2 * L + 2], beta, h, c);
+    const double ib = beta > 0.0 ? 1.0 / beta : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        scal[0] = beta;
+        scal[1] = h;
+        scal[2] = c;
+    }
+    const int64_t np = n >> 1, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += stride) {
+        const P vp = reinterpret_cast<const P *>(vt)[p];
+        const P wp = reinterpret_cast<const P *>(w)[p];
+        double a0 = (double)vp.x, a1 = (double)vp.y, b0 = (double)wp.x, b1 = (double)wp.y;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const P xp = reinterpret_cast<const P *>(X + i * ld)[p];
+            const double x0 = (double)xp.x, x1 = (double)xp.y;
+            a0 -= q[i] * x0;
+            a1 -= q[i] * x1;
+            b0 -= pv[i] * x0;
+            b1 -= pv[i] * x1;
+        }
+        P v, o;
+        v.x = (T)(a0 * ib);
+        v.y = (T)(a1 * ib);
+        o.x = (T)((b0 - h * (double)v.x) * c);
+        o.y = (T)((b1 - h * (double)v.y) * c);
+        reinterpret_cast<P *>(vt)[p] = v;
+        reinterpret_cast<P *>(out)[p] = o;
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        double a = (double)vt[n - 1], b = (double)w[n - 1];
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const double x = (double)X[i * ld + n - 1];
+            a -= q[i] * x;
+            b -= pv[i] * x;
+        }
+        const T v = (T)(a * ib);
+        vt[n - 1] = v;
+        out[n - 1] = (T)((b - h * (double)v) * c);
+    }
 }
 
 // Closing update of an Arnoldi step, normalisation included:
@@ -1182,32 +1261,31 @@ struct GmDots {
     }
 };
 
-// v -= X coef[0..L); coef[kGmC2 + i] = X_i . v, coef[kGmC2 + L] = v.v
+// coef[kGmD..] = [X^T vt (L), X^T w (L), vt.vt, vt.w, w.w]
 template <int L, typename T>
-struct GmOrthDots {
-    static hipError_t run(sem_gmres G, const T *X, T *v, hipStream_t s) {
+struct GmDots2 {
+    static hipError_t run(sem_gmres G, const T *X, const T *vt, const T *w, hipStream_t s) {
         static int per_cu = 0;
         const int64_t n = G->ctx->n_unique;
-        const unsigned g = resident_grid(k_gm_orth_dots<L, T>, per_cu, G->ctx->num_cus, n / 2);
-        hipLaunchKernelGGL((k_gm_orth_dots<L, T>), dim3(g), dim3(kGmBlock), 0, s, n, G->ld, X,
-                           (const double *)G->coef, v, G->part);
-        hipLaunchKernelGGL(k_gm_finish, dim3(1), dim3(kGmBlock), 0, s, (int)g, L + 1,
-                           (const double *)G->part, G->coef + kGmC2);
+        const unsigned g = resident_grid(k_gm_dots2<L, T>, per_cu, G->ctx->num_cus, n / 2);
+        hipLaunchKernelGGL((k_gm_dots2<L, T>), dim3(g), dim3(kGmBlock), 0, s, n, G->ld, X, vt, w,
+                           G->part);
+        hipLaunchKernelGGL(k_gm_finish, dim3(1), dim3(kGmBlock), 0, s, (int)g, 2 * L + 3,
+                           (const double *)G->part, G->coef + kGmD);
         return hipGetLastError();
     }
 };
 
-// out = (v - X coef[kGmC2..]) * inv; coef[kGmInv] = inv, coef[kGmRho] = out.out
+// vt <- final basis vector, out <- next once-projected vector (from coef[kGmD..]);
+// beta, h, c to coef[kGmScal..]
 template <int L, typename T>
-struct GmOrthScale {
-    static hipError_t run(sem_gmres G, const T *X, const T *v, T *out, hipStream_t s) {
+struct GmUpdate2 {
+    static hipError_t run(sem_gmres G, const T *X, T *vt, const T *w, T *out, hipStream_t s) {
         static int per_cu = 0;
         const int64_t n = G->ctx->n_unique;
-        const unsigned g = resident_grid(k_gm_orth_scale<L, T>, per_cu, G->ctx->num_cus, n / 2);
-        hipLaunchKernelGGL((k_gm_orth_scale<L, T>), dim3(g), dim3(kGmBlock), 0, s, n, G->ld, X,
-                           (const double *)(G->coef + kGmC2), v, out, G->part, G->coef + kGmInv);
-        hipLaunchKernelGGL(k_gm_finish, dim3(1), dim3(kGmBlock), 0, s, (int)g, 1,
-                           (const double *)G->part, G->coef + kGmRho);
+        const unsigned g = resident_grid(k_gm_update2<L, T>, per_cu, G->ctx->num_cus, n / 2);
+        hipLaunchKernelGGL((k_gm_update2<L, T>), dim3(g), dim3(kGmBlock), 0, s, n, G->ld, X,
+                           (const double *)(G->coef + kGmD), vt, w, out, G->coef + kGmScal);
         return hipGetLastError();
     }
 };
@@ -1236,41 +1314,20 @@ static hipError_t gm_norm2(sem_gmres G, const T *v, hipStream_t s) {
     return hipGetLastError();
 }
 
-// One Arnoldi orthogonalisation against V_0..V_{l-1}: classical
-// Gram-Schmidt twice, in three sweeps over the basis (dots; update fused
-// with the second dots; second update fused with the normalisation), then
-// one host read.  hcol[0..l) gets the summed coefficients, *hn the norm of
-// the orthogonalised w, and V_l = w / *hn (checked: a normalisation off by
-// more than rounding is redone exactly).
+// First Arnoldi step of a cycle (V_0 final, no vector awaiting its second
+// projection): coef[0] = p = V_0 . w, coef[1] = w.w, then
+// out = (w - p V_0) * c with c = 1/sqrt(w.w - p^2) (or 1/|w|), c stored
+// at coef[kGmScal + 2].
 template <typename T>
-static sem_status gm_arnoldi(sem_gmres G, int l, const T *V, T *w, T *Vl, double *hcol, double *hn,
-                             hipStream_t s) {
-    sem_ctx c = G->ctx;
-    SEM_HIP(c, (gm_dispatch<GmDots, T>(l, G, V, (const T *)w, s)));
-    SEM_HIP(c, (gm_dispatch<GmOrthDots, T>(l, G, V, w, s)));
-    SEM_HIP(c, (gm_dispatch<GmOrthScale, T>(l, G, V, (const T *)w, Vl, s)));
-    double h[kGmMisc];
-    SEM_HIP(c, hipMemcpyAsync(h, G->coef, 8 * kGmMisc, hipMemcpyDeviceToHost, s));
-    SEM_HIP(c, hipStreamSynchronize(s));
-    for (int i = 0; i < l; ++i) hcol[i] = h[i] + h[kGmC2 + i];
-    const double inv = h[kGmInv], rho = std::sqrt(h[kGmRho]);
-    if (!std::isfinite(inv) || !std::isfinite(rho)) return gfail(G, SEM_ERR_NAN, "non-finite Arnoldi vector");
-    if (inv == 0.0 || rho == 0.0) {                 // w lies in span(V): breakdown
-        *hn = 0.0;
-        return SEM_OK;
-    }
-    const double tol = std::is_same<T, double>::value ? 1e-11 : 1e-5;
-    if (std::fabs(rho - 1.0) > tol) {
-        const double r = 1.0 / rho;
-        SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMisc + 1, &r, 8, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL((k_gm_scale<T, T>), dim3(gm_grid(c->n_unique)), dim3(kGmBlock), 0, s,
-                           c->n_unique, (const T *)Vl, Vl, (const double *)(G->coef + kGmMisc + 1), 0);
-        SEM_HIP(c, hipGetLastError());
-        *hn = rho / inv;
-    } else {
-        *hn = 1.0 / inv;
-    }
-    return SEM_OK;
+static hipError_t gm_first_step(sem_gmres G, const T *V0, const T *w, T *out, hipStream_t s) {
+    static int per_cu = 0;
+    const int64_t n = G->ctx->n_unique;
+    hipError_t e = GmDots<1, T>::run(G, V0, w, s);
+    if (e != hipSuccess) return e;
+    const unsigned g = resident_grid(k_gm_orth_scale<1, T>, per_cu, G->ctx->num_cus, n / 2);
+    hipLaunchKernelGGL((k_gm_orth_scale<1, T>), dim3(g), dim3(kGmBlock), 0, s, n, G->ld, V0,
+                       (const double *)G->coef, w, out, G->part, G->coef + kGmScal + 2);
+    return hipGetLastError();
 }
 
 // Host copy of coef[0] after the stream has reached it.
@@ -1334,7 +1391,8 @@ static sem_status fgmres(sem_gmres G, int prec, const T *b, T *x, bool x_zero, d
     *res_out = beta;
     if (!std::isfinite(beta)) return gfail(G, SEM_ERR_NAN, "non-finite residual");
     if (beta <= atol) return SEM_OK;
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    std::vector<double> H((size_t)(m + 1) * m), Hr((size_t)(m + 1) * m), hs(m), cs(m), sn(m),
+        g(m + 1), y(m);
     for (;;) {
         const double inv = 1.0 / beta;                 // V_0 = r / beta
         SEM_HIP(c, hipMemcpyAsync(G->coef + kGmMisc + 1, &inv, 8, hipMemcpyHostToDevice, s));
@@ -1343,37 +1401,105 @@ static sem_status fgmres(sem_gmres G, int prec, const T *b, T *x, bool x_zero, d
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
+        std::fill(Hr.begin(), Hr.end(), 0.0);
+        // Column k of the Hessenberg matrix is complete once the vector in
+        // slot k+1 has had its second projection (during step k+1, or in a
+        // closing sweep): then it is rotated into H and g.
+        auto rotate = [&](int k) {
+            for (int i = 0; i <= k + 1; ++i) H[(size_t)i * m + k] = Hr[(size_t)i * m + k];
+            for (int i = 0; i < k; ++i) {
+                const double a = H[(size_t)i * m + k], bq = H[(size_t)(i + 1) * m + k];
+                H[(size_t)i * m + k] = cs[i] * a + sn[i] * bq;
+                H[(size_t)(i + 1) * m + k] = -sn[i] * a + cs[i] * bq;
+            }
+            const double a = H[(size_t)k * m + k], bq = H[(size_t)(k + 1) * m + k];
+            const double den = std::hypot(a, bq);
+            cs[k] = den > 0 ? a / den : 1.0;
+            sn[k] = den > 0 ? bq / den : 0.0;
+            H[(size_t)k * m + k] = den;
+            H[(size_t)(k + 1) * m + k] = 0.0;
+            g[k + 1] = -sn[k] * g[k];
+            g[k] = cs[k] * g[k];
+        };
+        // vector in slot k+1 = (beta v_{k+1} + V q) / c_k: add its second
+        // projection to column k (hs[k] = 1/c_k) and complete the column
+        auto complete = [&](int k, const double *q, double beta_k) {
+            for (int i = 0; i <= k; ++i) Hr[(size_t)i * m + k] += q[i] * hs[k];
+            Hr[(size_t)(k + 1) * m + k] = beta_k * hs[k];
+            rotate(k);
+        };
+        // residual norm if the provisional column k were complete
+        auto estimate = [&](int k) {
+            double col[kGmMaxVec + 1];
+            for (int i = 0; i <= k; ++i) col[i] = Hr[(size_t)i * m + k];
+            col[k + 1] = hs[k];                          // provisional h_{k+1,k}
+            for (int i = 0; i < k; ++i) {
+                const double a = col[i], bq = col[i + 1];
+                col[i] = cs[i] * a + sn[i] * bq;
+                col[i + 1] = -sn[i] * a + cs[i] * bq;
+            }
+            const double den = std::hypot(col[k], col[k + 1]);
+            return den > 0 ? std::fabs(col[k + 1] / den * g[k]) : std::fabs(g[k]);
+        };
         int jdone = 0;
         for (int j = 0; j < m; ++j) {
-            T *Vj = V + (size_t)j * ld, *Zj = Z + (size_t)j * ld;
+            T *Vj = V + (size_t)j * ld, *Zj = Z + (size_t)j * ld, *Vn = V + (size_t)(j + 1) * ld;
             e = precondition<T>(G, Vj, Zj, SEM_PC_SCHWARZ | SEM_PC_COARSE, s);
             if (e) return e;
             e = apply_A<T>(G, prec, Zj, w, s);
             if (e) return e;
-            double hcol[kGmMaxVec + 1] = {};
-            double hn = 0.0;
-            e = gm_arnoldi<T>(G, j + 1, V, w, V + (size_t)(j + 1) * ld, hcol, &hn, s);
-            if (e) return e;
-            // Givens rotations on column j of H
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i];
-            H[(size_t)(j + 1) * m + j] = hn;
-            for (int i = 0; i < j; ++i) {
-                const double a = H[(size_t)i * m + j], bq = H[(size_t)(i + 1) * m + j];
-                H[(size_t)i * m + j] = cs[i] * a + sn[i] * bq;
-                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bq;
+            double d[kGmScal + 3 - kGmD];
+            if (j == 0) {
+                SEM_HIP(c, gm_first_step<T>(G, V, w, Vn, s));
+                double d0[2], cc = 0.0;
+                SEM_HIP(c, hipMemcpyAsync(d0, G->coef, 16, hipMemcpyDeviceToHost, s));
+                SEM_HIP(c, hipMemcpyAsync(&cc, G->coef + kGmScal + 2, 8, hipMemcpyDeviceToHost, s));
+                SEM_HIP(c, hipStreamSynchronize(s));
+                if (!std::isfinite(d0[0]) || !std::isfinite(d0[1]) || !std::isfinite(cc))
+                    return gfail(G, SEM_ERR_NAN, "non-finite Arnoldi vector");
+                Hr[0] = d0[0];
+                hs[0] = cc > 0 ? 1.0 / cc : 0.0;
+            } else {
+                const int L = j;
+                SEM_HIP(c, (gm_dispatch<GmDots2, T>(L, G, (const T *)V, (const T *)Vj, (const T *)w, s)));
+                SEM_HIP(c, (gm_dispatch<GmUpdate2, T>(L, G, (const T *)V, Vj, (const T *)w, Vn, s)));
+                SEM_HIP(c, hipMemcpyAsync(d, G->coef + kGmD, sizeof(d), hipMemcpyDeviceToHost, s));
+                SEM_HIP(c, hipStreamSynchronize(s));
+                const double *sc = d + (kGmScal - kGmD);
+                for (int q = 0; q < 2 * L + 3; ++q)
+                    if (!std::isfinite(d[q])) return gfail(G, SEM_ERR_NAN, "non-finite Arnoldi vector");
+                complete(j - 1, d, sc[0]);               // q = d[0..L), beta = sc[0]
+                if (sc[0] == 0.0) {                      // the vector lies in span(V): done
+                    jdone = j;
+                    info->rel_residual = std::fabs(g[j]);
+                    break;
+                }
+                for (int q = 0; q < L; ++q) Hr[(size_t)q * m + j] = d[L + q];
+                Hr[(size_t)j * m + j] = sc[1];
+                hs[j] = sc[2] > 0 ? 1.0 / sc[2] : 0.0;
             }
-            const double a = H[(size_t)j * m + j], bq = H[(size_t)(j + 1) * m + j];
-            const double den = std::hypot(a, bq);
-            cs[j] = den > 0 ? a / den : 1.0;
-            sn[j] = den > 0 ? bq / den : 0.0;
-            H[(size_t)j * m + j] = den;
-            H[(size_t)(j + 1) * m + j] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
             info->iterations += 1;
             jdone = j + 1;
-            info->rel_residual = std::fabs(g[j + 1]);
-            if (std::fabs(g[j + 1]) <= atol || info->iterations >= max_iter || hn == 0) break;
+            const double est = estimate(j);
+            info->rel_residual = est;
+            if (est <= atol || info->iterations >= max_iter || j + 1 == m || hs[j] == 0) {
+                // closing sweep: second projection of the vector in slot j+1
+                double q[kGmMaxVec + 1] = {}, beta_j = 0.0;
+                if (hs[j] > 0) {
+                    SEM_HIP(c, (gm_dispatch<GmDots, T>(j + 1, G, (const T *)V, (const T *)Vn, s)));
+                    SEM_HIP(c, hipMemcpyAsync(q, G->coef, 8 * (j + 2), hipMemcpyDeviceToHost, s));
+                    SEM_HIP(c, hipStreamSynchronize(s));
+                    double qq = 0.0;
+                    for (int i = 0; i <= j; ++i) qq += q[i] * q[i];
+                    const double b2 = q[j + 1] - qq;
+                    if (!std::isfinite(b2)) return gfail(G, SEM_ERR_NAN, "non-finite Arnoldi vector");
+                    beta_j = b2 > 0 ? std::sqrt(b2) : 0.0;
+                    q[j + 1] = 0.0;
+                }
+                complete(j, q, beta_j);
+                info->rel_residual = std::fabs(g[j + 1]);
+                break;
+            }
         }
         // y = H^-1 g (upper triangular), x += Z y
         for (int i = jdone - 1; i >= 0; --i) {
