@@ -496,7 +496,19 @@ sem_status sem_batch_bind_workspace(sem_batch batch, void *dev_ptr, size_t bytes
  * of order N gets threads/(N+1)^2 elements per workgroup and workgroups of
  * exactly that many elements' lanes.  grid_cap as for sem_tile. */
 sem_status sem_batch_set_tile(sem_batch batch, const sem_tile *tile, sem_stream stream);
-/* Times every admissible batch tile (hipEvents) and keeps the fastest. */
+/* Tile of the problems of one order N only (the per-order tile; N must be
+ * the order of some problem of the batch, SEM_ERR_INVALID otherwise): the
+ * thread budget is a multiple of 64 in [(N+1)^2, 256].  sem_batch_set_tile
+ * sets every order's tile to the same value. */
+sem_status sem_batch_set_order_tile(sem_batch batch, int N, const sem_tile *tile,
+                                    sem_stream stream);
+sem_status sem_batch_get_order_tile(sem_batch batch, int N, sem_tile *tile);
+/* Tunes one tile per order present (the operator pass of each order is its
+ * own launch, Sec. II-A per element): for each order, heaviest first, every
+ * admissible (thread budget, grid cap) is timed over the whole operator
+ * pass (hipEvents) with the other orders' tiles held, and the fastest is
+ * kept.  *best receives the tile of the highest order, *best_ms the mean
+ * time of one operator pass with all tuned tiles. */
 sem_status sem_batch_autotune(sem_batch batch, int reps, sem_tile *best, double *best_ms,
                               sem_stream stream);
 /* rhs[p], x[p]: device vectors of problem p (solver order, FP64, 16-byte

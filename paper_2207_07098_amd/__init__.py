@@ -107,6 +107,7 @@ EXPORTS = ["sem_gll", "sem_setup", "sem_free", "sem_last_error", "sem_query",
            "sem_autotune", "sem_batch_create", "sem_batch_free", "sem_batch_last_error",
            "sem_batch_workspace_size", "sem_batch_bind_workspace", "sem_batch_set_tile",
            "sem_batch_autotune", "sem_batch_solve", "sem_cg_solve_static",
+           "sem_batch_set_order_tile", "sem_batch_get_order_tile",
            "sem_set_helmholtz", "sem_proj_create", "sem_proj_free", "sem_proj_last_error",
            "sem_proj_workspace_size", "sem_proj_bind_workspace", "sem_proj_reset",
            "sem_proj_size", "sem_proj_solve", "sem_gmres_create", "sem_gmres_free",
@@ -176,6 +177,8 @@ def lib():
         "sem_batch_bind_workspace": ([P, P, ctypes.c_size_t, P], i32),
         "sem_batch_set_tile": ([P, P, P], i32),
         "sem_batch_autotune": ([P, i32, P, P, P], i32),
+        "sem_batch_set_order_tile": ([P, i32, P, P], i32),
+        "sem_batch_get_order_tile": ([P, i32, P], i32),
         "sem_batch_solve": ([P, P, P, P, P, P], i32),
     }
     for name, (args, res) in sig.items():
@@ -631,12 +634,25 @@ class Batch:
         t = Tile(threads, grid_cap, 0, 0)
         self._check(lib().sem_batch_set_tile(self._b, ctypes.byref(t), _stream_handle()))
 
+    def set_order_tile(self, N: int, threads=256, grid_cap=0):
+        t = Tile(threads, grid_cap, 0, 0)
+        self._check(lib().sem_batch_set_order_tile(self._b, N, ctypes.byref(t), _stream_handle()))
+
+    def order_tile(self, N: int):
+        t = Tile()
+        self._check(lib().sem_batch_get_order_tile(self._b, N, ctypes.byref(t)))
+        return {"threads": t.elements_per_block, "grid_cap": t.grid_cap}
+
+    def orders(self):
+        return sorted({o.N for o in self.ops})
+
     def autotune(self, reps: int = 5):
+        """One tile per order present; returns ({N: tile}, ms of one operator pass)."""
         best = Tile()
         ms = ctypes.c_double()
         self._check(lib().sem_batch_autotune(self._b, reps, ctypes.byref(best), ctypes.byref(ms),
                                              _stream_handle()))
-        return {"threads": best.elements_per_block, "grid_cap": best.grid_cap}, ms.value
+        return {N: self.order_tile(N) for N in self.orders()}, ms.value
 
     def solve(self, rhs, xs=None, tol: float = 1e-8, max_iter: int = 100000,
               check_every: int = 50, use_graph: bool = True, raise_on_error: bool = True):

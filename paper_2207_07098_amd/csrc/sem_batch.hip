@@ -20,7 +20,11 @@ struct sem_batch_s {
     size_t ws_bytes = 0;
     size_t off_probs = 0, off_ax = 0, off_vec = 0, off_axp = 0, off_vecp = 0, off_st = 0;
     int cap_ax = 0, cap_vec = 0;           // capacity of the item tables
-    int threads = 256, grid_cap = 0;       // tile
+    // operator tile of each order present: thread budget per workgroup (a
+    // problem of order N gets threads/(N+1)^2 elements per workgroup) and
+    // grid cap
+    int threads[kMaxN1 + 1] = {}, grid_cap[kMaxN1 + 1] = {};
+    bool present[kMaxN1 + 1] = {};
     std::vector<BatchProb> probs;
     std::vector<BatchAxItem> ax;
     std::vector<BatchVecItem> vec;
@@ -51,7 +55,7 @@ static void build_items(sem_batch b) {
         const int p = o.second;
         sem_ctx c = b->ctxs[p];
         BatchProb &pb = b->probs[p];
-        pb.epb = std::max(1, b->threads / (c->n1 * c->n1));
+        pb.epb = std::max(1, b->threads[c->n1] / (c->n1 * c->n1));
         const int64_t ngroups = (c->E + pb.epb - 1) / pb.epb;
         pb.ax_begin = (int)b->ax.size();
         for (int64_t g = 0; g < ngroups; ++g) b->ax.push_back({p, 0, g});
@@ -76,10 +80,12 @@ static void fill_launch(sem_batch b) {
     bl.nprob = b->nprob;
     bl.ax_partials = reinterpret_cast<double *>(b->ws + b->off_axp);
     bl.vec_partials = reinterpret_cast<double *>(b->ws + b->off_vecp);
-    bl.threads = b->threads;
+    for (int n1 = 0; n1 <= sem::kMaxN1; ++n1) {
+        bl.threads[n1] = b->threads[n1];
+        bl.grid_cap[n1] = b->grid_cap[n1];
+    }
     const int ncu = b->ctxs[0]->num_cus;
-    bl.ax_grid = b->grid_cap > 0 ? std::min(b->grid_cap, bl.n_ax) : bl.n_ax;
-    bl.grid_cap = b->grid_cap;
+    bl.ax_grid = bl.n_ax;
     // items are ordered by decreasing order: one contiguous range per order
     for (int n1 = 0; n1 <= sem::kMaxN1; ++n1) bl.ax_lo[n1] = bl.ax_hi[n1] = 0;
     for (int w = 0; w < bl.n_ax; ++w) {
@@ -134,6 +140,7 @@ extern "C" sem_status sem_batch_create(const sem_ctx *ctxs, int nprob, sem_batch
         }
         b->max_n1 = std::max(b->max_n1, c->n1);
         b->max_c = std::max(b->max_c, c->n1 * c->n1);
+        b->present[c->n1] = true;
         BatchProb &pb = b->probs[p];
         std::memset(&pb, 0, sizeof(pb));
         pb.G = c->ws + c->L.G[0];
@@ -149,7 +156,10 @@ extern "C" sem_status sem_batch_create(const sem_ctx *ctxs, int nprob, sem_batch
         pb.n_u = c->n_unique;
         pb.n1 = c->n1;
     }
-    b->threads = 256;                      // thread budget per workgroup (tunable)
+    for (int n1 = 2; n1 <= kMaxN1; ++n1) {  // 256 threads, one workgroup per group
+        b->threads[n1] = 256;
+        b->grid_cap[n1] = 0;
+    }
     // capacities: one element per group is the largest possible table
     int64_t nax = 0, nvec = 0;
     for (int p = 0; p < nprob; ++p) {
@@ -200,22 +210,54 @@ extern "C" sem_status sem_batch_bind_workspace(sem_batch b, void *dev, size_t by
     b->ws_bytes = bytes;
     for (int p = 0; p < b->nprob; ++p)
         b->probs[p].st = reinterpret_cast<CgState *>(b->ws + b->off_st) + p;
-    const size_t lds = batch_lds_bytes(b->threads, b->max_n1);
-    if (lds > b->ctxs[0]->max_lds) return bfail(b, SEM_ERR_UNSUPPORTED, "batch tile exceeds LDS");
+    for (int n1 = 2; n1 <= kBatchMaxN1; ++n1)
+        if (b->present[n1] && batch_lds_bytes_n1(b->threads[n1], n1) > b->ctxs[0]->max_lds)
+            return bfail(b, SEM_ERR_UNSUPPORTED, "batch tile exceeds LDS");
     return upload_tables(b, (hipStream_t)stream);
+}
+
+// A tile is admissible for order n1 when its thread budget is a multiple of
+// 64 in [(N+1)^2, 256], its grid cap is not negative and its LDS fits.
+static bool order_tile_ok(sem_batch b, int n1, const sem_tile &t) {
+    const int thr = t.elements_per_block;
+    return thr >= n1 * n1 && thr <= 256 && (thr % 64) == 0 && t.grid_cap >= 0 &&
+           batch_lds_bytes_n1(thr, n1) <= b->ctxs[0]->max_lds;
 }
 
 extern "C" sem_status sem_batch_set_tile(sem_batch b, const sem_tile *t, sem_stream stream) {
     if (!b || !t || !b->ws) return fail(nullptr, SEM_ERR_INVALID, "bad argument");
-    const int thr = t->elements_per_block;   // for a batch: threads per workgroup
-    if (thr < b->max_c || thr > 256 || (thr % 64) || t->grid_cap < 0)
-        return bfail(b, SEM_ERR_INVALID, "batch tile: threads must be a multiple of 64 in "
-                                         "[max (N+1)^2, 256]");
-    if (batch_lds_bytes(thr, b->max_n1) > b->ctxs[0]->max_lds)
-        return bfail(b, SEM_ERR_INVALID, "batch tile exceeds LDS");
-    b->threads = thr;
-    b->grid_cap = t->grid_cap;
+    for (int n1 = 2; n1 <= kBatchMaxN1; ++n1)
+        if (b->present[n1] && !order_tile_ok(b, n1, *t))
+            return bfail(b, SEM_ERR_INVALID, "batch tile: threads must be a multiple of 64 in "
+                                             "[max (N+1)^2, 256] and fit in LDS");
+    for (int n1 = 2; n1 <= kBatchMaxN1; ++n1) {
+        b->threads[n1] = t->elements_per_block;
+        b->grid_cap[n1] = t->grid_cap;
+    }
     return upload_tables(b, (hipStream_t)stream);
+}
+
+extern "C" sem_status sem_batch_set_order_tile(sem_batch b, int N, const sem_tile *t,
+                                               sem_stream stream) {
+    if (!b || !t || !b->ws) return fail(nullptr, SEM_ERR_INVALID, "bad argument");
+    const int n1 = N + 1;
+    if (n1 < 2 || n1 > kBatchMaxN1 || !b->present[n1])
+        return bfail(b, SEM_ERR_INVALID, "no problem of order " + std::to_string(N) + " in the batch");
+    if (!order_tile_ok(b, n1, *t))
+        return bfail(b, SEM_ERR_INVALID, "batch tile: threads must be a multiple of 64 in "
+                                         "[(N+1)^2, 256] and fit in LDS");
+    b->threads[n1] = t->elements_per_block;
+    b->grid_cap[n1] = t->grid_cap;
+    return upload_tables(b, (hipStream_t)stream);
+}
+
+extern "C" sem_status sem_batch_get_order_tile(sem_batch b, int N, sem_tile *t) {
+    if (!b || !t) return fail(nullptr, SEM_ERR_INVALID, "bad argument");
+    const int n1 = N + 1;
+    if (n1 < 2 || n1 > kBatchMaxN1 || !b->present[n1])
+        return bfail(b, SEM_ERR_INVALID, "no problem of order " + std::to_string(N) + " in the batch");
+    *t = sem_tile{b->threads[n1], b->grid_cap[n1], 0, 0};
+    return SEM_OK;
 }
 
 extern "C" sem_status sem_batch_autotune(sem_batch b, int reps, sem_tile *best, double *best_ms,
@@ -233,38 +275,58 @@ extern "C" sem_status sem_batch_autotune(sem_batch b, int reps, sem_tile *best, 
     std::vector<hipEvent_t> ev(2 * reps);
     for (auto &e : ev) SEM_HIP(nullptr, hipEventCreate(&e));
     const int ncu = b->ctxs[0]->num_cus;
-    double bms = INFINITY;
-    sem_tile bt{b->threads, b->grid_cap, 0, 0};
-    for (int thr = 64; thr <= 256; thr += 64) {
-        if (thr < b->max_c || batch_lds_bytes(thr, b->max_n1) > b->ctxs[0]->max_lds) continue;
-        for (int cap : {0, 2 * ncu, 4 * ncu, 8 * ncu}) {
-            sem_tile t{thr, cap, 0, 0};
-            sem_status st = sem_batch_set_tile(b, &t, stream);
-            if (st) return st;
-            for (int r = 0; r < 2; ++r) SEM_HIP(nullptr, launch_batch_ax_only(b->bl, s));
-            for (int r = 0; r < reps; ++r) {
-                for (const BatchProb &pb : b->probs)
-                    SEM_HIP(nullptr, launch_fill(pb.w, pb.n_bnd, 0.0, s));
-                SEM_HIP(nullptr, hipEventRecord(ev[2 * r], s));
-                SEM_HIP(nullptr, launch_batch_ax_only(b->bl, s));
-                SEM_HIP(nullptr, hipEventRecord(ev[2 * r + 1], s));
-            }
-            SEM_HIP(nullptr, hipEventSynchronize(ev[2 * reps - 1]));
-            double ms = 0.0;
-            for (int r = 0; r < reps; ++r) {
-                float m = 0.f;
-                SEM_HIP(nullptr, hipEventElapsedTime(&m, ev[2 * r], ev[2 * r + 1]));
-                ms += m;
-            }
-            if (ms / reps < bms) {
-                bms = ms / reps;
-                bt = t;
-            }
+    // mean time of one operator pass over all problems
+    auto time_pass = [&](double &ms_out) -> sem_status {
+        for (int r = 0; r < 2; ++r) SEM_HIP(nullptr, launch_batch_ax_only(b->bl, s));
+        for (int r = 0; r < reps; ++r) {
+            for (const BatchProb &pb : b->probs) SEM_HIP(nullptr, launch_fill(pb.w, pb.n_bnd, 0.0, s));
+            SEM_HIP(nullptr, hipEventRecord(ev[2 * r], s));
+            SEM_HIP(nullptr, launch_batch_ax_only(b->bl, s));
+            SEM_HIP(nullptr, hipEventRecord(ev[2 * r + 1], s));
         }
+        SEM_HIP(nullptr, hipEventSynchronize(ev[2 * reps - 1]));
+        double ms = 0.0;
+        for (int r = 0; r < reps; ++r) {
+            float m = 0.f;
+            SEM_HIP(nullptr, hipEventElapsedTime(&m, ev[2 * r], ev[2 * r + 1]));
+            ms += m;
+        }
+        ms_out = ms / reps;
+        return SEM_OK;
+    };
+    // one tile per order: each order present, heaviest first, takes the
+    // candidate that makes the whole pass fastest with the others held
+    double bms = INFINITY;
+    for (int n1 = kBatchMaxN1; n1 >= 2; --n1) {
+        if (!b->present[n1]) continue;
+        sem_tile keep{b->threads[n1], b->grid_cap[n1], 0, 0};
+        double keep_ms = INFINITY;
+        for (int thr = 64; thr <= 256; thr += 64)
+            for (int cap : {0, 2 * ncu, 4 * ncu, 8 * ncu}) {
+                const sem_tile t{thr, cap, 0, 0};
+                if (!order_tile_ok(b, n1, t)) continue;
+                b->threads[n1] = thr;
+                b->grid_cap[n1] = cap;
+                sem_status st = upload_tables(b, s);
+                if (st) return st;
+                double ms = 0.0;
+                st = time_pass(ms);
+                if (st) return st;
+                if (ms < keep_ms) {
+                    keep_ms = ms;
+                    keep = t;
+                }
+            }
+        b->threads[n1] = keep.elements_per_block;
+        b->grid_cap[n1] = keep.grid_cap;
+        bms = keep_ms;
     }
+    sem_status st0 = upload_tables(b, s);
+    if (st0) return st0;
+    st0 = time_pass(bms);
+    if (st0) return st0;
+    const sem_tile bt{b->threads[b->max_n1], b->grid_cap[b->max_n1], 0, 0};
     for (auto &e : ev) (void)hipEventDestroy(e);
-    sem_status st = sem_batch_set_tile(b, &bt, stream);
-    if (st) return st;
     if (best) *best = bt;
     if (best_ms) *best_ms = bms;
     return SEM_OK;

@@ -203,12 +203,12 @@ struct BatchLaunch {             // host-side description of one batch launch
     const BatchVecItem *vec_items;
     int n_ax, n_vec, nprob;
     double *ax_partials, *vec_partials;
-    int threads, ax_grid, vec_grid, max_n1;
-    int grid_cap;
+    int ax_grid, vec_grid, max_n1;
     int ax_lo[sem::kMaxN1 + 1], ax_hi[sem::kMaxN1 + 1];   // operator items of each order
+    int threads[sem::kMaxN1 + 1], grid_cap[sem::kMaxN1 + 1];  // operator tile of each order
 };
 constexpr int kBatchMaxN1 = 10;
-size_t batch_lds_bytes(int threads, int max_n1);
+size_t batch_lds_bytes_n1(int threads, int n1);
 hipError_t launch_batch_iteration(const BatchLaunch &bl, hipStream_t s);
 hipError_t launch_batch_begin(const BatchLaunch &bl, hipStream_t s);
 hipError_t launch_batch_ax_only(const BatchLaunch &bl, hipStream_t s);

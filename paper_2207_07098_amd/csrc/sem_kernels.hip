@@ -1863,25 +1863,19 @@ static BatchArgs batch_args(const BatchLaunch &bl) {
     return A;
 }
 
-static size_t batch_lds_bytes_n1(int threads, int n1) {
+size_t batch_lds_bytes_n1(int threads, int n1) {
     const int C = n1 * n1;
     const int nslots = std::max(1, threads / C);    // the problems' elements per group
     return ((size_t)nslots * 3 * n1 * n1 * (n1 + 1) + C) * sizeof(double);
-}
-
-size_t batch_lds_bytes(int threads, int max_n1) {
-    size_t best = 0;
-    for (int n1 = 2; n1 <= max_n1; ++n1) best = std::max(best, batch_lds_bytes_n1(threads, n1));
-    return best;
 }
 
 static void launch_batch_operator(const BatchLaunch &bl, const BatchArgs &A, hipStream_t s) {
     for (int n1 = kBatchMaxN1; n1 >= 2; --n1) {
         const int lo = bl.ax_lo[n1], hi = bl.ax_hi[n1];
         if (hi <= lo) continue;
-        const int grid = bl.grid_cap > 0 ? std::min(bl.grid_cap, hi - lo) : hi - lo;
-        const size_t lds = batch_lds_bytes_n1(bl.threads, n1);
-        const int threads = std::max(1, bl.threads / (n1 * n1)) * n1 * n1;   // epb slots
+        const int grid = bl.grid_cap[n1] > 0 ? std::min(bl.grid_cap[n1], hi - lo) : hi - lo;
+        const size_t lds = batch_lds_bytes_n1(bl.threads[n1], n1);
+        const int threads = std::max(1, bl.threads[n1] / (n1 * n1)) * n1 * n1;   // epb slots
         switch (n1) {
 #define SEM_BAXN(n)                                                                       \
     case n:                                                                               \

@@ -65,12 +65,41 @@ def test_batch_tiles_and_autotune_agree():
     ref, _ = batch.solve(rhs, tol=1e-10)
     ref = [r.clone() for r in ref]
     best, ms = batch.autotune(reps=3)
-    assert ms > 0 and best["threads"] % 64 == 0
+    assert ms > 0 and set(best) == set(batch.orders())
+    for N, t in best.items():
+        assert t["threads"] % 64 == 0 and (N + 1) ** 2 <= t["threads"] <= 256
+        assert batch.order_tile(N) == t
     for thr, cap in ((128, 0), (256, 64)):
         batch.set_tile(thr, cap)
+        assert all(batch.order_tile(N) == {"threads": thr, "grid_cap": cap} for N in batch.orders())
         xs, infos = batch.solve(rhs, tol=1e-10)
         for a, b_ in zip(xs, ref):
             assert relerr(a.cpu().numpy(), b_.cpu().numpy()) < 1e-7
+
+
+def test_batch_tile_per_order():
+    """Each order's operator launch takes its own tile; solutions do not
+    depend on it; an order absent from the batch or a tile below (N+1)^2
+    threads is rejected."""
+    probs = _problems(4, seed=7, orders=(5, 7))
+    batch = sem.Batch([p[0] for p in probs])
+    rhs = [p[4] for p in probs]
+    ref, _ = batch.solve(rhs, tol=1e-10)
+    ref = [r.clone() for r in ref]
+    assert batch.orders() == sorted({p[0].N for p in probs})
+    for N, thr, cap in ((5, 64, 0), (5, 256, 512), (7, 192, 0), (7, 64, 1024)):
+        if N not in batch.orders():
+            continue
+        batch.set_order_tile(N, thr, cap)
+        assert batch.order_tile(N) == {"threads": thr, "grid_cap": cap}
+        xs, _ = batch.solve(rhs, tol=1e-10)
+        for a, b_ in zip(xs, ref):
+            assert relerr(a.cpu().numpy(), b_.cpu().numpy()) < 1e-7
+    absent = next(N for N in range(2, 10) if N not in batch.orders())
+    with pytest.raises(sem.SemError):
+        batch.set_order_tile(absent, 128, 0)
+    with pytest.raises(sem.SemError):                        # not a multiple of 64
+        batch.set_order_tile(batch.orders()[0], 96, 0)
 
 
 def test_batch_with_zero_rhs_and_order_limit():
