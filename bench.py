@@ -293,6 +293,10 @@ def bench_ogrid(args):
            "elements": op.E, "n_unique": op.n_unique, "setup_seconds": setup, "tile": best,
            "kernel_ms": k_ms, "GDOF_per_s_kernel": op.n_unique / (k_ms * 1e-3) / 1e9,
            "roofline_frac": B / (k_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "bytes_per_launch": B}
+    traffic, src = recorded_traffic("ogrid_N7", kernel_name(best, 7), best)
+    out["traffic"] = traffic
+    out["traffic_source"] = src
+    out["traffic_over_algorithmic"] = traffic / B if traffic else None
     log("ogrid kernel %.3f ms, %.1f%% of 8 TB/s" % (k_ms, 100 * out["roofline_frac"]))
     del u, y
     f = F.random_unique(op.n_unique, w.seed)
