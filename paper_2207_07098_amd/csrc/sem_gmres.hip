@@ -107,6 +107,11 @@ struct FdmParams {
     const double *lam;        // [E][3][NE]
     const int32_t *fmap;      // [E][NE][NE^2] box gather map: solver index or -1
     int64_t E;
+    // coarse restriction fused into the gather (b0 null: not done here)
+    const uint16_t *own;      // [E][NE^2] bit c: box point (a, b, c) is an owned node of e
+    double *b0;               // coarse right-hand side, summed atomically
+    const int32_t *cmap;      // [E][8] coarse index of each element corner or -1
+    const double *xi;         // GLL nodes [N+1]
 };
 
 // Box gather map of every element, built once when the workspace is bound:
@@ -115,13 +120,28 @@ struct FdmParams {
 // -1 where the box holds no data (edges and corners of the extension).
 template <int NE>
 __global__ void __launch_bounds__((NE * NE + 63) / 64 * 64)
-k_fdm_map(const int32_t *__restrict__ ghost, const int32_t *__restrict__ bmap, int64_t E,
-          int64_t n_bnd, int nb, int32_t *__restrict__ fmap) {
+k_fdm_map(const int32_t *__restrict__ ghost, const int32_t *__restrict__ bmap,
+          const uint8_t *__restrict__ owner, int64_t E, int64_t n_bnd, int nb,
+          int32_t *__restrict__ fmap, uint16_t *__restrict__ own) {
     constexpr int C = NE * NE, N = NE - 3, n1 = NE - 2;
     const int64_t e = blockIdx.x;
     const int t = threadIdx.x;
     if (t >= C || e >= E) return;
     const int i = t % NE - 1, j = t / NE - 1;
+    // owned own points of the column: interior points, and on the element
+    // boundary the first copy of a non-Dirichlet node
+    uint32_t mask = 0;
+    if (i >= 0 && i <= N && j >= 0 && j <= N)
+        for (int k = 0; k <= N; ++k) {
+            const bool bnd = i == 0 || i == N || j == 0 || j == N || k == 0 || k == N;
+            bool take = true;
+            if (bnd) {
+                const int b = gm_bpos(i, j, k, N + 1);
+                take = bmap[e * nb + b] >= 0 && owner[e * nb + b];
+            }
+            if (take) mask |= 1u << (k + 1);
+        }
+    own[(size_t)e * C + t] = (uint16_t)mask;
     for (int c = 0; c < NE; ++c) {
         const int k = c - 1;
         const int oi = (i < 0 || i > N), oj = (j < 0 || j > N), ok = (k < 0 || k > N);
@@ -155,9 +175,20 @@ k_fdm(FdmParams<VT> P) {
     __shared__ double Sl[3][C];
     __shared__ double Ll[3][NE];
     __shared__ double box[NE][NE][NE + 1];        // [c][b][a], padded
+    __shared__ double red8[NT / 64][8];            // restriction: per-wave corner sums
     const int t = threadIdx.x;
     const bool lane_on = t < C;
     const int a = t % NE, b = t / NE;
+    // restriction weights of the lane's column in r and s: the linear shape
+    // functions of the element corners at the GLL node (zero off the element)
+    double wab[4] = {0.0, 0.0, 0.0, 0.0};
+    if (P.b0 && lane_on && a >= 1 && a <= NE - 2 && b >= 1 && b <= NE - 2) {
+        const double xa = P.xi[a - 1], xb = P.xi[b - 1];
+        const double fa[2] = {0.5 * (1.0 - xa), 0.5 * (1.0 + xa)};
+        const double fb[2] = {0.5 * (1.0 - xb), 0.5 * (1.0 + xb)};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) wab[q] = fa[q & 1] * fb[q >> 1];
+    }
     int32_t idx[NE], nidx[NE];
     double sreg[QS], lreg[QL];
     auto fetch = [&](int64_t e, int32_t (&ix)[NE], double (&sr)[QS], double (&lr)[QL]) {
@@ -197,7 +228,36 @@ k_fdm(FdmParams<VT> P) {
         fetch(e + gridDim.x, nidx, sreg, lreg);   // next element, in flight meanwhile
 #pragma unroll
         for (int c = 0; c < NE; ++c) v[c] = idx[c] >= 0 ? v[c] : 0.0;
+        if (P.b0) {
+            // P^T r over the element's owned points: sum over c of the t-shape
+            // functions times r, then the r, s weights; one wave sum per corner
+            const uint32_t om = lane_on ? P.own[(size_t)e * C + t] : 0u;
+            double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+            for (int c = 1; c <= NE - 2; ++c) {
+                const double xc = P.xi[c - 1];
+                const double vc = ((om >> c) & 1u) ? v[c] : 0.0;
+                t0 += 0.5 * (1.0 - xc) * vc;
+                t1 += 0.5 * (1.0 + xc) * vc;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                double sum = wab[q & 3] * ((q & 4) ? t1 : t0);
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+                if ((t & 63) == 0) red8[t >> 6][q] = sum;
+            }
+        }
         __syncthreads();
+        if (P.b0 && t == 0)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                double sum = 0.0;
+#pragma unroll
+                for (int wv = 0; wv < NT / 64; ++wv) sum += red8[wv][q];
+                const int32_t gc = P.cmap[e * 8 + q];
+                if (gc >= 0) atomicAdd(P.b0 + gc, sum);
+            }
         // forward: w = (S_t^T x S_s^T x S_r^T) v
         double w[NE];
 #pragma unroll
@@ -754,6 +814,7 @@ struct sem_gmres_s {
     int32_t *dghost = nullptr, *dcmap = nullptr;
     uint8_t *downer = nullptr;
     int32_t *dfmap = nullptr;
+    uint16_t *down = nullptr;
     int fdm_per_cu = 0;              // resident FDM workgroups per CU
     double *zs = nullptr, *b0 = nullptr, *x0 = nullptr;
     double *V = nullptr, *Z = nullptr, *w = nullptr, *r = nullptr;
@@ -1054,12 +1115,13 @@ static size_t gm_layout(sem_gmres G, size_t *off) {
     off[17] = take(4 * (size_t)c->n_unique);          // FP32 inner correction
     off[18] = take((size_t)E * c->nb);                // owner flags
     off[19] = take(4 * (size_t)E * NE * NE * NE);    // box gather map
+    off[20] = take(2 * (size_t)E * NE * NE);         // owned-point masks of the box columns
     return o;
 }
 
 extern "C" sem_status sem_gmres_workspace_size(sem_gmres G, size_t *bytes) {
     if (!G || !bytes) return gfail(G, SEM_ERR_INVALID, "null argument");
-    size_t off[20];
+    size_t off[21];
     *bytes = gm_layout(G, off);
     return SEM_OK;
 }
@@ -1067,7 +1129,7 @@ extern "C" sem_status sem_gmres_workspace_size(sem_gmres G, size_t *bytes) {
 extern "C" sem_status sem_gmres_bind_workspace(sem_gmres G, void *dev, size_t bytes,
                                                sem_stream stream) {
     if (!G || !dev) return gfail(G, SEM_ERR_INVALID, "null argument");
-    size_t off[20];
+    size_t off[21];
     const size_t need = gm_layout(G, off);
     if (bytes < need)
         return gfail(G, SEM_ERR_OOM, "workspace of " + std::to_string(bytes) + " bytes, need " +
@@ -1102,6 +1164,7 @@ extern "C" sem_status sem_gmres_bind_workspace(sem_gmres G, void *dev, size_t by
     G->d32 = reinterpret_cast<float *>(w + off[17]);
     G->downer = reinterpret_cast<uint8_t *>(w + off[18]);
     G->dfmap = reinterpret_cast<int32_t *>(w + off[19]);
+    G->down = reinterpret_cast<uint16_t *>(w + off[20]);
     SEM_HIP(c, hipMemcpyAsync(G->dS, G->S.data(), 8 * G->S.size(), hipMemcpyHostToDevice, s));
     SEM_HIP(c, hipMemcpyAsync(G->dlam, G->lam.data(), 8 * G->lam.size(), hipMemcpyHostToDevice, s));
     SEM_HIP(c, hipMemcpyAsync(G->dghost, G->ghost.data(), 4 * G->ghost.size(), hipMemcpyHostToDevice, s));
@@ -1113,8 +1176,8 @@ extern "C" sem_status sem_gmres_bind_workspace(sem_gmres G, void *dev, size_t by
 #define SEM_FMAP(ne)                                                                            \
     case ne:                                                                                    \
         hipLaunchKernelGGL(k_fdm_map<ne>, dim3((unsigned)c->E), dim3(((ne) * (ne) + 63) / 64 * 64), 0, \
-                           s, (const int32_t *)G->dghost, dptr<int32_t>(c, c->L.bmap), c->E,   \
-                           c->n_bnd, c->nb, G->dfmap);                                          \
+                           s, (const int32_t *)G->dghost, dptr<int32_t>(c, c->L.bmap),        \
+                           (const uint8_t *)G->downer, c->E, c->n_bnd, c->nb, G->dfmap, G->down); \
         break;
     switch (G->NE) {
         SEM_FMAP(5) SEM_FMAP(6) SEM_FMAP(7) SEM_FMAP(8) SEM_FMAP(9) SEM_FMAP(10) SEM_FMAP(11)
@@ -1135,9 +1198,14 @@ static sem_status precondition(sem_gmres G, const VT *r, VT *z, unsigned parts, 
     sem_ctx c = G->ctx;
     const int64_t n = c->n_unique;
     const bool local = parts & SEM_PC_SCHWARZ, coarse = parts & SEM_PC_COARSE;
+    // with both parts the coarse restriction is summed in the local-solve
+    // kernel's gather (the residual is read once)
+    const bool fused = local && coarse;
+    if (coarse) SEM_HIP(c, launch_fill(G->b0, G->coarse->n_unique, 0.0, s));
     if (local) {
         SEM_HIP(c, launch_fill(G->zs, n, 0.0, s));
-        FdmParams<VT> P{r, G->zs, G->dS, G->dlam, G->dfmap, c->E};
+        FdmParams<VT> P{r,       G->zs, G->dS, G->dlam, G->dfmap, c->E,
+                        G->down, fused ? G->b0 : nullptr, G->dcmap, G->dxi};
         // persistent: the workgroups resident at once, each taking every
         // grid-th element
 #define SEM_FDM(ne)                                                                          \
@@ -1167,12 +1235,11 @@ static sem_status precondition(sem_gmres G, const VT *r, VT *z, unsigned parts, 
                        dptr<int32_t>(c, c->L.csr_idx), dptr<int32_t>(c, c->L.bpos2l), G->dxi,
                        c->E, c->n_bnd, n, c->N, c->nb};
     if (coarse) {
-        SEM_HIP(c, launch_fill(G->b0, G->coarse->n_unique, 0.0, s));
 #define SEM_RESTRICT(n1)                                                                    \
     case n1:                                                                                \
         hipLaunchKernelGGL((k_restrict_e<n1, VT>), dim3((unsigned)c->E), dim3(64), 0, s, C); \
         break;
-        switch (c->n1) {
+        if (!fused) switch (c->n1) {
             SEM_RESTRICT(3) SEM_RESTRICT(4) SEM_RESTRICT(5) SEM_RESTRICT(6) SEM_RESTRICT(7)
             SEM_RESTRICT(8) SEM_RESTRICT(9) SEM_RESTRICT(10) SEM_RESTRICT(11) SEM_RESTRICT(12)
             SEM_RESTRICT(13) SEM_RESTRICT(14)
