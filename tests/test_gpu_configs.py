@@ -133,10 +133,11 @@ def test_ogrid_full_size_sampled_parity():
 
 def test_box48_solves_checked_by_oracle():
     """48^3 deformed box, N = 7, f = 3 sin x sin y sin z: FP64 PCG and FP64
-    refinement around FP32 / FP16 / BF16 inner PCG to a true relative
+    refinement around FP32 / FP16 / BF16 inner PCG, and the GMRES pressure
+    solver in FP64 and refined around FP32 / FP16, to a true relative
     residual of 1e-10.  The oracle evaluates each GPU solution's true
     residual with its own operator and numbering; no solve hands over to
-    FP64 PCG; the mixed solutions agree with the FP64 one."""
+    FP64; every solution agrees with the FP64 PCG one."""
     t0 = time.time()
     w = F.periodic_box_deformed(48, 7, tol=1e-10)
     op = sem.Operator(w.mesh, 7, precisions=("fp64", "fp32", "fp16", "bf16"), solver=True)
@@ -164,6 +165,21 @@ def test_box48_solves_checked_by_oracle():
         log("  %s: %d its, %.3fs, oracle true residual %.3e, vs FP64 %.2e, vs exact %.2e, "
             "fallback %s" % (prec, info["iterations"], info["seconds"], res, d64, dex,
                              info["fallback"]))
+        assert info["status"] == "SEM_OK" and info["fallback"] == "none", info
+        assert res <= 1.01e-10, (prec, res, info)
+        assert d64 < 1e-8 and dex < 1e-6
+    # the pressure solver (Sec. II-B): FP64 GMRES with the hybrid Schwarz
+    # preconditioner, and FP64 refinement around FP32-vector GMRES
+    ps = sem.PressureSolver(op, restart=30)
+    for prec in ("fp64", "fp32", "fp16"):
+        x, info = ps.solve(bd, tol=1e-10, precision=prec)
+        xc = x.cpu().numpy()[pos]
+        res = ora.true_residual(xc, b)
+        d64 = relerr(xc, x64)
+        dex = np.max(np.abs(xc - ue))
+        log("  GMRES %s: %d its, %.3fs, oracle true residual %.3e, vs FP64 PCG %.2e, vs exact "
+            "%.2e, fallback %s" % (prec, info["iterations"], info["seconds"], res, d64, dex,
+                                   info["fallback"]))
         assert info["status"] == "SEM_OK" and info["fallback"] == "none", info
         assert res <= 1.01e-10, (prec, res, info)
         assert d64 < 1e-8 and dex < 1e-6
