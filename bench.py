@@ -194,7 +194,7 @@ def bench_batch(args, emit=True):
     probs = F.batch_problems(args.nprob, seed=0)
     ops, rhs = [], []
     for bp in probs:
-        op = sem.Operator(F.batch_mesh(bp), bp.N, precisions=("fp64",), solver=True)
+        op = sem.Operator(F.batch_mesh(bp), bp.N, precisions=("fp64", "fp32"), solver=True)
         gid, pos, _, _ = op.numbering()
         f = F.random_unique(op.n_unique, bp.seed)
         fs = np.empty_like(f)
@@ -211,6 +211,17 @@ def bench_batch(args, emit=True):
     xs, infos = batch.solve(rhs, tol=1e-8)
     secs = infos[0]["seconds"]
     its = [i["iterations"] for i in infos]
+    # FP64 refinement around the batched FP32 PCG, same problems and tolerance
+    batch.solve(rhs, tol=1e-8, precision="fp32", raise_on_error=False)      # warm-up
+    _, minf = batch.solve(rhs, tol=1e-8, precision="fp32", raise_on_error=False)
+    msecs = minf[0]["seconds"]
+    mixed = {"seconds_all_converged": msecs, "speedup_vs_fp64_batch": secs / msecs,
+             "all_ok": all(i["status"] == "SEM_OK" for i in minf),
+             "max_true_rel_residual": max(i["true_rel_residual"] for i in minf),
+             "max_outer_iterations": max(i["outer_iterations"] for i in minf),
+             "inner_iterations_sum": sum(i["iterations"] for i in minf),
+             "fp64_handovers": sum(1 for i in minf if i["fallback"] != "none")}
+    log("batch fp32-refined", json.dumps(mixed))
     # sequential reference: one problem after another with the same solver
     t1 = time.perf_counter()
     seq_its = 0
@@ -227,7 +238,7 @@ def bench_batch(args, emit=True):
            "iterations": {"min": min(its), "max": max(its), "sum": sum(its)},
            "all_ok": all(i["status"] == "SEM_OK" for i in infos),
            "max_true_rel_residual": max(i["true_rel_residual"] for i in infos),
-           "operator_pass_ms": tms, "tile": tile,
+           "operator_pass_ms": tms, "tile": tile, "fp32_refined": mixed,
            "problems": len(ops), "elements": sum(o.E for o in ops),
            "unique_nodes": sum(o.n_unique for o in ops),
            "bytes_per_iteration_all_problems": B}

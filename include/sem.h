@@ -512,11 +512,20 @@ sem_status sem_batch_get_order_tile(sem_batch batch, int N, sem_tile *tile);
 sem_status sem_batch_autotune(sem_batch batch, int reps, sem_tile *best, double *best_ms,
                               sem_stream stream);
 /* rhs[p], x[p]: device vectors of problem p (solver order, FP64, 16-byte
- * aligned); x is output (zero initial guess).  opts.precision must be
- * SEM_FP64.  infos[p] receives each problem's result; problems whose FP64
- * true residual misses tol after the batched iteration are finished with
- * sem_cg_solve.  Returns SEM_OK if every problem converged, else the first
- * failing status.  Blocks until all problems are done. */
+ * aligned); x is output (zero initial guess).  opts.precision SEM_FP64:
+ * batched Jacobi-PCG.  SEM_FP32 (every context created with FP32 factors
+ * and solver vectors, else SEM_ERR_UNSUPPORTED): FP64 iterative refinement
+ * (Sec. VI-B lower precision) around the batched FP32 PCG -- each step forms
+ * all unfinished problems' FP64 residuals in one batched FP64 operator pass,
+ * solves the scaled residual equations together with the FP32 operators and
+ * vectors to opts.inner_tol, and adds the corrections in FP64; a problem
+ * whose correction does not halve its residual, whose inner solve breaks
+ * down, or that reaches opts.max_outer is finished by FP64 PCG from its
+ * current x (infos[p].fallback says why).  Other precisions:
+ * SEM_ERR_UNSUPPORTED.  infos[p] receives each problem's result; problems
+ * whose FP64 true residual misses tol after the batched iteration are
+ * finished with sem_cg_solve.  Returns SEM_OK if every problem converged,
+ * else the first failing status.  Blocks until all problems are done. */
 sem_status sem_batch_solve(sem_batch batch, const double *const *rhs, double *const *x,
                            const sem_solve_options *opts, sem_solve_info *infos,
                            sem_stream stream);

@@ -655,8 +655,11 @@ class Batch:
         return {N: self.order_tile(N) for N in self.orders()}, ms.value
 
     def solve(self, rhs, xs=None, tol: float = 1e-8, max_iter: int = 100000,
-              check_every: int = 50, use_graph: bool = True, raise_on_error: bool = True):
-        """rhs: list of device vectors (solver order).  Returns (xs, infos)."""
+              check_every: int = 50, use_graph: bool = True, raise_on_error: bool = True,
+              precision: str = "fp64", inner_tol: float = 1e-4, max_outer: int = 50):
+        """rhs: list of device vectors (solver order).  precision "fp32": FP64
+        refinement around the batched FP32 PCG (the operators need FP32
+        factors).  Returns (xs, infos)."""
         n = len(self.ops)
         if xs is None:
             xs = [o.vector() for o in self.ops]
@@ -666,6 +669,9 @@ class Batch:
         o.max_iter = max_iter
         o.check_every = check_every
         o.use_graph = 1 if use_graph else 0
+        o.precision = PRECISIONS[precision]
+        o.inner_tol = inner_tol
+        o.max_outer = max_outer
         bp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in rhs])
         xp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in xs])
         infos = (SolveInfo * n)()

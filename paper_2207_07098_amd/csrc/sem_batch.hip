@@ -29,8 +29,8 @@ struct sem_batch_s {
     std::vector<BatchAxItem> ax;
     std::vector<BatchVecItem> vec;
     BatchLaunch bl{};
-    hipGraphExec_t graph = nullptr;
-    int graph_m = 0;
+    hipGraphExec_t graph = nullptr, graph32 = nullptr;   // FP64 CG, FP32 inner CG
+    int graph_m = 0, graph32_m = 0;
     hipStream_t stream = nullptr;
     hipEvent_t event = nullptr;
     std::string err;
@@ -112,6 +112,10 @@ static sem_status upload_tables(sem_batch b, hipStream_t s) {
         (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
     }
+    if (b->graph32) {
+        (void)hipGraphExecDestroy(b->graph32);
+        b->graph32 = nullptr;
+    }
     return SEM_OK;
 }
 
@@ -155,6 +159,18 @@ extern "C" sem_status sem_batch_create(const sem_ctx *ctxs, int nprob, sem_batch
         pb.n_bnd = c->n_bnd;
         pb.n_u = c->n_unique;
         pb.n1 = c->n1;
+        if (c->L.G[SEM_FP32] && c->L.r32) {      // FP32 factors and inner vectors
+            pb.G32 = c->ws + c->L.G[SEM_FP32];
+            pb.D32 = dptr<float>(c, c->L.dhat32);
+            pb.DT32 = dptr<float>(c, c->L.dhatT32);
+            pb.dinv32 = dptr<float>(c, c->L.dinv32);
+            pb.x32 = dptr<float>(c, c->L.d32);
+            pb.r32 = dptr<float>(c, c->L.r32);
+            pb.p32 = dptr<float>(c, c->L.p32);
+            pb.w32 = dptr<float>(c, c->L.w32);
+            pb.b32 = dptr<float>(c, c->L.z64);   // FP64 scratch vector, as floats
+        }
+        pb.scale = pb.unscale = 1.0;
     }
     for (int n1 = 2; n1 <= kMaxN1; ++n1) {  // 256 threads, one workgroup per group
         b->threads[n1] = 256;
@@ -179,6 +195,7 @@ extern "C" sem_status sem_batch_create(const sem_ctx *ctxs, int nprob, sem_batch
 extern "C" void sem_batch_free(sem_batch b) {
     if (!b) return;
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->graph32) (void)hipGraphExecDestroy(b->graph32);
     if (b->event) (void)hipEventDestroy(b->event);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
@@ -332,6 +349,177 @@ extern "C" sem_status sem_batch_autotune(sem_batch b, int reps, sem_tile *best, 
     return SEM_OK;
 }
 
+// Runs the batched PCG iterations (FP64, or the FP32 inner solve of the
+// refinement) until every problem's CgState is done; the iteration chunk of
+// check_every iterations is captured in a hipGraph once per precision.
+static sem_status batch_cg_loop(sem_batch b, const sem_solve_options &o, bool fp32, hipStream_t s,
+                                std::vector<CgState> &h) {
+    const int m = std::max(1, o.check_every);
+    hipGraphExec_t &graph = fp32 ? b->graph32 : b->graph;
+    int &graph_m = fp32 ? b->graph32_m : b->graph_m;
+    if (o.use_graph && (!graph || graph_m != m)) {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        graph = nullptr;
+        hipGraph_t g;
+        SEM_HIP(nullptr, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        for (int it = 0; it < m; ++it) {
+            hipError_t e = launch_batch_iteration(b->bl, s, fp32);
+            if (e != hipSuccess) {
+                hipGraph_t dummy;
+                (void)hipStreamEndCapture(s, &dummy);
+                return bfail(b, SEM_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+            }
+        }
+        SEM_HIP(nullptr, hipStreamEndCapture(s, &g));
+        SEM_HIP(nullptr, hipGraphInstantiate(&graph, g, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(g);
+        graph_m = m;
+    }
+    h.resize(b->nprob);
+    int64_t launched = 0;
+    for (;;) {
+        if (launched > o.max_iter + 2 * (int64_t)m + 2)
+            return bfail(b, SEM_ERR_DEVICE, "batched CG did not terminate");
+        launched += m;
+        if (o.use_graph) {
+            SEM_HIP(nullptr, hipGraphLaunch(graph, s));
+        } else {
+            for (int it = 0; it < m; ++it) SEM_HIP(nullptr, launch_batch_iteration(b->bl, s, fp32));
+        }
+        SEM_HIP(nullptr, hipMemcpyAsync(h.data(), b->ws + b->off_st, sizeof(CgState) * h.size(),
+                                        hipMemcpyDeviceToHost, s));
+        SEM_HIP(nullptr, hipStreamSynchronize(s));
+        bool all = true;
+        for (auto &st : h) all = all && st.done;
+        if (all) return SEM_OK;
+    }
+}
+
+// FP64 iterative refinement around the batched FP32 PCG (A10 over a batch):
+// all problems step together; each outer step forms every unfinished
+// problem's FP64 residual r = b - A x (FP64 operator and summation), solves
+// A d = r / |r| with the FP32 operator and vectors to the relative inner
+// tolerance, and adds |r| d to x in FP64.  A problem leaves the loop when
+// its FP64 residual meets tol, or is handed to FP64 PCG (warm start) when
+// a correction fails to halve it, its inner solve fails, or max_outer steps
+// are used up.
+static sem_status batch_refine(sem_batch b, const double *const *rhs, double *const *x,
+                               const sem_solve_options &o, sem_solve_info *infos, hipStream_t s,
+                               std::chrono::steady_clock::time_point t0) {
+    const int np = b->nprob;
+    const double eta = (o.inner_tol > 0 && o.inner_tol < 1) ? o.inner_tol : 1e-4;
+    const int max_outer = o.max_outer > 0 ? o.max_outer : 50;
+    std::vector<double> prev(np, INFINITY), rel(np, 0.0);
+    std::vector<int> outer(np, 0), fall(np, SEM_FALLBACK_NONE);
+    std::vector<int64_t> its(np, 0);
+    std::vector<CgState> h(np);
+    auto upload_probs = [&]() -> sem_status {
+        SEM_HIP(nullptr, hipMemcpyAsync(b->ws + b->off_probs, b->probs.data(),
+                                        sizeof(BatchProb) * np, hipMemcpyHostToDevice, s));
+        return SEM_OK;
+    };
+    SEM_HIP(nullptr, launch_batch_refine(b->bl, s, 0));              // x = 0
+    for (int step = 0;; ++step) {
+        SEM_HIP(nullptr, launch_batch_refine(b->bl, s, 1));          // r = b - A x, r.r, b.b
+        SEM_HIP(nullptr, hipMemcpyAsync(h.data(), b->ws + b->off_st, sizeof(CgState) * np,
+                                        hipMemcpyDeviceToHost, s));
+        SEM_HIP(nullptr, hipStreamSynchronize(s));
+        bool all = true;
+        for (int p = 0; p < np; ++p) {
+            BatchProb &pb = b->probs[p];
+            if (pb.outer_done) continue;
+            const double rr = h[p].rr, bb = h[p].bb;
+            rel[p] = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+            if (rel[p] <= o.tol) {
+                pb.outer_done = 1;
+            } else if (!std::isfinite(rel[p])) {
+                pb.outer_done = 1;
+                fall[p] = SEM_FALLBACK_NONFINITE;
+            } else if (step > 0 && rel[p] > 0.5 * prev[p]) {
+                pb.outer_done = 1;
+                fall[p] = SEM_FALLBACK_STAGNATION;
+            } else if (outer[p] >= max_outer) {
+                pb.outer_done = 1;
+                fall[p] = SEM_FALLBACK_OUTER_CAP;
+            } else {
+                all = false;
+                pb.unscale = std::sqrt(rr);
+                pb.scale = 1.0 / pb.unscale;
+            }
+            prev[p] = rel[p];
+        }
+        if (all) break;
+        sem_status st = upload_probs();
+        if (st) return st;
+        SEM_HIP(nullptr, launch_batch_refine(b->bl, s, 2));          // b32 = r / |r|
+        std::vector<CgState> init(np);
+        std::memset(init.data(), 0, sizeof(CgState) * np);
+        for (int p = 0; p < np; ++p) {
+            init[p].tol2 = eta * eta;
+            init[p].max_iter = std::max<int64_t>(1, o.max_iter - its[p]);
+            init[p].narrow = 1;
+            init[p].done = b->probs[p].outer_done;
+        }
+        SEM_HIP(nullptr, hipMemcpyAsync(b->ws + b->off_st, init.data(), sizeof(CgState) * np,
+                                        hipMemcpyHostToDevice, s));
+        SEM_HIP(nullptr, launch_batch_begin(b->bl, s, true));
+        st = batch_cg_loop(b, o, true, s, h);
+        if (st) return st;
+        for (int p = 0; p < np; ++p) {
+            BatchProb &pb = b->probs[p];
+            if (pb.outer_done) continue;
+            its[p] += h[p].iter;
+            if (h[p].status == CG_NONFINITE || h[p].status == CG_BREAKDOWN) {
+                pb.outer_done = 1;                   // keep x: FP64 finishes from it
+                fall[p] = h[p].status == CG_NONFINITE ? SEM_FALLBACK_NONFINITE
+                                                      : SEM_FALLBACK_BREAKDOWN;
+            } else {
+                outer[p] += 1;
+            }
+        }
+        st = upload_probs();
+        if (st) return st;
+        SEM_HIP(nullptr, launch_batch_refine(b->bl, s, 3));          // x += |r| d
+        // the problems just handed over are excluded from the next residual
+        // pass as well; outer_done stays set for them
+    }
+    // FP64 true residual per problem; FP64 PCG (warm start) where the
+    // refinement stopped short of tol
+    sem_status worst = SEM_OK;
+    for (int p = 0; p < np; ++p) {
+        sem_solve_info &inf = infos[p];
+        std::memset(&inf, 0, sizeof(inf));
+        inf.iterations = its[p];
+        inf.outer_iterations = outer[p];
+        inf.rel_residual = rel[p];
+        double tr = 0.0;
+        sem_status st = true_residual(b->ctxs[p], rhs[p], x[p], s, &tr);
+        if (st) return st;
+        inf.true_rel_residual = tr;
+        inf.status = SEM_OK;
+        if (!(tr <= o.tol)) {
+            if (fall[p] == SEM_FALLBACK_NONE) fall[p] = SEM_FALLBACK_STAGNATION;
+            sem_solve_options o2 = o;
+            o2.precision = SEM_FP64;
+            o2.zero_guess = std::isfinite(tr) ? 0 : 1;
+            o2.max_iter = std::max<int64_t>(1, o.max_iter - its[p]);
+            sem_solve_info i2;
+            const sem_status st2 = sem_cg_solve(b->ctxs[p], rhs[p], x[p], &o2, &i2, (sem_stream)s);
+            inf.iterations += i2.iterations;
+            inf.fallback_iterations = i2.iterations;
+            inf.true_rel_residual = i2.true_rel_residual;
+            inf.rel_residual = i2.rel_residual;
+            inf.status = st2;
+        }
+        inf.fallback = fall[p];
+        if (inf.status != SEM_OK && worst == SEM_OK) worst = inf.status;
+    }
+    SEM_HIP(nullptr, hipStreamSynchronize(s));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int p = 0; p < np; ++p) infos[p].seconds = secs;
+    return worst;
+}
+
 extern "C" sem_status sem_batch_solve(sem_batch b, const double *const *rhs, double *const *x,
                                       const sem_solve_options *opts, sem_solve_info *infos,
                                       sem_stream stream) {
@@ -339,7 +527,14 @@ extern "C" sem_status sem_batch_solve(sem_batch b, const double *const *rhs, dou
     if (!b->ws) return bfail(b, SEM_ERR_STATE, "no batch workspace bound");
     sem_solve_options o;
     if (opts) o = *opts; else sem_default_solve_options(&o);
-    if (o.precision != SEM_FP64) return bfail(b, SEM_ERR_UNSUPPORTED, "batched solve is FP64");
+    const bool mixed = o.precision == SEM_FP32;
+    if (o.precision != SEM_FP64 && !mixed)
+        return bfail(b, SEM_ERR_UNSUPPORTED, "batched solve: FP64, or FP64 refinement around FP32");
+    if (mixed)
+        for (int p = 0; p < b->nprob; ++p)
+            if (!b->probs[p].G32)
+                return bfail(b, SEM_ERR_UNSUPPORTED, "problem " + std::to_string(p) +
+                                                         ": no FP32 factors or solver vectors");
     if (!(o.tol > 0) || o.max_iter < 1) return bfail(b, SEM_ERR_INVALID, "bad tolerance or cap");
     for (int p = 0; p < b->nprob; ++p)
         if (!rhs[p] || !x[p] || ((uintptr_t)rhs[p] & 15) || ((uintptr_t)x[p] & 15))
@@ -356,8 +551,10 @@ extern "C" sem_status sem_batch_solve(sem_batch b, const double *const *rhs, dou
         b->probs[p].b = rhs[p];
         b->probs[p].x = x[p];
     }
+    for (auto &pb : b->probs) pb.outer_done = 0;
     SEM_HIP(nullptr, hipMemcpyAsync(b->ws + b->off_probs, b->probs.data(),
                                     sizeof(BatchProb) * b->probs.size(), hipMemcpyHostToDevice, s));
+    if (mixed) return batch_refine(b, rhs, x, o, infos, s, t0);
     std::vector<CgState> init(b->nprob);
     std::memset(init.data(), 0, sizeof(CgState) * init.size());
     for (auto &st : init) {

@@ -183,6 +183,16 @@ struct BatchProb {               // device-resident, one per problem
     const int32_t *bmap;
     const double *dinv, *b;
     double *x, *r, *p, *w;
+    // FP64 refinement around batched FP32 PCG (null without FP32 factors):
+    // FP32 factors, D, D^T and Jacobi weights, and the inner vectors (x32:
+    // the correction, b32: the scaled residual)
+    const void *G32;
+    const float *D32, *DT32, *dinv32;
+    float *x32, *r32, *p32, *w32, *b32;
+    double scale;                // inner right-hand side = scale * r
+    double unscale;              // 1 / scale
+    int outer_done;              // refinement finished (or handed to FP64)
+    int pad_;
     CgState *st;
     int64_t E, n_bnd, n_u;
     int n1, epb;
@@ -209,9 +219,14 @@ struct BatchLaunch {             // host-side description of one batch launch
 };
 constexpr int kBatchMaxN1 = 10;
 size_t batch_lds_bytes_n1(int threads, int n1);
-hipError_t launch_batch_iteration(const BatchLaunch &bl, hipStream_t s);
-hipError_t launch_batch_begin(const BatchLaunch &bl, hipStream_t s);
+// fp32: the inner FP32 PCG of the refinement (FP32 factors and vectors)
+hipError_t launch_batch_iteration(const BatchLaunch &bl, hipStream_t s, bool fp32 = false);
+hipError_t launch_batch_begin(const BatchLaunch &bl, hipStream_t s, bool fp32 = false);
 hipError_t launch_batch_ax_only(const BatchLaunch &bl, hipStream_t s);
+// Refinement steps over the problems not yet done: mode 0 x = 0, 1 the FP64
+// residual r = b - A x with r.r and b.b into each problem's CgState (rr,
+// bb), 2 b32 = scale r, 3 x += unscale x32.
+hipError_t launch_batch_refine(const BatchLaunch &bl, hipStream_t s, int mode);
 
 // FP64 true relative residual ||b - A x|| / ||b|| of a context (sem_host).
 sem_status true_residual(sem_ctx c, const double *b, const double *x, hipStream_t s, double *rel);

@@ -1388,6 +1388,8 @@ struct BatchArgs {
     int n_ax, n_vec;
     double *ax_partials;     // [n_ax][4]
     double *vec_partials;    // [n_vec][4]
+    int phase;               // operator: 0 FP64 CG (p -> w), 1 FP32 inner CG
+                             // (p32 -> w32), 2 FP64 residual (x -> w)
 };
 
 // factor planes in flight in the batched operator: a ring of two for the
@@ -1395,41 +1397,59 @@ struct BatchArgs {
 template <int N1>
 constexpr int kBatchPF = N1 >= 9 ? 2 : N1;
 
-template <int N1>
+template <int N1, typename T>
 __device__ __forceinline__ void batch_group(const BatchArgs &A, const BatchProb &pb,
-                                            int64_t group, double *lds, double &dot) {
-    constexpr int C = N1 * N1, BUF = N1 * N1 * (N1 + 1);
+                                            int64_t group, T *lds, double &dot) {
+    constexpr int BUF = N1 * N1 * (N1 + 1);
     const Lane<N1> L(threadIdx.x);
-    double *S0 = lds + (size_t)L.slot * 3 * BUF;
-    double *Dl = lds + (size_t)pb.epb * 3 * BUF;
-    fill_dl<N1, double>(Dl, pb.D);
+    T *S0 = lds + (size_t)L.slot * 3 * BUF;
+    T *Dl = lds + (size_t)pb.epb * 3 * BUF;
+    const T *D, *DT;
+    const void *G, *in;
+    void *out;
+    if constexpr (std::is_same<T, double>::value) {
+        D = pb.D;
+        DT = pb.DT;
+        G = pb.G;
+        in = A.phase == 2 ? (const void *)pb.x : (const void *)pb.p;
+        out = pb.w;
+    } else {
+        D = pb.D32;
+        DT = pb.DT32;
+        G = pb.G32;
+        in = pb.p32;
+        out = pb.w32;
+    }
+    fill_dl<N1, T>(Dl, D);
     const int64_t e = group * pb.epb + L.slot;
     const bool active = L.slot < pb.epb && e < pb.E;
     const int64_t ec = active ? e : 0;
-    AxMesh<double> M{pb.p, pb.w, nullptr, reinterpret_cast<const double *>(pb.G), nullptr,
-                     pb.bmap, pb.E, pb.n_bnd, 0, OUT_ATOMIC, nullptr, 1.0, 0.0};
+    AxMesh<T> M{in, out, nullptr, reinterpret_cast<const T *>(G), nullptr,
+                pb.bmap, pb.E, pb.n_bnd, 0, OUT_ATOMIC, nullptr, 1.0, 0.0};
     int32_t bm[N1];
     load_map<N1>(pb.bmap, L, ec, bm);
     __syncthreads();
-    ax_element<N1, double, MODE_ATOMIC, double, kBatchPF<N1>>(M, pb.D, pb.DT, Dl, L, S0, ec, active,
-                                                              -1, bm, true, dot);
+    ax_element<N1, T, MODE_ATOMIC, T, kBatchPF<N1>>(M, D, DT, Dl, L, S0, ec, active, -1, bm, true,
+                                                    dot);
 }
 
 // Operator pass over the work items [lo, hi) of the problems of one order:
 // one launch per order present, so that each order gets its own register
 // budget (a single kernel for all orders would run every order at the
-// occupancy of the largest).
-template <int N1>
+// occupancy of the largest).  T: FP64 factors and vectors, or FP32 ones
+// (the inner solve of the refinement).
+template <int N1, typename T>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, 256),
-                               amdgpu_waves_per_eu(AxOcc<N1, double, kBatchPF<N1>>::value)))
+                               amdgpu_waves_per_eu(AxOcc<N1, T, kBatchPF<N1>>::value)))
 k_ax_batch(BatchArgs A, int lo, int hi) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    double *lds = reinterpret_cast<double *>(smem_raw);
+    T *lds = reinterpret_cast<T *>(smem_raw);
     for (int w = lo + blockIdx.x; w < hi; w += gridDim.x) {
         const BatchAxItem it = A.ax_items[w];
         const BatchProb &pb = A.probs[it.prob];
         double dot = 0.0;
-        if (!pb.st->done) batch_group<N1>(A, pb, it.group, lds, dot);
+        const bool skip = A.phase == 2 ? pb.outer_done != 0 : pb.st->done != 0;
+        if (!skip) batch_group<N1, T>(A, pb, it.group, lds, dot);
         __shared__ double red[16];
         const double sdot = block_sum(dot, red);
         if (threadIdx.x == 0) A.ax_partials[(size_t)w * 4] = sdot;
@@ -1440,68 +1460,92 @@ k_ax_batch(BatchArgs A, int lo, int hi) {
 // mode 0: begin (x = 0, r = b, p = dinv r, w_bnd = 0; partials r.z, r.r, b.b)
 // mode 1: update (x += alpha p, r -= alpha w; partials r.r, r.z)
 // mode 2: p = dinv r + beta p, w_bnd = 0 (no partials)
+// T = double: the problem's FP64 CG vectors; T = float: the FP32 inner
+// vectors of the refinement (sums in FP64 either way).
+template <typename T>
 __global__ void __launch_bounds__(256) k_vec_batch(BatchArgs A, int mode) {
     for (int w = blockIdx.x; w < A.n_vec; w += gridDim.x) {
         const BatchVecItem it = A.vec_items[w];
         const BatchProb &pb = A.probs[it.prob];
         double s0 = 0, s1 = 0, s2 = 0;
-        const bool skip = mode != 0 && pb.st->done;
+        const bool skip = (mode != 0 && pb.st->done) || (A.phase == 1 && pb.outer_done);
         if (!skip) {
-            double *x = pb.x, *r = pb.r, *p = pb.p, *wv = pb.w;
-            const double *b = pb.b, *dinv = pb.dinv;
+            T *x, *r, *p, *wv;
+            const T *b, *dinv;
+            if constexpr (std::is_same<T, double>::value) {
+                x = pb.x; r = pb.r; p = pb.p; wv = pb.w; b = pb.b; dinv = pb.dinv;
+            } else {
+                x = pb.x32; r = pb.r32; p = pb.p32; wv = pb.w32; b = pb.b32; dinv = pb.dinv32;
+            }
             const double alpha = pb.st->alpha, beta = pb.st->beta;
             for (int64_t q = it.begin + threadIdx.x; mode == 0 && q < it.end; q += blockDim.x) {
-                {
-                    const double bq = b[q], zq = dinv[q] * bq;
-                    x[q] = 0.0;
-                    r[q] = bq;
-                    p[q] = zq;
-                    if (q < pb.n_bnd) wv[q] = 0.0;
-                    s0 += bq * zq;
-                    s1 += bq * bq;
-                    s2 += bq * bq;
-                }
+                const T bq = b[q], zq = dinv[q] * bq;
+                x[q] = T(0);
+                r[q] = bq;
+                p[q] = zq;
+                if (q < pb.n_bnd) wv[q] = T(0);
+                s0 += (double)bq * (double)zq;
+                s1 += (double)bq * (double)bq;
+                s2 += (double)bq * (double)bq;
             }
-            if (mode == 1) {
-                // 16-byte streaming accesses over whole pairs (items start at
-                // even nodes), the odd last node of a problem separately
-                const int64_t ve = it.end >> 1;
-                for (int64_t v = (it.begin >> 1) + threadIdx.x; v < ve; v += blockDim.x) {
-                    d2v xv = vld(reinterpret_cast<const d2v *>(x) + v);
-                    d2v rv = vld(reinterpret_cast<const d2v *>(r) + v);
-                    const d2v pv = vld(reinterpret_cast<const d2v *>(p) + v);
-                    const d2v wq = vld(reinterpret_cast<const d2v *>(wv) + v);
-                    const d2v dv = vld(reinterpret_cast<const d2v *>(dinv) + v);
-                    xv += alpha * pv;
-                    rv -= alpha * wq;
-                    vst(xv, reinterpret_cast<d2v *>(x) + v);
-                    vst(rv, reinterpret_cast<d2v *>(r) + v);
-                    s0 += rv.x * rv.x + rv.y * rv.y;
-                    s1 += rv.x * (dv.x * rv.x) + rv.y * (dv.y * rv.y);
+            if constexpr (std::is_same<T, double>::value) {
+                if (mode == 1) {
+                    // 16-byte streaming accesses over whole pairs (items start
+                    // at even nodes), the odd last node of a problem separately
+                    const int64_t ve = it.end >> 1;
+                    for (int64_t v = (it.begin >> 1) + threadIdx.x; v < ve; v += blockDim.x) {
+                        d2v xv = vld(reinterpret_cast<const d2v *>(x) + v);
+                        d2v rv = vld(reinterpret_cast<const d2v *>(r) + v);
+                        const d2v pv = vld(reinterpret_cast<const d2v *>(p) + v);
+                        const d2v wq = vld(reinterpret_cast<const d2v *>(wv) + v);
+                        const d2v dv = vld(reinterpret_cast<const d2v *>(dinv) + v);
+                        xv += alpha * pv;
+                        rv -= alpha * wq;
+                        vst(xv, reinterpret_cast<d2v *>(x) + v);
+                        vst(rv, reinterpret_cast<d2v *>(r) + v);
+                        s0 += rv.x * rv.x + rv.y * rv.y;
+                        s1 += rv.x * (dv.x * rv.x) + rv.y * (dv.y * rv.y);
+                    }
+                    if ((it.end & 1) && threadIdx.x == 0) {
+                        const int64_t q = it.end - 1;
+                        x[q] += alpha * p[q];
+                        const double rq = r[q] - alpha * wv[q];
+                        r[q] = rq;
+                        s0 += rq * rq;
+                        s1 += rq * (dinv[q] * rq);
+                    }
+                } else if (mode == 2) {
+                    const int64_t ve = it.end >> 1, nb = pb.n_bnd;
+                    for (int64_t v = (it.begin >> 1) + threadIdx.x; v < ve; v += blockDim.x) {
+                        const d2v rv = vld(reinterpret_cast<const d2v *>(r) + v);
+                        const d2v dv = vld(reinterpret_cast<const d2v *>(dinv) + v);
+                        d2v pv = vld(reinterpret_cast<const d2v *>(p) + v);
+                        pv = dv * rv + beta * pv;
+                        vst(pv, reinterpret_cast<d2v *>(p) + v);
+                        if (2 * v + 1 < nb) vst(d2v{0.0, 0.0}, reinterpret_cast<d2v *>(wv) + v);
+                        else if (2 * v < nb) wv[2 * v] = 0.0;
+                    }
+                    if ((it.end & 1) && threadIdx.x == 0) {
+                        const int64_t q = it.end - 1;
+                        p[q] = dinv[q] * r[q] + beta * p[q];
+                        if (q < nb) wv[q] = 0.0;
+                    }
                 }
-                if ((it.end & 1) && threadIdx.x == 0) {
-                    const int64_t q = it.end - 1;
-                    x[q] += alpha * p[q];
-                    const double rq = r[q] - alpha * wv[q];
-                    r[q] = rq;
-                    s0 += rq * rq;
-                    s1 += rq * (dinv[q] * rq);
-                }
-            } else if (mode == 2) {
-                const int64_t ve = it.end >> 1, nb = pb.n_bnd;
-                for (int64_t v = (it.begin >> 1) + threadIdx.x; v < ve; v += blockDim.x) {
-                    const d2v rv = vld(reinterpret_cast<const d2v *>(r) + v);
-                    const d2v dv = vld(reinterpret_cast<const d2v *>(dinv) + v);
-                    d2v pv = vld(reinterpret_cast<const d2v *>(p) + v);
-                    pv = dv * rv + beta * pv;
-                    vst(pv, reinterpret_cast<d2v *>(p) + v);
-                    if (2 * v + 1 < nb) vst(d2v{0.0, 0.0}, reinterpret_cast<d2v *>(wv) + v);
-                    else if (2 * v < nb) wv[2 * v] = 0.0;
-                }
-                if ((it.end & 1) && threadIdx.x == 0) {
-                    const int64_t q = it.end - 1;
-                    p[q] = dinv[q] * r[q] + beta * p[q];
-                    if (q < nb) wv[q] = 0.0;
+            } else {
+                const T af = (T)alpha, bf = (T)beta;
+                if (mode == 1) {
+                    for (int64_t q = it.begin + threadIdx.x; q < it.end; q += blockDim.x) {
+                        x[q] += af * p[q];
+                        const T rq = r[q] - af * wv[q];
+                        r[q] = rq;
+                        s0 += (double)rq * (double)rq;
+                        s1 += (double)rq * (double)(dinv[q] * rq);
+                    }
+                } else if (mode == 2) {
+                    for (int64_t q = it.begin + threadIdx.x; q < it.end; q += blockDim.x) {
+                        p[q] = dinv[q] * r[q] + bf * p[q];
+                        if (q < pb.n_bnd) wv[q] = T(0);
+                    }
                 }
             }
         }
@@ -1517,12 +1561,67 @@ __global__ void __launch_bounds__(256) k_vec_batch(BatchArgs A, int mode) {
     }
 }
 
+// Steps of the FP64 refinement over the problems not yet done:
+// mode 0: x = 0; 1: w_bnd = 0 (before the residual operator); 2: r = b - w
+// with partials r.r and b.b; 3: b32 = scale r (the inner right-hand side);
+// 4: x += unscale x32 (the inner correction).
+__global__ void __launch_bounds__(256) k_ref_batch(BatchArgs A, int mode) {
+    for (int w = blockIdx.x; w < A.n_vec; w += gridDim.x) {
+        const BatchVecItem it = A.vec_items[w];
+        const BatchProb &pb = A.probs[it.prob];
+        double s0 = 0.0, s1 = 0.0;
+        if (!pb.outer_done) {
+            for (int64_t q = it.begin + threadIdx.x; q < it.end; q += blockDim.x) {
+                if (mode == 0) {
+                    pb.x[q] = 0.0;
+                } else if (mode == 1) {
+                    if (q < pb.n_bnd) pb.w[q] = 0.0;
+                } else if (mode == 2) {
+                    const double bq = pb.b[q], rq = bq - pb.w[q];
+                    pb.r[q] = rq;
+                    s0 += rq * rq;
+                    s1 += bq * bq;
+                } else if (mode == 3) {
+                    pb.b32[q] = (float)(pb.scale * pb.r[q]);
+                } else {
+                    pb.x[q] += pb.unscale * (double)pb.x32[q];
+                }
+            }
+        }
+        if (mode == 2) {
+            __shared__ double red[16];
+            const double a0 = block_sum(s0, red), a1 = block_sum(s1, red);
+            if (threadIdx.x == 0) {
+                A.vec_partials[(size_t)w * 4 + 0] = a0;
+                A.vec_partials[(size_t)w * 4 + 1] = a1;
+            }
+        }
+    }
+}
+
+// One workgroup per problem: r.r and b.b of the refinement's residual into
+// the problem's CgState (fixed order).
+__global__ void __launch_bounds__(256) k_ref_norms(BatchArgs A) {
+    BatchProb &pb = A.probs[blockIdx.x];
+    if (pb.outer_done) return;
+    __shared__ double red[16];
+    double acc[2] = {0.0, 0.0};
+    for (int q = pb.vec_begin + threadIdx.x; q < pb.vec_end; q += blockDim.x)
+        for (int a = 0; a < 2; ++a) acc[a] += A.vec_partials[(size_t)q * 4 + a];
+    const double rr = block_sum(acc[0], red), bb = block_sum(acc[1], red);
+    if (threadIdx.x == 0) {
+        pb.st->rr = rr;
+        pb.st->bb = bb;
+    }
+}
+
 // One workgroup per problem: fixed-order sum of its items' partials, then
 // the same scalar logic as k_finish.
 __global__ void __launch_bounds__(256) k_finish_batch(BatchArgs A, int site) {
     BatchProb &pb = A.probs[blockIdx.x];
     CgState *st = pb.st;
     if ((site == FIN_AX || site == FIN_UPDATE) && st->done) return;
+    if (A.phase == 1 && pb.outer_done) return;    // refinement done: no inner solve
     const bool ax = site == FIN_AX;
     const double *part = ax ? A.ax_partials : A.vec_partials;
     const int lo = ax ? pb.ax_begin : pb.vec_begin, hi = ax ? pb.ax_end : pb.vec_end;
@@ -1851,7 +1950,7 @@ hipError_t launch_reliable_reset(sem_ctx c, const double *r64, float *r, float *
 // ---------------------------------------------------------------------------
 // Batched launchers
 // ---------------------------------------------------------------------------
-static BatchArgs batch_args(const BatchLaunch &bl) {
+static BatchArgs batch_args(const BatchLaunch &bl, int phase = 0) {
     BatchArgs A;
     A.probs = bl.probs;
     A.ax_items = bl.ax_items;
@@ -1860,6 +1959,7 @@ static BatchArgs batch_args(const BatchLaunch &bl) {
     A.n_vec = bl.n_vec;
     A.ax_partials = bl.ax_partials;
     A.vec_partials = bl.vec_partials;
+    A.phase = phase;
     return A;
 }
 
@@ -1869,6 +1969,7 @@ size_t batch_lds_bytes_n1(int threads, int n1) {
     return ((size_t)nslots * 3 * n1 * n1 * (n1 + 1) + C) * sizeof(double);
 }
 
+template <typename T>
 static void launch_batch_operator(const BatchLaunch &bl, const BatchArgs &A, hipStream_t s) {
     for (int n1 = kBatchMaxN1; n1 >= 2; --n1) {
         const int lo = bl.ax_lo[n1], hi = bl.ax_hi[n1];
@@ -1877,9 +1978,9 @@ static void launch_batch_operator(const BatchLaunch &bl, const BatchArgs &A, hip
         const size_t lds = batch_lds_bytes_n1(bl.threads[n1], n1);
         const int threads = std::max(1, bl.threads[n1] / (n1 * n1)) * n1 * n1;   // epb slots
         switch (n1) {
-#define SEM_BAXN(n)                                                                       \
-    case n:                                                                               \
-        hipLaunchKernelGGL(k_ax_batch<n>, dim3(grid), dim3(threads), lds, s, A, lo, hi);  \
+#define SEM_BAXN(n)                                                                          \
+    case n:                                                                                  \
+        hipLaunchKernelGGL((k_ax_batch<n, T>), dim3(grid), dim3(threads), lds, s, A, lo, hi); \
         break;
             SEM_BAXN(2) SEM_BAXN(3) SEM_BAXN(4) SEM_BAXN(5) SEM_BAXN(6) SEM_BAXN(7) SEM_BAXN(8)
             SEM_BAXN(9) SEM_BAXN(10)
@@ -1889,26 +1990,52 @@ static void launch_batch_operator(const BatchLaunch &bl, const BatchArgs &A, hip
     }
 }
 
-hipError_t launch_batch_iteration(const BatchLaunch &bl, hipStream_t s) {
-    BatchArgs A = batch_args(bl);
-    launch_batch_operator(bl, A, s);
+template <typename T>
+static hipError_t batch_iteration(const BatchLaunch &bl, hipStream_t s, int phase) {
+    BatchArgs A = batch_args(bl, phase);
+    launch_batch_operator<T>(bl, A, s);
     hipLaunchKernelGGL(k_finish_batch, dim3(bl.nprob), dim3(256), 0, s, A, (int)FIN_AX);
-    hipLaunchKernelGGL(k_vec_batch, dim3(bl.vec_grid), dim3(256), 0, s, A, 1);
+    hipLaunchKernelGGL(k_vec_batch<T>, dim3(bl.vec_grid), dim3(256), 0, s, A, 1);
     hipLaunchKernelGGL(k_finish_batch, dim3(bl.nprob), dim3(256), 0, s, A, (int)FIN_UPDATE);
-    hipLaunchKernelGGL(k_vec_batch, dim3(bl.vec_grid), dim3(256), 0, s, A, 2);
+    hipLaunchKernelGGL(k_vec_batch<T>, dim3(bl.vec_grid), dim3(256), 0, s, A, 2);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_begin(const BatchLaunch &bl, hipStream_t s) {
-    BatchArgs A = batch_args(bl);
-    hipLaunchKernelGGL(k_vec_batch, dim3(bl.vec_grid), dim3(256), 0, s, A, 0);
+hipError_t launch_batch_iteration(const BatchLaunch &bl, hipStream_t s, bool fp32) {
+    return fp32 ? batch_iteration<float>(bl, s, 1) : batch_iteration<double>(bl, s, 0);
+}
+
+hipError_t launch_batch_begin(const BatchLaunch &bl, hipStream_t s, bool fp32) {
+    BatchArgs A = batch_args(bl, fp32 ? 1 : 0);
+    if (fp32)
+        hipLaunchKernelGGL(k_vec_batch<float>, dim3(bl.vec_grid), dim3(256), 0, s, A, 0);
+    else
+        hipLaunchKernelGGL(k_vec_batch<double>, dim3(bl.vec_grid), dim3(256), 0, s, A, 0);
     hipLaunchKernelGGL(k_finish_batch, dim3(bl.nprob), dim3(256), 0, s, A, (int)FIN_BEGIN);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_ax_only(const BatchLaunch &bl, hipStream_t s) {
-    BatchArgs A = batch_args(bl);
-    launch_batch_operator(bl, A, s);
+    BatchArgs A = batch_args(bl, 0);
+    launch_batch_operator<double>(bl, A, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_refine(const BatchLaunch &bl, hipStream_t s, int mode) {
+    BatchArgs A = batch_args(bl, 2);
+    const dim3 g(bl.vec_grid), t(256);
+    switch (mode) {
+        case 0: hipLaunchKernelGGL(k_ref_batch, g, t, 0, s, A, 0); break;
+        case 1:
+            hipLaunchKernelGGL(k_ref_batch, g, t, 0, s, A, 1);
+            launch_batch_operator<double>(bl, A, s);
+            hipLaunchKernelGGL(k_ref_batch, g, t, 0, s, A, 2);
+            hipLaunchKernelGGL(k_ref_norms, dim3(bl.nprob), t, 0, s, A);
+            break;
+        case 2: hipLaunchKernelGGL(k_ref_batch, g, t, 0, s, A, 3); break;
+        case 3: hipLaunchKernelGGL(k_ref_batch, g, t, 0, s, A, 4); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

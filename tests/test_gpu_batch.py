@@ -21,11 +21,11 @@ if not torch.cuda.is_available():
 import paper_2207_07098_amd as sem  # noqa: E402
 
 
-def _problems(nprob, seed, kmax=4, orders=(3, 5, 7, 9)):
+def _problems(nprob, seed, kmax=4, orders=(3, 5, 7, 9), precisions=("fp64",)):
     out = []
     for bp in F.batch_problems(nprob, seed=seed, kmin=1, kmax=kmax, orders=orders):
         m = F.batch_mesh(bp)
-        op = sem.Operator(m, bp.N, precisions=("fp64",), solver=True)
+        op = sem.Operator(m, bp.N, precisions=precisions, solver=True)
         ora = oracle.setup(m, bp.N)
         gid, pos, _, _ = op.numbering()
         f = F.random_unique(op.n_unique, bp.seed)
@@ -112,4 +112,41 @@ def test_batch_with_zero_rhs_and_order_limit():
     big = sem.Operator(F.box(1), 11, precisions=("fp64",), solver=True)
     with pytest.raises(sem.SemError) as e:
         sem.Batch([probs[0][0], big])
+    assert e.value.status == 8
+
+
+def test_batched_refinement_matches_oracle():
+    """FP64 refinement around the batched FP32 PCG (Sec. VI-B lower
+    precision, over a batch): every problem reaches the oracle's true
+    residual 1e-10 without an FP64 hand-over, in a few corrections, and
+    agrees with the FP64 batched solve; a zero right-hand side gives x = 0."""
+    probs = _problems(6, seed=11, precisions=("fp64", "fp32"))
+    batch = sem.Batch([p[0] for p in probs])
+    rhs = [p[4] for p in probs]
+    rhs[2] = torch.zeros_like(rhs[2])
+    ref, _ = batch.solve(rhs, tol=1e-10)
+    ref = [r.clone() for r in ref]
+    for graph in (True, False):
+        xs, infos = batch.solve(rhs, tol=1e-10, precision="fp32", inner_tol=1e-4, use_graph=graph,
+                                check_every=7)
+        for q, ((op, ora, pos, b, _), x, info) in enumerate(zip(probs, xs, infos)):
+            assert info["status"] == "SEM_OK" and info["fallback"] == "none", (q, info)
+            if q == 2:
+                assert torch.count_nonzero(x) == 0
+                continue
+            res = ora.true_residual(x.cpu().numpy()[pos], b)
+            assert res <= 1.01e-10, (q, res, info)
+            assert 1 <= info["outer_iterations"] <= 6, info
+            assert relerr(x.cpu().numpy(), ref[q].cpu().numpy()) < 1e-7
+
+
+def test_batched_refinement_rejections():
+    probs = _problems(3, seed=12)                        # FP64 factors only
+    batch = sem.Batch([p[0] for p in probs])
+    rhs = [p[4] for p in probs]
+    with pytest.raises(sem.SemError) as e:
+        batch.solve(rhs, tol=1e-8, precision="fp32")
+    assert e.value.status == 8                           # unsupported
+    with pytest.raises(sem.SemError) as e:
+        batch.solve(rhs, tol=1e-8, precision="fp16")
     assert e.value.status == 8

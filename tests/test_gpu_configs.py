@@ -221,13 +221,14 @@ def test_box16_solutions_against_oracle_pcg():
 def test_batch_config_64_problems():
     """The 64-problem batch (K ~ U{2..12}, N in {5,7,9}, per-axis widths ~
     U[0.5,2], random right-hand sides, seed 0) solved together to 1e-8 with
-    the autotuned batch tile: each problem's oracle true residual <= 1e-8."""
+    the autotuned batch tile, in FP64 and as FP64 refinement around the
+    batched FP32 PCG: each problem's oracle true residual <= 1e-8."""
     t0 = time.time()
     probs = F.batch_problems(64, seed=0)
     ops, oras, poss, bs, bds = [], [], [], [], []
     for bp in probs:
         m = F.batch_mesh(bp)
-        op = sem.Operator(m, bp.N, precisions=("fp64",), solver=True)
+        op = sem.Operator(m, bp.N, precisions=("fp64", "fp32"), solver=True)
         ora = oracle.setup(m, bp.N)
         gid, pos, _, _ = op.numbering()
         assert np.array_equal(gid, ora.gid)
@@ -249,3 +250,13 @@ def test_batch_config_64_problems():
         assert res <= 1.01e-8, (p, probs[p], res, info)
     log("batch tile %s, %.3f ms per operator pass, %.3fs to all converged, worst oracle "
         "residual %.2e" % (tile, ms, infos[0]["seconds"], worst))
+    # FP64 refinement around the batched FP32 PCG: the same oracle check
+    xs, infos = batch.solve(bds, tol=1e-8, precision="fp32")
+    worst = 0.0
+    for p, (x, info) in enumerate(zip(xs, infos)):
+        res = oras[p].true_residual(x.cpu().numpy()[poss[p]], bs[p])
+        worst = max(worst, res)
+        assert info["status"] == "SEM_OK" and info["fallback"] == "none", (p, info)
+        assert res <= 1.01e-8, (p, probs[p], res, info)
+    log("FP32-refined batch: %.3fs to all converged, at most %d corrections, worst oracle "
+        "residual %.2e" % (infos[0]["seconds"], max(i["outer_iterations"] for i in infos), worst))
