@@ -342,13 +342,11 @@ struct CoarseParams {
     const double *W;          // counting weights (interp)
     const int32_t *cmap;      // [E][8] coarse solver index or -1
     const uint8_t *owner;     // [E][n_b] 1 on the first copy of each boundary node
-    const int32_t *bmap, *csr_off, *csr_idx, *bpos2l;
+    const int32_t *bmap;      // [E][n_b] element-boundary map
     const double *xi;         // GLL nodes [N+1]
-    int64_t E, n_bnd, n_u;
-    int N, nb;
+    int64_t E, n_bnd;
+    int nb;
 };
-
-__device__ __forceinline__ double phi(double x, int side) { return side ? 0.5 * (1.0 + x) : 0.5 * (1.0 - x); }
 
 // Element-based forms (one 64-lane workgroup per element, N1 known at
 // compile time so that each lane's points are unrolled and their loads are
@@ -1230,10 +1228,8 @@ static sem_status precondition(sem_gmres G, const VT *r, VT *z, unsigned parts, 
 #undef SEM_FDM
         SEM_HIP(c, hipGetLastError());
     }
-    CoarseParams<VT> C{r, G->b0, z, G->x0, local ? G->zs : nullptr, G->dW, G->dcmap, G->downer,
-                       dptr<int32_t>(c, c->L.bmap), dptr<int32_t>(c, c->L.csr_off),
-                       dptr<int32_t>(c, c->L.csr_idx), dptr<int32_t>(c, c->L.bpos2l), G->dxi,
-                       c->E, c->n_bnd, n, c->N, c->nb};
+    CoarseParams<VT> C{r,       G->b0,   z,     G->x0, local ? G->zs : nullptr, G->dW, G->dcmap,
+                       G->downer, dptr<int32_t>(c, c->L.bmap), G->dxi, c->E, c->n_bnd, c->nb};
     if (coarse) {
 #define SEM_RESTRICT(n1)                                                                    \
     case n1:                                                                                \
