@@ -129,6 +129,26 @@ def test_gmres_box16_against_pcg():
     assert relerr(xc, p.from_dev(xp)) < 1e-8
 
 
+@pytest.mark.parametrize("restart", [1, 2, 4])
+def test_gmres_short_restarts_match_oracle(restart):
+    """Short restart lengths: every cycle ends in a closing sweep (the
+    delayed second projection of the last vector) and a true-residual
+    restart; iteration counts stay within 10% (and 3) of the oracle's
+    GMRES with the same restart, and the solution meets 1e-10."""
+    p, hs, _ = case("ogrid_N3")
+    ps = sem.PressureSolver(p.op, restart=restart)
+    b = p.ora.rhs_unique(F.random_unique(p.op.n_unique, 31))
+    x, info = ps.solve(p.to_dev(b), tol=1e-10, max_iter=5000)
+    xc = p.from_dev(x)
+    res = p.ora.true_residual(xc, b)
+    _, oinfo = HY.fgmres(p.ora.apply, hs.apply, b, 1e-10, restart=restart, max_iter=5000)
+    print("restart %d: gmres %d its, %d restarts (oracle %d), res %.2e" % (
+        restart, info["iterations"], info["restarts"], oinfo["iterations"], res), flush=True)
+    assert info["status"] == "SEM_OK" and res <= 1.01e-10
+    assert info["restarts"] >= 1
+    assert abs(info["iterations"] - oinfo["iterations"]) <= max(3, 0.1 * oinfo["iterations"])
+
+
 def test_gmres_rejections():
     p, _, _ = case("box3_N4_mixed")
     with pytest.raises(sem.SemError):
