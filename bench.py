@@ -319,9 +319,7 @@ def bench_ogrid(args):
     for prec in ("fp64", "fp32", "bf16"):
         if prec == "bf16":
             op.set_tile("bf16", elements_per_block=2, grid_cap=0, xcd_remap=0, pipeline=2)
-        # on the stretched O-grid the inner cycles end at the restart length
-        # before a tight inner tolerance is met, so the looser one is used
-        x, info = ps.solve(b, tol=1e-10, precision=prec, inner_tol=1e-3, raise_on_error=False)
+        x, info = ps.solve(b, tol=1e-10, precision=prec, raise_on_error=False)
         key = "gmres_hybrid_schwarz" + ("" if prec == "fp64" else "_%s_refined" % prec)
         solves[key] = info
         log("ogrid", key, json.dumps(info))

@@ -576,14 +576,10 @@ class PressureSolver:
         return z
 
     def solve(self, b, x=None, tol: float = 1e-10, max_iter: int = 10000,
-              precision: str = "fp64", inner_tol=None, max_outer: int = 50,
+              precision: str = "fp64", inner_tol: float = 1e-3, max_outer: int = 50,
               raise_on_error: bool = True):
         """FP64 GMRES, or (precision fp32/fp16/bf16) FP64 refinement around
-        FP32-vector GMRES with that operator.  inner_tol defaults to 1e-5 for
-        the FP32 operator and 1e-3 for the 16-bit ones (about their operator
-        accuracy).  Returns (x, info dict)."""
-        if inner_tol is None:
-            inner_tol = 1e-5 if precision == "fp32" else 1e-3
+        FP32-vector GMRES with that operator.  Returns (x, info dict)."""
         o = SolveOptions()
         lib().sem_default_solve_options(ctypes.byref(o))
         o.tol = tol
