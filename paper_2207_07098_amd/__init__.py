@@ -656,10 +656,11 @@ class Batch:
 
     def solve(self, rhs, xs=None, tol: float = 1e-8, max_iter: int = 100000,
               check_every: int = 50, use_graph: bool = True, raise_on_error: bool = True,
-              precision: str = "fp64", inner_tol: float = 1e-4, max_outer: int = 50):
+              precision: str = "fp64", inner_tol: float = 1e-2, max_outer: int = 50):
         """rhs: list of device vectors (solver order).  precision "fp32": FP64
         refinement around the batched FP32 PCG (the operators need FP32
-        factors).  Returns (xs, infos)."""
+        factors); each correction restarts the inner PCG, so a loose inner
+        tolerance (1e-2) costs the fewest iterations.  Returns (xs, infos)."""
         n = len(self.ops)
         if xs is None:
             xs = [o.vector() for o in self.ops]
