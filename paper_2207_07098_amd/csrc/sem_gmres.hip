@@ -11,16 +11,20 @@
 //    and lumped mass M of the neighbour-element-neighbour line (mean edge
 //    lengths), solved by fast diagonalisation: per direction K S = M S Lambda
 //    (host, once), then u = S (Lambda_r + Lambda_s + Lambda_t)^-1 S^T r with
-//    three tensor contractions each way (one workgroup per element, k-column
-//    in registers, r/s contractions through LDS).
+//    three tensor contractions each way (a persistent kernel, one workgroup
+//    per element at a time, k-column in registers, r/s contractions through
+//    LDS, the box gathered through a map built at bind time).
 //  * Additive combination with counting weights W (1 / number of subdomains
 //    holding the node).
 //  * Coarse grid: the N = 1 operator of the same library on the element
 //    vertices (its own context), trilinear interpolation P and restriction
-//    P^T, 10 Jacobi-PCG iterations from zero.
+//    P^T (summed in the local-solve gather when both parts run), 10
+//    Jacobi-PCG iterations from zero.
 //  * Flexible GMRES(m) (the coarse PCG makes the preconditioner nonlinear):
-//    Arnoldi with two classical Gram-Schmidt passes, Givens rotations on the
-//    host, FP64 throughout.
+//    Arnoldi with classical Gram-Schmidt twice, the second projection of
+//    each new vector delayed to the next step (two sweeps over the basis
+//    per step), Givens rotations on the host, FP64 sums throughout; or FP64
+//    refinement around FP32-vector GMRES.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
