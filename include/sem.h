@@ -336,6 +336,8 @@ typedef struct {
     double     seconds;           /* wall time of the call                   */
     int        fallback;          /* sem_fallback: 0, or why the solve was
                                      finished by FP64 PCG                    */
+    int        fp32_outer;        /* refined GMRES: steps made with the FP32
+                                     operator after a 16-bit one stalled     */
     int64_t    fallback_iterations; /* FP64 PCG iterations after the hand-over
                                      (included in iterations)                */
 } sem_solve_info;
@@ -448,9 +450,10 @@ sem_status sem_proj_solve(sem_proj proj, const double *b, double *x,
  * GMRES cycle (at most `restart` steps, stopped when its recurrence estimate
  * reaches opts.inner_tol) with FP32 vectors and that precision's operator on
  * A d = r / ||r||, x += ||r|| d (the preconditioner computes in FP64 on FP32
- * vectors); two corrections in a row that do not halve the FP64 residual,
- * or max_outer corrections, hand over to FP64 GMRES from the current x
- * (info->fallback).  info->iterations counts GMRES steps of all levels,
+ * vectors); two corrections in a row that do not halve the FP64 residual
+ * switch a 16-bit operator to the FP32 one when SEM_FP32 is configured, and
+ * otherwise (or with FP32 already) hand over to FP64 GMRES from the current
+ * x, as max_outer corrections do (info->fallback).  info->iterations counts GMRES steps of all levels,
  * info->restarts restarts, info->outer_iterations corrections.  sem_gmres_precondition applies the
  * preconditioner (parts: SEM_PC_SCHWARZ and/or SEM_PC_COARSE) to r -> z.
  * ------------------------------------------------------------------------- */

@@ -85,7 +85,7 @@ class SolveInfo(ctypes.Structure):
                 ("outer_iterations", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("true_rel_residual", ctypes.c_double), ("rel_residual", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("fallback", ctypes.c_int),
-                ("fallback_iterations", ctypes.c_int64)]
+                ("fp32_outer", ctypes.c_int), ("fallback_iterations", ctypes.c_int64)]
 
     def as_dict(self):
         return {"status": STATUS.get(self.status, self.status),
@@ -96,6 +96,7 @@ class SolveInfo(ctypes.Structure):
                 "rel_residual": float(self.rel_residual),
                 "seconds": float(self.seconds),
                 "fallback": FALLBACK.get(self.fallback, self.fallback),
+                "fp32_outer": int(self.fp32_outer),
                 "fallback_iterations": int(self.fallback_iterations)}
 
 
@@ -579,7 +580,9 @@ class PressureSolver:
               precision: str = "fp64", inner_tol: float = 1e-3, max_outer: int = 50,
               raise_on_error: bool = True):
         """FP64 GMRES, or (precision fp32/fp16/bf16) FP64 refinement around
-        FP32-vector GMRES with that operator.  Returns (x, info dict)."""
+        FP32-vector GMRES with that operator; a stalled 16-bit refinement
+        continues with the FP32 operator when it is configured, a stalled
+        FP32 one finishes in FP64 GMRES.  Returns (x, info dict)."""
         o = SolveOptions()
         lib().sem_default_solve_options(ctypes.byref(o))
         o.tol = tol

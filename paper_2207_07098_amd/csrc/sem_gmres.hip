@@ -1640,11 +1640,14 @@ extern "C" sem_status sem_gmres_solve(sem_gmres G, const double *b, double *x,
     }
     // FP64 iterative refinement around FP32-vector GMRES with the operator
     // of precision prec: r = b - A x (FP64), inner A d = r / ||r|| to
-    // inner_tol, x += ||r|| d; two corrections in a row that do not halve
-    // the FP64 residual hand over to FP64 GMRES from the current x.
+    // inner_tol, x += ||r|| d.  Two corrections in a row that do not halve
+    // the FP64 residual mean the operator's accuracy is reached: a 16-bit
+    // operator then gives way to the FP32 one (when configured), which
+    // gives way to FP64 GMRES from the current x.
     if (o.zero_guess) SEM_HIP(c, launch_fill(x, n, 0.0, s));
     double prev = INFINITY, prev2 = INFINITY;
-    for (int outer = 0;; ++outer) {
+    int cur = prec, since = 0;            // inner precision, steps since it was set
+    for (int outer = 0;; ++outer, ++since) {
         double rn = 0.0;
         // FP64 residual into G->r
         sem_status e = residual<double>(G, SEM_FP64, b, x, G->r, G->w, false, &rn, s);
@@ -1653,8 +1656,13 @@ extern "C" sem_status sem_gmres_solve(sem_gmres G, const double *b, double *x,
         info->outer_iterations = outer;
         if (!std::isfinite(rn)) return done(gfail(G, SEM_ERR_NAN, "non-finite residual"));
         if (rn <= o.tol * bn) return done(SEM_OK);
-        const bool stalled = outer >= 2 && rn > 0.5 * prev2;
-        if (stalled || outer >= o.max_outer || info->iterations >= o.max_iter) {
+        const bool stalled = since >= 2 && rn > 0.5 * prev2;
+        if (stalled && cur != SEM_FP32 && ((c->precisions >> SEM_FP32) & 1u) &&
+            outer < o.max_outer && info->iterations < o.max_iter) {
+            cur = SEM_FP32;                    // 16-bit accuracy reached: FP32 operator
+            since = 0;
+            prev = prev2 = INFINITY;
+        } else if (stalled || outer >= o.max_outer || info->iterations >= o.max_iter) {
             info->fallback = stalled ? SEM_FALLBACK_STAGNATION : SEM_FALLBACK_OUTER_CAP;
             const int64_t before = info->iterations;
             const sem_status st = fgmres<double>(G, SEM_FP64, b, x, false, o.tol * bn,
@@ -1672,9 +1680,9 @@ extern "C" sem_status sem_gmres_solve(sem_gmres G, const double *b, double *x,
                            (const double *)G->r, G->rhs32, (const double *)(G->coef + kGmMisc + 1), 0);
         SEM_HIP(c, hipGetLastError());
         double rin = 0.0;
-        e = fgmres<float>(G, prec, G->rhs32, G->d32, true, o.inner_tol,
-                          std::max<int64_t>(1, o.max_iter - info->iterations), info, &rin, s,
-                          true);
+        if (cur != prec) ++info->fp32_outer;
+        e = fgmres<float>(G, cur, G->rhs32, G->d32, true, o.inner_tol, o.max_iter, info, &rin,
+                          s, true);
         if (e != SEM_OK && e != SEM_ERR_NOT_CONVERGED) return done(e);
         // x += ||r|| d
         SEM_HIP(c, launch_ir_update(c, x, G->d32, nullptr, 0, s, rn));

@@ -110,6 +110,43 @@ def test_refined_gmres(name, prec):
     assert relerr(xc, xp) < 1e-8
 
 
+@pytest.mark.parametrize("setup", ["bf16", "fp32", "bf16_without_fp32"])
+def test_refined_gmres_precision_ladder(setup):
+    """A relative tolerance no FP64 residual can reach makes every stage of
+    the refinement stall: a 16-bit operator gives way to the FP32 one when
+    FP32 is configured (at least two FP32 steps: a stall needs two), then
+    FP64 GMRES runs to the iteration cap.  FP32 itself, or BF16 without
+    FP32 factors, hands over to FP64 directly.  The solution is still the
+    oracle's to FP64 accuracy."""
+    name = "deformed4_N5"
+    _, hs, _ = case(name)
+    key = name + ("_nofp32" if setup.endswith("without_fp32") else "_lowprec")
+    if key not in _cache:
+        m, N = _meshes()[name]
+        precs = ("fp64", "bf16") if key.endswith("nofp32") else ("fp64", "fp32", "fp16", "bf16")
+        q = Pair(m, N, precisions=precs)
+        _cache[key] = (q, hs, sem.PressureSolver(q.op, restart=30))
+    p, _, ps = _cache[key]
+    prec = setup.split("_")[0]
+    b = p.ora.rhs_unique(F.random_unique(p.op.n_unique, 31))
+    x, info = ps.solve(p.to_dev(b), tol=1e-18, max_iter=400, precision=prec,
+                       raise_on_error=False)
+    xc = p.from_dev(x)
+    res = p.ora.true_residual(xc, b)
+    xp, _ = p.ora.pcg(b, 1e-12)
+    print(setup, "its %d outer %d fp32 steps %d fallback %s (%d its) res %.2e" % (
+        info["iterations"], info["outer_iterations"], info["fp32_outer"], info["fallback"],
+        info["fallback_iterations"], res), flush=True)
+    assert info["status"] == "SEM_ERR_NOT_CONVERGED" and 400 <= info["iterations"] <= 430, info
+    assert info["fallback"] == "stagnation" and info["fallback_iterations"] > 0, info
+    if setup == "bf16":
+        assert info["fp32_outer"] >= 2, info
+    else:
+        assert info["fp32_outer"] == 0, info
+    assert res <= 1e-13
+    assert relerr(xc, xp) < 1e-8
+
+
 def test_gmres_box16_against_pcg():
     """16^3 deformed box, N = 7 (1.44M unique nodes): the GMRES solution
     reaches 1e-10 (oracle true residual) in far fewer iterations than
