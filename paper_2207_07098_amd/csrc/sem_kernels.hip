@@ -181,6 +181,8 @@ enum { FIN_AX = 0, FIN_BEGIN = 1, FIN_UPDATE = 2, FIN_RESID = 3, FIN_RESET = 4 }
 // CG logic that depends on them.
 __global__ void __launch_bounds__(1024) k_finish(int site, const double *__restrict__ partials,
                                                  int nblocks, CgState *st) {
+    // the direction update of the previous iteration has run: no x step owed
+    if (site == FIN_AX && threadIdx.x == 0) st->xstep = 0;
     if ((site == FIN_AX || site == FIN_UPDATE) && st->done) return;
     if (site == FIN_AX && st->pause) {          // the operator skipped this iteration
         if (threadIdx.x == 0) st->done = 2;
@@ -1267,9 +1269,11 @@ __device__ __forceinline__ void vst(V v, V *p) {
     else *p = v;
 }
 
+// r -= alpha w and the reductions r.r, r.z (z = dinv r) for beta.  The
+// matching x += alpha p is left to k_cg_p, which reads the old p anyway, so
+// p is read once per iteration.
 template <typename T>
-__global__ void k_cg_update(int64_t n, T *__restrict__ x, T *__restrict__ r,
-                            const T *__restrict__ p, const T *__restrict__ w,
+__global__ void k_cg_update(int64_t n, T *__restrict__ r, const T *__restrict__ w,
                             const T *__restrict__ dinv, double *partials, CgState *st) {
     if (st->done) return;
     using V = typename Vec<T>::type;
@@ -1279,14 +1283,10 @@ __global__ void k_cg_update(int64_t n, T *__restrict__ x, T *__restrict__ r,
     const int64_t nv = n / W, stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t v = t0; v < nv; v += stride) {
-        V xv = vld(reinterpret_cast<V *>(x) + v);
         V rv = vld(reinterpret_cast<V *>(r) + v);
-        const V pv = vld(reinterpret_cast<const V *>(p) + v);
         const V wv = vld(reinterpret_cast<const V *>(w) + v);
         const V dv = vld(reinterpret_cast<const V *>(dinv) + v);
-        xv += alpha * pv;
         rv -= alpha * wv;
-        vst(xv, reinterpret_cast<V *>(x) + v);
         vst(rv, reinterpret_cast<V *>(r) + v);
 #pragma unroll
         for (int c = 0; c < W; ++c) {
@@ -1295,7 +1295,6 @@ __global__ void k_cg_update(int64_t n, T *__restrict__ x, T *__restrict__ r,
         }
     }
     for (int64_t q = nv * W + t0; q < n; q += stride) {
-        x[q] += alpha * p[q];
         const T rq = r[q] - alpha * w[q];
         r[q] = rq;
         rr += (double)rq * (double)rq;
@@ -1305,27 +1304,48 @@ __global__ void k_cg_update(int64_t n, T *__restrict__ x, T *__restrict__ r,
     block_partial<2>(v2, partials);
 }
 
-// p = dinv r + beta p; zero w on boundary nodes for the next operator.
+// x += alpha p with the old p (owed by this iteration's residual update),
+// then, unless the CG has stopped, p = dinv r + beta p and w = 0 on boundary
+// nodes for the next operator.  A stopped CG keeps its p (a residual
+// replacement may continue along it).
 template <typename T>
 __global__ void k_cg_p(int64_t n, int64_t n_bnd, const T *__restrict__ r, T *__restrict__ p,
-                       T *__restrict__ w, const T *__restrict__ dinv, const CgState *st) {
-    if (st->done) return;
+                       T *__restrict__ w, const T *__restrict__ dinv, T *__restrict__ x,
+                       const CgState *st) {
+    if (!st->xstep) return;                   // no update ran in this iteration
+    const bool dir = !st->done;
     using V = typename Vec<T>::type;
     constexpr int W = Vec<T>::W;
-    const T beta = (T)st->beta;
+    const T alpha = (T)st->alpha, beta = (T)st->beta;
     const int64_t nv = n / W, stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nbv = n_bnd / W;            // whole vectors inside the boundary block
-    for (int64_t v = t0; v < nv; v += stride) {
-        const V rv = vld(reinterpret_cast<const V *>(r) + v);
-        const V dv = vld(reinterpret_cast<const V *>(dinv) + v);
-        V pv = vld(reinterpret_cast<V *>(p) + v);
-        pv = dv * rv + beta * pv;
-        vst(pv, reinterpret_cast<V *>(p) + v);
-        if (v < nbv) vst(V(0), reinterpret_cast<V *>(w) + v);
+    if (dir) {
+        for (int64_t v = t0; v < nv; v += stride) {
+            const V rv = vld(reinterpret_cast<const V *>(r) + v);
+            const V dv = vld(reinterpret_cast<const V *>(dinv) + v);
+            V pv = vld(reinterpret_cast<V *>(p) + v);
+            V xv = vld(reinterpret_cast<V *>(x) + v);
+            xv += alpha * pv;
+            pv = dv * rv + beta * pv;
+            vst(xv, reinterpret_cast<V *>(x) + v);
+            vst(pv, reinterpret_cast<V *>(p) + v);
+            if (v < nbv) vst(V(0), reinterpret_cast<V *>(w) + v);
+        }
+        for (int64_t q = nbv * W + t0; q < n_bnd; q += stride) w[q] = 0;
+        for (int64_t q = nv * W + t0; q < n; q += stride) {
+            x[q] += alpha * p[q];
+            p[q] = dinv[q] * r[q] + beta * p[q];
+        }
+    } else {
+        for (int64_t v = t0; v < nv; v += stride) {
+            const V pv = vld(reinterpret_cast<const V *>(p) + v);
+            V xv = vld(reinterpret_cast<V *>(x) + v);
+            xv += alpha * pv;
+            vst(xv, reinterpret_cast<V *>(x) + v);
+        }
+        for (int64_t q = nv * W + t0; q < n; q += stride) x[q] += alpha * p[q];
     }
-    for (int64_t q = nbv * W + t0; q < n_bnd; q += stride) w[q] = 0;
-    for (int64_t q = nv * W + t0; q < n; q += stride) p[q] = dinv[q] * r[q] + beta * p[q];
 }
 
 // r = b - y (FP64), reduces r.r and b.b into st (rr, bb).
@@ -1890,22 +1910,22 @@ hipError_t launch_cg_iteration(sem_ctx c, int level, int prec, void *x, void *r,
     if (e != hipSuccess) return e;
     if (vec64) {
         hipLaunchKernelGGL(k_cg_update<double>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n,
-                           (double *)x, (double *)r, (const double *)p, (const double *)w,
-                           dptr<double>(c, L.dinv64), partials_site(c, 2), st);
+                           (double *)r, (const double *)w, dptr<double>(c, L.dinv64),
+                           partials_site(c, 2), st);
         hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, (int)FIN_UPDATE,
                            (const double *)partials_site(c, 2), (int)vec_grid(n), st);
         hipLaunchKernelGGL(k_cg_p<double>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n, c->n_bnd,
                            (const double *)r, (double *)p, (double *)w, dptr<double>(c, L.dinv64),
-                           (const CgState *)st);
+                           (double *)x, (const CgState *)st);
     } else {
         hipLaunchKernelGGL(k_cg_update<float>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n,
-                           (float *)x, (float *)r, (const float *)p, (const float *)w,
-                           dptr<float>(c, L.dinv32), partials_site(c, 2), st);
+                           (float *)r, (const float *)w, dptr<float>(c, L.dinv32),
+                           partials_site(c, 2), st);
         hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, (int)FIN_UPDATE,
                            (const double *)partials_site(c, 2), (int)vec_grid(n), st);
         hipLaunchKernelGGL(k_cg_p<float>, dim3(vec_grid(n)), dim3(kVecBlock), 0, s, n, c->n_bnd,
                            (const float *)r, (float *)p, (float *)w, dptr<float>(c, L.dinv32),
-                           (const CgState *)st);
+                           (float *)x, (const CgState *)st);
     }
     return hipGetLastError();
 }

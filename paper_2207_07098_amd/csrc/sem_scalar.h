@@ -39,7 +39,11 @@ struct CgState {
     int pause;        // set with that update; the next iteration then stops
     int narrow;       // 1: this level's vectors are FP32, so alpha and beta must
                       // be finite as floats
-    double pad[2];
+    int xstep;        // 1: the residual update of this iteration ran, so the
+                      // direction update still owes x += alpha p (cleared by
+                      // the next p^T A p reduction)
+    int pad_i;
+    double pad;
 };
 
 enum { CG_RUNNING = 0, CG_CAP = 1, CG_BREAKDOWN = 2, CG_NONFINITE = 3 };
@@ -78,6 +82,7 @@ SEM_HD inline void cg_finish_begin(CgState &st, double rz, double rr, double bb)
     st.status = CG_RUNNING;
     st.done = 0;
     st.pause = 0;
+    st.xstep = 0;
     if (!(fabs(rz) <= DBL_MAX) || !(fabs(rr) <= DBL_MAX)) cg_stop(st, CG_NONFINITE);
     else if (rr <= st.tol2) st.done = 1;
 }
@@ -86,6 +91,7 @@ SEM_HD inline void cg_finish_begin(CgState &st, double rz, double rr, double bb)
 // happens only with r = 0 (dinv > 0 off the mask), where the iteration has
 // converged and the next direction is not needed, so beta is 0 then.
 SEM_HD inline void cg_finish_update(CgState &st, double rr, double rz) {
+    st.xstep = 1;                      // x += alpha p with the old p is due
     st.rr = rr;
     st.beta = st.rz != 0.0 ? rz / st.rz : 0.0;
     st.rz = rz;
@@ -107,6 +113,7 @@ SEM_HD inline void cg_finish_reset(CgState &st, double rz, double rr) {
     st.rr = rr;
     st.done = 0;
     st.pause = 0;
+    st.xstep = 0;
     st.status = CG_RUNNING;
     if (!(fabs(rz) <= DBL_MAX) || !(fabs(rr) <= DBL_MAX)) cg_stop(st, CG_NONFINITE);
 }

@@ -141,6 +141,10 @@ int main() {
         n.rz = 1.0;
         cg_finish_update(n, NAN, 1.0);
         CHECK(n.done == 1 && n.status == CG_NONFINITE);
+        // every outcome of the update owes the x step of its iteration
+        // (converged, non-finite, capped, paused or running alike)
+        CHECK(st.xstep == 1 && b.xstep == 1 && b64.xstep == 1 && c.xstep == 1 && p.xstep == 1 &&
+              n.xstep == 1);
     }
     std::printf("beta ok\n");
 
@@ -160,8 +164,13 @@ int main() {
         CgState r = fresh(1);
         r.done = 2;
         r.pause = 1;
+        r.xstep = 1;
         cg_finish_reset(r, 1.0, 1.0);
-        CHECK(r.done == 0 && r.pause == 0 && r.rz == 1.0);
+        CHECK(r.done == 0 && r.pause == 0 && r.rz == 1.0 && r.xstep == 0);
+        CgState bx = fresh(0);
+        bx.xstep = 1;
+        cg_finish_begin(bx, 1.0, 1.0, 1.0);
+        CHECK(bx.xstep == 0);
         CgState ri = fresh(1);
         cg_finish_reset(ri, INFINITY, 1.0);
         CHECK(ri.done == 1 && ri.status == CG_NONFINITE);
