@@ -1488,7 +1488,11 @@ __global__ void __launch_bounds__(256) k_vec_batch(BatchArgs A, int mode) {
         const BatchVecItem it = A.vec_items[w];
         const BatchProb &pb = A.probs[it.prob];
         double s0 = 0, s1 = 0, s2 = 0;
-        const bool skip = (mode != 0 && pb.st->done) || (A.phase == 1 && pb.outer_done);
+        // mode 1: r -= alpha w (x is left to mode 2); mode 2: x += alpha p
+        // with the old p when the update ran, then p and w unless stopped
+        const bool skip = (A.phase == 1 && pb.outer_done) ||
+                          (mode == 1 && pb.st->done) || (mode == 2 && !pb.st->xstep);
+        const bool dir = !pb.st->done;
         if (!skip) {
             T *x, *r, *p, *wv;
             const T *b, *dinv;
@@ -1514,48 +1518,49 @@ __global__ void __launch_bounds__(256) k_vec_batch(BatchArgs A, int mode) {
                     // at even nodes), the odd last node of a problem separately
                     const int64_t ve = it.end >> 1;
                     for (int64_t v = (it.begin >> 1) + threadIdx.x; v < ve; v += blockDim.x) {
-                        d2v xv = vld(reinterpret_cast<const d2v *>(x) + v);
                         d2v rv = vld(reinterpret_cast<const d2v *>(r) + v);
-                        const d2v pv = vld(reinterpret_cast<const d2v *>(p) + v);
                         const d2v wq = vld(reinterpret_cast<const d2v *>(wv) + v);
                         const d2v dv = vld(reinterpret_cast<const d2v *>(dinv) + v);
-                        xv += alpha * pv;
                         rv -= alpha * wq;
-                        vst(xv, reinterpret_cast<d2v *>(x) + v);
                         vst(rv, reinterpret_cast<d2v *>(r) + v);
                         s0 += rv.x * rv.x + rv.y * rv.y;
                         s1 += rv.x * (dv.x * rv.x) + rv.y * (dv.y * rv.y);
                     }
                     if ((it.end & 1) && threadIdx.x == 0) {
                         const int64_t q = it.end - 1;
-                        x[q] += alpha * p[q];
                         const double rq = r[q] - alpha * wv[q];
                         r[q] = rq;
                         s0 += rq * rq;
                         s1 += rq * (dinv[q] * rq);
                     }
-                } else if (mode == 2) {
+                } else if (mode == 2 && dir) {
                     const int64_t ve = it.end >> 1, nb = pb.n_bnd;
                     for (int64_t v = (it.begin >> 1) + threadIdx.x; v < ve; v += blockDim.x) {
                         const d2v rv = vld(reinterpret_cast<const d2v *>(r) + v);
                         const d2v dv = vld(reinterpret_cast<const d2v *>(dinv) + v);
                         d2v pv = vld(reinterpret_cast<const d2v *>(p) + v);
+                        d2v xv = vld(reinterpret_cast<const d2v *>(x) + v);
+                        xv += alpha * pv;
                         pv = dv * rv + beta * pv;
+                        vst(xv, reinterpret_cast<d2v *>(x) + v);
                         vst(pv, reinterpret_cast<d2v *>(p) + v);
                         if (2 * v + 1 < nb) vst(d2v{0.0, 0.0}, reinterpret_cast<d2v *>(wv) + v);
                         else if (2 * v < nb) wv[2 * v] = 0.0;
                     }
                     if ((it.end & 1) && threadIdx.x == 0) {
                         const int64_t q = it.end - 1;
+                        x[q] += alpha * p[q];
                         p[q] = dinv[q] * r[q] + beta * p[q];
                         if (q < nb) wv[q] = 0.0;
                     }
+                } else if (mode == 2) {
+                    for (int64_t q = it.begin + threadIdx.x; q < it.end; q += blockDim.x)
+                        x[q] += alpha * p[q];
                 }
             } else {
                 const T af = (T)alpha, bf = (T)beta;
                 if (mode == 1) {
                     for (int64_t q = it.begin + threadIdx.x; q < it.end; q += blockDim.x) {
-                        x[q] += af * p[q];
                         const T rq = r[q] - af * wv[q];
                         r[q] = rq;
                         s0 += (double)rq * (double)rq;
@@ -1563,8 +1568,12 @@ __global__ void __launch_bounds__(256) k_vec_batch(BatchArgs A, int mode) {
                     }
                 } else if (mode == 2) {
                     for (int64_t q = it.begin + threadIdx.x; q < it.end; q += blockDim.x) {
-                        p[q] = dinv[q] * r[q] + bf * p[q];
-                        if (q < pb.n_bnd) wv[q] = T(0);
+                        const T pq = p[q];
+                        x[q] += af * pq;
+                        if (dir) {
+                            p[q] = dinv[q] * r[q] + bf * pq;
+                            if (q < pb.n_bnd) wv[q] = T(0);
+                        }
                     }
                 }
             }
@@ -1640,6 +1649,8 @@ __global__ void __launch_bounds__(256) k_ref_norms(BatchArgs A) {
 __global__ void __launch_bounds__(256) k_finish_batch(BatchArgs A, int site) {
     BatchProb &pb = A.probs[blockIdx.x];
     CgState *st = pb.st;
+    // the direction pass of the previous iteration has run: no x step owed
+    if (site == FIN_AX && threadIdx.x == 0) st->xstep = 0;
     if ((site == FIN_AX || site == FIN_UPDATE) && st->done) return;
     if (A.phase == 1 && pb.outer_done) return;    // refinement done: no inner solve
     const bool ax = site == FIN_AX;
