@@ -147,6 +147,33 @@ def test_refined_gmres_precision_ladder(setup):
     assert relerr(xc, xp) < 1e-8
 
 
+@pytest.mark.parametrize("name", ["single_all_dirichlet_N4", "single_one_face_N3",
+                                  "pair_mixed_N4"])
+def test_gmres_tiny_meshes(name):
+    """Degenerate sizes: one element whose every face is a boundary (no
+    extension data at all, every coarse vertex masked or a single free
+    corner), and two elements.  The one-element all-Dirichlet problem is
+    solved exactly by its own local solve (one iteration)."""
+    m, N = {"single_all_dirichlet_N4": (F.box(1), 4),
+            "single_one_face_N3": (F.box(1, dirichlet=(1, 0, 0, 0, 0, 0)), 3),
+            "pair_mixed_N4": (F.box((2, 1, 1), dirichlet=(1, 0, 0, 0, 0, 0)), 4)}[name]
+    print("case", name, flush=True)
+    p = Pair(m, N, precisions=("fp64",))
+    hs = HY.HybridSchwarz(m, p.ora)
+    ps = sem.PressureSolver(p.op, restart=30)
+    b = p.ora.rhs_unique(F.random_unique(p.op.n_unique, 5))
+    x, info = ps.solve(p.to_dev(b), tol=1e-10)
+    xc = p.from_dev(x)
+    res = p.ora.true_residual(xc, b)
+    _, oinfo = HY.fgmres(p.ora.apply, hs.apply, b, 1e-10)
+    xp, _ = p.ora.pcg(b, 1e-12)
+    print(name, "gmres its %d (oracle %d) res %.2e" % (info["iterations"], oinfo["iterations"], res),
+          flush=True)
+    assert info["status"] == "SEM_OK" and res <= 1.01e-10
+    assert abs(info["iterations"] - oinfo["iterations"]) <= 2
+    assert relerr(xc, xp) < 1e-8
+
+
 def test_gmres_box16_against_pcg():
     """16^3 deformed box, N = 7 (1.44M unique nodes): the GMRES solution
     reaches 1e-10 (oracle true residual) in far fewer iterations than
