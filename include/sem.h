@@ -449,8 +449,10 @@ sem_status sem_proj_solve(sem_proj proj, const double *b, double *x,
  * (configured at set-up): FP64 iterative refinement r = b - A x, then one
  * GMRES cycle (at most `restart` steps, stopped when its recurrence estimate
  * reaches opts.inner_tol) with FP32 vectors and that precision's operator on
- * A d = r / ||r||, x += ||r|| d (the preconditioner computes in FP64 on FP32
- * vectors); two corrections in a row that do not halve the FP64 residual
+ * A d = r / ||r||, x += ||r|| d (the local solves of the preconditioner
+ * compute in FP32 with eigenvector tables rounded at bind time, the coarse
+ * grid in FP64; the FP32 tables take 4 (3 (N+3)^2 + 3 (N+3)) bytes per
+ * element of workspace when a reduced precision is configured); two corrections in a row that do not halve the FP64 residual
  * switch a 16-bit operator to the FP32 one when SEM_FP32 is configured, and
  * otherwise (or with FP32 already) hand over to FP64 GMRES from the current
  * x, as max_outer corrections do (info->fallback).  info->iterations counts GMRES steps of all levels,

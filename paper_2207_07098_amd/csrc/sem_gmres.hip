@@ -103,12 +103,16 @@ __device__ __forceinline__ int64_t gm_node(const int32_t *bmap, int64_t n_bnd, i
     return gm_interior(n_bnd, e, i, j, k, N);
 }
 
+// The local solves compute in the precision of the vectors they act on:
+// FP64 for the FP64 GMRES, FP32 (tables rounded once at bind time) for the
+// FP32 inner solves of the refinement, whose corrections the FP64 outer
+// residual judges.
 template <typename VT>
 struct FdmParams {
     const VT *r;              // residual (unique, solver order; FP64 or FP32)
-    double *z;                // sum of local solutions (atomic)
-    const double *S;          // [E][3][NE][NE] eigenvectors S[a][m]
-    const double *lam;        // [E][3][NE]
+    VT *z;                    // sum of local solutions (atomic)
+    const VT *S;              // [E][3][NE][NE] eigenvectors S[a][m]
+    const VT *lam;            // [E][3][NE]
     const int32_t *fmap;      // [E][NE][NE^2] box gather map: solver index or -1
     int64_t E;
     // coarse restriction fused into the gather (b0 null: not done here)
@@ -170,15 +174,23 @@ k_fdm_map(const int32_t *__restrict__ ghost, const int32_t *__restrict__ bmap,
 // element waits for one memory round trip (its residual values) instead of
 // three (map, then values; tables).  Register budget: three waves per SIMD
 // up to NE = 11 (FP32 residuals would otherwise take two), two above.
+// Waves per SIMD: FP64 three up to NE = 11 (a few spilled registers at
+// four), FP32 four up to NE = 10 (NE = 11 spills 29 registers at four).
+template <int NE, typename VT>
+struct FdmOcc {
+    static constexpr int value =
+        sizeof(VT) == 8 ? (NE <= 11 ? 3 : 2) : (NE <= 10 ? 4 : (NE <= 11 ? 3 : 2));
+};
+
 template <int NE, typename VT>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, (NE * NE + 63) / 64 * 64),
-                               amdgpu_waves_per_eu(NE <= 11 ? 3 : 2)))
+                               amdgpu_waves_per_eu(FdmOcc<NE, VT>::value)))
 k_fdm(FdmParams<VT> P) {
     constexpr int C = NE * NE, NT = (C + 63) / 64 * 64;
     constexpr int QS = (3 * C + NT - 1) / NT, QL = (3 * NE + NT - 1) / NT;
-    __shared__ double Sl[3][C];
-    __shared__ double Ll[3][NE];
-    __shared__ double box[NE][NE][NE + 1];        // [c][b][a], padded
+    __shared__ VT Sl[3][C];
+    __shared__ VT Ll[3][NE];
+    __shared__ VT box[NE][NE][NE + 1];            // [c][b][a], padded
     __shared__ double red8[NT / 64][8];            // restriction: per-wave corner sums
     const int t = threadIdx.x;
     const bool lane_on = t < C;
@@ -194,8 +206,8 @@ k_fdm(FdmParams<VT> P) {
         for (int q = 0; q < 4; ++q) wab[q] = fa[q & 1] * fb[q >> 1];
     }
     int32_t idx[NE], nidx[NE];
-    double sreg[QS], lreg[QL];
-    auto fetch = [&](int64_t e, int32_t (&ix)[NE], double (&sr)[QS], double (&lr)[QL]) {
+    VT sreg[QS], lreg[QL];
+    auto fetch = [&](int64_t e, int32_t (&ix)[NE], VT (&sr)[QS], VT (&lr)[QL]) {
         const bool ok = e < P.E;
 #pragma unroll
         for (int c = 0; c < NE; ++c)
@@ -203,21 +215,21 @@ k_fdm(FdmParams<VT> P) {
 #pragma unroll
         for (int q = 0; q < QS; ++q) {
             const int x = t + q * NT;
-            sr[q] = (ok && x < 3 * C) ? __builtin_nontemporal_load(P.S + (size_t)e * 3 * C + x) : 0.0;
+            sr[q] = (ok && x < 3 * C) ? __builtin_nontemporal_load(P.S + (size_t)e * 3 * C + x) : VT(0);
         }
 #pragma unroll
         for (int q = 0; q < QL; ++q) {
             const int x = t + q * NT;
-            lr[q] = (ok && x < 3 * NE) ? P.lam[(size_t)e * 3 * NE + x] : 0.0;
+            lr[q] = (ok && x < 3 * NE) ? P.lam[(size_t)e * 3 * NE + x] : VT(0);
         }
     };
     fetch(blockIdx.x, idx, sreg, lreg);
     for (int64_t e = blockIdx.x; e < P.E; e += gridDim.x) {
         // gather the box column (zero where the box holds no data): one
         // unconditional load per point from a valid address, masked after
-        double v[NE];
+        VT v[NE];
 #pragma unroll
-        for (int c = 0; c < NE; ++c) v[c] = (double)P.r[idx[c] >= 0 ? idx[c] : 0];
+        for (int c = 0; c < NE; ++c) v[c] = P.r[idx[c] >= 0 ? idx[c] : 0];
         __syncthreads();                           // previous element done with LDS
 #pragma unroll
         for (int q = 0; q < QS; ++q) {
@@ -231,7 +243,7 @@ k_fdm(FdmParams<VT> P) {
         }
         fetch(e + gridDim.x, nidx, sreg, lreg);   // next element, in flight meanwhile
 #pragma unroll
-        for (int c = 0; c < NE; ++c) v[c] = idx[c] >= 0 ? v[c] : 0.0;
+        for (int c = 0; c < NE; ++c) v[c] = idx[c] >= 0 ? v[c] : VT(0);
         if (P.b0) {
             // P^T r over the element's owned points: sum over c of the t-shape
             // functions times r, then the r, s weights; one wave sum per corner
@@ -240,7 +252,7 @@ k_fdm(FdmParams<VT> P) {
 #pragma unroll
             for (int c = 1; c <= NE - 2; ++c) {
                 const double xc = P.xi[c - 1];
-                const double vc = ((om >> c) & 1u) ? v[c] : 0.0;
+                const double vc = ((om >> c) & 1u) ? (double)v[c] : 0.0;
                 t0 += 0.5 * (1.0 - xc) * vc;
                 t1 += 0.5 * (1.0 + xc) * vc;
             }
@@ -263,10 +275,10 @@ k_fdm(FdmParams<VT> P) {
                 if (gc >= 0) atomicAdd(P.b0 + gc, sum);
             }
         // forward: w = (S_t^T x S_s^T x S_r^T) v
-        double w[NE];
+        VT w[NE];
 #pragma unroll
         for (int m = 0; m < NE; ++m) {             // t-direction, register-local
-            double acc = 0.0;
+            VT acc = 0;
 #pragma unroll
             for (int c = 0; c < NE; ++c) acc += Sl[2][c * NE + m] * v[c];
             w[m] = acc;
@@ -275,11 +287,11 @@ k_fdm(FdmParams<VT> P) {
 #pragma unroll
             for (int c = 0; c < NE; ++c) box[c][b][a] = w[c];
         __syncthreads();
-        double w2[NE];
+        VT w2[NE];
         if (lane_on)                               // s-direction: lane (a, b) -> mode b
 #pragma unroll
             for (int c = 0; c < NE; ++c) {
-                double acc = 0.0;
+                VT acc = 0;
                 for (int bb = 0; bb < NE; ++bb) acc += Sl[1][bb * NE + b] * box[c][bb][a];
                 w2[c] = acc;
             }
@@ -291,12 +303,13 @@ k_fdm(FdmParams<VT> P) {
         if (lane_on)                               // r-direction: lane (a, b) -> mode a
 #pragma unroll
             for (int c = 0; c < NE; ++c) {
-                double acc = 0.0;
+                VT acc = 0;
                 for (int aa = 0; aa < NE; ++aa) acc += Sl[0][aa * NE + a] * box[c][b][aa];
-                const double lsum = Ll[0][a] + Ll[1][b] + Ll[2][c];
+                const VT lsum = Ll[0][a] + Ll[1][b] + Ll[2][c];
                 // a zero sum only for an element without any neighbour or
                 // Dirichlet face (its constant mode): pseudo-inverse
-                w2[c] = lsum > 1e-13 * (Ll[0][NE - 1] + Ll[1][NE - 1] + Ll[2][NE - 1]) ? acc / lsum : 0.0;
+                w2[c] = lsum > VT(1e-13) * (Ll[0][NE - 1] + Ll[1][NE - 1] + Ll[2][NE - 1]) ? acc / lsum
+                                                                                         : VT(0);
             }
         __syncthreads();
         if (lane_on)
@@ -307,7 +320,7 @@ k_fdm(FdmParams<VT> P) {
         if (lane_on)                               // r-direction: point a
 #pragma unroll
             for (int c = 0; c < NE; ++c) {
-                double acc = 0.0;
+                VT acc = 0;
                 for (int aa = 0; aa < NE; ++aa) acc += Sl[0][a * NE + aa] * box[c][b][aa];
                 w2[c] = acc;
             }
@@ -319,13 +332,13 @@ k_fdm(FdmParams<VT> P) {
         if (lane_on) {                             // s-direction: point b
 #pragma unroll
             for (int c = 0; c < NE; ++c) {
-                double acc = 0.0;
+                VT acc = 0;
                 for (int bb = 0; bb < NE; ++bb) acc += Sl[1][b * NE + bb] * box[c][bb][a];
                 w2[c] = acc;
             }
 #pragma unroll
             for (int c = 0; c < NE; ++c) {         // t-direction: point c, then scatter
-                double acc = 0.0;
+                VT acc = 0;
 #pragma unroll
                 for (int m = 0; m < NE; ++m) acc += Sl[2][c * NE + m] * w2[m];
                 if (idx[c] >= 0) atomicAdd(P.z + idx[c], acc);
@@ -342,7 +355,7 @@ struct CoarseParams {
     double *b0;               // coarse right-hand side (restrict)
     VT *y;                    // fine output z (combine)
     const double *x0;         // coarse solution (interp)
-    const double *zs;         // Schwarz sum (interp)
+    const VT *zs;             // Schwarz sum (interp)
     const double *W;          // counting weights (interp)
     const int32_t *cmap;      // [E][8] coarse solver index or -1
     const uint8_t *owner;     // [E][n_b] 1 on the first copy of each boundary node
@@ -443,7 +456,7 @@ __global__ void __launch_bounds__(64) k_combine_e(CoarseParams<VT> P) {
                 double zc = 0.0;
 #pragma unroll
                 for (int c = 0; c < 8; ++c) zc += wi[c & 1] * wj[(c >> 1) & 1] * wk[(c >> 2) & 1] * xc[c];
-                const double zsv = P.zs ? P.W[g] * P.zs[g] : 0.0;
+                const double zsv = P.zs ? P.W[g] * (double)P.zs[g] : 0.0;
                 P.y[g] = (VT)(dir ? 0.0 : zsv + zc);
             }
         }
@@ -813,11 +826,12 @@ struct sem_gmres_s {
     size_t ws_bytes = 0;
     size_t coarse_ws = 0;
     double *dS = nullptr, *dlam = nullptr, *dW = nullptr, *dxi = nullptr;
+    float *dS32 = nullptr, *dlam32 = nullptr;   // FP32 copies (reduced precisions only)
     int32_t *dghost = nullptr, *dcmap = nullptr;
     uint8_t *downer = nullptr;
     int32_t *dfmap = nullptr;
     uint16_t *down = nullptr;
-    int fdm_per_cu = 0;              // resident FDM workgroups per CU
+    int fdm_per_cu[2] = {0, 0};      // resident FDM workgroups per CU (FP64, FP32)
     double *zs = nullptr, *b0 = nullptr, *x0 = nullptr;
     double *V = nullptr, *Z = nullptr, *w = nullptr, *r = nullptr;
     double *part = nullptr, *coef = nullptr;
@@ -1118,12 +1132,16 @@ static size_t gm_layout(sem_gmres G, size_t *off) {
     off[18] = take((size_t)E * c->nb);                // owner flags
     off[19] = take(4 * (size_t)E * NE * NE * NE);    // box gather map
     off[20] = take(2 * (size_t)E * NE * NE);         // owned-point masks of the box columns
+    // FP32 eigenvector tables for the inner solves of the refinement
+    const bool low = (c->precisions & ~SEM_PREC_BIT(SEM_FP64)) != 0;
+    off[21] = take(low ? 4 * (size_t)E * 3 * NE * NE : 0);
+    off[22] = take(low ? 4 * (size_t)E * 3 * NE : 0);
     return o;
 }
 
 extern "C" sem_status sem_gmres_workspace_size(sem_gmres G, size_t *bytes) {
     if (!G || !bytes) return gfail(G, SEM_ERR_INVALID, "null argument");
-    size_t off[21];
+    size_t off[23];
     *bytes = gm_layout(G, off);
     return SEM_OK;
 }
@@ -1131,7 +1149,7 @@ extern "C" sem_status sem_gmres_workspace_size(sem_gmres G, size_t *bytes) {
 extern "C" sem_status sem_gmres_bind_workspace(sem_gmres G, void *dev, size_t bytes,
                                                sem_stream stream) {
     if (!G || !dev) return gfail(G, SEM_ERR_INVALID, "null argument");
-    size_t off[21];
+    size_t off[23];
     const size_t need = gm_layout(G, off);
     if (bytes < need)
         return gfail(G, SEM_ERR_OOM, "workspace of " + std::to_string(bytes) + " bytes, need " +
@@ -1169,6 +1187,17 @@ extern "C" sem_status sem_gmres_bind_workspace(sem_gmres G, void *dev, size_t by
     G->down = reinterpret_cast<uint16_t *>(w + off[20]);
     SEM_HIP(c, hipMemcpyAsync(G->dS, G->S.data(), 8 * G->S.size(), hipMemcpyHostToDevice, s));
     SEM_HIP(c, hipMemcpyAsync(G->dlam, G->lam.data(), 8 * G->lam.size(), hipMemcpyHostToDevice, s));
+    G->dS32 = G->dlam32 = nullptr;
+    if (off[22] > off[21]) {
+        G->dS32 = reinterpret_cast<float *>(w + off[21]);
+        G->dlam32 = reinterpret_cast<float *>(w + off[22]);
+        // rounded once; the copies are synchronous (the host buffers are
+        // temporaries)
+        std::vector<float> s32(G->S.begin(), G->S.end()), l32(G->lam.begin(), G->lam.end());
+        SEM_HIP(c, hipMemcpyAsync(G->dS32, s32.data(), 4 * s32.size(), hipMemcpyHostToDevice, s));
+        SEM_HIP(c, hipMemcpyAsync(G->dlam32, l32.data(), 4 * l32.size(), hipMemcpyHostToDevice, s));
+        SEM_HIP(c, hipStreamSynchronize(s));
+    }
     SEM_HIP(c, hipMemcpyAsync(G->dghost, G->ghost.data(), 4 * G->ghost.size(), hipMemcpyHostToDevice, s));
     SEM_HIP(c, hipMemcpyAsync(G->dcmap, G->cmap.data(), 4 * G->cmap.size(), hipMemcpyHostToDevice, s));
     SEM_HIP(c, hipMemcpyAsync(G->dW, G->W.data(), 8 * G->W.size(), hipMemcpyHostToDevice, s));
@@ -1193,8 +1222,8 @@ extern "C" sem_status sem_gmres_bind_workspace(sem_gmres G, void *dev, size_t by
 }
 
 // z = M^-1 r: parts & 1 local Schwarz solves, parts & 2 coarse grid.  r and
-// z are FP64 or FP32 vectors; the local solves and the coarse grid compute
-// in FP64 either way.
+// z are FP64 or FP32 vectors; the local solves compute in the vectors'
+// precision, the coarse grid in FP64 either way.
 template <typename VT>
 static sem_status precondition(sem_gmres G, const VT *r, VT *z, unsigned parts, hipStream_t s) {
     sem_ctx c = G->ctx;
@@ -1204,23 +1233,38 @@ static sem_status precondition(sem_gmres G, const VT *r, VT *z, unsigned parts, 
     // kernel's gather (the residual is read once)
     const bool fused = local && coarse;
     if (coarse) SEM_HIP(c, launch_fill(G->b0, G->coarse->n_unique, 0.0, s));
+    // the Schwarz sum in the vectors' precision (an FP32 sum uses the first
+    // half of the FP64 buffer)
+    VT *zs = reinterpret_cast<VT *>(G->zs);
+    constexpr bool f32 = std::is_same<VT, float>::value;
     if (local) {
-        SEM_HIP(c, launch_fill(G->zs, n, 0.0, s));
-        FdmParams<VT> P{r,       G->zs, G->dS, G->dlam, G->dfmap, c->E,
+        const VT *S, *lam;
+        if constexpr (f32) {
+            if (!G->dS32) return gfail(G, SEM_ERR_STATE, "no FP32 tables: no reduced precision at set-up");
+            S = G->dS32;
+            lam = G->dlam32;
+            SEM_HIP(c, launch_fill32(zs, n, 0.0f, s));
+        } else {
+            S = G->dS;
+            lam = G->dlam;
+            SEM_HIP(c, launch_fill(zs, n, 0.0, s));
+        }
+        FdmParams<VT> P{r,       zs, S, lam, G->dfmap, c->E,
                         G->down, fused ? G->b0 : nullptr, G->dcmap, G->dxi};
         // persistent: the workgroups resident at once, each taking every
         // grid-th element
 #define SEM_FDM(ne)                                                                          \
     case ne: {                                                                               \
         const int nt = ((ne) * (ne) + 63) / 64 * 64;                                         \
-        if (G->fdm_per_cu == 0) {                                                            \
+        int &per_cu = G->fdm_per_cu[f32 ? 1 : 0];                                            \
+        if (per_cu == 0) {                                                                   \
             int nb = 0;                                                                      \
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fdm<ne, VT>, nt, 0) !=   \
                     hipSuccess || nb < 1)                                                    \
                 nb = 1;                                                                      \
-            G->fdm_per_cu = nb;                                                              \
+            per_cu = nb;                                                                     \
         }                                                                                    \
-        const int64_t grid = std::min<int64_t>(c->E, (int64_t)G->fdm_per_cu * c->num_cus);   \
+        const int64_t grid = std::min<int64_t>(c->E, (int64_t)per_cu * c->num_cus);         \
         hipLaunchKernelGGL((k_fdm<ne, VT>), dim3((unsigned)grid), dim3(nt), 0, s, P);        \
         break;                                                                               \
     }
@@ -1232,7 +1276,7 @@ static sem_status precondition(sem_gmres G, const VT *r, VT *z, unsigned parts, 
 #undef SEM_FDM
         SEM_HIP(c, hipGetLastError());
     }
-    CoarseParams<VT> C{r,       G->b0,   z,     G->x0, local ? G->zs : nullptr, G->dW, G->dcmap,
+    CoarseParams<VT> C{r,       G->b0,   z,     G->x0, local ? zs : nullptr, G->dW, G->dcmap,
                        G->downer, dptr<int32_t>(c, c->L.bmap), G->dxi, c->E, c->n_bnd, c->nb};
     if (coarse) {
 #define SEM_RESTRICT(n1)                                                                    \

@@ -88,7 +88,7 @@ def test_gmres_solve_matches_oracle(name):
 @pytest.mark.parametrize("name", ["deformed4_N5", "ogrid_N3", "deformed3_N7"])
 def test_refined_gmres(name, prec):
     """FP64 refinement around FP32-vector GMRES with the FP32, FP16 or BF16
-    operator (hybrid Schwarz preconditioner in FP64 on FP32 vectors): oracle
+    operator (local solves in FP32, coarse grid in FP64): oracle
     true residual 1e-10 without a hand-over to FP64, solution as the
     oracle's PCG."""
     _, hs, _ = case(name)
