@@ -148,15 +148,19 @@ def test_refined_gmres_precision_ladder(setup):
 
 
 @pytest.mark.parametrize("name", ["single_all_dirichlet_N4", "single_one_face_N3",
-                                  "pair_mixed_N4"])
+                                  "pair_mixed_N4", "pair_mixed_N2", "pair_mixed_N13"])
 def test_gmres_tiny_meshes(name):
     """Degenerate sizes: one element whose every face is a boundary (no
     extension data at all, every coarse vertex masked or a single free
-    corner), and two elements.  The one-element all-Dirichlet problem is
-    solved exactly by its own local solve (one iteration)."""
+    corner), and two elements, also at the smallest and the largest order
+    the local solves take (N = 2 and 13: boxes of 5^3 and 16^3 points).
+    The one-element all-Dirichlet problem is solved exactly by its own
+    local solve (one iteration)."""
+    pair = F.box((2, 1, 1), dirichlet=(1, 0, 0, 0, 0, 0))
     m, N = {"single_all_dirichlet_N4": (F.box(1), 4),
             "single_one_face_N3": (F.box(1, dirichlet=(1, 0, 0, 0, 0, 0)), 3),
-            "pair_mixed_N4": (F.box((2, 1, 1), dirichlet=(1, 0, 0, 0, 0, 0)), 4)}[name]
+            "pair_mixed_N4": (pair, 4), "pair_mixed_N2": (pair, 2),
+            "pair_mixed_N13": (pair, 13)}[name]
     print("case", name, flush=True)
     p = Pair(m, N, precisions=("fp64",))
     hs = HY.HybridSchwarz(m, p.ora)
@@ -220,3 +224,6 @@ def test_gmres_rejections():
     q = Pair(F.box(2), 1, precisions=("fp64",))
     with pytest.raises(sem.SemError):
         sem.PressureSolver(q.op)                       # N = 1
+    big = sem.Operator(F.box(1), 14, precisions=("fp64",), solver=True)
+    with pytest.raises(sem.SemError):
+        sem.PressureSolver(big)                        # N = 14: beyond the local solves
