@@ -104,30 +104,41 @@ def kernel_ms(op, prec, u, y, nb, stream, reps=20):
 
 
 def mfma_compare(op, u32, nb, stream):
-    """16-bit operator on matrix cores (tile pipeline 2) against the tuned
-    SIMT tile: kernel times and algorithmic GB/s (1.21 GB per application at
-    48^3, N = 7)."""
+    """16-bit operators on matrix cores against the SIMT kernel (best of 1,
+    2, 4 elements per workgroup each): tile pipeline 2 (16-bit hi + lo
+    operand pairs) and pipeline 3 (FP32 operands); kernel times and
+    algorithmic GB/s (1.21 GB per application at 48^3, N = 7)."""
     import torch
     y = torch.zeros_like(u32)
     B = op.n_local * (6 * 2 + 4) + 2 * 4 * op.n_unique                 # FP32 vectors
     out = {}
     for prec in ("fp16", "bf16"):
         tuned = op.get_tile(prec)
-        simt = kernel_ms(op, prec, u32, y, nb, stream)
-        best = None
-        for epb in (1, 2, 4):
-            op.set_tile(prec, elements_per_block=epb, grid_cap=0, xcd_remap=0, pipeline=2)
-            ms = kernel_ms(op, prec, u32, y, nb, stream)
-            if best is None or ms < best[1]:
-                best = (epb, ms)
+
+        def best_of(pipe):
+            best = None
+            for epb in (1, 2, 4):
+                op.set_tile(prec, elements_per_block=epb, grid_cap=0, xcd_remap=0, pipeline=pipe)
+                ms = kernel_ms(op, prec, u32, y, nb, stream)
+                if best is None or ms < best[1]:
+                    best = (epb, ms)
+            return best
+        simt, m16, m32 = best_of(0), best_of(2), best_of(3)
         op.set_tile(prec, **tuned)
-        # issued matrix-core work: 36 v_mfma_f32_16x16x16 per element (hi/lo
-        # operand pairs, three directions forward and back, two column halves)
-        flops = 36 * 2 * 16 ** 3 * op.E
-        out[prec] = {"simt_ms": simt, "mfma_ms": best[1], "mfma_elements_per_block": best[0],
-                     "simt_GBps": B / simt / 1e6, "mfma_GBps": B / best[1] / 1e6,
-                     "mfma_issued_TFLOPs": flops / (best[1] * 1e-3) / 1e12,
-                     "mfma_frac_of_dense_peak": flops / (best[1] * 1e-3) / 2.5e15}
+        # issued matrix-core work per element: pipeline 2, 36
+        # v_mfma_f32_16x16x16 (hi/lo pairs, three directions forward and
+        # back, two column halves); pipeline 3, 48 v_mfma_f32_16x16x4f32
+        f16 = 36 * 2 * 16 ** 3 * op.E
+        f32 = 48 * 2 * 16 * 16 * 4 * op.E
+        out[prec] = {"simt_ms": simt[1], "simt_elements_per_block": simt[0],
+                     "mfma_ms": m16[1], "mfma_elements_per_block": m16[0],
+                     "simt_GBps": B / simt[1] / 1e6, "mfma_GBps": B / m16[1] / 1e6,
+                     "mfma_issued_TFLOPs": f16 / (m16[1] * 1e-3) / 1e12,
+                     "mfma_frac_of_dense_peak": f16 / (m16[1] * 1e-3) / 2.5e15,
+                     "mfma_fp32_ms": m32[1], "mfma_fp32_elements_per_block": m32[0],
+                     "mfma_fp32_GBps": B / m32[1] / 1e6,
+                     "mfma_fp32_issued_TFLOPs": f32 / (m32[1] * 1e-3) / 1e12,
+                     "mfma_fp32_frac_of_dense_fp32_peak": f32 / (m32[1] * 1e-3) / 157.3e12}
         log("mfma", prec, out[prec])
     return out
 

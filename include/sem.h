@@ -248,7 +248,15 @@ typedef struct {
                                      weighted derivatives enter as pairs of
                                      16-bit numbers (hi + lo), products
                                      accumulate in FP32; sem_autotune tries
-                                     it for FP16 factors only                */
+                                     it for FP16 factors only;
+                                     3: element operator with the derivative
+                                     contractions on FP32 matrix cores (FP32
+                                     operands, FP32 accumulation: the SIMT
+                                     kernel's precision), FP32/FP16/BF16
+                                     factors at N = 7; sem_autotune tries it
+                                     for each of them. Pipelines 2 and 3
+                                     apply to the atomic assembled operator;
+                                     the other forms use pipeline 0.         */
 } sem_tile;
 
 typedef struct {

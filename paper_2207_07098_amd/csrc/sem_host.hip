@@ -566,14 +566,16 @@ static bool tile_valid(sem_ctx c, int prec, const sem_tile &t) {
     const int C = c->n1 * c->n1;
     if (t.elements_per_block < 1 || t.elements_per_block * C > 256) return false;
     if (t.grid_cap < 0 || (t.grid_cap % 8) != 0) return false;
-    if (t.pipeline < 0 || t.pipeline > 2 || t.xcd_remap < 0 || t.xcd_remap > 1) return false;
+    if (t.pipeline < 0 || t.pipeline > 3 || t.xcd_remap < 0 || t.xcd_remap > 1) return false;
     // 2: matrix-core element operator, for 16-bit factors at N = 7
     if (t.pipeline == 2 && !(c->n1 == 8 && (prec == SEM_FP16_SCALED || prec == SEM_BF16_SCALED)))
         return false;
+    // 3: FP32 matrix-core element operator, for FP32 and 16-bit factors at N = 7
+    if (t.pipeline == 3 && !(c->n1 == 8 && prec != SEM_FP64)) return false;
     const size_t sz = prec == SEM_FP64 ? 8 : 4;
     const int nslots = t.elements_per_block;        // one LDS slot per element
     // three LDS buffers per element slot plus D (the operator kernels' layout)
-    const size_t lds = t.pipeline == 2
+    const size_t lds = t.pipeline >= 2
                            ? (size_t)nslots * kMfmaSlotBytes
                            : ((size_t)nslots * 3 * c->n1 * c->n1 * (c->n1 + 1) + C) * sz;
     return lds <= c->max_lds;
@@ -672,13 +674,15 @@ extern "C" sem_status sem_autotune(sem_ctx c, sem_precision prec, int reps, cons
     double best_ms = INFINITY;
     AxTile best_t = saved;
     int nres = 0;
-    // pipeline 2 (matrix cores) is a candidate for FP16 factors at N = 7,
-    // where the hi + lo operand pairs keep ~22 bits (FP32 arithmetic: 24);
-    // with BF16 pairs (~17 bits) the refined solves take more iterations
-    // than with the SIMT kernel (48^3: 1683 against 1474), so BF16 uses the
-    // matrix cores only when the tile is set explicitly
-    const int npipe = prec == SEM_FP16_SCALED ? 3 : 2;
-    for (int pipe = 0; pipe < npipe; ++pipe)
+    // pipeline 2 (matrix cores, 16-bit operand pairs) is a candidate for
+    // FP16 factors at N = 7, where the hi + lo pairs keep ~22 bits (FP32
+    // arithmetic: 24); with BF16 pairs (~17 bits) the refined solves take
+    // more iterations than with the SIMT kernel (48^3: 1683 against 1474),
+    // so BF16 uses it only when the tile is set explicitly.  Pipeline 3
+    // (FP32 matrix cores) keeps FP32 arithmetic and is a candidate for every
+    // reduced precision at N = 7 (tile_valid rules out the rest).
+    for (int pipe = 0; pipe < 4; ++pipe)
+    if (pipe != 2 || prec == SEM_FP16_SCALED)
     for (int epb : epbs)
         for (int cap : caps)
             for (int xcd = 0; xcd < 2; ++xcd) {

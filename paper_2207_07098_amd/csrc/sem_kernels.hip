@@ -255,24 +255,34 @@ __device__ __forceinline__ void load_g6(const float *plane, int col, float (&g)[
         c = __builtin_nontemporal_load(q + 2 * C);
     g[0] = a.x; g[1] = a.y; g[2] = b.x; g[3] = b.y; g[4] = c.x; g[5] = c.y;
 }
-template <int C>
-__device__ __forceinline__ void load_g6(const _Float16 *plane, int col, float (&g)[6]) {
-    // the six 16-bit values of a point are 12 contiguous bytes: one load
-    const u3v w = __builtin_nontemporal_load(reinterpret_cast<const u3v *>(plane + (size_t)col * 6));
+// the six 16-bit values of a point are 12 contiguous bytes: one load, kept
+// packed until use where registers are short (the stride is 12 bytes, not
+// sizeof(u3v), which is padded to 16)
+__device__ __forceinline__ u3v load_g6_raw(const void *plane, int col) {
+    return __builtin_nontemporal_load(
+        reinterpret_cast<const u3v *>(static_cast<const char *>(plane) + (size_t)col * 12));
+}
+__device__ __forceinline__ void unpack_g6(const _Float16 *, const u3v w, float (&g)[6]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         g[2 * a] = (float)__builtin_bit_cast(_Float16, (uint16_t)(w[a] & 0xffffu));
         g[2 * a + 1] = (float)__builtin_bit_cast(_Float16, (uint16_t)(w[a] >> 16));
     }
 }
-template <int C>
-__device__ __forceinline__ void load_g6(const bf16_t *plane, int col, float (&g)[6]) {
-    const u3v w = __builtin_nontemporal_load(reinterpret_cast<const u3v *>(plane + (size_t)col * 6));
+__device__ __forceinline__ void unpack_g6(const bf16_t *, const u3v w, float (&g)[6]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         g[2 * a] = __uint_as_float(w[a] << 16);
         g[2 * a + 1] = __uint_as_float(w[a] & 0xffff0000u);
     }
+}
+template <int C>
+__device__ __forceinline__ void load_g6(const _Float16 *plane, int col, float (&g)[6]) {
+    unpack_g6(plane, load_g6_raw(plane, col), g);
+}
+template <int C>
+__device__ __forceinline__ void load_g6(const bf16_t *plane, int col, float (&g)[6]) {
+    unpack_g6(plane, load_g6_raw(plane, col), g);
 }
 
 // Waves per SIMD the compiler must allow for: bounds the register budget.
@@ -841,6 +851,170 @@ __global__ void __launch_bounds__(256) k_ax_mfma(AxParams<8, GS> P) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Element operator on FP32 matrix cores (N = 7; FP32, FP16 or BF16 factors):
+// the six derivative contractions of Eq. (9) as 16x16x4 FP32 MFMAs with the
+// block-diagonal A = diag(D, D) (two 8-column groups of an element share one
+// 16x16 product), so the arithmetic keeps FP32 precision, as in the SIMT
+// kernel, with no operand splitting and no scaling of u.  The vector units
+// keep the gather, the G-weighting and the summation.  The operands are
+// staged in LDS in the three layouts of the 16-bit matrix-core kernel
+// (contraction index fastest within groups of 8), as FP32 values.  Like the
+// SIMT kernel, the map entries of the next element are fetched while the
+// current one is computed.
+// ---------------------------------------------------------------------------
+
+// out = diag(M, M) * B over the 64 columns of an element (B read from `src`,
+// result to `dst`, both with the contraction index fastest within groups of
+// 8; column c addresses the group at c * 8).  16x16x4 layout: lane l holds
+// A[l % 16][k], B[k][l % 16] with k = 4 s + l / 16 in step s, and C rows
+// 4 (l / 16) .. +3 of column l % 16.  Rows k < 8 of B are column group 0 of
+// the 16-column tile, rows k >= 8 group 1 (32 columns further).
+__device__ __forceinline__ void mfma32_dir(const float (&a)[4], const float *src, float *dst,
+                                           int lane) {
+    const int q = lane >> 4, grp = q >> 1, m0 = 4 * (q & 1);
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+        const int c0 = 16 * n + (lane & 15);
+        f4v acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const float b = src[(c0 + 32 * (s >> 1)) * 8 + 4 * (s & 1) + q];
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b, acc, 0, 0, 0);
+        }
+        *reinterpret_cast<f4v *>(dst + (c0 + 32 * grp) * 8 + m0) = acc;
+    }
+}
+
+template <typename GS, typename VT>
+__global__ void __launch_bounds__(256) k_ax_mfma32(AxParams<8, GS> P) {
+    // three waves per SIMD (about 160 registers with the MFMA results);
+    // capped at four it spills 10 registers and is 10% slower
+    constexpr int N1 = 8, N = 7, C = 64, NP = 512;
+    static_assert(6 * NP * 4 == kMfmaSlotBytes, "FP32 matrix-core slot layout");
+    constexpr bool SCALED = sizeof(GS) == 2;
+    CgState *st = P.st;
+    if (st && (st->done || st->pause)) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Lane<N1> L(threadIdx.x);
+    const int lane = threadIdx.x & 63;
+    float *UR = reinterpret_cast<float *>(smem_raw + (size_t)L.slot * kMfmaSlotBytes);
+    float *US = UR + NP, *UT = US + NP, *FR = UT + NP, *FS = FR + NP, *FT = FS + NP;
+    // A operands diag(D, D) and diag(D^T, D^T): step s, row lane % 16,
+    // contraction entry 4 s + lane / 16
+    float aF[4], aB[4];
+    {
+        const int row = lane & 15, q = lane >> 4;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int kk = 4 * s + q;
+            const bool blk = (row >> 3) == (kk >> 3);
+            aF[s] = blk ? (float)P.D[(row & 7) * N1 + (kk & 7)] : 0.f;
+            aB[s] = blk ? (float)P.D[(kk & 7) * N1 + (row & 7)] : 0.f;
+        }
+    }
+    AxMesh<GS> M{P.u, P.y, P.wb, P.G, P.gscale, P.bmap, P.E, P.n_bnd, 0, OUT_ATOMIC,
+                 nullptr, 1.0, 0.0};
+    VT *__restrict__ Y = reinterpret_cast<VT *>(P.y);
+    const int i = L.i, j = L.j, col = L.col;
+    auto elem_of = [&](int64_t git, bool &act) {
+        const int64_t e = git * P.epb + L.slot;
+        act = (L.slot < P.epb) && (e < P.E);
+        return act ? e : (int64_t)0;           // inactive waves work on element 0
+    };
+    int32_t bm[N1];
+    {
+        bool act;
+        load_map<N1>(P.bmap, L, elem_of(blockIdx.x, act), bm);
+    }
+    double dot = 0.0;
+    for (int64_t git = blockIdx.x; git < P.ngroups; git += gridDim.x) {
+        bool active, act_n;
+        const int64_t ec = elem_of(git, active);
+        int32_t bidx[N1];
+        float u[N1];
+        // factors: 16-bit ones stay packed (3 registers per point) until use
+        float g[SCALED ? 1 : N1][6];
+        u3v graw[SCALED ? N1 : 1];
+        gather_u<N1, GS, VT>(M, L, ec, active, bm, u, bidx);
+        const GS *Ge = P.G + (size_t)ec * NP * 6;
+#pragma unroll
+        for (int k = 0; k < N1; ++k) {
+            if constexpr (SCALED) graw[k] = load_g6_raw(Ge + (size_t)k * C * 6, col);
+            else load_g6<C>(Ge + (size_t)k * C * 6, col, g[k]);
+        }
+        if (git + gridDim.x < P.ngroups) load_map<N1>(P.bmap, L, elem_of(git + gridDim.x, act_n), bm);
+#pragma unroll
+        for (int k = 0; k < N1; ++k) {
+            UR[k * C + j * N1 + i] = u[k];
+            US[k * C + i * N1 + j] = u[k];
+        }
+        *reinterpret_cast<f4v *>(UT + col * N1) = f4v{u[0], u[1], u[2], u[3]};
+        *reinterpret_cast<f4v *>(UT + col * N1 + 4) = f4v{u[4], u[5], u[6], u[7]};
+        __syncthreads();
+        mfma32_dir(aF, UR, FR, lane);
+        mfma32_dir(aF, US, FS, lane);
+        mfma32_dir(aF, UT, FT, lane);
+        __syncthreads();
+        // G-weighting at the lane's own column
+        double edot = 0.0;
+        {
+            const f4v t0 = *reinterpret_cast<const f4v *>(FT + col * N1);
+            const f4v t1 = *reinterpret_cast<const f4v *>(FT + col * N1 + 4);
+            const float utv[N1] = {t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z, t1.w};
+            float wtv[N1];
+#pragma unroll
+            for (int k = 0; k < N1; ++k) {
+                const float ur = FR[k * C + j * N1 + i];
+                const float us = FS[k * C + i * N1 + j];
+                const float ut = utv[k];
+                float gk[6];
+                if constexpr (SCALED) unpack_g6(Ge, graw[k], gk);
+                else
+#pragma unroll
+                    for (int a = 0; a < 6; ++a) gk[a] = g[k][a];
+                const float wr = gk[0] * ur + gk[3] * us + gk[4] * ut;
+                const float ws = gk[3] * ur + gk[1] * us + gk[5] * ut;
+                wtv[k] = gk[4] * ur + gk[5] * us + gk[2] * ut;
+                if (P.partials) edot += (double)(ur * wr + us * ws + ut * wtv[k]);
+                UR[k * C + j * N1 + i] = wr;
+                US[k * C + i * N1 + j] = ws;
+            }
+            *reinterpret_cast<f4v *>(UT + col * N1) = f4v{wtv[0], wtv[1], wtv[2], wtv[3]};
+            *reinterpret_cast<f4v *>(UT + col * N1 + 4) = f4v{wtv[4], wtv[5], wtv[6], wtv[7]};
+        }
+        __syncthreads();
+        mfma32_dir(aB, UR, FR, lane);
+        mfma32_dir(aB, US, FS, lane);
+        mfma32_dir(aB, UT, FT, lane);
+        __syncthreads();
+        const float sc = SCALED ? P.gscale[ec] : 1.f;
+        if (P.partials && active) dot += SCALED ? edot * (double)sc : edot;
+        {
+            const f4v t0 = *reinterpret_cast<const f4v *>(FT + col * N1);
+            const f4v t1 = *reinterpret_cast<const f4v *>(FT + col * N1 + 4);
+            const float wtv[N1] = {t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z, t1.w};
+#pragma unroll
+            for (int k = 0; k < N1; ++k) {
+                float w = FR[k * C + j * N1 + i] + FS[k * C + i * N1 + j] + wtv[k];
+                if (SCALED) w *= sc;
+                if (active) {
+                    if (L.bpt(k)) {
+                        if (bidx[k] >= 0) unsafeAtomicAdd(Y + bidx[k], (VT)w);
+                    } else {
+                        __builtin_nontemporal_store((VT)w, Y + interior_index(P.n_bnd, ec, i, j, k, N));
+                    }
+                }
+            }
+        }
+        __syncthreads();                        // LDS is rewritten by the next element
+    }
+    if (P.partials) {
+        double v[1] = {dot};
+        block_partial<1>(v, P.partials);
+    }
+}
+
 template <int N1, typename GS>
 hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const void *Dp,
                          const void *DTp, const void *u, void *y, int in_local, int out_mode,
@@ -855,8 +1029,11 @@ hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const v
     // matrix-core variant: 16-bit factors, N = 7, atomic summation
     constexpr bool MFMA_OK = N1 == 8 && sizeof(GS) == 2;
     const bool mfma = MFMA_OK && t.pipeline == 2 && !in_local && out_mode == OUT_ATOMIC;
-    const size_t lds = mfma ? (size_t)nslots * kMfmaSlotBytes
-                            : ((size_t)nslots * 3 * BUF + C) * sizeof(T);
+    // FP32 matrix cores: FP32, FP16 or BF16 factors, N = 7, atomic summation
+    constexpr bool MFMA32_OK = N1 == 8 && sizeof(GS) <= 4;
+    const bool mfma32 = MFMA32_OK && t.pipeline == 3 && !in_local && out_mode == OUT_ATOMIC;
+    const size_t lds = (mfma || mfma32) ? (size_t)nslots * kMfmaSlotBytes
+                                        : ((size_t)nslots * 3 * BUF + C) * sizeof(T);
     if (lds > c->max_lds) return hipErrorInvalidConfiguration;
     AxParams<N1, GS> P;
     P.u = u;
@@ -904,6 +1081,20 @@ hipError_t ax_dispatch_n(sem_ctx c, const void *Gp, const float *gscale, const v
             return hipGetLastError();
         } else {
             return hipErrorInvalidValue;
+        }
+    }
+    if constexpr (MFMA32_OK) {
+        if (mfma32) {
+            if (vec64)
+                hipLaunchKernelGGL((k_ax_mfma32<GS, double>), dim3((unsigned)grid), dim3(threads),
+                                   lds, s, P);
+            else
+                hipLaunchKernelGGL((k_ax_mfma32<GS, float>), dim3((unsigned)grid), dim3(threads),
+                                   lds, s, P);
+            if (partials)
+                hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, (int)FIN_AX,
+                                   (const double *)partials, (int)grid, st);
+            return hipGetLastError();
         }
     }
     if constexpr (MFMA_OK) {
