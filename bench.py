@@ -328,8 +328,8 @@ def bench_ogrid(args):
     solves = {}
     ps = sem.PressureSolver(op, restart=args.ogrid_restart)
     for prec in ("fp64", "fp32", "bf16"):
-        if prec == "bf16":
-            op.set_tile("bf16", elements_per_block=2, grid_cap=0, xcd_remap=0, pipeline=2)
+        if prec == "bf16":      # BF16 factors, contractions on FP32 matrix cores
+            op.set_tile("bf16", elements_per_block=1, grid_cap=0, xcd_remap=0, pipeline=3)
         x, info = ps.solve(b, tol=1e-10, precision=prec, raise_on_error=False)
         key = "gmres_hybrid_schwarz" + ("" if prec == "fp64" else "_%s_refined" % prec)
         solves[key] = info
