@@ -510,6 +510,21 @@ __device__ __forceinline__ void gm_store_sums(const double *acc, double *part, d
     }
 }
 
+// The basis sweeps stream every vector once per pass (the basis exceeds
+// the caches at the sizes that matter): non-temporal loads and stores.
+template <typename T>
+struct NtPair {
+    typedef T type __attribute__((ext_vector_type(2)));
+};
+template <typename T>
+__device__ __forceinline__ typename NtPair<T>::type gm_ld(const T *base, int64_t p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const typename NtPair<T>::type *>(base) + p);
+}
+template <typename T>
+__device__ __forceinline__ void gm_st(typename NtPair<T>::type v, T *base, int64_t p) {
+    __builtin_nontemporal_store(v, reinterpret_cast<typename NtPair<T>::type *>(base) + p);
+}
+
 // part[blk][i] = X_i . v (i < L), part[blk][L] = v . v
 template <int L, typename T>
 __global__ void __launch_bounds__(kGmBlock) k_gm_dots(int64_t n, int64_t ld,
@@ -523,11 +538,11 @@ __global__ void __launch_bounds__(kGmBlock) k_gm_dots(int64_t n, int64_t ld,
     for (int i = 0; i <= L; ++i) acc[i] = 0.0;
     const int64_t np = n >> 1, stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += stride) {
-        const P vp = reinterpret_cast<const P *>(v)[p];
+        const auto vp = gm_ld(v, p);
         const double v0 = (double)vp.x, v1 = (double)vp.y;
 #pragma unroll
         for (int i = 0; i < L; ++i) {
-            const P xp = reinterpret_cast<const P *>(X + i * ld)[p];
+            const auto xp = gm_ld(X + i * ld, p);
             acc[i] += (double)xp.x * v0 + (double)xp.y * v1;
         }
         acc[L] += v0 * v0 + v1 * v1;
@@ -561,12 +576,12 @@ __global__ void __launch_bounds__(kGmBlock) k_gm_dots2(int64_t n, int64_t ld,
     for (int i = 0; i < M; ++i) acc[i] = 0.0;
     const int64_t np = n >> 1, stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += stride) {
-        const P vp = reinterpret_cast<const P *>(vt)[p];
-        const P wp = reinterpret_cast<const P *>(w)[p];
+        const auto vp = gm_ld(vt, p);
+        const auto wp = gm_ld(w, p);
         const double v0 = (double)vp.x, v1 = (double)vp.y, w0 = (double)wp.x, w1 = (double)wp.y;
 #pragma unroll
         for (int i = 0; i < L; ++i) {
-            const P xp = reinterpret_cast<const P *>(X + i * ld)[p];
+            const auto xp = gm_ld(X + i * ld, p);
             const double x0 = (double)xp.x, x1 = (double)xp.y;
             acc[i] += x0 * v0 + x1 * v1;
             acc[L + i] += x0 * w0 + x1 * w1;
@@ -644,25 +659,25 @@ __global__ void __launch_bounds__(kGmBlock) k_gm_update2(int64_t n, int64_t ld,
     }
     const int64_t np = n >> 1, stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += stride) {
-        const P vp = reinterpret_cast<const P *>(vt)[p];
-        const P wp = reinterpret_cast<const P *>(w)[p];
+        const auto vp = gm_ld(vt, p);
+        const auto wp = gm_ld(w, p);
         double a0 = (double)vp.x, a1 = (double)vp.y, b0 = (double)wp.x, b1 = (double)wp.y;
 #pragma unroll
         for (int i = 0; i < L; ++i) {
-            const P xp = reinterpret_cast<const P *>(X + i * ld)[p];
+            const auto xp = gm_ld(X + i * ld, p);
             const double x0 = (double)xp.x, x1 = (double)xp.y;
             a0 -= q[i] * x0;
             a1 -= q[i] * x1;
             b0 -= pv[i] * x0;
             b1 -= pv[i] * x1;
         }
-        P v, o;
+        typename NtPair<T>::type v, o;
         v.x = (T)(a0 * ib);
         v.y = (T)(a1 * ib);
         o.x = (T)((b0 - h * (double)v.x) * c);
         o.y = (T)((b1 - h * (double)v.y) * c);
-        reinterpret_cast<P *>(vt)[p] = v;
-        reinterpret_cast<P *>(out)[p] = o;
+        gm_st<T>(v, vt, p);
+        gm_st<T>(o, out, p);
     }
     if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
         double a = (double)vt[n - 1], b = (double)w[n - 1];
