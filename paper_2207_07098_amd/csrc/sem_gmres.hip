@@ -556,6 +556,38 @@ __global__ void __launch_bounds__(kGmBlock) k_gm_dots(int64_t n, int64_t ld,
     gm_store_sums<L>(acc, part, red);
 }
 
+// x += sum_{i<L} y_i Z_i at the end of a cycle (y = coef[0..L)), summed in
+// the order of i; exact L so that all loads of a point are in flight
+// together, basis pairs streamed non-temporally (x may be only 8-byte
+// aligned: scalar accesses).
+template <int L, typename T>
+__global__ void __launch_bounds__(kGmBlock) k_gm_xupd(int64_t n, int64_t ld,
+                                                      const T *__restrict__ Z,
+                                                      const double *__restrict__ y,
+                                                      T *__restrict__ x) {
+    double c[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) c[i] = y[i];
+    const int64_t np = n >> 1, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += stride) {
+        double s0 = (double)x[2 * p], s1 = (double)x[2 * p + 1];
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const auto zp = gm_ld(Z + i * ld, p);
+            s0 += c[i] * (double)zp.x;
+            s1 += c[i] * (double)zp.y;
+        }
+        x[2 * p] = (T)s0;
+        x[2 * p + 1] = (T)s1;
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {   // odd length: last point
+        double s = (double)x[n - 1];
+#pragma unroll
+        for (int i = 0; i < L; ++i) s += c[i] * (double)Z[i * ld + n - 1];
+        x[n - 1] = (T)s;
+    }
+}
+
 // Arnoldi with delayed reorthogonalisation (classical Gram-Schmidt twice,
 // the second projection of each new vector done during the next step).
 // At step j the basis V_0..V_{L-1} (L = j) is final and slot j holds the
@@ -1387,6 +1419,19 @@ struct GmDots {
     }
 };
 
+// x += Z y, y = coef[0..L)
+template <int L, typename T>
+struct GmXupd {
+    static hipError_t run(sem_gmres G, const T *Z, T *x, hipStream_t s) {
+        static int per_cu = 0;
+        const int64_t n = G->ctx->n_unique;
+        const unsigned g = resident_grid(k_gm_xupd<L, T>, per_cu, G->ctx->num_cus, n / 2);
+        hipLaunchKernelGGL((k_gm_xupd<L, T>), dim3(g), dim3(kGmBlock), 0, s, n, G->ld, Z,
+                           (const double *)G->coef, x);
+        return hipGetLastError();
+    }
+};
+
 // coef[kGmD..] = [X^T vt (L), X^T w (L), vt.vt, vt.w, w.w]
 template <int L, typename T>
 struct GmDots2 {
@@ -1634,9 +1679,7 @@ static sem_status fgmres(sem_gmres G, int prec, const T *b, T *x, bool x_zero, d
             y[i] = sum / H[(size_t)i * m + i];
         }
         SEM_HIP(c, hipMemcpyAsync(G->coef, y.data(), 8 * jdone, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL((k_gm_update<T, T>), dim3(grid), dim3(kGmBlock), 0, s, n, jdone, ld,
-                           (const T *)Z, (const double *)G->coef, x);
-        SEM_HIP(c, hipGetLastError());
+        SEM_HIP(c, (gm_dispatch<GmXupd, T>(jdone, G, (const T *)Z, x, s)));
         if (one_cycle) {
             *res_out = std::fabs(g[jdone]);
             return SEM_OK;
