@@ -13,7 +13,8 @@
 //    (host, once), then u = S (Lambda_r + Lambda_s + Lambda_t)^-1 S^T r with
 //    three tensor contractions each way (a persistent kernel, one workgroup
 //    per element at a time, k-column in registers, r/s contractions through
-//    LDS, the box gathered through a map built at bind time).
+//    LDS, the box gathered through a map built at bind time), in the
+//    precision of the vectors (FP32 tables for the inner FP32 solves).
 //  * Additive combination with counting weights W (1 / number of subdomains
 //    holding the node).
 //  * Coarse grid: the N = 1 operator of the same library on the element
@@ -23,8 +24,10 @@
 //  * Flexible GMRES(m) (the coarse PCG makes the preconditioner nonlinear):
 //    Arnoldi with classical Gram-Schmidt twice, the second projection of
 //    each new vector delayed to the next step (two sweeps over the basis
-//    per step), Givens rotations on the host, FP64 sums throughout; or FP64
-//    refinement around FP32-vector GMRES.
+//    per step, each compiled for the exact basis size and streamed with
+//    non-temporal accesses), Givens rotations on the host, FP64 sums
+//    throughout; or FP64 refinement around FP32-vector GMRES, whose 16-bit
+//    operator steps down to FP32 when its corrections stall.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
