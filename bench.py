@@ -291,6 +291,83 @@ def bench_pressure(op, b, fp64_info, restart=30):
     return out
 
 
+def bench_helmholtz(op, b, h1=0.01, h2=20.0):
+    """The velocity operator h1 A + h2 B on the same mesh: the fused FP64
+    operator (kernel time, roofline on n_L (6s + 4 + 8) + 2 s n_u bytes: the
+    lumped mass is streamed with the factors) and Jacobi-PCG to 1e-10 in
+    FP64 and as FP64 refinement around FP32.  The operator is set back to
+    the Poisson one at the end."""
+    import torch
+    op.set_helmholtz(h1, h2)
+    try:
+        u = torch.from_numpy(F_random(op.n_unique, 3)).cuda()
+        y = torch.zeros_like(u)
+        k_ms = kernel_ms(op, "fp64", u, y, op.n_boundary, torch.cuda.current_stream(), reps=50)
+        B = op.n_local * (6 * 8 + 4 + 8) + 2 * 8 * op.n_unique
+        out = {"h1": h1, "h2": h2, "kernel_ms": k_ms, "bytes_per_launch": B,
+               "roofline_frac": B / (k_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+               "GDOF_per_s_kernel": op.n_unique / (k_ms * 1e-3) / 1e9}
+        log("helmholtz kernel %.3f ms, %.1f%% of 8 TB/s" % (k_ms, 100 * out["roofline_frac"]))
+        del u, y
+        solves = {}
+        for prec in ("fp64", "fp32"):
+            x, info = op.solve(b, tol=1e-10, precision=prec, raise_on_error=False)
+            solves[prec] = info
+            log("helmholtz", prec, json.dumps(info))
+            del x
+        if solves["fp32"]["seconds"] > 0:
+            solves["fp32"]["speedup_vs_fp64"] = solves["fp64"]["seconds"] / solves["fp32"]["seconds"]
+        out["solve"] = solves
+        return out
+    finally:
+        op.set_helmholtz(1.0, 0.0)
+
+
+def F_random(n, seed):
+    import fixtures as F
+    return F.random_unique(n, seed)
+
+
+def bench_projection(op, w, steps=8, max_vectors=20):
+    """Projection of successive solutions: a source moving slowly in time,
+    b_k = B f(x - 0.05 k, y + 0.025 k, z), solved to 1e-10 in FP64
+    Jacobi-PCG with and without the projection space (up to max_vectors
+    corrections)."""
+    import torch
+    import paper_2207_07098_amd as sem
+    xi = sem.gll(op.N)[0]
+    xyz = w.mesh.coords(xi)
+    X0, X1, X2 = (np.ascontiguousarray(xyz[:, a]).reshape(-1) for a in range(3))
+    del xyz
+
+    def rhs(k):
+        fL = np.sin(X0 - 0.05 * k) * np.sin(X1 + 0.025 * k) * np.sin(X2)
+        return op.rhs(f_local=torch.from_numpy(fL).cuda())
+    pr = sem.Projection(op, max_vectors=max_vectors)
+    plain, proj = [], []
+    for k in range(steps):
+        bk = rhs(k)
+        x, i0 = op.solve(bk, tol=1e-10, raise_on_error=False)
+        del x
+        x, i1 = pr.solve(bk, tol=1e-10, raise_on_error=False)
+        del x, bk
+        plain.append(i0)
+        proj.append(i1)
+        log("projection step %d: plain %d its %.3f s, projected %d its %.3f s, start %.2e" % (
+            k, i0["iterations"], i0["seconds"], i1["iterations"], i1["seconds"],
+            i1["start_rel_residual"]))
+    t0 = sum(i["seconds"] for i in plain)
+    t1 = sum(i["seconds"] for i in proj)
+    del pr
+    return {"steps": steps, "max_vectors": max_vectors,
+            "plain_iterations": [i["iterations"] for i in plain],
+            "projected_iterations": [i["iterations"] for i in proj],
+            "projected_start_rel_residual": [i["start_rel_residual"] for i in proj],
+            "plain_seconds": t0, "projected_seconds": t1,
+            "speedup": t0 / t1 if t1 > 0 else None,
+            "all_ok": all(i["status"] == "SEM_OK" for i in plain + proj)}
+
+
 def bench_ogrid(args):
     """256x64x32 O-grid, N = 7: the fused FP64 operator (kernel time,
     roofline), FP64 Jacobi-PCG, FP64 refinement around FP32 and BF16 (matrix
@@ -403,6 +480,10 @@ def main():
     ap.add_argument("--tile", default=None,
                     help="with --operator: elements_per_block:grid_cap:xcd_remap:pipeline")
     ap.add_argument("--no-pressure", action="store_true", help="skip the GMRES pressure solve")
+    ap.add_argument("--no-helmholtz", action="store_true",
+                    help="skip the Helmholtz operator and solves")
+    ap.add_argument("--no-projection", action="store_true",
+                    help="skip the projection of successive solutions")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch")
     ap.add_argument("--no-ogrid", action="store_true",
                     help="skip the 256x64x32 O-grid section (operator and solves)")
@@ -604,6 +685,12 @@ def main():
     if not args.no_solve and not args.no_pressure:
         log("pressure solver (GMRES + hybrid Schwarz) ...")
         result["pressure"] = bench_pressure(op, b, solves.get("fp64"))
+    if not args.no_solve and not args.no_helmholtz:
+        log("helmholtz ...")
+        result["helmholtz"] = bench_helmholtz(op, b)
+    if not args.no_solve and not args.no_projection:
+        log("projection ...")
+        result["projection"] = bench_projection(op, w)
     del op
     torch.cuda.empty_cache()
     if not args.no_batch and args.workload == "box":
